@@ -1,0 +1,519 @@
+/*
+ * cx_oracle.c -- TEST INFRASTRUCTURE ONLY (see cx_oracle.h).
+ *
+ * Plain scalar FP64 implementation of one Chargax environment step, written from
+ * the paper's Appendix A.  Nothing here is blocked, fused or reordered beyond
+ * what the equations state; each env is simulated on its own.  Build flags keep
+ * IEEE semantics: -O2 -ffp-contract=off, no fast-math.
+ */
+#include "cx_oracle.h"
+
+#include <math.h>
+#include <pthread.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+
+struct ox_class {
+  int32_t n_ports, n_nodes, max_depth;
+  int32_t *node_parent, *node_depth;
+  double *node_cap;          /* eta_H * I_H: the right side of Eq. (ArchConst) times eta_H */
+  unsigned char *anc;        /* anc[h * n_ports + i] = 1 iff node h lies on port i's path   */
+  double *pmax, *peta;
+  double p[OXP_COUNT];
+  int32_t ip[OXI_COUNT];
+  uint32_t *tpois;           /* [steps_per_episode][24] */
+  uint32_t *tdwell;          /* [dwell_max], entry 0 unused */
+};
+
+/* ------------------------------------------------------------------------- */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy
+ * as 1, 2, 3", SC'11): ten rounds of two 32x32->64 multiplies with the round
+ * keys bumped by the Weyl constants between rounds.                          */
+void ox_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  const uint32_t m0 = 0xD2511F53u, m1 = 0xCD9E8D57u;
+  const uint32_t w0 = 0x9E3779B9u, w1 = 0xBB67AE85u;
+  uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
+  for (int round = 0; round < 10; ++round) {
+    if (round > 0) {
+      k0 += w0;
+      k1 += w1;
+    }
+    uint64_t prod0 = (uint64_t)m0 * (uint64_t)x0;
+    uint64_t prod1 = (uint64_t)m1 * (uint64_t)x2;
+    uint32_t y0 = (uint32_t)(prod1 >> 32) ^ x1 ^ k0;
+    uint32_t y1 = (uint32_t)prod1;
+    uint32_t y2 = (uint32_t)(prod0 >> 32) ^ x3 ^ k1;
+    uint32_t y3 = (uint32_t)prod0;
+    x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+  }
+  out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+static void philox_seeded(uint64_t seed, uint32_t a, uint32_t b, uint32_t c, uint32_t d,
+                          uint32_t out[4]) {
+  uint32_t ctr[4] = {a, b, c, d};
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  ox_philox4x32_10(ctr, key, out);
+}
+
+double ox_u24(uint32_t w) { return (double)(w >> 8) * (1.0 / 16777216.0); }
+
+/* ------------------------------------------------------------------------- */
+/* Integer thresholds: T = clamp(ceil(2^32 * F) - 1, 0, 2^32 - 1), so that for a
+ * uniform 32-bit word w, P(w <= T) = (T + 1) / 2^32 ~= F.                     */
+static uint32_t threshold_u32(double cdf) {
+  double x = ceil(cdf * 4294967296.0) - 1.0;
+  if (x < 0.0) x = 0.0;
+  if (x > 4294967295.0) x = 4294967295.0;
+  return (uint32_t)x;
+}
+
+/* Arrival counts, Supp. B.1: M(t) ~ Poisson(lambda(t)).  The synthetic average
+ * lambda(t) = peak * (1 - cos(2 pi t / S)) / 2 replaces the bundled per-step
+ * averages.  The CDF is accumulated with the pmf recurrence. */
+static void build_tpois(ox_class *c) {
+  const int32_t S = c->ip[OXI_STEPS_PER_EPISODE];
+  const double peak = c->p[OXP_ARRIVAL_PEAK];
+  for (int32_t t = 0; t < S; ++t) {
+    double lam = 0.5 * peak * (1.0 - cos(2.0 * M_PI * (double)t / (double)S));
+    double pmf = exp(-lam);
+    double cdf = pmf;
+    for (int32_t k = 0; k < OX_K_POIS; ++k) {
+      if (k > 0) {
+        pmf = pmf * lam / (double)k;
+        cdf = cdf + pmf;
+      }
+      c->tpois[t * OX_K_POIS + k] = threshold_u32(cdf);
+    }
+  }
+}
+
+/* Dwell time, App. A.1 "User Profiles": the lognormal stay length rounded to
+ * the nearest step, lumped into 1 below 1.5 and capped at dwell_max.
+ * F(x) = erfc(-(ln x - mu) / (sigma sqrt 2)) / 2 is the lognormal CDF. */
+static void build_tdwell(ox_class *c) {
+  const int32_t D = c->ip[OXI_DWELL_MAX];
+  const double mu = c->p[OXP_DWELL_MU], sigma = c->p[OXP_DWELL_SIGMA];
+  c->tdwell[0] = 0;
+  for (int32_t k = 1; k < D; ++k) {
+    double x = (double)k + 0.5;
+    double F = 0.5 * erfc(-(log(x) - mu) / (sigma * sqrt(2.0)));
+    c->tdwell[k] = threshold_u32(F);
+  }
+}
+
+ox_class *ox_class_new(int32_t n_ports, int32_t n_nodes, const int32_t *node_parent,
+                       const double *node_limit, const double *node_eta,
+                       const int32_t *port_parent, const double *port_pmax,
+                       const double *port_eta, const double *params, const int32_t *iparams) {
+  if (n_ports < 1 || n_ports > OX_MAX_PORTS || n_nodes < 1 || n_nodes > OX_MAX_NODES) return NULL;
+  ox_class *c = (ox_class *)calloc(1, sizeof(ox_class));
+  c->n_ports = n_ports;
+  c->n_nodes = n_nodes;
+  memcpy(c->p, params, sizeof(c->p));
+  memcpy(c->ip, iparams, sizeof(c->ip));
+  c->node_parent = (int32_t *)malloc(sizeof(int32_t) * n_nodes);
+  c->node_depth = (int32_t *)malloc(sizeof(int32_t) * n_nodes);
+  c->node_cap = (double *)malloc(sizeof(double) * n_nodes);
+  c->anc = (unsigned char *)calloc((size_t)n_nodes * n_ports, 1);
+  c->pmax = (double *)malloc(sizeof(double) * n_ports);
+  c->peta = (double *)malloc(sizeof(double) * n_ports);
+  c->max_depth = 0;
+  for (int32_t h = 0; h < n_nodes; ++h) {
+    c->node_parent[h] = node_parent[h];
+    c->node_cap[h] = node_eta[h] * node_limit[h];
+    int32_t d = 0;
+    for (int32_t a = node_parent[h]; a >= 0; a = node_parent[a]) ++d;
+    c->node_depth[h] = d;
+    if (d > c->max_depth) c->max_depth = d;
+  }
+  for (int32_t i = 0; i < n_ports; ++i) {
+    c->pmax[i] = port_pmax[i];
+    c->peta[i] = port_eta[i];
+    for (int32_t a = port_parent[i]; a >= 0; a = node_parent[a]) c->anc[(size_t)a * n_ports + i] = 1;
+  }
+  c->tpois = (uint32_t *)malloc(sizeof(uint32_t) * c->ip[OXI_STEPS_PER_EPISODE] * OX_K_POIS);
+  c->tdwell = (uint32_t *)malloc(sizeof(uint32_t) * c->ip[OXI_DWELL_MAX]);
+  build_tpois(c);
+  build_tdwell(c);
+  return c;
+}
+
+void ox_class_free(ox_class *c) {
+  if (!c) return;
+  free(c->node_parent); free(c->node_depth); free(c->node_cap); free(c->anc);
+  free(c->pmax); free(c->peta); free(c->tpois); free(c->tdwell);
+  free(c);
+}
+
+int32_t ox_class_ports(const ox_class *c) { return c->n_ports; }
+int32_t ox_obs_dim(const ox_class *c) { return 6 * c->n_ports + 4; }
+
+void ox_class_tables(const ox_class *c, uint32_t *tpois, uint32_t *tdwell) {
+  if (tpois) memcpy(tpois, c->tpois, sizeof(uint32_t) * c->ip[OXI_STEPS_PER_EPISODE] * OX_K_POIS);
+  if (tdwell) memcpy(tdwell, c->tdwell, sizeof(uint32_t) * c->ip[OXI_DWELL_MAX]);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Charging curve r_hat(SoC) of App. A.1 "Car Profiles", with r_bar = port max. */
+static double charge_rate(double pmax, double tau, double soc) {
+  if (soc <= tau) return pmax;
+  return (1.0 - soc) * pmax / (1.0 - tau);
+}
+
+/* Eq. (ArchConst): for every subtree H, sum of its leaves' powers <= eta_H I_H.
+ * Violations are removed by rescaling the leaves of the violated subtree
+ * proportionally, deepest subtrees first, so that a parent sees the already
+ * rescaled loads of its children. */
+void ox_project(const ox_class *c, double *P) {
+  const int32_t N = c->n_ports;
+  for (int32_t d = c->max_depth; d >= 0; --d) {
+    for (int32_t h = 0; h < c->n_nodes; ++h) {
+      if (c->node_depth[h] != d) continue;
+      const unsigned char *in = c->anc + (size_t)h * N;
+      double S = 0.0;
+      for (int32_t i = 0; i < N; ++i)
+        if (in[i]) S += P[i];
+      if (S > c->node_cap[h]) {
+        double f = c->node_cap[h] / S;
+        for (int32_t i = 0; i < N; ++i)
+          if (in[i]) P[i] = P[i] * f;
+      }
+    }
+  }
+}
+
+/* App. A.2 "Apply Actions" with absolute discrete levels (Supp. B.1): the
+ * requested power k/L * pmax is clipped by the car's current charge rate and by
+ * the energy that would fill its battery within one step. */
+void ox_apply_actions(const ox_class *c, const int32_t *dwell, const double *soc,
+                      const double *cap, const int32_t *k, double *P) {
+  const double tau = c->p[OXP_TAU], dt = c->p[OXP_DT];
+  const int32_t L = c->ip[OXI_N_LEVELS];
+  for (int32_t i = 0; i < c->n_ports; ++i) {
+    if (dwell[i] > 0) {
+      double req = (double)k[i] / (double)L * c->pmax[i];
+      double rhat = charge_rate(c->pmax[i], tau, soc[i]);
+      double room = (1.0 - soc[i]) * cap[i] / dt;
+      double v = req;
+      if (rhat < v) v = rhat;
+      if (room < v) v = room;
+      P[i] = v;
+    } else {
+      P[i] = 0.0;
+    }
+  }
+  ox_project(c, P);
+}
+
+/* ------------------------------------------------------------------------- */
+void ox_draw_exo(const ox_class *c, uint64_t seed, uint32_t env, uint32_t g, int32_t t_day,
+                 ox_exo *x) {
+  const int32_t S = c->ip[OXI_STEPS_PER_EPISODE];
+  uint32_t w[4];
+  philox_seeded(seed, env, g, 0u, OX_DOM_ENV, w);
+  /* arrivals: M = number of thresholds the word exceeds */
+  const uint32_t *row = c->tpois + (size_t)t_day * OX_K_POIS;
+  int32_t M = 0;
+  for (int32_t k = 0; k < OX_K_POIS; ++k)
+    if (w[0] > row[k]) ++M;
+  x->M = M;
+  /* price noise: Box-Muller on two 24-bit uniforms */
+  double u1 = ((double)(w[1] >> 8) + 1.0) * (1.0 / 16777216.0);
+  double u2 = ox_u24(w[2]);
+  x->z = sqrt(-2.0 * log(u1)) * cos(2.0 * M_PI * u2);
+  x->p_buy = c->p[OXP_PRICE_BASE] + c->p[OXP_PRICE_AMP] * sin(2.0 * M_PI * (double)t_day / (double)S) +
+             c->p[OXP_PRICE_SIGMA] * x->z;
+  /* car and user profiles of every arriving car j (App. A.2 "Arrival of new Cars") */
+  const int32_t D = c->ip[OXI_DWELL_MAX];
+  for (int32_t j = 0; j < M; ++j) {
+    uint32_t b[4];
+    philox_seeded(seed, env, g, (uint32_t)j, OX_DOM_CAR, b);
+    x->car_cap[j] = c->p[OXP_CAP_LO] + (c->p[OXP_CAP_HI] - c->p[OXP_CAP_LO]) * ox_u24(b[0]);
+    x->car_soc[j] = c->p[OXP_SOC0_LO] + (c->p[OXP_SOC0_HI] - c->p[OXP_SOC0_LO]) * ox_u24(b[1]);
+    x->car_tgt[j] = c->p[OXP_TGT_LO] + (c->p[OXP_TGT_HI] - c->p[OXP_TGT_LO]) * ox_u24(b[2]);
+    int32_t d = 1;
+    for (int32_t k = 1; k < D; ++k)
+      if (b[3] > c->tdwell[k]) ++d;
+    x->car_dwell[j] = d;
+  }
+}
+
+void ox_draw_actions(const ox_class *c, int32_t mode, uint64_t seed, uint32_t env, uint32_t g,
+                     const uint8_t *ext, int32_t *k) {
+  const int32_t L = c->ip[OXI_N_LEVELS];
+  for (int32_t i = 0; i < c->n_ports; ++i) {
+    if (mode == OX_ACT_RANDOM) {
+      uint32_t w[4];
+      philox_seeded(seed, env, g >> 2, (uint32_t)i, OX_DOM_ACT, w);
+      k[i] = (int32_t)(((uint64_t)w[g & 3u] * (uint64_t)(L + 1)) >> 32);
+    } else if (mode == OX_ACT_MAX) {
+      k[i] = L;
+    } else {
+      k[i] = ext[i] > L ? L : (int32_t)ext[i];
+    }
+  }
+}
+
+/* ------------------------------------------------------------------------- */
+void ox_observe(const ox_class *c, const int32_t *dwell, const double *soc, const double *e_rem,
+                const double *cap, const double *p_last, int32_t t_day, double *obs) {
+  const int32_t N = c->n_ports, S = c->ip[OXI_STEPS_PER_EPISODE];
+  const double tau = c->p[OXP_TAU];
+  int32_t n_occ = 0;
+  for (int32_t i = 0; i < N; ++i) {
+    int32_t occ = dwell[i] > 0;
+    n_occ += occ;
+    obs[0 * N + i] = occ ? 1.0 : 0.0;
+    obs[1 * N + i] = occ ? soc[i] : 0.0;
+    obs[2 * N + i] = occ ? e_rem[i] / cap[i] : 0.0;
+    obs[3 * N + i] = (double)dwell[i] / (double)S;
+    obs[4 * N + i] = occ ? charge_rate(c->pmax[i], tau, soc[i]) / c->pmax[i] : 0.0;
+    obs[5 * N + i] = occ ? p_last[i] / c->pmax[i] : 0.0;
+  }
+  double ang = 2.0 * M_PI * (double)t_day / (double)S;
+  obs[6 * N + 0] = sin(ang);
+  obs[6 * N + 1] = cos(ang);
+  obs[6 * N + 2] = c->p[OXP_PRICE_BASE] + c->p[OXP_PRICE_AMP] * sin(ang);
+  obs[6 * N + 3] = (double)n_occ / (double)N;
+}
+
+static void clear_port(int32_t i, int32_t *dwell, double *soc, double *e_rem, double *cap,
+                       double *p_last) {
+  dwell[i] = 0; soc[i] = 0.0; e_rem[i] = 0.0; cap[i] = 0.0; p_last[i] = 0.0;
+}
+
+/* App. A.2: (i) apply actions, (ii) charge, (iii) departures, (iv) arrivals;
+ * then the reward of App. A.3 and the day boundary of Supp. B.1. */
+void ox_transition(const ox_class *c, int32_t *dwell, double *soc, double *e_rem, double *cap,
+                   double *p_last, double *ret, int32_t *t_day, const int32_t *k,
+                   const ox_exo *x, ox_step_info *info, double *obs, double *P_out) {
+  const int32_t N = c->n_ports;
+  const double dt = c->p[OXP_DT];
+  double P[OX_MAX_PORTS];
+  unsigned char was_occ[OX_MAX_PORTS];
+
+  /* (i) apply actions */
+  ox_apply_actions(c, dwell, soc, cap, k, P);
+  if (P_out)
+    for (int32_t i = 0; i < N; ++i) P_out[i] = P[i];
+
+  /* (ii) charge stationed cars; energies of App. A.3 (charging only) */
+  double e_net = 0.0, e_grid = 0.0;
+  for (int32_t i = 0; i < N; ++i) {
+    was_occ[i] = dwell[i] > 0;
+    if (!was_occ[i]) continue;
+    double e = dt * P[i];
+    double s = soc[i] + e / cap[i];
+    soc[i] = s > 1.0 ? 1.0 : s;
+    e_rem[i] = e_rem[i] - e;
+    e_net += e;
+    e_grid += e / c->peta[i];
+    p_last[i] = P[i];
+    dwell[i] -= 1;
+  }
+
+  /* (iii) departures of time-sensitive users; c_satisfaction,0 */
+  double c_sat = 0.0;
+  int32_t n_dep = 0;
+  for (int32_t i = 0; i < N; ++i) {
+    if (was_occ[i] && dwell[i] == 0) {
+      c_sat += e_rem[i] > 0.0 ? e_rem[i] : 0.0;
+      ++n_dep;
+      clear_port(i, dwell, soc, e_rem, cap, p_last);
+    }
+  }
+
+  /* (iv) arrivals: clip by free spots, first free ports in port order */
+  int32_t n_free = 0;
+  for (int32_t i = 0; i < N; ++i) n_free += dwell[i] == 0;
+  int32_t acc = x->M < n_free ? x->M : n_free;
+  int32_t rej = x->M - acc;
+  int32_t j = 0;
+  for (int32_t i = 0; i < N && j < acc; ++i) {
+    if (dwell[i] != 0) continue;
+    dwell[i] = x->car_dwell[j];
+    soc[i] = x->car_soc[j];
+    cap[i] = x->car_cap[j];
+    e_rem[i] = (x->car_tgt[j] - x->car_soc[j]) * x->car_cap[j];
+    p_last[i] = 0.0;
+    ++j;
+  }
+
+  /* reward: profit minus penalties */
+  double price = e_grid > 0.0 ? x->p_buy : c->p[OXP_P_SELL_GRID];
+  double profit = c->p[OXP_P_SELL] * e_net - price * e_grid - c->p[OXP_FIXED_COST];
+  double reward = profit - c->p[OXP_ALPHA_SAT] * c_sat - c->p[OXP_ALPHA_DEC] * (double)rej;
+  *ret += reward;
+
+  /* time and the end of the day */
+  *t_day += 1;
+  int32_t done = *t_day == c->ip[OXI_STEPS_PER_EPISODE];
+  if (done) {
+    for (int32_t i = 0; i < N; ++i) clear_port(i, dwell, soc, e_rem, cap, p_last);
+    *t_day = 0;
+  }
+  int32_t n_occ = 0;
+  for (int32_t i = 0; i < N; ++i) n_occ += dwell[i] > 0;
+
+  if (info) {
+    info->reward = reward; info->profit = profit; info->e_net = e_net; info->e_grid = e_grid;
+    info->c_sat = c_sat; info->M = x->M; info->acc = acc; info->rej = rej; info->n_dep = n_dep;
+    info->done = done; info->n_occ = n_occ;
+  }
+  if (obs) ox_observe(c, dwell, soc, e_rem, cap, p_last, *t_day, obs);
+}
+
+/* ------------------------------------------------------------------------- */
+typedef struct {
+  ox_class *const *classes;
+  const int32_t *env_class;
+  const int64_t *port_off, *obs_off;
+  int64_t total_ports, total_obs, n_envs;
+  int64_t e_begin, e_end;
+  uint64_t seed;
+  uint32_t g0;
+  int32_t t0, T, mode;
+  const uint8_t *act_in;
+  int32_t *dwell;
+  double *soc, *e_rem, *cap, *p_last, *ret, *obs, *reward;
+  uint8_t *act, *done;
+  ox_step_info *info;
+} rollout_job;
+
+static void *rollout_worker(void *arg) {
+  rollout_job *J = (rollout_job *)arg;
+  int32_t k[OX_MAX_PORTS];
+  ox_exo x;
+  for (int64_t e = J->e_begin; e < J->e_end; ++e) {
+    const ox_class *c = J->classes[J->env_class[e]];
+    const int64_t po = J->port_off[e], oo = J->obs_off[e];
+    const int32_t N = c->n_ports;
+    int32_t t_day = J->t0;
+    for (int32_t t = 0; t < J->T; ++t) {
+      uint32_t g = J->g0 + (uint32_t)t;
+      const uint8_t *ext = J->act_in ? J->act_in + (size_t)t * J->total_ports + po : NULL;
+      ox_draw_actions(c, J->mode, J->seed, (uint32_t)e, g, ext, k);
+      ox_draw_exo(c, J->seed, (uint32_t)e, g, t_day, &x);
+      ox_step_info inf;
+      double *o = J->obs ? J->obs + (size_t)t * J->total_obs + oo : NULL;
+      ox_transition(c, J->dwell + po, J->soc + po, J->e_rem + po, J->cap + po, J->p_last + po,
+                    J->ret + e, &t_day, k, &x, &inf, o, NULL);
+      if (J->act)
+        for (int32_t i = 0; i < N; ++i) J->act[(size_t)t * J->total_ports + po + i] = (uint8_t)k[i];
+      if (J->reward) J->reward[(size_t)t * J->n_envs + e] = inf.reward;
+      if (J->done) J->done[(size_t)t * J->n_envs + e] = (uint8_t)inf.done;
+      if (J->info) J->info[(size_t)t * J->n_envs + e] = inf;
+    }
+  }
+  return NULL;
+}
+
+int32_t ox_rollout(ox_class *const *classes, const int32_t *env_class, int64_t n_envs,
+                   uint64_t seed, uint32_t *g, int32_t *t_day, int32_t T, int32_t mode,
+                   const uint8_t *act_in, int32_t *dwell, double *soc, double *e_rem,
+                   double *cap, double *p_last, double *ret, double *obs, uint8_t *act,
+                   double *reward, uint8_t *done, ox_step_info *info, int32_t n_threads) {
+  int64_t *port_off = (int64_t *)malloc(sizeof(int64_t) * (n_envs + 1));
+  int64_t *obs_off = (int64_t *)malloc(sizeof(int64_t) * (n_envs + 1));
+  port_off[0] = obs_off[0] = 0;
+  for (int64_t e = 0; e < n_envs; ++e) {
+    const ox_class *c = classes[env_class[e]];
+    port_off[e + 1] = port_off[e] + c->n_ports;
+    obs_off[e + 1] = obs_off[e] + 6 * c->n_ports + 4;
+  }
+  if (n_threads < 1) n_threads = 1;
+  if (n_threads > n_envs) n_threads = n_envs > 0 ? (int32_t)n_envs : 1;
+  rollout_job *jobs = (rollout_job *)calloc((size_t)n_threads, sizeof(rollout_job));
+  pthread_t *th = (pthread_t *)calloc((size_t)n_threads, sizeof(pthread_t));
+  for (int32_t w = 0; w < n_threads; ++w) {
+    rollout_job *J = &jobs[w];
+    J->classes = classes; J->env_class = env_class; J->port_off = port_off; J->obs_off = obs_off;
+    J->total_ports = port_off[n_envs]; J->total_obs = obs_off[n_envs]; J->n_envs = n_envs;
+    J->e_begin = n_envs * w / n_threads; J->e_end = n_envs * (w + 1) / n_threads;
+    J->seed = seed; J->g0 = *g; J->t0 = *t_day; J->T = T; J->mode = mode; J->act_in = act_in;
+    J->dwell = dwell; J->soc = soc; J->e_rem = e_rem; J->cap = cap; J->p_last = p_last;
+    J->ret = ret; J->obs = obs; J->act = act; J->reward = reward; J->done = done; J->info = info;
+  }
+  if (n_threads == 1) {
+    rollout_worker(&jobs[0]);
+  } else {
+    for (int32_t w = 0; w < n_threads; ++w) pthread_create(&th[w], NULL, rollout_worker, &jobs[w]);
+    for (int32_t w = 0; w < n_threads; ++w) pthread_join(th[w], NULL);
+  }
+  *g += (uint32_t)T;
+  *t_day = (int32_t)(((int64_t)*t_day + T) % classes[env_class[0]]->ip[OXI_STEPS_PER_EPISODE]);
+  free(jobs); free(th); free(port_off); free(obs_off);
+  return n_threads;
+}
+
+/* ------------------------------------------------------------------------- */
+/* BF16 = the upper 16 bits of an IEEE single; round-to-nearest-even from FP64. */
+double ox_bf16_round(double x) {
+  if (x == 0.0 || !isfinite(x)) return (double)(float)x;
+  int e;
+  frexp(x, &e);                       /* x = m 2^e, 0.5 <= |m| < 1 */
+  double ulp = ldexp(1.0, e - 8);     /* 8 significant bits */
+  double q = x / ulp;
+  double r = nearbyint(q);            /* default rounding mode: nearest-even */
+  return r * ulp;
+}
+
+static double bf16_bits_to_double(uint16_t b) {
+  uint32_t u = (uint32_t)b << 16;
+  float f;
+  memcpy(&f, &u, sizeof f);
+  return (double)f;
+}
+
+/* Policy of the policy-in-the-loop workload: a two-layer perceptron over the
+ * observation, tanh hidden units, one logit per (port, level), and a level per
+ * port drawn by the Gumbel-max rule with Philox noise. */
+void ox_policy(const ox_class *c, int32_t hidden, const uint16_t *w1, const uint16_t *b1,
+               const uint16_t *w2, const uint16_t *b2, const double *obs, uint64_t seed,
+               uint32_t env, uint32_t g, double *logits, int32_t *k) {
+  const int32_t N = c->n_ports, L = c->ip[OXI_N_LEVELS];
+  const int32_t in = 6 * N + 4, out = N * (L + 1);
+  double *x = (double *)malloc(sizeof(double) * in);
+  double *h = (double *)malloc(sizeof(double) * hidden);
+  double *z = (double *)malloc(sizeof(double) * out);
+  for (int32_t i = 0; i < in; ++i) x[i] = ox_bf16_round(obs[i]);
+  for (int32_t j = 0; j < hidden; ++j) {
+    double a = bf16_bits_to_double(b1[j]);
+    for (int32_t i = 0; i < in; ++i) a += x[i] * bf16_bits_to_double(w1[(size_t)i * hidden + j]);
+    h[j] = ox_bf16_round(tanh(a));
+  }
+  for (int32_t o = 0; o < out; ++o) {
+    double a = bf16_bits_to_double(b2[o]);
+    for (int32_t j = 0; j < hidden; ++j) a += h[j] * bf16_bits_to_double(w2[(size_t)j * out + o]);
+    z[o] = a;
+  }
+  const int32_t Q = (L + 1 + 3) / 4;
+  for (int32_t i = 0; i < N; ++i) {
+    int32_t best = 0;
+    double best_v = -INFINITY;
+    for (int32_t q = 0; q < Q; ++q) {
+      uint32_t w[4];
+      philox_seeded(seed, env, g, (uint32_t)(i * Q + q), OX_DOM_GUM, w);
+      for (int32_t r = 0; r < 4; ++r) {
+        int32_t lev = 4 * q + r;
+        if (lev > L) break;
+        double u = ((double)(w[r] >> 8) + 0.5) * (1.0 / 16777216.0);
+        double v = z[i * (L + 1) + lev] - log(-log(u));
+        if (v > best_v) {
+          best_v = v;
+          best = lev;
+        }
+      }
+    }
+    k[i] = best;
+  }
+  if (logits)
+    for (int32_t o = 0; o < out; ++o) logits[o] = z[o];
+  free(x); free(h); free(z);
+}

@@ -1,0 +1,274 @@
+"""ctypes wrapper of the FP64 C oracle -- TEST INFRASTRUCTURE ONLY.
+
+Only tests, the smoke entry point and the benchmark's CPU-baseline leg use this
+module.  It shares no code with the HIP library.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "libcx_oracle.so")
+
+ACT_EXTERNAL, ACT_RANDOM, ACT_MAX = 0, 1, 2
+K_POIS = 24
+
+_P_ORDER = ["dt_hours", "tau", "p_sell", "p_sell_grid", "fixed_cost", "alpha_sat", "alpha_declined",
+            "price_base", "price_amp", "price_sigma", "arrival_peak", "cap_lo", "cap_hi", "soc0_lo",
+            "soc0_hi", "tgt_lo", "tgt_hi", "dwell_mu", "dwell_sigma"]
+_I_ORDER = ["steps_per_episode", "n_levels", "dwell_max"]
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (IEEE semantics: no fast-math, no FMA contraction)."""
+    if force or not os.path.exists(_SO):
+        src = os.path.join(_HERE, "cx_oracle.c")
+        tmp = _SO + ".tmp"
+        subprocess.check_call(["gcc", "-O3", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+                               "-pthread", "-o", tmp, src, "-lm"])
+        os.replace(tmp, _SO)
+    return _SO
+
+
+class StepInfo(C.Structure):
+    _fields_ = [("reward", C.c_double), ("profit", C.c_double), ("e_net", C.c_double),
+                ("e_grid", C.c_double), ("c_sat", C.c_double), ("M", C.c_int32), ("acc", C.c_int32),
+                ("rej", C.c_int32), ("n_dep", C.c_int32), ("done", C.c_int32), ("n_occ", C.c_int32)]
+
+
+class Exo(C.Structure):
+    _fields_ = [("M", C.c_int32), ("z", C.c_double), ("p_buy", C.c_double),
+                ("car_cap", C.c_double * K_POIS), ("car_soc", C.c_double * K_POIS),
+                ("car_tgt", C.c_double * K_POIS), ("car_dwell", C.c_int32 * K_POIS)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            build(force=False)
+        L = C.CDLL(_SO)
+        P, I = C.c_void_p, C.c_int32
+        L.ox_class_new.restype = P
+        L.ox_class_new.argtypes = [I, I, P, P, P, P, P, P, P, P]
+        L.ox_class_free.argtypes = [P]
+        L.ox_class_tables.argtypes = [P, P, P]
+        L.ox_philox4x32_10.argtypes = [P, P, P]
+        L.ox_u24.restype = C.c_double
+        L.ox_u24.argtypes = [C.c_uint32]
+        L.ox_project.argtypes = [P, P]
+        L.ox_apply_actions.argtypes = [P, P, P, P, P, P]
+        L.ox_draw_exo.argtypes = [P, C.c_uint64, C.c_uint32, C.c_uint32, I, P]
+        L.ox_draw_actions.argtypes = [P, I, C.c_uint64, C.c_uint32, C.c_uint32, P, P]
+        L.ox_transition.argtypes = [P] * 13
+        L.ox_observe.argtypes = [P, P, P, P, P, P, I, P]
+        L.ox_rollout.restype = I
+        L.ox_rollout.argtypes = [P, P, C.c_int64, C.c_uint64, P, P, I, I, P, P, P, P, P, P, P, P,
+                                 P, P, P, P, I]
+        L.ox_policy.argtypes = [P, I, P, P, P, P, P, C.c_uint64, C.c_uint32, C.c_uint32, P, P]
+        L.ox_bf16_round.restype = C.c_double
+        L.ox_bf16_round.argtypes = [C.c_double]
+        _lib = L
+    return _lib
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def philox(ctr: Sequence[int], key: Sequence[int]) -> np.ndarray:
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib().ox_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def bf16_round(x: float) -> float:
+    return lib().ox_bf16_round(float(x))
+
+
+class OracleClass:
+    """One station class inside the oracle (architecture + parameters + its tables)."""
+
+    def __init__(self, spec):
+        self.spec = spec
+        self._keep = [
+            np.ascontiguousarray(spec.node_parent, dtype=np.int32),
+            np.ascontiguousarray(spec.node_limit_kw, dtype=np.float64),
+            np.ascontiguousarray(spec.node_eta, dtype=np.float64),
+            np.ascontiguousarray(spec.port_parent, dtype=np.int32),
+            np.ascontiguousarray(spec.port_pmax_kw, dtype=np.float64),
+            np.ascontiguousarray(spec.port_eta, dtype=np.float64),
+            np.array([getattr(spec, k) for k in _P_ORDER], dtype=np.float64),
+            np.array([getattr(spec, k) for k in _I_ORDER], dtype=np.int32),
+        ]
+        h = lib().ox_class_new(spec.n_ports, len(spec.node_parent), *[_ptr(a) for a in self._keep])
+        if not h:
+            raise ValueError("oracle rejected the station spec")
+        self.h = C.c_void_p(h)
+        self.n = spec.n_ports
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                lib().ox_class_free(self.h)
+        except Exception:
+            pass
+
+    @property
+    def obs_dim(self) -> int:
+        return 6 * self.n + 4
+
+    def tables(self):
+        tp = np.zeros((self.spec.steps_per_episode, K_POIS), dtype=np.uint32)
+        td = np.zeros(self.spec.dwell_max, dtype=np.uint32)
+        lib().ox_class_tables(self.h, _ptr(tp), _ptr(td))
+        return tp, td
+
+    def project(self, P) -> np.ndarray:
+        P = np.array(P, dtype=np.float64)
+        lib().ox_project(self.h, _ptr(P))
+        return P
+
+    def apply_actions(self, dwell, soc, cap, k) -> np.ndarray:
+        d = np.ascontiguousarray(dwell, dtype=np.int32)
+        s = np.ascontiguousarray(soc, dtype=np.float64)
+        c = np.ascontiguousarray(cap, dtype=np.float64)
+        kk = np.ascontiguousarray(k, dtype=np.int32)
+        P = np.zeros(self.n, dtype=np.float64)
+        lib().ox_apply_actions(self.h, _ptr(d), _ptr(s), _ptr(c), _ptr(kk), _ptr(P))
+        return P
+
+    def draw_exo(self, seed: int, env: int, g: int, t_day: int) -> Exo:
+        x = Exo()
+        lib().ox_draw_exo(self.h, seed, env, g, t_day, C.byref(x))
+        return x
+
+    def draw_actions(self, mode: int, seed: int, env: int, g: int, ext=None) -> np.ndarray:
+        k = np.zeros(self.n, dtype=np.int32)
+        e = None if ext is None else np.ascontiguousarray(ext, dtype=np.uint8)
+        lib().ox_draw_actions(self.h, mode, seed, env, g, _ptr(e), _ptr(k))
+        return k
+
+    def observe(self, st: "EnvState") -> np.ndarray:
+        obs = np.zeros(self.obs_dim, dtype=np.float64)
+        lib().ox_observe(self.h, _ptr(st.dwell), _ptr(st.soc), _ptr(st.e_rem), _ptr(st.cap),
+                         _ptr(st.p_last), st.t_day, _ptr(obs))
+        return obs
+
+    def transition(self, st: "EnvState", k, exo: Exo):
+        """One step of one env, state in place; returns (StepInfo, obs, applied powers)."""
+        kk = np.ascontiguousarray(k, dtype=np.int32)
+        info = StepInfo()
+        obs = np.zeros(self.obs_dim, dtype=np.float64)
+        P = np.zeros(self.n, dtype=np.float64)
+        ret = C.c_double(st.ret)
+        t_day = C.c_int32(st.t_day)
+        lib().ox_transition(self.h, _ptr(st.dwell), _ptr(st.soc), _ptr(st.e_rem), _ptr(st.cap),
+                            _ptr(st.p_last), C.byref(ret), C.byref(t_day), _ptr(kk), C.byref(exo),
+                            C.byref(info), _ptr(obs), _ptr(P))
+        st.ret = ret.value
+        st.t_day = t_day.value
+        return info, obs, P
+
+    def policy(self, hidden: int, weights, obs, seed: int, env: int, g: int):
+        w1, b1, w2, b2 = [np.ascontiguousarray(w, dtype=np.uint16) for w in weights]
+        o = np.ascontiguousarray(obs, dtype=np.float64)
+        L = self.spec.n_levels
+        logits = np.zeros(self.n * (L + 1), dtype=np.float64)
+        k = np.zeros(self.n, dtype=np.int32)
+        lib().ox_policy(self.h, hidden, _ptr(w1), _ptr(b1), _ptr(w2), _ptr(b2), _ptr(o), seed, env, g,
+                        _ptr(logits), _ptr(k))
+        return logits, k
+
+
+class EnvState:
+    """Mutable state of one env (port-major arrays) for single-env tests."""
+
+    def __init__(self, n_ports: int):
+        self.dwell = np.zeros(n_ports, dtype=np.int32)
+        self.soc = np.zeros(n_ports, dtype=np.float64)
+        self.e_rem = np.zeros(n_ports, dtype=np.float64)
+        self.cap = np.zeros(n_ports, dtype=np.float64)
+        self.p_last = np.zeros(n_ports, dtype=np.float64)
+        self.ret = 0.0
+        self.t_day = 0
+
+    def put_car(self, port: int, soc: float, cap: float, dwell: int, e_rem: float):
+        self.dwell[port] = dwell
+        self.soc[port] = soc
+        self.cap[port] = cap
+        self.e_rem[port] = e_rem
+
+
+def exo(M: int = 0, p_buy: float = 0.25, cars=()) -> Exo:
+    """Hand-built exogenous input: cars = [(cap, soc0, tgt, dwell), ...]."""
+    x = Exo()
+    x.M = M
+    x.z = 0.0
+    x.p_buy = p_buy
+    for j, (cap, soc0, tgt, dwell) in enumerate(cars):
+        x.car_cap[j], x.car_soc[j], x.car_tgt[j], x.car_dwell[j] = cap, soc0, tgt, dwell
+    return x
+
+
+class BatchState:
+    """State of many envs for ox_rollout (port-major, envs concatenated)."""
+
+    def __init__(self, classes: Sequence[OracleClass], env_class: np.ndarray):
+        self.classes = list(classes)
+        self.env_class = np.ascontiguousarray(env_class, dtype=np.int32)
+        ports = np.array([c.n for c in self.classes], dtype=np.int64)[self.env_class]
+        self.port_off = np.concatenate([[0], np.cumsum(ports)])
+        obs = 6 * ports + 4
+        self.obs_off = np.concatenate([[0], np.cumsum(obs)])
+        P = int(self.port_off[-1])
+        self.n_envs = len(self.env_class)
+        self.total_ports = P
+        self.total_obs = int(self.obs_off[-1])
+        self.dwell = np.zeros(P, dtype=np.int32)
+        self.soc = np.zeros(P)
+        self.e_rem = np.zeros(P)
+        self.cap = np.zeros(P)
+        self.p_last = np.zeros(P)
+        self.ret = np.zeros(self.n_envs)
+        self.g = 0
+        self.t_day = 0
+
+
+def rollout(bs: BatchState, seed: int, T: int, mode: int = ACT_RANDOM, act_in=None,
+            want_obs: bool = True, want_act: bool = True, want_info: bool = False,
+            n_threads: int = 0):
+    """Run T steps of every env; returns dict of outputs (obs, act, reward, done, info)."""
+    if n_threads <= 0:
+        n_threads = max(1, min(16, os.cpu_count() or 1))
+    handles = (C.c_void_p * len(bs.classes))(*[c.h.value for c in bs.classes])
+    obs = np.zeros((T, bs.total_obs)) if want_obs else None
+    act = np.zeros((T, bs.total_ports), dtype=np.uint8) if want_act else None
+    rew = np.zeros((T, bs.n_envs))
+    done = np.zeros((T, bs.n_envs), dtype=np.uint8)
+    info = (StepInfo * (T * bs.n_envs))() if want_info else None
+    ain = None if act_in is None else np.ascontiguousarray(act_in, dtype=np.uint8)
+    g = C.c_uint32(bs.g)
+    t_day = C.c_int32(bs.t_day)
+    used = lib().ox_rollout(handles, _ptr(bs.env_class), bs.n_envs, seed, C.byref(g), C.byref(t_day),
+                            T, mode, _ptr(ain), _ptr(bs.dwell), _ptr(bs.soc), _ptr(bs.e_rem),
+                            _ptr(bs.cap), _ptr(bs.p_last), _ptr(bs.ret), _ptr(obs), _ptr(act),
+                            _ptr(rew), _ptr(done), None if info is None else C.cast(info, C.c_void_p),
+                            n_threads)
+    bs.g = g.value
+    bs.t_day = t_day.value
+    out = {"obs": obs, "act": act, "reward": rew, "done": done, "threads": used}
+    if want_info:
+        arr = np.ctypeslib.as_array(info).reshape(T, bs.n_envs)
+        out["info"] = {f: np.array(arr[f]) for f, _ in StepInfo._fields_}
+    return out

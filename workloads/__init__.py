@@ -1,0 +1,252 @@
+"""Seeded synthetic inputs shared by the oracle tests, the GPU tests and the benchmark.
+
+This module describes *inputs* only -- station architectures, their parameters,
+class mixtures, request streams and random policy weights.  It contains none of
+the simulator's arithmetic; both the oracle and the HIP library consume what it
+returns.
+
+The paper's bundled datasets (price series, car and user profiles, traffic
+levels; Table 1) are not available, so the synthetic distributions below stand
+in for them:
+
+* arrivals: Poisson with a day-shaped rate peaking at 0.3 cars per 5-minute step
+  for a 16-port station (scaled by ports/16 for other sizes);
+* cars: capacity U[40, 100] kWh, arrival SoC U[0.1, 0.5], target SoC U[0.7, 1.0],
+  dwell lognormal(mu = ln 36 steps, sigma = 0.5);
+* grid price 0.25 + 0.1 sin(2 pi t / 288) + N(0, 0.02) EUR/kWh, sell price 0.45;
+* architectures as trees of splitters/transformers (Sec. 3 "EV Station Layout").
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Sequence, Tuple
+
+import numpy as np
+
+STEPS_PER_DAY = 288          # 24 h of 5-minute steps (Table 3)
+PMAX_KW = 22.0
+
+
+@dataclasses.dataclass
+class StationSpec:
+    """One station architecture plus its environment parameters.
+
+    Nodes are the internal tree nodes (node 0 is the grid connection, every
+    node's parent has a smaller index); ports are the leaves, listed in
+    depth-first order so that every node's ports are contiguous.
+    """
+
+    n_ports: int
+    node_parent: List[int]
+    node_limit_kw: List[float]
+    node_eta: List[float]
+    port_parent: List[int]
+    port_pmax_kw: List[float]
+    port_eta: List[float]
+    dt_hours: float = 5.0 / 60.0
+    tau: float = 0.8
+    p_sell: float = 0.45
+    p_sell_grid: float = 0.25
+    fixed_cost: float = 0.0
+    alpha_sat: float = 0.0
+    alpha_declined: float = 0.0
+    steps_per_episode: int = STEPS_PER_DAY
+    n_levels: int = 10
+    price_base: float = 0.25
+    price_amp: float = 0.1
+    price_sigma: float = 0.02
+    arrival_peak: float = 0.3
+    cap_lo: float = 40.0
+    cap_hi: float = 100.0
+    soc0_lo: float = 0.1
+    soc0_hi: float = 0.5
+    tgt_lo: float = 0.7
+    tgt_hi: float = 1.0
+    dwell_mu: float = math.log(36.0)
+    dwell_sigma: float = 0.5
+    dwell_max: int = 1024
+    name: str = ""
+
+    @property
+    def n_nodes(self) -> int:
+        return len(self.node_parent)
+
+    @property
+    def obs_dim(self) -> int:
+        return 6 * self.n_ports + 4
+
+    def replace(self, **kw) -> "StationSpec":
+        return dataclasses.replace(self, **kw)
+
+
+def _ports(n: int, parent_of) -> Tuple[List[int], List[float], List[float]]:
+    return [parent_of(p) for p in range(n)], [PMAX_KW] * n, [1.0] * n
+
+
+def single_transformer(n_ports: int = 16, root_kw: float = 150.0, **kw) -> StationSpec:
+    """All ports directly under one transformer (the tiny parity workload)."""
+    pp, pm, pe = _ports(n_ports, lambda p: 0)
+    return StationSpec(n_ports, [-1], [root_kw], [1.0], pp, pm, pe,
+                       arrival_peak=0.3 * n_ports / 16.0, name=f"flat{n_ports}_{root_kw:g}kW", **kw)
+
+
+def splitter_tree(n_splitters: int = 4, ports_per_splitter: int = 4, splitter_kw: float = 60.0,
+                  root_kw: float = 200.0, **kw) -> StationSpec:
+    """A transformer feeding equal splitters, each feeding equal ports."""
+    n = n_splitters * ports_per_splitter
+    parents = [-1] + [0] * n_splitters
+    limits = [root_kw] + [splitter_kw] * n_splitters
+    pp, pm, pe = _ports(n, lambda p: 1 + p // ports_per_splitter)
+    return StationSpec(n, parents, limits, [1.0] * len(parents), pp, pm, pe,
+                       arrival_peak=0.3 * n / 16.0,
+                       name=f"split{n_splitters}x{ports_per_splitter}_{splitter_kw:g}_{root_kw:g}kW", **kw)
+
+
+def fanout4_tree(n_ports: int, depth: int, factor: float = 0.7, **kw) -> StationSpec:
+    """Class tree of the uneven-batching workload.
+
+    ``depth`` counts internal levels (1 = a single transformer).  Ports are
+    grouped four per deepest node, each higher level groups four nodes per
+    parent, and the root takes whatever remains.  A node's limit is ``factor``
+    times the sum of its children's maxima (port max for a port, limit for a
+    node).
+    """
+    assert depth >= 1 and n_ports >= 1
+    # level sizes from the deepest internal level up to (excluding) the root
+    levels: List[int] = []
+    if depth >= 2:
+        levels.append(-(-n_ports // 4))
+        for _ in range(depth - 2):
+            levels.append(-(-levels[-1] // 4))
+    # node ids: root 0, then shallowest level first so parents precede children
+    parents = [-1]
+    level_ids: List[List[int]] = []
+    for size in reversed(levels):
+        prev = level_ids[-1] if level_ids else [0]
+        ids = list(range(len(parents), len(parents) + size))
+        for j in range(size):
+            parents.append(prev[j // 4] if level_ids else 0)
+        level_ids.append(ids)
+    deepest = level_ids[-1] if level_ids else [0]
+    port_parent = [deepest[p // 4] if level_ids else 0 for p in range(n_ports)]
+    # limits bottom-up
+    limit = [0.0] * len(parents)
+    child_max = [0.0] * len(parents)
+    for p in range(n_ports):
+        child_max[port_parent[p]] += PMAX_KW
+    for ids in reversed(level_ids):
+        for h in ids:
+            limit[h] = factor * child_max[h]
+            child_max[parents[h]] += limit[h]
+    limit[0] = factor * child_max[0]
+    return StationSpec(n_ports, parents, limit, [1.0] * len(parents), port_parent,
+                       [PMAX_KW] * n_ports, [1.0] * n_ports,
+                       arrival_peak=0.3 * n_ports / 16.0, name=f"fan4_n{n_ports}_d{depth}", **kw)
+
+
+def two_charger_types(n_dc: int = 10, n_ac: int = 6, dc_kw: float = 150.0, ac_kw: float = 11.5,
+                      dc_split_kw: float = 800.0, ac_split_kw: float = 50.0,
+                      root_kw: float = 700.0, **kw) -> StationSpec:
+    """Sec. 3 / Fig. 3(b): one splitter per charger type under the grid connection."""
+    n = n_dc + n_ac
+    pp = [1] * n_dc + [2] * n_ac
+    pm = [dc_kw] * n_dc + [ac_kw] * n_ac
+    return StationSpec(n, [-1, 0, 0], [root_kw, dc_split_kw, ac_split_kw], [1.0, 1.0, 1.0], pp, pm,
+                       [1.0] * n, arrival_peak=0.3 * n / 16.0, name=f"types{n_dc}dc{n_ac}ac", **kw)
+
+
+# ---- the five workloads ------------------------------------------------------
+
+def tiny_parity_station() -> StationSpec:
+    """64 envs x 288 steps; 16 ports under a 150 kW transformer."""
+    return single_transformer(16, 150.0)
+
+
+def scale_station() -> StationSpec:
+    """4096 envs x 288 steps; 4 splitters of 60 kW x 4 ports, transformer 200 kW."""
+    return splitter_tree(4, 4, 60.0, 200.0)
+
+
+def policy_station() -> StationSpec:
+    """32-port two-level tree: 8 splitters of 60 kW x 4 ports under 400 kW."""
+    return splitter_tree(8, 4, 60.0, 400.0)
+
+
+MIX_PORTS = (8, 16, 32, 64, 128)
+MIX_PROBS = (0.3, 0.3, 0.2, 0.15, 0.05)
+MIX_DEPTHS = (1, 2, 3)
+
+
+def mixture_classes() -> List[StationSpec]:
+    """The 15 station classes (ports x depth) of the uneven-batching workload."""
+    return [fanout4_tree(n, d) for n in MIX_PORTS for d in MIX_DEPTHS]
+
+
+def mixture_env_classes(n_envs: int, seed: int = 1003) -> np.ndarray:
+    """Class index per env (into mixture_classes()), sorted so each class is contiguous."""
+    rng = np.random.default_rng(seed)
+    size_idx = rng.choice(len(MIX_PORTS), size=n_envs, p=MIX_PROBS)
+    depth_idx = rng.integers(0, len(MIX_DEPTHS), size=n_envs)
+    cls = (size_idx * len(MIX_DEPTHS) + depth_idx).astype(np.int32)
+    return np.sort(cls, kind="stable")
+
+
+def compact_classes(classes: Sequence[StationSpec], env_class: np.ndarray):
+    """Drop classes no env uses; returns (used classes, remapped env_class)."""
+    used = sorted(set(int(c) for c in np.unique(env_class)))
+    remap = {c: i for i, c in enumerate(used)}
+    return [classes[c] for c in used], np.array([remap[int(c)] for c in env_class], dtype=np.int32)
+
+
+# ---- serving request stream ----------------------------------------------------
+
+@dataclasses.dataclass
+class Request:
+    arrival_s: float
+    class_index: int
+    n_envs: int
+    horizon: int
+    seed: int
+
+
+def request_stream(n: int, rate_per_s: float, seed: int = 2000,
+                   horizons: Sequence[int] = (96, 288, 2016),
+                   env_lo: int = 64, env_hi: int = 8192) -> List[Request]:
+    """Poisson arrivals; n_envs log-uniform in [env_lo, env_hi]; horizon uniform over
+    ``horizons``; station class from the uneven-batching mixture."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for i in range(n):
+        t += rng.exponential(1.0 / rate_per_s)
+        size_idx = rng.choice(len(MIX_PORTS), p=MIX_PROBS)
+        depth_idx = rng.integers(0, len(MIX_DEPTHS))
+        n_envs = int(round(math.exp(rng.uniform(math.log(env_lo), math.log(env_hi)))))
+        out.append(Request(t, int(size_idx * len(MIX_DEPTHS) + depth_idx), n_envs,
+                           int(rng.choice(horizons)), int((seed * 1000003 + i) & 0xFFFFFFFFFFFF)))
+    return out
+
+
+# ---- policy weights -----------------------------------------------------------
+
+def bf16_bits(x: np.ndarray) -> np.ndarray:
+    """Round FP64 values to BF16 (nearest-even) and return the uint16 bit patterns."""
+    f = np.asarray(x, dtype=np.float64).astype(np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    rounded = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+    return rounded.astype(np.uint16)
+
+
+def policy_weights(n_ports: int, hidden: int = 256, n_levels: int = 10, std: float = 0.02,
+                   seed: int = 5):
+    """Random-init MLP weights N(0, std) drawn in FP64, returned as BF16 bits:
+    W1 [obs_dim][hidden], b1 [hidden], W2 [hidden][n_ports*(n_levels+1)], b2."""
+    rng = np.random.default_rng(seed)
+    d_in = 6 * n_ports + 4
+    d_out = n_ports * (n_levels + 1)
+    w1 = rng.normal(0.0, std, size=(d_in, hidden))
+    b1 = rng.normal(0.0, std, size=hidden)
+    w2 = rng.normal(0.0, std, size=(hidden, d_out))
+    b2 = rng.normal(0.0, std, size=d_out)
+    return bf16_bits(w1), bf16_bits(b1), bf16_bits(w2), bf16_bits(b2)
