@@ -1,0 +1,273 @@
+/*
+ * cx.h -- C ABI of the MI355X batched EV charging-station simulator.
+ *
+ * The library advances many independent charging stations by the Chargax
+ * transition (Ponse et al., arXiv 2507.01522): per step it applies the agent's
+ * per-port power levels (App. A.2 "Apply Actions"), projects them onto the
+ * station's capacity tree (Eq. ArchConst), charges the connected cars along the
+ * piecewise-linear charging curve (App. A.1 "Car Profiles", App. A.2 "Charge
+ * Stationed Cars"), lets time-sensitive users leave (App. A.2 "Departure of
+ * Cars"), admits Poisson arrivals first-come-first-served (App. A.2 "Arrival of
+ * new Cars", Supp. B.1), computes the profit/penalty reward (App. A.3) and
+ * auto-resets stations at the end of the day (Supp. B.1, Table 3).
+ *
+ * Conventions for every entry point:
+ *  - Pointers named *_dev are device memory owned by the caller; they must stay
+ *    valid until the context's stream has passed the call.  Pointers named
+ *    *_host, specs and descriptor structs are host memory, read during the call.
+ *  - All device work is asynchronous on the context's stream (cx_set_stream;
+ *    the null stream by default).  cx_synchronize waits for it.
+ *  - Errors are returned as cx_status; no exception crosses the ABI.  A failed
+ *    kernel launch or device error makes the context sticky-failed
+ *    (CX_E_DEVICE from then on).  cx_last_error() gives a thread-local message.
+ *  - Determinism: results depend only on the specs, the seed, the env index and
+ *    the global step counter g -- not on the launch form, the packing or the
+ *    other work sharing the GPU.  Integer outputs are exact; FP32 outputs agree
+ *    with an FP64 evaluation of the same equations to ~1e-5 relative.
+ *  - A context is used from one thread at a time; the server (cx_server_*) is
+ *    thread-safe.
+ */
+#ifndef CX_H
+#define CX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CX_OK = 0,
+  CX_E_INVALID = -1,   /* bad argument or station spec (checked before any device work) */
+  CX_E_OOM = -2,       /* device or host allocation failed */
+  CX_E_DEVICE = -3,    /* HIP error; sticky for the context */
+  CX_E_BUSY = -4,      /* serving: request still running */
+  CX_E_BUDGET = -5,    /* serving: request can never fit the memory budget */
+  CX_E_CANCELLED = -6, /* serving: request was cancelled */
+  CX_E_NOTFOUND = -7   /* serving: unknown ticket */
+} cx_status;
+
+/* Where the per-port power levels come from.  A level k in 0..n_levels asks for
+ * k / n_levels of the port's maximum power (Supp. B.1: discretisation 10). */
+typedef enum {
+  CX_ACT_EXTERNAL = 0, /* caller-provided uint8 levels (values above n_levels are clamped) */
+  CX_ACT_RANDOM = 1,   /* uniform levels from Philox: k = (w * (n_levels + 1)) >> 32      */
+  CX_ACT_MAX = 2,      /* every port asks for its maximum (the paper's baseline policy)   */
+  CX_ACT_POLICY = 3    /* the MLP set by cx_set_policy, Gumbel-max sampled               */
+} cx_action_mode;
+
+/* Which per-step records a rollout writes. */
+typedef enum {
+  CX_OUT_FULL = 0,       /* obs + actions + reward + done */
+  CX_OUT_REWARD = 1,     /* reward + done                 */
+  CX_OUT_ACT_REWARD = 2  /* actions + reward + done       */
+} cx_out_mode;
+
+/* One station architecture and its environment parameters (Sec. 3 "EV Station
+ * Layout", App. A.1, Table 3).  The architecture is a tree: internal nodes are
+ * splitters / cables / transformers with a power limit and efficiency; node 0
+ * is the grid connection and node_parent[i] < i.  Ports (EVSEs) are the leaves
+ * and must be listed in depth-first order, i.e. every node's ports are one
+ * contiguous range.  All arrays are host memory copied at create.
+ * Units: kW, kWh, hours, EUR. */
+typedef struct {
+  int32_t n_ports;              /* 1..256 */
+  int32_t n_nodes;              /* 1..256 */
+  const int32_t *node_parent;   /* [n_nodes]; -1 for node 0 */
+  const double *node_limit_kw;  /* [n_nodes] > 0 : I_H of Eq. (ArchConst) */
+  const double *node_eta;       /* [n_nodes] in (0,1]: eta_H of Eq. (ArchConst) */
+  const int32_t *port_parent;   /* [n_ports] node index */
+  const double *port_pmax_kw;   /* [n_ports] > 0 : maximum charging rate of the port */
+  const double *port_eta;       /* [n_ports] in (0,1]: charging efficiency (App. A.3) */
+  double dt_hours;              /* step length (5 min = 1/12) */
+  double tau;                   /* charging-curve knee, in (0,1) */
+  double p_sell;                /* price charged to car owners, EUR/kWh */
+  double p_sell_grid;           /* price when net grid energy <= 0 */
+  double fixed_cost;            /* c_dt per step */
+  double alpha_sat;             /* weight of c_satisfaction,0 (missing kWh at departure) */
+  double alpha_declined;        /* weight of c_declined (rejected cars) */
+  int32_t steps_per_episode;    /* 288: one day of 5-minute steps */
+  int32_t n_levels;             /* action discretisation (10) */
+  double price_base, price_amp, price_sigma; /* p_buy = base + amp sin(2 pi t/S) + sigma z */
+  double arrival_peak;          /* Poisson mean at midday: lambda(t) = peak (1 - cos 2 pi t/S)/2 */
+  double cap_lo, cap_hi;        /* battery capacity ~ U[cap_lo, cap_hi) kWh */
+  double soc0_lo, soc0_hi;      /* arrival SoC ~ U[...)  */
+  double tgt_lo, tgt_hi;        /* desired SoC ~ U[...)  */
+  double dwell_mu, dwell_sigma; /* stay ~ round(lognormal(mu, sigma)) steps */
+  int32_t dwell_max;            /* cap on the stay in steps (<= 4096) */
+} cx_station_spec;
+
+typedef struct cx_ctx cx_ctx;
+
+/* Per-step output buffers of a rollout (device memory, caller-owned).  With T
+ * steps, record t of every array starts at t * (its per-step size):
+ *   obs     float [T][obs_elems]   FULL only; env e at obs_offset(e), 6N+4 floats:
+ *           [occupied, SoC, e_rem/C, dwell/S, r_hat/pmax, p_last/pmax] x N ports
+ *           (feature-major: feature f of port p at f*N + p), then
+ *           [sin 2 pi t/S, cos 2 pi t/S, base price(t), occupied ports / N].
+ *   actions uint8 [T][total_ports] FULL and ACT_REWARD: the level applied per port.
+ *   reward  float [T][n_envs]
+ *   done    uint8 [T][n_envs]       1 when the step ended the day (the obs is then the
+ *                                   observation of the reset station).
+ * A NULL member is not written. */
+typedef struct {
+  float *obs;
+  uint8_t *actions;
+  float *reward;
+  uint8_t *done;
+} cx_traj;
+
+typedef struct {
+  int64_t n_envs;
+  int64_t total_ports;    /* actions per step */
+  int64_t obs_elems;      /* floats of obs per step */
+  int32_t n_classes;
+  int32_t steps_per_episode;
+  uint32_t g;             /* global step counter (advances by every step) */
+  int32_t t_day;          /* step within the day, 0..steps_per_episode-1 */
+  uint64_t seed;
+  size_t state_bytes;     /* size of a cx_get_state snapshot */
+  int64_t device_bytes;   /* device memory the context holds */
+} cx_info;
+
+typedef struct {
+  int64_t env_begin, n_envs;     /* the class's env range */
+  int64_t port_offset;           /* actions offset of its first env */
+  int64_t obs_offset;            /* obs offset of its first env */
+  int32_t n_ports, obs_dim;
+  int32_t slots;                 /* ports padded to the aligned power-of-two layout */
+  int32_t levels;                /* depth of the capacity tree (levels incl. root) */
+  int32_t lanes_per_station;     /* current packing: lanes per station */
+  int32_t waves_per_block;
+} cx_class_info;
+
+/* Create a context of n_envs stations of one class, state = empty stations at
+ * t_day = 0, g = 0.  seed keys every Philox draw.  The spec is validated here
+ * (CX_E_INVALID with a message); no later call re-checks it. */
+cx_status cx_create(const cx_station_spec *spec, int64_t n_envs, uint64_t seed, cx_ctx **out);
+
+/* Create a context with several station classes (the uneven-batching form):
+ * env e has class env_class[e]; env_class must be non-decreasing so that every
+ * class is one contiguous env range.  All specs must share steps_per_episode. */
+cx_status cx_create_multi(const cx_station_spec *specs, int32_t n_specs, const int32_t *env_class,
+                          int64_t n_envs, uint64_t seed, cx_ctx **out);
+
+/* Use this HIP stream (hipStream_t passed as void*) for all later device work. */
+cx_status cx_set_stream(cx_ctx *ctx, void *hip_stream);
+
+cx_status cx_get_info(const cx_ctx *ctx, cx_info *info);
+cx_status cx_get_class_info(const cx_ctx *ctx, int32_t cls, cx_class_info *info);
+
+/* Empty every station and set t_day = 0 and the returns to 0; g is kept, so a
+ * new day draws new noise.  obs_dev (nullable) receives the reset observation
+ * in the obs layout of one step. */
+cx_status cx_reset(cx_ctx *ctx, float *obs_dev);
+
+/* One environment step, one kernel launch, state read from and written back to
+ * HBM (the plain form).  actions_dev: uint8 levels [total_ports] (EXTERNAL).
+ * obs/reward/done receive one record each (layouts of cx_traj with T = 1);
+ * obs_dev may be NULL. */
+cx_status cx_step(cx_ctx *ctx, const uint8_t *actions_dev, float *obs_dev, float *reward_dev,
+                  uint8_t *done_dev);
+
+/* cx_step with any action mode and every output of cx_traj (T = 1).
+ * actions_in_dev is read only for CX_ACT_EXTERNAL. */
+cx_status cx_step_ex(cx_ctx *ctx, cx_action_mode mode, const uint8_t *actions_in_dev,
+                     const cx_traj *out);
+
+/* T steps in one persistent launch: each wave keeps its stations' state in
+ * registers for all T steps and streams the records selected by out_mode to
+ * *out.  actions_in_dev ([T][total_ports] uint8) is read only for EXTERNAL.
+ * The launch is captured once per (T, modes, buffers) into a HIP graph and
+ * replayed.  Results equal T calls of cx_step_ex. */
+cx_status cx_rollout(cx_ctx *ctx, int32_t T, cx_action_mode mode, cx_out_mode out_mode,
+                     const uint8_t *actions_in_dev, const cx_traj *out);
+
+/* Policy for CX_ACT_POLICY: a two-layer perceptron obs -> hidden (tanh) ->
+ * n_ports*(n_levels+1) logits, BF16 weights (uint16 bit patterns, host memory):
+ * w1 [obs_dim][hidden], b1 [hidden], w2 [hidden][n_ports*(n_levels+1)], b2.
+ * Products run on the matrix cores in BF16 with FP32 accumulation; the level of
+ * each port is argmax over its logits plus Gumbel noise from Philox.
+ * Only single-class contexts. */
+cx_status cx_set_policy(cx_ctx *ctx, int32_t hidden, const uint16_t *w1_host, const uint16_t *b1_host,
+                        const uint16_t *w2_host, const uint16_t *b2_host);
+
+/* Logits of the policy for n observations (obs_dev [n][obs_dim] float) into
+ * logits_dev [n][n_ports*(n_levels+1)] float: the policy's first half alone. */
+cx_status cx_policy_logits(cx_ctx *ctx, const float *obs_dev, int64_t n, float *logits_dev);
+
+/* Snapshot / restore of the whole state (all stations, returns, g, t_day) in a
+ * packing-independent host format of cx_info.state_bytes bytes.  Both calls
+ * synchronise the context's stream.  Format (little endian):
+ *   u64 magic 0x31305843 ('CX01'), i64 n_envs, i64 total_ports, u32 g, i32 t_day,
+ *   then per port in env/port order: i32 dwell, f32 soc, f32 e_rem, f32 cap,
+ *   f32 p_last; then per env: f64 return. */
+cx_status cx_get_state(cx_ctx *ctx, void *host, size_t bytes);
+cx_status cx_set_state(cx_ctx *ctx, const void *host, size_t bytes);
+
+/* Copies of class cls's integer sampling tables, as built on the host in FP64:
+ * tpois_host [steps_per_episode][24] (arrival thresholds), tdwell_host
+ * [dwell_max] (entry 0 unused).  Either pointer may be NULL. */
+cx_status cx_get_tables(const cx_ctx *ctx, int32_t cls, uint32_t *tpois_host, uint32_t *tdwell_host);
+
+/* Packing of class cls: lanes per station (a power of two, 4..64, dividing or
+ * equal to the padded slot count / 1, 2 or 4 slots per lane) and waves per
+ * block (1..16).  Results do not depend on it beyond FP32 rounding order. */
+cx_status cx_set_packing(cx_ctx *ctx, int32_t cls, int32_t lanes_per_station, int32_t waves_per_block);
+
+/* Time every legal packing of every class on a T_probe-step rollout (state is
+ * saved and restored) and keep the fastest.  cache_path (nullable) is a JSON
+ * file of earlier results keyed by class shape, read first and updated. */
+cx_status cx_autotune(cx_ctx *ctx, int32_t T_probe, const char *cache_path);
+
+cx_status cx_synchronize(cx_ctx *ctx);
+const char *cx_last_error(void);
+void cx_destroy(cx_ctx *ctx);
+
+/* ---- serving: continuous batching of rollout requests ---------------------
+ * A server owns a memory budget on the current device.  Requests (one station
+ * class, n_envs, horizon T, seed, out_mode) are admitted first-come-first-served
+ * as soon as their state and output buffers fit the budget; the scheduler
+ * thread advances all admitted requests together, chunk_steps steps per launch,
+ * so requests that arrive while others run join the next chunk.  A request's
+ * results are identical alone or in any mix. */
+typedef struct cx_server cx_server;
+
+typedef struct {
+  int32_t chunk_steps;      /* steps per launch (default 32) */
+  int32_t max_active;       /* cap on concurrently admitted requests (default 256) */
+  int32_t waves_per_block;  /* default 4 */
+} cx_server_opts;
+
+typedef struct {
+  cx_station_spec spec;     /* copied at submit */
+  int64_t n_envs;
+  int32_t T;
+  uint64_t seed;
+  cx_out_mode out_mode;
+  cx_action_mode act_mode;  /* RANDOM or MAX */
+} cx_request;
+
+typedef struct {
+  cx_status status;
+  int64_t n_envs;
+  int32_t T;
+  cx_traj traj;             /* device buffers owned by the server until cx_release */
+  double submit_s, admit_s, done_s;  /* server clock, seconds */
+  int64_t bytes;
+} cx_result;
+
+cx_status cx_server_create(size_t hbm_budget_bytes, const cx_server_opts *opts, cx_server **out);
+cx_status cx_submit(cx_server *s, const cx_request *req, uint64_t *ticket);
+cx_status cx_poll(cx_server *s, uint64_t ticket, cx_result *res);   /* CX_E_BUSY while queued/running */
+cx_status cx_wait(cx_server *s, uint64_t ticket, cx_result *res);
+cx_status cx_cancel(cx_server *s, uint64_t ticket);
+cx_status cx_release(cx_server *s, uint64_t ticket);                /* frees the request's buffers */
+cx_status cx_server_stats(cx_server *s, double *busy_s, int64_t *env_steps, int64_t *launches);
+void cx_server_destroy(cx_server *s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -4,7 +4,7 @@
  * Plain scalar FP64 implementation of one Chargax environment step, written from
  * the paper's Appendix A.  Nothing here is blocked, fused or reordered beyond
  * what the equations state; each env is simulated on its own.  Build flags keep
- * IEEE semantics: -O2 -ffp-contract=off, no fast-math.
+ * IEEE semantics: -O3 -ffp-contract=off, no fast-math.
  */
 #include "cx_oracle.h"
 
@@ -373,6 +373,7 @@ void ox_transition(const ox_class *c, int32_t *dwell, double *soc, double *e_rem
 typedef struct {
   ox_class *const *classes;
   const int32_t *env_class;
+  const int64_t *env_ids;
   const int64_t *port_off, *obs_off;
   int64_t total_ports, total_obs, n_envs;
   int64_t e_begin, e_end;
@@ -395,11 +396,12 @@ static void *rollout_worker(void *arg) {
     const int64_t po = J->port_off[e], oo = J->obs_off[e];
     const int32_t N = c->n_ports;
     int32_t t_day = J->t0;
+    const uint32_t eid = (uint32_t)(J->env_ids ? J->env_ids[e] : e);
     for (int32_t t = 0; t < J->T; ++t) {
       uint32_t g = J->g0 + (uint32_t)t;
       const uint8_t *ext = J->act_in ? J->act_in + (size_t)t * J->total_ports + po : NULL;
-      ox_draw_actions(c, J->mode, J->seed, (uint32_t)e, g, ext, k);
-      ox_draw_exo(c, J->seed, (uint32_t)e, g, t_day, &x);
+      ox_draw_actions(c, J->mode, J->seed, eid, g, ext, k);
+      ox_draw_exo(c, J->seed, eid, g, t_day, &x);
       ox_step_info inf;
       double *o = J->obs ? J->obs + (size_t)t * J->total_obs + oo : NULL;
       ox_transition(c, J->dwell + po, J->soc + po, J->e_rem + po, J->cap + po, J->p_last + po,
@@ -414,8 +416,8 @@ static void *rollout_worker(void *arg) {
   return NULL;
 }
 
-int32_t ox_rollout(ox_class *const *classes, const int32_t *env_class, int64_t n_envs,
-                   uint64_t seed, uint32_t *g, int32_t *t_day, int32_t T, int32_t mode,
+int32_t ox_rollout(ox_class *const *classes, const int32_t *env_class, const int64_t *env_ids,
+                   int64_t n_envs, uint64_t seed, uint32_t *g, int32_t *t_day, int32_t T, int32_t mode,
                    const uint8_t *act_in, int32_t *dwell, double *soc, double *e_rem,
                    double *cap, double *p_last, double *ret, double *obs, uint8_t *act,
                    double *reward, uint8_t *done, ox_step_info *info, int32_t n_threads) {
@@ -433,7 +435,7 @@ int32_t ox_rollout(ox_class *const *classes, const int32_t *env_class, int64_t n
   pthread_t *th = (pthread_t *)calloc((size_t)n_threads, sizeof(pthread_t));
   for (int32_t w = 0; w < n_threads; ++w) {
     rollout_job *J = &jobs[w];
-    J->classes = classes; J->env_class = env_class; J->port_off = port_off; J->obs_off = obs_off;
+    J->classes = classes; J->env_class = env_class; J->env_ids = env_ids; J->port_off = port_off; J->obs_off = obs_off;
     J->total_ports = port_off[n_envs]; J->total_obs = obs_off[n_envs]; J->n_envs = n_envs;
     J->e_begin = n_envs * w / n_threads; J->e_end = n_envs * (w + 1) / n_threads;
     J->seed = seed; J->g0 = *g; J->t0 = *t_day; J->T = T; J->mode = mode; J->act_in = act_in;

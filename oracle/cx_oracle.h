@@ -40,7 +40,6 @@
  *                        Gumbel-max frequencies equal softmax (chi-square);
  *                        BF16 rounding equal to torch's
  *
-
  * All quantities: power in kW, energy in kWh, time step dt in hours.  The fixed
  * EVSE voltage of Sec. 3 cancels, so currents and powers are interchangeable.
  */
@@ -142,8 +141,11 @@ void ox_observe(const ox_class *c, const int32_t *dwell, const double *soc, cons
  *   reward [T][n_envs], done [T][n_envs]  (may be NULL)
  *   info   [T][n_envs] (may be NULL)
  * act_in (EXTERNAL mode) has the act layout.  g and t_day are common to all envs
- * and are advanced.  Returns the number of threads used. */
-int32_t ox_rollout(ox_class *const *classes, const int32_t *env_class, int64_t n_envs,
+ * and are advanced.  env_ids (may be NULL = 0..n_envs-1) gives each env's index
+ * in the Philox counters, so a subset of a large batch can be replayed.
+ * Returns the number of threads used. */
+int32_t ox_rollout(ox_class *const *classes, const int32_t *env_class, const int64_t *env_ids,
+                   int64_t n_envs,
                    uint64_t seed, uint32_t *g, int32_t *t_day, int32_t T, int32_t mode,
                    const uint8_t *act_in, int32_t *dwell, double *soc, double *e_rem,
                    double *cap, double *p_last, double *ret, double *obs, uint8_t *act,

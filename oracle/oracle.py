@@ -71,7 +71,7 @@ def lib():
         L.ox_transition.argtypes = [P] * 13
         L.ox_observe.argtypes = [P, P, P, P, P, P, I, P]
         L.ox_rollout.restype = I
-        L.ox_rollout.argtypes = [P, P, C.c_int64, C.c_uint64, P, P, I, I, P, P, P, P, P, P, P, P,
+        L.ox_rollout.argtypes = [P, P, P, C.c_int64, C.c_uint64, P, P, I, I, P, P, P, P, P, P, P, P,
                                  P, P, P, P, I]
         L.ox_policy.argtypes = [P, I, P, P, P, P, P, C.c_uint64, C.c_uint32, C.c_uint32, P, P]
         L.ox_bf16_round.restype = C.c_double
@@ -224,9 +224,10 @@ def exo(M: int = 0, p_buy: float = 0.25, cars=()) -> Exo:
 class BatchState:
     """State of many envs for ox_rollout (port-major, envs concatenated)."""
 
-    def __init__(self, classes: Sequence[OracleClass], env_class: np.ndarray):
+    def __init__(self, classes: Sequence[OracleClass], env_class: np.ndarray, env_ids=None):
         self.classes = list(classes)
         self.env_class = np.ascontiguousarray(env_class, dtype=np.int32)
+        self.env_ids = None if env_ids is None else np.ascontiguousarray(env_ids, dtype=np.int64)
         ports = np.array([c.n for c in self.classes], dtype=np.int64)[self.env_class]
         self.port_off = np.concatenate([[0], np.cumsum(ports)])
         obs = 6 * ports + 4
@@ -260,7 +261,7 @@ def rollout(bs: BatchState, seed: int, T: int, mode: int = ACT_RANDOM, act_in=No
     ain = None if act_in is None else np.ascontiguousarray(act_in, dtype=np.uint8)
     g = C.c_uint32(bs.g)
     t_day = C.c_int32(bs.t_day)
-    used = lib().ox_rollout(handles, _ptr(bs.env_class), bs.n_envs, seed, C.byref(g), C.byref(t_day),
+    used = lib().ox_rollout(handles, _ptr(bs.env_class), _ptr(bs.env_ids), bs.n_envs, seed, C.byref(g), C.byref(t_day),
                             T, mode, _ptr(ain), _ptr(bs.dwell), _ptr(bs.soc), _ptr(bs.e_rem),
                             _ptr(bs.cap), _ptr(bs.p_last), _ptr(bs.ret), _ptr(obs), _ptr(act),
                             _ptr(rew), _ptr(done), None if info is None else C.cast(info, C.c_void_p),

@@ -1,0 +1,462 @@
+// cx_api.cpp -- contexts and the C ABI of include/cx.h (everything but serving
+// and the policy kernels).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <string>
+#include <vector>
+
+#include "cx_ctx.h"
+#include "cx_layout.h"
+
+namespace cx {
+
+thread_local std::string g_last_error;
+
+cx_status fail_status(cx_status st, const std::string &msg) {
+  g_last_error = msg;
+  return st;
+}
+
+cx_status hip_fail(cx_ctx *ctx, hipError_t e, const char *what) {
+  if (ctx) ctx->failed = true;
+  return fail_status(CX_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Upload one class's constants, per-slot arrays and tables into one device block.
+static cx_status upload_class(cx_ctx *ctx, ClassRt &c) {
+  const Compiled &k = c.comp;
+  const Tables &t = c.tab;
+  const cx_station_spec &s = c.spec.s;
+  size_t off = align256(sizeof(ClassDev));
+  auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
+  const size_t o_port = take(sizeof(int32_t) * k.S);
+  const size_t o_pmax = take(sizeof(float) * k.S);
+  const size_t o_ipmax = take(sizeof(float) * k.S);
+  const size_t o_ieta = take(sizeof(float) * k.S);
+  const size_t o_lb = take(sizeof(uint32_t) * k.S);
+  const size_t o_cap = take(sizeof(float) * k.S * k.D);
+  const size_t o_tp = take(sizeof(uint32_t) * t.tpois_dev.size());
+  const size_t o_td = take(sizeof(uint32_t) * t.tdwell_dev.size());
+  const size_t o_gl = take(sizeof(float) * t.glob.size());
+  std::vector<unsigned char> host(off, 0);
+  hipError_t e = hipMalloc(&c.dev_mem, off);
+  if (e != hipSuccess) return fail_status(CX_E_OOM, "hipMalloc of class constants failed");
+  ctx->device_bytes += (int64_t)off;
+  unsigned char *base = static_cast<unsigned char *>(c.dev_mem);
+  ClassDev d{};
+  d.n_ports = k.N; d.S = k.S; d.D = k.D; d.n_levels = s.n_levels;
+  d.steps_ep = s.steps_per_episode; d.obs_dim = 6 * k.N + 4; d.dwell_log2 = t.dwell_log2;
+  d.uniform_eta = k.uniform_eta ? 1 : 0;
+  d.dt = (float)s.dt_hours; d.inv_dt = (float)(1.0 / s.dt_hours); d.inv_1mtau = (float)(1.0 / (1.0 - s.tau));
+  d.p_sell = (float)s.p_sell; d.p_sell_grid = (float)s.p_sell_grid; d.fixed_cost = (float)s.fixed_cost;
+  d.alpha_sat = (float)s.alpha_sat; d.alpha_dec = (float)s.alpha_declined; d.price_sigma = (float)s.price_sigma;
+  d.cap_lo = (float)s.cap_lo; d.cap_span = (float)(s.cap_hi - s.cap_lo);
+  d.soc_lo = (float)s.soc0_lo; d.soc_span = (float)(s.soc0_hi - s.soc0_lo);
+  d.tgt_lo = (float)s.tgt_lo; d.tgt_span = (float)(s.tgt_hi - s.tgt_lo);
+  d.inv_steps_ep = (float)(1.0 / s.steps_per_episode); d.inv_n_levels = (float)(1.0 / s.n_levels);
+  d.inv_eta_uniform = k.inv_eta_uniform;
+  d.slot_port = reinterpret_cast<const int32_t *>(base + o_port);
+  d.slot_pmax = reinterpret_cast<const float *>(base + o_pmax);
+  d.slot_inv_pmax = reinterpret_cast<const float *>(base + o_ipmax);
+  d.slot_inv_eta = reinterpret_cast<const float *>(base + o_ieta);
+  d.slot_lb = reinterpret_cast<const uint32_t *>(base + o_lb);
+  d.slot_cap = reinterpret_cast<const float *>(base + o_cap);
+  d.tpois = reinterpret_cast<const uint32_t *>(base + o_tp);
+  d.tdwell = reinterpret_cast<const uint32_t *>(base + o_td);
+  d.glob = reinterpret_cast<const float *>(base + o_gl);
+  std::memcpy(host.data(), &d, sizeof d);
+  std::memcpy(host.data() + o_port, k.slot_port.data(), sizeof(int32_t) * k.S);
+  std::memcpy(host.data() + o_pmax, k.slot_pmax.data(), sizeof(float) * k.S);
+  std::memcpy(host.data() + o_ipmax, k.slot_inv_pmax.data(), sizeof(float) * k.S);
+  std::memcpy(host.data() + o_ieta, k.slot_inv_eta.data(), sizeof(float) * k.S);
+  std::memcpy(host.data() + o_lb, k.slot_lb.data(), sizeof(uint32_t) * k.S);
+  std::memcpy(host.data() + o_cap, k.slot_cap.data(), sizeof(float) * k.S * k.D);
+  std::memcpy(host.data() + o_tp, t.tpois_dev.data(), sizeof(uint32_t) * t.tpois_dev.size());
+  std::memcpy(host.data() + o_td, t.tdwell_dev.data(), sizeof(uint32_t) * t.tdwell_dev.size());
+  std::memcpy(host.data() + o_gl, t.glob.data(), sizeof(float) * t.glob.size());
+  e = hipMemcpy(c.dev_mem, host.data(), off, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(ctx, e, "upload of class constants");
+  c.dev = reinterpret_cast<ClassDev *>(c.dev_mem);
+  c.host_view = d;
+  return CX_OK;
+}
+
+bool legal_packing(int S, int lanes) {
+  if (lanes < 4 || lanes > 64 || (lanes & (lanes - 1))) return false;
+  if (S % lanes) return false;
+  const int P = S / lanes;
+  return P == 1 || P == 2 || P == 4;
+}
+
+int default_lanes(int S) { return S <= 64 ? S : 64; }
+
+// Lay out the launch: one segment per class, heaviest (most slots) first.
+cx_status rebuild_segments(cx_ctx *ctx) {
+  std::vector<int> order(ctx->classes.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return ctx->classes[a].comp.S > ctx->classes[b].comp.S;
+  });
+  ctx->segs_host.clear();
+  int blocks = 0;
+  for (int ci : order) {
+    ClassRt &c = ctx->classes[ci];
+    if (c.n_envs == 0) continue;
+    SegDev sg{};
+    const int L = c.lanes, P = c.comp.S / c.lanes;
+    const int spw = 64 / L;
+    sg.cls = c.dev;
+    sg.env0 = c.env_begin;
+    sg.n_envs = c.n_envs;
+    sg.n_groups = (int32_t)((c.n_envs + spw - 1) / spw);
+    sg.block_begin = blocks;
+    sg.pack = pack_id(L, P);
+    sg.seed = ctx->seed;
+    const int64_t so = c.slot_off;
+    sg.soc = ctx->soc + so; sg.e_rem = ctx->e_rem + so; sg.cap = ctx->cap + so; sg.p_last = ctx->p_last + so;
+    sg.dwell = ctx->dwell + so;
+    sg.ret = ctx->ret + c.env_begin;
+    sg.obs_off = c.obs_off;
+    sg.act_off = c.port_off;
+    sg.env_off = c.env_begin;
+    blocks += (sg.n_groups + ctx->wpb - 1) / ctx->wpb;
+    ctx->segs_host.push_back(sg);
+  }
+  ctx->n_blocks = blocks;
+  if (!ctx->segs_dev) {
+    hipError_t e = hipMalloc(&ctx->segs_dev, sizeof(SegDev) * std::max<size_t>(1, ctx->classes.size()));
+    if (e != hipSuccess) return fail_status(CX_E_OOM, "hipMalloc of segment table failed");
+  }
+  if (!ctx->segs_host.empty()) {
+    hipError_t e = hipMemcpy(ctx->segs_dev, ctx->segs_host.data(), sizeof(SegDev) * ctx->segs_host.size(),
+                             hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(ctx, e, "upload of segment table");
+  }
+  graph_destroy(ctx->graph);
+  return CX_OK;
+}
+
+LaunchArgs base_args(const cx_ctx *ctx) {
+  LaunchArgs a{};
+  a.segs = ctx->segs_dev;
+  a.n_segs = (int32_t)ctx->segs_host.size();
+  a.per_segment = 0;
+  a.t_day0 = ctx->t_day;
+  a.g0 = ctx->g;
+  a.obs_stride = ctx->obs_elems;
+  a.act_stride = ctx->total_ports;
+  a.env_stride = ctx->n_envs;
+  return a;
+}
+
+void advance_clock(cx_ctx *ctx, int32_t T) {
+  ctx->g += (uint32_t)T;
+  ctx->t_day = (int32_t)(((int64_t)ctx->t_day + T) % ctx->steps_ep);
+}
+
+static void free_ctx(cx_ctx *ctx) {
+  if (!ctx) return;
+  graph_destroy(ctx->graph);
+  for (auto &c : ctx->classes)
+    if (c.dev_mem) (void)hipFree(c.dev_mem);
+  if (ctx->state_mem) (void)hipFree(ctx->state_mem);
+  if (ctx->segs_dev) (void)hipFree(ctx->segs_dev);
+  free_policy(ctx);
+  delete ctx;
+}
+
+static cx_status create_impl(const cx_station_spec *specs, int32_t n_specs, const int32_t *env_class,
+                             int64_t n_envs, uint64_t seed, cx_ctx **out) {
+  if (!out) return fail_status(CX_E_INVALID, "out must not be NULL");
+  *out = nullptr;
+  if (!specs || n_specs < 1 || n_specs > 4096) return fail_status(CX_E_INVALID, "need 1..4096 station specs");
+  if (n_envs < 1 || n_envs > (int64_t)1 << 31) return fail_status(CX_E_INVALID, "n_envs must be in 1..2^31");
+  std::vector<int64_t> count(n_specs, 0);
+  for (int64_t e = 0; e < n_envs; ++e) {
+    const int32_t c = env_class ? env_class[e] : 0;
+    if (c < 0 || c >= n_specs) return fail_status(CX_E_INVALID, "env_class out of range");
+    if (e > 0 && env_class && env_class[e - 1] > c)
+      return fail_status(CX_E_INVALID, "env_class must be non-decreasing (classes contiguous)");
+    count[c] += 1;
+  }
+  cx_ctx *ctx = new cx_ctx();
+  ctx->seed = seed;
+  ctx->n_envs = n_envs;
+  ctx->classes.resize(n_specs);
+  int64_t env_begin = 0, port_off = 0, obs_off = 0, slot_off = 0;
+  for (int i = 0; i < n_specs; ++i) {
+    ClassRt &c = ctx->classes[i];
+    std::string err;
+    if (!copy_spec(specs[i], &c.spec, &err) || !compile_spec(c.spec, &c.comp, &err)) {
+      free_ctx(ctx);
+      return fail_status(CX_E_INVALID, "station spec " + std::to_string(i) + ": " + err);
+    }
+    if (i > 0 && specs[i].steps_per_episode != specs[0].steps_per_episode) {
+      free_ctx(ctx);
+      return fail_status(CX_E_INVALID, "all specs must share steps_per_episode");
+    }
+    build_tables(c.spec, &c.tab);
+    if (!tables_monotone(c.tab)) {
+      free_ctx(ctx);
+      return fail_status(CX_E_INVALID, "sampling tables are not monotone");
+    }
+    c.env_begin = env_begin;
+    c.n_envs = count[i];
+    c.port_off = port_off;
+    c.obs_off = obs_off;
+    c.slot_off = slot_off;
+    c.lanes = default_lanes(c.comp.S);
+    env_begin += c.n_envs;
+    port_off += c.n_envs * c.comp.N;
+    obs_off += c.n_envs * (6 * c.comp.N + 4);
+    slot_off += c.n_envs * c.comp.S;
+  }
+  if (hipGetDevice(&ctx->device) != hipSuccess) {
+    free_ctx(ctx);
+    return fail_status(CX_E_DEVICE, "no HIP device");
+  }
+  ctx->steps_ep = specs[0].steps_per_episode;
+  ctx->total_ports = port_off;
+  ctx->obs_elems = obs_off;
+  ctx->total_slots = slot_off;
+  // state: 4 float arrays + int16 dwell over all slots, double return per env
+  const size_t fbytes = align256(sizeof(float) * (size_t)slot_off);
+  const size_t dbytes = align256(sizeof(int16_t) * (size_t)slot_off);
+  const size_t rbytes = align256(sizeof(double) * (size_t)n_envs);
+  const size_t total = 4 * fbytes + dbytes + rbytes;
+  if (hipMalloc(&ctx->state_mem, total) != hipSuccess) {
+    free_ctx(ctx);
+    return fail_status(CX_E_OOM, "hipMalloc of station state failed");
+  }
+  ctx->state_bytes_dev = total;
+  ctx->device_bytes += (int64_t)total;
+  unsigned char *b = static_cast<unsigned char *>(ctx->state_mem);
+  ctx->soc = reinterpret_cast<float *>(b);
+  ctx->e_rem = reinterpret_cast<float *>(b + fbytes);
+  ctx->cap = reinterpret_cast<float *>(b + 2 * fbytes);
+  ctx->p_last = reinterpret_cast<float *>(b + 3 * fbytes);
+  ctx->dwell = reinterpret_cast<int16_t *>(b + 4 * fbytes);
+  ctx->ret = reinterpret_cast<double *>(b + 4 * fbytes + dbytes);
+  if (hipMemset(ctx->state_mem, 0, total) != hipSuccess) {
+    free_ctx(ctx);
+    return fail_status(CX_E_DEVICE, "hipMemset of station state failed");
+  }
+  for (auto &c : ctx->classes) {
+    cx_status st = upload_class(ctx, c);
+    if (st != CX_OK) {
+      free_ctx(ctx);
+      return st;
+    }
+  }
+  cx_status st = rebuild_segments(ctx);
+  if (st != CX_OK) {
+    free_ctx(ctx);
+    return st;
+  }
+  *out = ctx;
+  return CX_OK;
+}
+
+}  // namespace cx
+
+using namespace cx;
+
+#define CTX_CHECK(ctx)                                                                 \
+  do {                                                                                 \
+    if (!(ctx)) return fail_status(CX_E_INVALID, "context is NULL");                   \
+    if ((ctx)->failed) return fail_status(CX_E_DEVICE, "context has a sticky device error"); \
+  } while (0)
+
+extern "C" {
+
+cx_status cx_create(const cx_station_spec *spec, int64_t n_envs, uint64_t seed, cx_ctx **out) {
+  return create_impl(spec, 1, nullptr, n_envs, seed, out);
+}
+
+cx_status cx_create_multi(const cx_station_spec *specs, int32_t n_specs, const int32_t *env_class,
+                          int64_t n_envs, uint64_t seed, cx_ctx **out) {
+  if (!env_class) return fail_status(CX_E_INVALID, "env_class must not be NULL");
+  return create_impl(specs, n_specs, env_class, n_envs, seed, out);
+}
+
+cx_status cx_set_stream(cx_ctx *ctx, void *hip_stream) {
+  CTX_CHECK(ctx);
+  ctx->stream = static_cast<hipStream_t>(hip_stream);
+  return CX_OK;
+}
+
+cx_status cx_get_info(const cx_ctx *ctx, cx_info *info) {
+  if (!ctx || !info) return fail_status(CX_E_INVALID, "NULL argument");
+  info->n_envs = ctx->n_envs;
+  info->total_ports = ctx->total_ports;
+  info->obs_elems = ctx->obs_elems;
+  info->n_classes = (int32_t)ctx->classes.size();
+  info->steps_per_episode = ctx->steps_ep;
+  info->g = ctx->g;
+  info->t_day = ctx->t_day;
+  info->seed = ctx->seed;
+  info->state_bytes = state_blob_bytes(ctx);
+  info->device_bytes = ctx->device_bytes;
+  return CX_OK;
+}
+
+cx_status cx_get_class_info(const cx_ctx *ctx, int32_t cls, cx_class_info *info) {
+  if (!ctx || !info) return fail_status(CX_E_INVALID, "NULL argument");
+  if (cls < 0 || cls >= (int32_t)ctx->classes.size()) return fail_status(CX_E_INVALID, "class out of range");
+  const ClassRt &c = ctx->classes[cls];
+  info->env_begin = c.env_begin;
+  info->n_envs = c.n_envs;
+  info->port_offset = c.port_off;
+  info->obs_offset = c.obs_off;
+  info->n_ports = c.comp.N;
+  info->obs_dim = 6 * c.comp.N + 4;
+  info->slots = c.comp.S;
+  info->levels = c.comp.D;
+  info->lanes_per_station = c.lanes;
+  info->waves_per_block = ctx->wpb;
+  return CX_OK;
+}
+
+cx_status cx_reset(cx_ctx *ctx, float *obs_dev) {
+  CTX_CHECK(ctx);
+  hipError_t e = hipMemsetAsync(ctx->state_mem, 0, ctx->state_bytes_dev, ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "cx_reset memset");
+  ctx->t_day = 0;
+  if (obs_dev) {
+    for (auto &c : ctx->classes) {
+      e = launch_reset_obs_one(c.dev, c.n_envs, obs_dev + c.obs_off, ctx->stream);
+      if (e != hipSuccess) return hip_fail(ctx, e, "cx_reset observation kernel");
+    }
+  }
+  return CX_OK;
+}
+
+cx_status cx_step_ex(cx_ctx *ctx, cx_action_mode mode, const uint8_t *actions_in_dev, const cx_traj *out) {
+  CTX_CHECK(ctx);
+  if (mode < CX_ACT_EXTERNAL || mode > CX_ACT_POLICY) return fail_status(CX_E_INVALID, "bad action mode");
+  if (mode == CX_ACT_EXTERNAL && !actions_in_dev) return fail_status(CX_E_INVALID, "EXTERNAL needs actions");
+  if (mode == CX_ACT_POLICY) return policy_step(ctx, 1, CX_OUT_FULL, out, /*graph=*/false);
+  LaunchArgs a = base_args(ctx);
+  a.T = 1;
+  a.mode = mode;
+  a.out_mode = CX_OUT_FULL;
+  a.act_in = actions_in_dev;
+  if (out) {
+    a.obs = out->obs; a.act = out->actions; a.reward = out->reward; a.done = out->done;
+  }
+  hipError_t e = launch_rollout(a, ctx->n_blocks, ctx->wpb, ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "cx_step launch");
+  advance_clock(ctx, 1);
+  return CX_OK;
+}
+
+cx_status cx_step(cx_ctx *ctx, const uint8_t *actions_dev, float *obs_dev, float *reward_dev,
+                  uint8_t *done_dev) {
+  cx_traj t{obs_dev, nullptr, reward_dev, done_dev};
+  return cx_step_ex(ctx, CX_ACT_EXTERNAL, actions_dev, &t);
+}
+
+cx_status cx_rollout(cx_ctx *ctx, int32_t T, cx_action_mode mode, cx_out_mode out_mode,
+                     const uint8_t *actions_in_dev, const cx_traj *out) {
+  CTX_CHECK(ctx);
+  if (T < 0 || T > (1 << 24)) return fail_status(CX_E_INVALID, "T must be in 0..2^24");
+  if (mode < CX_ACT_EXTERNAL || mode > CX_ACT_POLICY) return fail_status(CX_E_INVALID, "bad action mode");
+  if (out_mode < CX_OUT_FULL || out_mode > CX_OUT_ACT_REWARD) return fail_status(CX_E_INVALID, "bad out mode");
+  if (mode == CX_ACT_EXTERNAL && !actions_in_dev && T > 0) return fail_status(CX_E_INVALID, "EXTERNAL needs actions");
+  if (T == 0) return CX_OK;
+  if (mode == CX_ACT_POLICY) return policy_step(ctx, T, out_mode, out, /*graph=*/true);
+  LaunchArgs a = base_args(ctx);
+  a.T = T;
+  a.mode = mode;
+  a.out_mode = out_mode;
+  a.act_in = actions_in_dev;
+  if (out) {
+    a.obs = out_mode == CX_OUT_FULL ? out->obs : nullptr;
+    a.act = out_mode != CX_OUT_REWARD ? out->actions : nullptr;
+    a.reward = out->reward;
+    a.done = out->done;
+  }
+  hipError_t e = graph_rollout(ctx->graph, a, ctx->n_blocks, ctx->wpb, ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "cx_rollout graph launch");
+  advance_clock(ctx, T);
+  return CX_OK;
+}
+
+cx_status cx_get_tables(const cx_ctx *ctx, int32_t cls, uint32_t *tpois_host, uint32_t *tdwell_host) {
+  if (!ctx) return fail_status(CX_E_INVALID, "context is NULL");
+  if (cls < 0 || cls >= (int32_t)ctx->classes.size()) return fail_status(CX_E_INVALID, "class out of range");
+  const Tables &t = ctx->classes[cls].tab;
+  if (tpois_host) std::memcpy(tpois_host, t.tpois.data(), sizeof(uint32_t) * t.tpois.size());
+  if (tdwell_host) std::memcpy(tdwell_host, t.tdwell.data(), sizeof(uint32_t) * t.tdwell.size());
+  return CX_OK;
+}
+
+cx_status cx_set_packing(cx_ctx *ctx, int32_t cls, int32_t lanes_per_station, int32_t waves_per_block) {
+  CTX_CHECK(ctx);
+  if (cls < 0 || cls >= (int32_t)ctx->classes.size()) return fail_status(CX_E_INVALID, "class out of range");
+  if (!legal_packing(ctx->classes[cls].comp.S, lanes_per_station))
+    return fail_status(CX_E_INVALID, "lanes_per_station must be a power of two in 4..64 with 1, 2 or 4 slots per lane");
+  if (waves_per_block < 1 || waves_per_block > kMaxWaves) return fail_status(CX_E_INVALID, "waves_per_block must be in 1..8");
+  ctx->classes[cls].lanes = lanes_per_station;
+  ctx->wpb = waves_per_block;
+  return rebuild_segments(ctx);
+}
+
+cx_status cx_synchronize(cx_ctx *ctx) {
+  CTX_CHECK(ctx);
+  hipError_t e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "stream synchronize");
+  return CX_OK;
+}
+
+const char *cx_last_error(void) { return g_last_error.c_str(); }
+
+void cx_destroy(cx_ctx *ctx) {
+  if (!ctx) return;
+  (void)hipStreamSynchronize(ctx->stream);
+  free_ctx(ctx);
+}
+
+}  // extern "C"
+
+extern "C" {
+
+cx_status cx_compile_layout(const cx_station_spec *spec, int32_t *slots, int32_t *levels, int32_t *slot_port,
+                            uint32_t *slot_lb, float *slot_cap) {
+  if (!spec) return fail_status(CX_E_INVALID, "spec is NULL");
+  SpecCopy sc;
+  Compiled k;
+  std::string err;
+  if (!copy_spec(*spec, &sc, &err) || !compile_spec(sc, &k, &err)) return fail_status(CX_E_INVALID, err);
+  if (slots) *slots = k.S;
+  if (levels) *levels = k.D;
+  for (int s = 0; s < kMaxSlots; ++s) {
+    if (slot_port) slot_port[s] = s < k.S ? k.slot_port[s] : -1;
+    if (slot_lb) slot_lb[s] = s < k.S ? k.slot_lb[s] : 0u;
+    for (int d = 0; d < kMaxLevels && slot_cap; ++d)
+      slot_cap[d * kMaxSlots + s] =
+          (s < k.S && d < k.D) ? k.slot_cap[(size_t)d * k.S + s] : std::numeric_limits<float>::infinity();
+  }
+  return CX_OK;
+}
+
+cx_status cx_build_tables(const cx_station_spec *spec, uint32_t *tpois, uint32_t *tdwell) {
+  if (!spec) return fail_status(CX_E_INVALID, "spec is NULL");
+  SpecCopy sc;
+  Compiled k;
+  std::string err;
+  if (!copy_spec(*spec, &sc, &err) || !compile_spec(sc, &k, &err)) return fail_status(CX_E_INVALID, err);
+  Tables t;
+  build_tables(sc, &t);
+  if (tpois) std::memcpy(tpois, t.tpois.data(), sizeof(uint32_t) * t.tpois.size());
+  if (tdwell) std::memcpy(tdwell, t.tdwell.data(), sizeof(uint32_t) * t.tdwell.size());
+  return CX_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,69 @@
+// cx_ctx.h -- the context object behind cx_ctx* and helpers shared by the
+// host translation units.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "cx_spec.h"
+
+namespace cx {
+
+struct ClassRt {
+  SpecCopy spec;
+  Compiled comp;
+  Tables tab;
+  int64_t env_begin = 0, n_envs = 0, port_off = 0, obs_off = 0, slot_off = 0;
+  int lanes = 16;                 // current packing
+  void *dev_mem = nullptr;        // ClassDev + per-slot arrays + tables
+  ClassDev *dev = nullptr;
+  ClassDev host_view{};           // host copy (pointers are device addresses)
+};
+
+struct PolicyRt;                  // defined with the policy kernels
+
+}  // namespace cx
+
+struct cx_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  uint64_t seed = 0;
+  uint32_t g = 0;
+  int32_t t_day = 0;
+  int32_t steps_ep = 288;
+  int64_t n_envs = 0, total_ports = 0, obs_elems = 0, total_slots = 0;
+  std::vector<cx::ClassRt> classes;
+  // state, env-major slot layout: soc/e_rem/cap/p_last float, dwell int16, return double
+  void *state_mem = nullptr;
+  size_t state_bytes_dev = 0;
+  float *soc = nullptr, *e_rem = nullptr, *cap = nullptr, *p_last = nullptr;
+  int16_t *dwell = nullptr;
+  double *ret = nullptr;
+  // launch layout
+  cx::SegDev *segs_dev = nullptr;
+  std::vector<cx::SegDev> segs_host;
+  int n_blocks = 0;
+  int wpb = 4;
+  bool failed = false;
+  int64_t device_bytes = 0;
+  cx::RolloutGraph graph;
+  cx::PolicyRt *policy = nullptr;
+};
+
+namespace cx {
+
+extern thread_local std::string g_last_error;
+cx_status fail_status(cx_status st, const std::string &msg);
+cx_status hip_fail(cx_ctx *ctx, hipError_t e, const char *what);
+cx_status rebuild_segments(cx_ctx *ctx);
+LaunchArgs base_args(const cx_ctx *ctx);
+void advance_clock(cx_ctx *ctx, int32_t T);
+bool legal_packing(int S, int lanes);
+int default_lanes(int S);
+size_t state_blob_bytes(const cx_ctx *ctx);
+
+// policy (cx_policy.hip)
+void free_policy(cx_ctx *ctx);
+cx_status policy_step(cx_ctx *ctx, int32_t T, cx_out_mode out_mode, const cx_traj *out, bool graph);
+
+}  // namespace cx

@@ -1,0 +1,118 @@
+// cx_internal.h -- data structures shared by the host runtime and the gfx950
+// kernels of the batched EV charging-station step.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "cx.h"
+
+namespace cx {
+
+constexpr int kMaxLevels = 4;    // capacity-tree depth, root included
+constexpr int kMaxSlots = 256;   // padded ports per station
+constexpr int kPoisK = 24;       // arrival counts are capped at 24 per step
+constexpr int kPoisStride = 32;  // threshold row padded with 0xFFFFFFFF for a 5-step bisection
+constexpr int kMaxWaves = 8;     // waves per block
+
+// Philox counter domains (word 3 of the counter); see the action / arrival
+// / noise derivations in the kernels.
+enum : uint32_t { kDomEnv = 0, kDomAct = 1, kDomCar = 2, kDomGum = 3 };
+
+// Packings: lanes per station L in {4,...,64} and slots per lane P in {1,2,4};
+// L * P = padded slots of the class.
+constexpr int kNumPackings = 15;
+__host__ __device__ constexpr int pack_lanes(int id) { return 4 << (id % 5); }
+__host__ __device__ constexpr int pack_per_lane(int id) { return 1 << (id / 5); }
+inline int pack_id(int lanes, int per_lane) {
+  int li = 0;
+  while ((4 << li) != lanes) ++li;
+  int pi = per_lane == 1 ? 0 : per_lane == 2 ? 1 : 2;
+  return pi * 5 + li;
+}
+
+// One compiled station class, in device memory.  Per-slot arrays use the
+// padded, aligned slot layout: slot s of a station holds port slot_port[s]
+// (-1 for a padding slot that never holds a car).
+struct ClassDev {
+  int32_t n_ports, S, D, n_levels;
+  int32_t steps_ep, obs_dim, dwell_log2, uniform_eta;
+  float dt, inv_dt, inv_1mtau, p_sell;
+  float p_sell_grid, fixed_cost, alpha_sat, alpha_dec;
+  float price_sigma, cap_lo, cap_span, soc_lo;
+  float soc_span, tgt_lo, tgt_span, inv_steps_ep;
+  float inv_n_levels, inv_eta_uniform, pad0, pad1;
+  const int32_t *slot_port;    // [S]
+  const float *slot_pmax;      // [S]
+  const float *slot_inv_pmax;  // [S]
+  const float *slot_inv_eta;   // [S]
+  const uint32_t *slot_lb;     // [S]: log2 block size per level, 8 bits each, level 0 = deepest
+  const float *slot_cap;       // [D][S]: eta_H * I_H of the level's node holding the slot (+inf if none)
+  const uint32_t *tpois;       // [steps_ep][32]
+  const uint32_t *tdwell;      // [1 << dwell_log2]: thresholds for stays of 2, 3, ... steps
+  const float *glob;           // [steps_ep][4]: sin, cos, base price, 0
+};
+
+// One class's env range inside a launch.  Static fields are set when the
+// context (or serving request) is laid out; dynamic fields are used when the
+// launch says so (serving), otherwise the launch arguments apply.
+struct SegDev {
+  const ClassDev *cls;
+  int64_t env0;         // Philox env index of the segment's first env
+  int64_t n_envs;
+  int32_t n_groups;     // waves needed: ceil(n_envs / stations per wave)
+  int32_t block_begin;  // first block of this segment in the launch
+  int32_t pack;
+  int32_t pad_;
+  uint64_t seed;
+  // state, env-major slot layout, at the segment's first env
+  float *soc, *e_rem, *cap, *p_last;
+  int16_t *dwell;
+  double *ret;
+  // offsets of the segment's first env inside the output records
+  int64_t obs_off, act_off, env_off;
+  // dynamic (per-segment launches only)
+  int32_t T, t_day0;
+  uint32_t g0;
+  int32_t mode, out_mode, pad2;
+  float *obs;
+  uint8_t *act;
+  float *reward;
+  uint8_t *done;
+  const uint8_t *act_in;
+  int64_t obs_stride, act_stride, env_stride;
+};
+
+// Launch-wide arguments (by value).
+struct LaunchArgs {
+  const SegDev *segs;
+  int32_t n_segs;
+  int32_t per_segment;  // 1: take T/g0/t_day0/modes/outputs from each segment
+  int32_t T, t_day0;
+  uint32_t g0;
+  int32_t mode, out_mode, pad_;
+  float *obs;
+  uint8_t *act;
+  float *reward;
+  uint8_t *done;
+  const uint8_t *act_in;
+  int64_t obs_stride, act_stride, env_stride;
+};
+
+// A one-kernel HIP graph of the persistent rollout, instantiated once and
+// re-parameterised per call.
+struct RolloutGraph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipGraphNode_t node = nullptr;
+  int blocks = -1, waves = -1;
+};
+
+// Host-side launchers (defined in cx_kernels.hip).
+hipError_t graph_rollout(RolloutGraph &g, const LaunchArgs &a, int n_blocks, int waves_per_block,
+                         hipStream_t st);
+void graph_destroy(RolloutGraph &g);
+hipError_t launch_rollout(const LaunchArgs &a, int n_blocks, int waves_per_block, hipStream_t st);
+hipError_t launch_reset_obs_one(const ClassDev *cls_dev, int64_t n_envs, float *obs, hipStream_t st);
+
+}  // namespace cx

@@ -1,0 +1,517 @@
+// cx_kernels.hip -- gfx950 kernels of the batched EV charging-station step.
+//
+// One station occupies L lanes of a 64-wide wavefront and each lane holds P
+// slots (L * P = the station's padded slot count); a wave carries 64 / L
+// stations.  Slot s of a station lives in lane s % L, register s / L.  A wave
+// runs its stations for T steps with the whole state in registers and writes
+// the per-step records out; the plain one-step form is the same kernel with
+// T = 1.  Per step (App. A.2 order):
+//   exogenous draws  (arrivals, price noise; computed L steps ahead, one step
+//                     per lane, and broadcast -- they do not depend on the agent)
+//   actions          (Philox levels / max / external)
+//   apply actions    (clip by port max, charge curve, battery room)
+//   projection       (Eq. ArchConst, deepest level first, butterfly sums over
+//                     aligned power-of-two slot blocks: DPP inside a row,
+//                     ds_swizzle / bpermute across rows, adds across registers)
+//   charge, departures, arrivals (ballot + popcount ranks), reward, day end,
+//   records.
+#include <hip/hip_runtime.h>
+
+#include "cx_internal.h"
+
+namespace cx {
+namespace {
+
+struct U4 {
+  uint32_t x, y, z, w;
+};
+
+// Philox4x32-10 (Salmon et al., SC'11).  The key is wave-uniform, so its
+// schedule stays in scalar registers.
+__device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                     uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t hi0 = __umulhi(0xD2511F53u, c0);
+    const uint32_t lo0 = 0xD2511F53u * c0;
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
+    const uint32_t lo1 = 0xCD9E8D57u * c2;
+    c0 = hi1 ^ c1 ^ k0;
+    c1 = lo1;
+    c2 = hi0 ^ c3 ^ k1;
+    c3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return U4{c0, c1, c2, c3};
+}
+
+__device__ __forceinline__ float u24(uint32_t w) { return (float)(w >> 8) * 0x1p-24f; }
+
+// Number of entries of a non-decreasing table (size 2^log2n, last entry
+// 0xFFFFFFFF) that are strictly below w.
+__device__ __forceinline__ int count_below(const uint32_t *__restrict__ tab, int log2n, uint32_t w) {
+  int pos = 0;
+  for (int s = 1 << (log2n - 1); s >= 1; s >>= 1)
+    if (tab[pos + s - 1] < w) pos += s;
+  return pos;
+}
+
+// Exchange with the lane whose index differs in bit K (K = 0..5), for use in
+// butterfly all-reductions.  For K = 2, 3 the partner is the mirror lane of
+// the same half-row / row: after the steps below K every lane of an aligned
+// 2^K group holds the same value, so the mirror is as good as the XOR partner.
+template <int K>
+__device__ __forceinline__ float xlane(float v) {
+  const int iv = __float_as_int(v);
+  if constexpr (K == 0) return __int_as_float(__builtin_amdgcn_update_dpp(0, iv, 0xB1, 0xF, 0xF, false));
+  if constexpr (K == 1) return __int_as_float(__builtin_amdgcn_update_dpp(0, iv, 0x4E, 0xF, 0xF, false));
+  if constexpr (K == 2) return __int_as_float(__builtin_amdgcn_update_dpp(0, iv, 0x141, 0xF, 0xF, false));
+  if constexpr (K == 3) return __int_as_float(__builtin_amdgcn_update_dpp(0, iv, 0x140, 0xF, 0xF, false));
+  if constexpr (K == 4) return __int_as_float(__builtin_amdgcn_ds_swizzle(iv, 0x401F));
+  if constexpr (K == 5) {
+    const int lane = __lane_id();
+    return __int_as_float(__builtin_amdgcn_ds_bpermute((lane ^ 32) << 2, iv));
+  }
+  return v;
+}
+
+template <int L>
+__device__ __forceinline__ float station_sum(float v) {
+  if constexpr (L > 1) v += xlane<0>(v);
+  if constexpr (L > 2) v += xlane<1>(v);
+  if constexpr (L > 4) v += xlane<2>(v);
+  if constexpr (L > 8) v += xlane<3>(v);
+  if constexpr (L > 16) v += xlane<4>(v);
+  if constexpr (L > 32) v += xlane<5>(v);
+  return v;
+}
+
+// Masked butterfly step: lanes whose block is smaller than 2^(K+1) send 0.
+template <int K>
+__device__ __forceinline__ float masked_step(float v, int lb) {
+  const float u = (K < lb) ? v : 0.0f;
+  return v + xlane<K>(u);
+}
+
+template <int L>
+__device__ __forceinline__ float block_sum_lanes(float v, int lb) {
+  if constexpr (L > 1) v = masked_step<0>(v, lb);
+  if constexpr (L > 2) v = masked_step<1>(v, lb);
+  if constexpr (L > 4) v = masked_step<2>(v, lb);
+  if constexpr (L > 8) v = masked_step<3>(v, lb);
+  if constexpr (L > 16) v = masked_step<4>(v, lb);
+  if constexpr (L > 32) v = masked_step<5>(v, lb);
+  return v;
+}
+
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+template <int L>
+__device__ __forceinline__ int bcast(int v, int src) {
+  if constexpr (L == 64) return __builtin_amdgcn_readlane(v, src);
+  const int lane = __lane_id();
+  return __builtin_amdgcn_ds_bpermute(((lane & ~(L - 1)) + src) << 2, v);
+}
+template <int L>
+__device__ __forceinline__ float bcastf(float v, int src) {
+  return __int_as_float(bcast<L>(__float_as_int(v), src));
+}
+
+struct Dyn {
+  int32_t T, t_day0;
+  uint32_t g0;
+  int32_t mode, out_mode;
+  float *obs;
+  uint8_t *act;
+  float *reward;
+  uint8_t *done;
+  const uint8_t *act_in;
+  int64_t obs_stride, act_stride, env_stride;
+};
+
+template <int L, int P>
+__device__ void run_group(const SegDev &sg, const Dyn &dy, int group) {
+  constexpr int SPW = 64 / L;
+  constexpr int LOGL = (L == 4) ? 2 : (L == 8) ? 3 : (L == 16) ? 4 : (L == 32) ? 5 : 6;
+  const ClassDev &C = *sg.cls;
+  const int lane = __lane_id();
+  const int l = lane & (L - 1);
+  const int sbase = lane & ~(L - 1);
+  const int64_t env = (int64_t)group * SPW + (lane >> LOGL);
+  const bool active = env < sg.n_envs;
+  const int S = C.S;
+  const int D = C.D;
+  const int N = C.n_ports;
+
+  // ---- per-slot constants
+  int port[P];
+  float pmax[P], inv_pmax[P], inv_eta[P], lcap[kMaxLevels][P];
+  uint32_t lbp[P];
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    const int s = j * L + l;
+    port[j] = C.slot_port[s];
+    pmax[j] = C.slot_pmax[s];
+    inv_pmax[j] = C.slot_inv_pmax[s];
+    inv_eta[j] = C.slot_inv_eta[s];
+    lbp[j] = C.slot_lb[s];
+#pragma unroll
+    for (int d = 0; d < kMaxLevels; ++d) lcap[d][j] = d < D ? C.slot_cap[d * S + s] : __builtin_inff();
+  }
+
+  // ---- state
+  float soc[P], erem[P], cap[P], plast[P];
+  int dw[P];
+  const int64_t sofs = env * S;
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    const int64_t i = sofs + j * L + l;
+    soc[j] = active ? sg.soc[i] : 0.f;
+    erem[j] = active ? sg.e_rem[i] : 0.f;
+    cap[j] = active ? sg.cap[i] : 0.f;
+    plast[j] = active ? sg.p_last[i] : 0.f;
+    dw[j] = active ? (int)sg.dwell[i] : 0;
+  }
+  double ret = active ? sg.ret[env] : 0.0;
+
+  const uint32_t k0 = (uint32_t)sg.seed, k1 = (uint32_t)(sg.seed >> 32);
+  const uint32_t env_id = (uint32_t)(sg.env0 + env);
+  const int steps_ep = C.steps_ep;
+  const int n_levels = C.n_levels;
+  int t_day = dy.t_day0;
+  uint32_t g = dy.g0;
+  int bM = 0;
+  float bpb = 0.f;
+  U4 aw[P];
+#pragma unroll
+  for (int j = 0; j < P; ++j) aw[j] = U4{0, 0, 0, 0};
+  const uint64_t smask = (L == 64) ? ~0ull : (((1ull << L) - 1ull) << sbase);
+  const uint64_t below_mask = (1ull << lane) - 1ull;
+
+  float *obs_e = dy.obs ? dy.obs + sg.obs_off + env * C.obs_dim : nullptr;
+  uint8_t *act_e = dy.act ? dy.act + sg.act_off + env * N : nullptr;
+  const uint8_t *ain_e = dy.act_in ? dy.act_in + sg.act_off + env * N : nullptr;
+  const int64_t renv = sg.env_off + env;
+
+  for (int t = 0; t < dy.T; ++t, ++g) {
+    // ---- exogenous draws for the next L steps, lane l -> step t + l
+    if ((t & (L - 1)) == 0) {
+      int td = t_day + l;
+      while (td >= steps_ep) td -= steps_ep;
+      const U4 w = philox(env_id, g + (uint32_t)l, 0u, kDomEnv, k0, k1);
+      bM = active ? count_below(C.tpois + td * kPoisStride, 5, w.x) : 0;
+      const float u1 = (float)((w.y >> 8) + 1u) * 0x1p-24f;
+      const float u2 = u24(w.z);
+      const float z = __builtin_amdgcn_sqrtf(-2.0f * __logf(u1)) * __builtin_amdgcn_cosf(u2);
+      bpb = C.glob[td * 4 + 2] + C.price_sigma * z;
+    }
+    const int tb = t & (L - 1);
+    const int M = bcast<L>(bM, tb);
+    const float pbuy = bcastf<L>(bpb, tb);
+
+    // ---- actions
+    int k[P];
+    if (dy.mode == CX_ACT_RANDOM) {
+      if (t == 0 || (g & 3u) == 0) {
+#pragma unroll
+        for (int j = 0; j < P; ++j) aw[j] = philox(env_id, g >> 2, (uint32_t)port[j], kDomAct, k0, k1);
+      }
+      const uint32_t sel = g & 3u;
+#pragma unroll
+      for (int j = 0; j < P; ++j) {
+        const uint32_t w = sel == 0 ? aw[j].x : sel == 1 ? aw[j].y : sel == 2 ? aw[j].z : aw[j].w;
+        k[j] = (int)__umulhi(w, (uint32_t)(n_levels + 1));
+      }
+    } else if (dy.mode == CX_ACT_MAX) {
+#pragma unroll
+      for (int j = 0; j < P; ++j) k[j] = n_levels;
+    } else {
+#pragma unroll
+      for (int j = 0; j < P; ++j) {
+        int v = 0;
+        if (active && port[j] >= 0) v = ain_e[(int64_t)t * dy.act_stride + port[j]];
+        k[j] = v > n_levels ? n_levels : v;
+      }
+    }
+
+    // ---- apply actions: clip by request, charge curve, battery room
+    float pw[P];
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      const float one_m = 1.0f - soc[j];
+      const float req = (float)k[j] * C.inv_n_levels * pmax[j];
+      const float rhat = pmax[j] * fminf(1.0f, one_m * C.inv_1mtau);
+      const float room = one_m * cap[j] * C.inv_dt;
+      pw[j] = dw[j] > 0 ? fminf(fminf(req, rhat), room) : 0.0f;
+    }
+
+    // ---- projection onto the capacity tree, deepest level first
+    for (int d = 0; d < D; ++d) {
+      float s[P];
+#pragma unroll
+      for (int j = 0; j < P; ++j) s[j] = block_sum_lanes<L>(pw[j], (int)((lbp[j] >> (8 * d)) & 0xFF));
+      // blocks wider than a row of L slots span whole registers: add across them
+      if constexpr (P >= 2) {
+        const int lb0 = (int)((lbp[0] >> (8 * d)) & 0xFF);
+        const int lb2 = (int)((lbp[P - 1] >> (8 * d)) & 0xFF);
+        if (lb0 > LOGL) {  // registers 0,1 pair up (lb uniform over the block)
+          const float a = s[0] + s[1];
+          s[0] = a; s[1] = a;
+        }
+        if constexpr (P == 4) {
+          if (lb2 > LOGL) {
+            const float a = s[2] + s[3];
+            s[2] = a; s[3] = a;
+          }
+          if (lb0 > LOGL + 1) {
+            const float a = s[0] + s[2];
+            s[0] = a; s[1] = a; s[2] = a; s[3] = a;
+          }
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < P; ++j) {
+        const float c = lcap[d][j];
+        pw[j] = s[j] > c ? pw[j] * (c * frcp(s[j])) : pw[j];
+      }
+    }
+    // delivered energy and grid energy of the step (App. A.3, charging only)
+    float e_net, e_grid;
+    {
+      float tot = 0.f;
+#pragma unroll
+      for (int j = 0; j < P; ++j) tot += pw[j];
+      tot = station_sum<L>(tot);
+      e_net = C.dt * tot;
+      if (C.uniform_eta) {
+        e_grid = e_net * C.inv_eta_uniform;
+      } else {
+        float tg = 0.f;
+#pragma unroll
+        for (int j = 0; j < P; ++j) tg += pw[j] * inv_eta[j];
+        e_grid = C.dt * station_sum<L>(tg);
+      }
+    }
+
+    // ---- charge, departures
+    float csat = 0.f;
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      if (dw[j] > 0) {
+        const float e = C.dt * pw[j];
+        soc[j] = fminf(1.0f, soc[j] + e * frcp(cap[j]));
+        erem[j] -= e;
+        plast[j] = pw[j];
+        dw[j] -= 1;
+        if (dw[j] == 0) {
+          csat += fmaxf(0.0f, erem[j]);
+          soc[j] = 0.f; erem[j] = 0.f; cap[j] = 0.f; plast[j] = 0.f;
+        }
+      }
+    }
+    if (C.alpha_sat != 0.0f) csat = station_sum<L>(csat);
+
+    // ---- arrivals: first free ports in port order take the accepted cars
+    int cnt[P], below[P];
+    bool fr[P];
+    int n_free = 0;
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      fr[j] = dw[j] == 0 && port[j] >= 0;
+      const uint64_t m = __ballot(fr[j]) & smask;
+      cnt[j] = __popcll(m);
+      below[j] = __popcll(m & below_mask);
+      n_free += cnt[j];
+    }
+    const int acc = M < n_free ? M : n_free;
+    const int rej = M - acc;
+    if (acc > 0) {
+      int run = 0;
+#pragma unroll
+      for (int j = 0; j < P; ++j) {
+        const int rank = run + below[j];
+        if (fr[j] && rank < acc) {
+          const U4 b = philox(env_id, g, (uint32_t)rank, kDomCar, k0, k1);
+          const float cp = C.cap_lo + C.cap_span * u24(b.x);
+          const float s0 = C.soc_lo + C.soc_span * u24(b.y);
+          const float tg = C.tgt_lo + C.tgt_span * u24(b.z);
+          dw[j] = 1 + count_below(C.tdwell, C.dwell_log2, b.w);
+          cap[j] = cp;
+          soc[j] = s0;
+          erem[j] = (tg - s0) * cp;
+          plast[j] = 0.f;
+        }
+        run += cnt[j];
+      }
+    }
+
+    // ---- reward (App. A.3)
+    const float price = e_grid > 0.0f ? pbuy : C.p_sell_grid;
+    const float r = C.p_sell * e_net - price * e_grid - C.fixed_cost - C.alpha_sat * csat -
+                    C.alpha_dec * (float)rej;
+    ret += (double)r;
+
+    // ---- end of day
+    t_day += 1;
+    const bool done = t_day == steps_ep;
+    if (done) {
+      t_day = 0;
+#pragma unroll
+      for (int j = 0; j < P; ++j) {
+        dw[j] = 0; soc[j] = 0.f; erem[j] = 0.f; cap[j] = 0.f; plast[j] = 0.f;
+      }
+    }
+
+    // ---- records
+    if (active) {
+      if (dy.out_mode == CX_OUT_FULL && obs_e) {
+        float *o = obs_e + (int64_t)t * dy.obs_stride;
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+          if (port[j] >= 0) {
+            const bool occ = dw[j] > 0;
+            const int p = port[j];
+            o[0 * N + p] = occ ? 1.0f : 0.0f;
+            o[1 * N + p] = soc[j];
+            o[2 * N + p] = occ ? erem[j] * frcp(cap[j]) : 0.0f;
+            o[3 * N + p] = (float)dw[j] * C.inv_steps_ep;
+            o[4 * N + p] = occ ? fminf(1.0f, (1.0f - soc[j]) * C.inv_1mtau) : 0.0f;
+            o[5 * N + p] = plast[j] * inv_pmax[j];
+          }
+        }
+        if (l < 4) {
+          const int n_occ = done ? 0 : (N - n_free + acc);
+          const float gv = l == 3 ? (float)n_occ * (1.0f / (float)N) : C.glob[t_day * 4 + l];
+          o[6 * N + l] = gv;
+        }
+      }
+      if ((dy.out_mode == CX_OUT_FULL || dy.out_mode == CX_OUT_ACT_REWARD) && act_e) {
+        uint8_t *a = act_e + (int64_t)t * dy.act_stride;
+#pragma unroll
+        for (int j = 0; j < P; ++j)
+          if (port[j] >= 0) a[port[j]] = (uint8_t)k[j];
+      }
+      if (l == 0) {
+        if (dy.reward) dy.reward[(int64_t)t * dy.env_stride + renv] = r;
+        if (dy.done) dy.done[(int64_t)t * dy.env_stride + renv] = done ? 1 : 0;
+      }
+    }
+  }
+
+  // ---- state back to HBM
+  if (active) {
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      const int64_t i = sofs + j * L + l;
+      sg.soc[i] = soc[j];
+      sg.e_rem[i] = erem[j];
+      sg.cap[i] = cap[j];
+      sg.p_last[i] = plast[j];
+      sg.dwell[i] = (int16_t)dw[j];
+    }
+    if (l == 0) sg.ret[env] = ret;
+  }
+}
+
+__global__ __launch_bounds__(512) void k_rollout(LaunchArgs a) {
+  const int b = blockIdx.x;
+  int lo = 0, hi = a.n_segs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (a.segs[mid].block_begin <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const SegDev &sg = a.segs[lo];
+  const int W = blockDim.x >> 6;
+  const int group = __builtin_amdgcn_readfirstlane((b - sg.block_begin) * W + (int)(threadIdx.x >> 6));
+  if (group >= sg.n_groups) return;
+  Dyn dy;
+  if (a.per_segment) {
+    dy = Dyn{sg.T, sg.t_day0, sg.g0, sg.mode, sg.out_mode, sg.obs, sg.act, sg.reward, sg.done, sg.act_in,
+             sg.obs_stride, sg.act_stride, sg.env_stride};
+  } else {
+    dy = Dyn{a.T, a.t_day0, a.g0, a.mode, a.out_mode, a.obs, a.act, a.reward, a.done, a.act_in,
+             a.obs_stride, a.act_stride, a.env_stride};
+  }
+  switch (sg.pack) {
+    case 0: run_group<4, 1>(sg, dy, group); break;
+    case 1: run_group<8, 1>(sg, dy, group); break;
+    case 2: run_group<16, 1>(sg, dy, group); break;
+    case 3: run_group<32, 1>(sg, dy, group); break;
+    case 4: run_group<64, 1>(sg, dy, group); break;
+    case 5: run_group<4, 2>(sg, dy, group); break;
+    case 6: run_group<8, 2>(sg, dy, group); break;
+    case 7: run_group<16, 2>(sg, dy, group); break;
+    case 8: run_group<32, 2>(sg, dy, group); break;
+    case 9: run_group<64, 2>(sg, dy, group); break;
+    case 10: run_group<4, 4>(sg, dy, group); break;
+    case 11: run_group<8, 4>(sg, dy, group); break;
+    case 12: run_group<16, 4>(sg, dy, group); break;
+    case 13: run_group<32, 4>(sg, dy, group); break;
+    case 14: run_group<64, 4>(sg, dy, group); break;
+    default: break;
+  }
+}
+
+// Observation of empty stations at t_day = 0 for every env of one segment.
+__global__ void k_reset_obs(const ClassDev *cls, int64_t n_envs, float *obs) {
+  const int64_t dim = cls->obs_dim;
+  const int N = cls->n_ports;
+  const int64_t total = n_envs * dim;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t f = i % dim;
+    float v = 0.f;
+    if (f >= 6 * N && f < 6 * N + 3) v = cls->glob[f - 6 * N];
+    obs[i] = v;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_rollout(const LaunchArgs &a, int n_blocks, int waves_per_block, hipStream_t st) {
+  if (n_blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rollout, dim3(n_blocks), dim3(64 * waves_per_block), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t graph_rollout(RolloutGraph &g, const LaunchArgs &a, int n_blocks, int waves_per_block,
+                         hipStream_t st) {
+  if (n_blocks <= 0) return hipSuccess;
+  LaunchArgs args = a;
+  void *params[1] = {&args};
+  hipKernelNodeParams p{};
+  p.func = reinterpret_cast<void *>(&k_rollout);
+  p.gridDim = dim3(n_blocks);
+  p.blockDim = dim3(64 * waves_per_block);
+  p.sharedMemBytes = 0;
+  p.kernelParams = params;
+  p.extra = nullptr;
+  hipError_t e;
+  if (!g.exec || g.blocks != n_blocks || g.waves != waves_per_block) {
+    graph_destroy(g);
+    if ((e = hipGraphCreate(&g.graph, 0)) != hipSuccess) return e;
+    if ((e = hipGraphAddKernelNode(&g.node, g.graph, nullptr, 0, &p)) != hipSuccess) return e;
+    if ((e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0)) != hipSuccess) return e;
+    g.blocks = n_blocks;
+    g.waves = waves_per_block;
+  } else if ((e = hipGraphExecKernelNodeSetParams(g.exec, g.node, &p)) != hipSuccess) {
+    return e;
+  }
+  return hipGraphLaunch(g.exec, st);
+}
+
+void graph_destroy(RolloutGraph &g) {
+  if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  if (g.graph) (void)hipGraphDestroy(g.graph);
+  g = RolloutGraph{};
+}
+
+hipError_t launch_reset_obs_one(const ClassDev *cls_dev, int64_t n_envs, float *obs, hipStream_t st) {
+  if (n_envs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_reset_obs, dim3(256), dim3(256), 0, st, cls_dev, n_envs, obs);
+  return hipGetLastError();
+}
+
+}  // namespace cx

@@ -1,0 +1,47 @@
+// cx_spec.h -- station spec validation, tree compilation and sampling tables.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "cx_internal.h"
+
+namespace cx {
+
+// Owning copy of a cx_station_spec (the caller's arrays are copied at create).
+struct SpecCopy {
+  cx_station_spec s;
+  std::vector<int32_t> node_parent, port_parent;
+  std::vector<double> node_limit, node_eta, port_pmax, port_eta;
+};
+
+// The capacity tree in the kernels' layout.  Every node owns an aligned block of
+// 2^b slots; children are placed in port order, each aligned to its own block
+// size, so the slot order of ports equals their port order.  Level 0 is the
+// deepest node level, level D-1 the root.
+struct Compiled {
+  int N = 0, S = 0, D = 0;
+  std::vector<int32_t> slot_port;   // [S], -1 = padding
+  std::vector<int32_t> port_slot;   // [N]
+  std::vector<uint32_t> slot_lb;    // [S], 8 bits per level
+  std::vector<float> slot_cap;      // [D][S]
+  std::vector<float> slot_pmax, slot_inv_pmax, slot_inv_eta;
+  bool uniform_eta = true;
+  float inv_eta_uniform = 1.f;
+};
+
+struct Tables {
+  std::vector<uint32_t> tpois;      // [steps][24] as defined
+  std::vector<uint32_t> tpois_dev;  // [steps][32] padded with 0xFFFFFFFF
+  std::vector<uint32_t> tdwell;     // [dwell_max], entry 0 unused
+  std::vector<uint32_t> tdwell_dev; // [2^dwell_log2]: entries 1.. of tdwell, then 0xFFFFFFFF
+  int dwell_log2 = 1;
+  std::vector<float> glob;          // [steps][4]
+};
+
+bool copy_spec(const cx_station_spec &in, SpecCopy *out, std::string *err);
+bool compile_spec(const SpecCopy &sc, Compiled *c, std::string *err);
+void build_tables(const SpecCopy &sc, Tables *t);
+bool tables_monotone(const Tables &t);
+
+}  // namespace cx

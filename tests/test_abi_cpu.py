@@ -1,0 +1,121 @@
+"""CPU checks of the HIP library's host side: it loads, exports every symbol the
+headers declare, validates specs, compiles capacity trees into the aligned slot
+layout, and builds integer sampling tables identical to the oracle's (the hard
+gate for integer bit-exactness).  No kernel is launched."""
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def cxm():
+    from paper_2507_01522_amd import cx
+    cx.lib()
+    return cx
+
+
+def declared_symbols():
+    names = set()
+    for h in os.listdir(os.path.join(ROOT, "include")):
+        if h.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", h)).read()
+            txt = re.sub(r"/\*.*?\*/", " ", txt, flags=re.S)          # drop comments
+            names |= set(re.findall(r"(?:cx_status|void|char\s*\*)\s+(cx_[a-z_]+)\s*\(", txt))
+    return names
+
+
+def test_library_exports_every_declared_symbol(cxm):
+    names = declared_symbols()
+    assert len(names) >= 25
+    L = cxm.lib()
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing
+    assert set(cxm.EXPORTS) >= names
+
+
+SPECS = [W.tiny_parity_station(), W.scale_station(), W.policy_station(), W.two_charger_types(),
+         W.tiny_parity_station().replace(arrival_peak=0.0, dwell_max=1),
+         W.fanout4_tree(32, 2).replace(steps_per_episode=96, dwell_max=300, dwell_mu=math.log(12.0)),
+         W.fanout4_tree(128, 3).replace(arrival_peak=8.0)] + W.mixture_classes()
+
+
+@pytest.mark.parametrize("spec", SPECS, ids=[s.name or str(i) for i, s in enumerate(SPECS)])
+def test_tables_equal_oracle(cxm, oracle_lib, spec):
+    tp, td = cxm.build_tables(spec)
+    otp, otd = oracle_lib.OracleClass(spec).tables()
+    assert np.array_equal(tp, otp)
+    assert np.array_equal(td[1:], otd[1:])
+
+
+def leaves_of(spec, h):
+    out = []
+    for i, p in enumerate(spec.port_parent):
+        a = p
+        while a >= 0:
+            if a == h:
+                out.append(i)
+                break
+            a = spec.node_parent[a]
+    return out
+
+
+@pytest.mark.parametrize("spec", SPECS[:4] + W.mixture_classes(), ids=lambda s: s.name)
+def test_layout_is_aligned_and_order_preserving(cxm, spec):
+    lay = cxm.compile_layout(spec)
+    S, D = lay["slots"], lay["levels"]
+    port = lay["slot_port"]
+    assert S >= spec.n_ports and S & (S - 1) == 0
+    used = port[port >= 0]
+    assert np.array_equal(used, np.arange(spec.n_ports))          # port order = slot order
+    depth = [0] * spec.n_nodes
+    for h in range(1, spec.n_nodes):
+        depth[h] = depth[spec.node_parent[h]] + 1
+    assert D == max(depth) + 1
+    slot_of = {int(p): s for s, p in enumerate(port) if p >= 0}
+    for h in range(spec.n_nodes):
+        lvl = D - 1 - depth[h]
+        slots = [slot_of[i] for i in leaves_of(spec, h)]
+        lb = (lay["slot_lb"][slots] >> (8 * lvl)) & 0xFF
+        assert len(set(lb.tolist())) == 1
+        B = 1 << int(lb[0])
+        base = min(slots) // B * B
+        assert max(slots) < base + B                               # one aligned block holds the subtree
+        assert np.allclose(lay["slot_cap"][lvl, base:base + B], spec.node_limit_kw[h] * spec.node_eta[h])
+
+
+def test_uneven_tree_is_padded(cxm):
+    lay = cxm.compile_layout(W.two_charger_types())                 # 10 DC + 6 AC ports
+    assert lay["slots"] == 32 and lay["levels"] == 2
+    assert list(lay["slot_port"][:16]) == list(range(10)) + [-1] * 6
+    assert list(lay["slot_port"][16:24]) == list(range(10, 16)) + [-1] * 2
+
+
+BAD = [
+    ("n_ports", dict(n_ports=0, port_parent=[], port_pmax_kw=[], port_eta=[])),
+    ("node_parent", dict(node_parent=[0])),
+    ("limits", dict(node_limit_kw=[-1.0])),
+    ("tau", dict(tau=1.0)),
+    ("eta", dict(port_eta=[0.0] * 16)),
+    ("dfs", None),
+    ("depth", None),
+]
+
+
+@pytest.mark.parametrize("what,kw", BAD)
+def test_invalid_specs_rejected(cxm, what, kw):
+    if what == "dfs":
+        spec = W.StationSpec(4, [-1, 0, 0], [100, 50, 50], [1, 1, 1], [1, 2, 1, 2], [22.0] * 4, [1.0] * 4)
+    elif what == "depth":
+        spec = W.StationSpec(1, [-1, 0, 1, 2, 3], [9.0] * 5, [1.0] * 5, [4], [22.0], [1.0])
+    else:
+        spec = W.tiny_parity_station().replace(**kw)
+    with pytest.raises(cxm.CxError) as ei:
+        cxm.compile_layout(spec)
+    assert ei.value.status == -1 and str(ei.value)
