@@ -35,8 +35,9 @@ def record_bytes(n_ports: np.ndarray) -> np.ndarray:
 
 
 def state_bytes(n_ports: np.ndarray) -> np.ndarray:
-    """Per env: soc, e_rem, cap, p_last f32 + dwell i16 per port, f64 return."""
-    return 18 * n_ports + 8
+    """Per env: 1 - SoC (f64), 1 - target, capacity, last power (f32) and dwell (i16)
+    per port, plus the f64 return."""
+    return 22 * n_ports + 8
 
 
 def workload():

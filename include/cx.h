@@ -198,11 +198,14 @@ cx_status cx_set_policy(cx_ctx *ctx, int32_t hidden, const uint16_t *w1_host, co
 cx_status cx_policy_logits(cx_ctx *ctx, const float *obs_dev, int64_t n, float *logits_dev);
 
 /* Snapshot / restore of the whole state (all stations, returns, g, t_day) in a
- * packing-independent host format of cx_info.state_bytes bytes.  Both calls
- * synchronise the context's stream.  Format (little endian):
+ * packing-independent host format of cx_info.state_bytes bytes, bit-exact, so a
+ * restored context continues exactly as the original.  Both calls synchronise
+ * the context's stream.  Format (little endian):
  *   u64 magic 0x31305843 ('CX01'), i64 n_envs, i64 total_ports, u32 g, i32 t_day,
- *   then per port in env/port order: i32 dwell, f32 soc, f32 e_rem, f32 cap,
- *   f32 p_last; then per env: f64 return. */
+ *   then per port in env/port order (24 bytes): i32 dwell (steps left, 0 = empty),
+ *   f64 1 - SoC, f32 1 - target SoC, f32 battery capacity C, f32 last power;
+ *   then per env: f64 return.  The energy still wanted is (target - SoC) * C.
+ *   An empty port is all zeros. */
 cx_status cx_get_state(cx_ctx *ctx, void *host, size_t bytes);
 cx_status cx_set_state(cx_ctx *ctx, const void *host, size_t bytes);
 

@@ -96,17 +96,41 @@ bool legal_packing(int S, int lanes) {
 
 int default_lanes(int S) { return S <= 64 ? S : 64; }
 
-// Lay out the launch: one segment per class, heaviest (most slots) first.
+// Group segments by slots per lane (one kernel each); inside a group the
+// heaviest classes (most slots) come first so they start first.
+void build_groups(const std::vector<SegDev> &in, const std::vector<int> &log2_dwell, int wpb,
+                  std::vector<SegDev> *out, std::vector<LaunchGroup> *groups) {
+  out->clear();
+  groups->clear();
+  for (int P : {4, 2, 1}) {
+    LaunchGroup g;
+    g.per_lane = P;
+    g.seg_begin = (int)out->size();
+    int blocks = 0;
+    std::vector<int> idx;
+    for (size_t i = 0; i < in.size(); ++i)
+      if (pack_per_lane(in[i].pack) == P) idx.push_back((int)i);
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
+      return pack_lanes(in[a].pack) * P > pack_lanes(in[b].pack) * P;
+    });
+    for (int i : idx) {
+      SegDev sg = in[i];
+      sg.block_begin = blocks;
+      blocks += (sg.n_groups + wpb - 1) / wpb;
+      g.max_dwell_log2 = std::max(g.max_dwell_log2, log2_dwell[i]);
+      g.max_T = std::max(g.max_T, sg.T);
+      out->push_back(sg);
+    }
+    g.n_segs = (int)out->size() - g.seg_begin;
+    g.n_blocks = blocks;
+    if (g.n_segs > 0) groups->push_back(g);
+  }
+}
+
 cx_status rebuild_segments(cx_ctx *ctx) {
-  std::vector<int> order(ctx->classes.size());
-  for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-    return ctx->classes[a].comp.S > ctx->classes[b].comp.S;
-  });
-  ctx->segs_host.clear();
-  int blocks = 0;
-  for (int ci : order) {
-    ClassRt &c = ctx->classes[ci];
+  std::vector<SegDev> segs;
+  std::vector<int> dl;
+  for (ClassRt &c : ctx->classes) {
     if (c.n_envs == 0) continue;
     SegDev sg{};
     const int L = c.lanes, P = c.comp.S / c.lanes;
@@ -115,20 +139,22 @@ cx_status rebuild_segments(cx_ctx *ctx) {
     sg.env0 = c.env_begin;
     sg.n_envs = c.n_envs;
     sg.n_groups = (int32_t)((c.n_envs + spw - 1) / spw);
-    sg.block_begin = blocks;
     sg.pack = pack_id(L, P);
     sg.seed = ctx->seed;
     const int64_t so = c.slot_off;
-    sg.soc = ctx->soc + so; sg.e_rem = ctx->e_rem + so; sg.cap = ctx->cap + so; sg.p_last = ctx->p_last + so;
+    sg.q = ctx->q + so;
+    sg.u = ctx->u + so;
+    sg.cap = ctx->cap + so;
+    sg.p_last = ctx->p_last + so;
     sg.dwell = ctx->dwell + so;
     sg.ret = ctx->ret + c.env_begin;
     sg.obs_off = c.obs_off;
     sg.act_off = c.port_off;
     sg.env_off = c.env_begin;
-    blocks += (sg.n_groups + ctx->wpb - 1) / ctx->wpb;
-    ctx->segs_host.push_back(sg);
+    segs.push_back(sg);
+    dl.push_back(c.tab.dwell_log2);
   }
-  ctx->n_blocks = blocks;
+  build_groups(segs, dl, ctx->wpb, &ctx->segs_host, &ctx->groups);
   if (!ctx->segs_dev) {
     hipError_t e = hipMalloc(&ctx->segs_dev, sizeof(SegDev) * std::max<size_t>(1, ctx->classes.size()));
     if (e != hipSuccess) return fail_status(CX_E_OOM, "hipMalloc of segment table failed");
@@ -225,11 +251,12 @@ static cx_status create_impl(const cx_station_spec *specs, int32_t n_specs, cons
   ctx->total_ports = port_off;
   ctx->obs_elems = obs_off;
   ctx->total_slots = slot_off;
-  // state: 4 float arrays + int16 dwell over all slots, double return per env
+  // state: q (double), u / cap / p_last (float), dwell (int16) over all slots; return per env
+  const size_t qbytes = align256(sizeof(double) * (size_t)slot_off);
   const size_t fbytes = align256(sizeof(float) * (size_t)slot_off);
   const size_t dbytes = align256(sizeof(int16_t) * (size_t)slot_off);
   const size_t rbytes = align256(sizeof(double) * (size_t)n_envs);
-  const size_t total = 4 * fbytes + dbytes + rbytes;
+  const size_t total = qbytes + 3 * fbytes + dbytes + rbytes;
   if (hipMalloc(&ctx->state_mem, total) != hipSuccess) {
     free_ctx(ctx);
     return fail_status(CX_E_OOM, "hipMalloc of station state failed");
@@ -237,12 +264,12 @@ static cx_status create_impl(const cx_station_spec *specs, int32_t n_specs, cons
   ctx->state_bytes_dev = total;
   ctx->device_bytes += (int64_t)total;
   unsigned char *b = static_cast<unsigned char *>(ctx->state_mem);
-  ctx->soc = reinterpret_cast<float *>(b);
-  ctx->e_rem = reinterpret_cast<float *>(b + fbytes);
-  ctx->cap = reinterpret_cast<float *>(b + 2 * fbytes);
-  ctx->p_last = reinterpret_cast<float *>(b + 3 * fbytes);
-  ctx->dwell = reinterpret_cast<int16_t *>(b + 4 * fbytes);
-  ctx->ret = reinterpret_cast<double *>(b + 4 * fbytes + dbytes);
+  ctx->q = reinterpret_cast<double *>(b);
+  ctx->u = reinterpret_cast<float *>(b + qbytes);
+  ctx->cap = reinterpret_cast<float *>(b + qbytes + fbytes);
+  ctx->p_last = reinterpret_cast<float *>(b + qbytes + 2 * fbytes);
+  ctx->dwell = reinterpret_cast<int16_t *>(b + qbytes + 3 * fbytes);
+  ctx->ret = reinterpret_cast<double *>(b + qbytes + 3 * fbytes + dbytes);
   if (hipMemset(ctx->state_mem, 0, total) != hipSuccess) {
     free_ctx(ctx);
     return fail_status(CX_E_DEVICE, "hipMemset of station state failed");
@@ -350,7 +377,7 @@ cx_status cx_step_ex(cx_ctx *ctx, cx_action_mode mode, const uint8_t *actions_in
   if (out) {
     a.obs = out->obs; a.act = out->actions; a.reward = out->reward; a.done = out->done;
   }
-  hipError_t e = launch_rollout(a, ctx->n_blocks, ctx->wpb, ctx->stream);
+  hipError_t e = launch_groups(a, ctx->groups.data(), (int)ctx->groups.size(), ctx->wpb, ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "cx_step launch");
   advance_clock(ctx, 1);
   return CX_OK;
@@ -382,7 +409,8 @@ cx_status cx_rollout(cx_ctx *ctx, int32_t T, cx_action_mode mode, cx_out_mode ou
     a.reward = out->reward;
     a.done = out->done;
   }
-  hipError_t e = graph_rollout(ctx->graph, a, ctx->n_blocks, ctx->wpb, ctx->stream);
+  hipError_t e = graph_rollout(ctx->graph, a, ctx->groups.data(), (int)ctx->groups.size(), ctx->wpb,
+                               ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "cx_rollout graph launch");
   advance_clock(ctx, T);
   return CX_OK;

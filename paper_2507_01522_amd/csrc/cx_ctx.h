@@ -33,16 +33,18 @@ struct cx_ctx {
   int32_t steps_ep = 288;
   int64_t n_envs = 0, total_ports = 0, obs_elems = 0, total_slots = 0;
   std::vector<cx::ClassRt> classes;
-  // state, env-major slot layout: soc/e_rem/cap/p_last float, dwell int16, return double
+  // state, env-major slot layout: q = 1 - SoC (double), u = 1 - target SoC,
+  // capacity and last power (float), dwell (int16); return per env (double)
   void *state_mem = nullptr;
   size_t state_bytes_dev = 0;
-  float *soc = nullptr, *e_rem = nullptr, *cap = nullptr, *p_last = nullptr;
+  double *q = nullptr;
+  float *u = nullptr, *cap = nullptr, *p_last = nullptr;
   int16_t *dwell = nullptr;
   double *ret = nullptr;
-  // launch layout
+  // launch layout: segments grouped by slots per lane, one kernel per group
   cx::SegDev *segs_dev = nullptr;
   std::vector<cx::SegDev> segs_host;
-  int n_blocks = 0;
+  std::vector<cx::LaunchGroup> groups;
   int wpb = 4;
   bool failed = false;
   int64_t device_bytes = 0;
@@ -56,6 +58,8 @@ extern thread_local std::string g_last_error;
 cx_status fail_status(cx_status st, const std::string &msg);
 cx_status hip_fail(cx_ctx *ctx, hipError_t e, const char *what);
 cx_status rebuild_segments(cx_ctx *ctx);
+void build_groups(const std::vector<SegDev> &in, const std::vector<int> &log2_dwell, int wpb,
+                  std::vector<SegDev> *out, std::vector<LaunchGroup> *groups);
 LaunchArgs base_args(const cx_ctx *ctx);
 void advance_clock(cx_ctx *ctx, int32_t T);
 bool legal_packing(int S, int lanes);

@@ -65,8 +65,12 @@ struct SegDev {
   int32_t pack;
   int32_t pad_;
   uint64_t seed;
-  // state, env-major slot layout, at the segment's first env
-  float *soc, *e_rem, *cap, *p_last;
+  // state, env-major slot layout, at the segment's first env.  A car is kept
+  // as q = 1 - SoC (FP64: the per-step increments are accumulated here),
+  // u = 1 - target SoC, its capacity and the last applied power; the energy
+  // still wanted is e_rem = (q - u) * cap.  Empty slots hold zeros.
+  double *q;
+  float *u, *cap, *p_last;
   int16_t *dwell;
   double *ret;
   // offsets of the segment's first env inside the output records
@@ -90,7 +94,8 @@ struct LaunchArgs {
   int32_t per_segment;  // 1: take T/g0/t_day0/modes/outputs from each segment
   int32_t T, t_day0;
   uint32_t g0;
-  int32_t mode, out_mode, pad_;
+  int32_t mode, out_mode;
+  int32_t lds_tdwell;   // 1: stage the stay thresholds in LDS (set per launch group)
   float *obs;
   uint8_t *act;
   float *reward;
@@ -99,20 +104,36 @@ struct LaunchArgs {
   int64_t obs_stride, act_stride, env_stride;
 };
 
-// A one-kernel HIP graph of the persistent rollout, instantiated once and
-// re-parameterised per call.
+// One launch group: the segments whose packing has P slots per lane, launched
+// by the kernel instantiated for that P.
+struct LaunchGroup {
+  int per_lane = 1;     // P
+  int seg_begin = 0;    // index of the first segment in the device segment table
+  int n_segs = 0;
+  int n_blocks = 0;
+  int max_dwell_log2 = 1;  // largest stay table among its classes (LDS bytes = 4 << this)
+  int max_T = 0;           // per-segment launches: the longest horizon among its segments
+};
+
+// The persistent rollout as a HIP graph with one kernel node per launch group
+// (no dependencies between them), instantiated once per launch shape and
+// re-parameterised on every call.
 struct RolloutGraph {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  hipGraphNode_t node = nullptr;
-  int blocks = -1, waves = -1;
+  hipGraphNode_t node[3] = {nullptr, nullptr, nullptr};
+  int n_nodes = 0;
+  int shape[3][3] = {};
+  int waves = -1;
 };
 
-// Host-side launchers (defined in cx_kernels.hip).
-hipError_t graph_rollout(RolloutGraph &g, const LaunchArgs &a, int n_blocks, int waves_per_block,
+// Host-side launchers (defined in cx_kernels.hip).  `a.segs` is the base of
+// the device segment table; each group launches with its own slice.
+hipError_t launch_groups(const LaunchArgs &a, const LaunchGroup *groups, int n_groups, int waves_per_block,
                          hipStream_t st);
+hipError_t graph_rollout(RolloutGraph &g, const LaunchArgs &a, const LaunchGroup *groups, int n_groups,
+                         int waves_per_block, hipStream_t st);
 void graph_destroy(RolloutGraph &g);
-hipError_t launch_rollout(const LaunchArgs &a, int n_blocks, int waves_per_block, hipStream_t st);
 hipError_t launch_reset_obs_one(const ClassDev *cls_dev, int64_t n_envs, float *obs, hipStream_t st);
 
 }  // namespace cx

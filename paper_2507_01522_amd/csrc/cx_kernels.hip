@@ -50,11 +50,20 @@ __device__ __forceinline__ float u24(uint32_t w) { return (float)(w >> 8) * 0x1p
 
 // Number of entries of a non-decreasing table (size 2^log2n, last entry
 // 0xFFFFFFFF) that are strictly below w.
-__device__ __forceinline__ int count_below(const uint32_t *__restrict__ tab, int log2n, uint32_t w) {
+__device__ __forceinline__ int count_below(const uint32_t *tab, int log2n, uint32_t w) {
   int pos = 0;
   for (int s = 1 << (log2n - 1); s >= 1; s >>= 1)
     if (tab[pos + s - 1] < w) pos += s;
   return pos;
+}
+
+// Arrivals of one step: thresholds exceeded by w in a 32-entry row.  The
+// first four entries come in one 16-byte load; the full bisection runs only
+// when w exceeds all four (rare for the rates used here).
+__device__ __forceinline__ int arrivals(const uint32_t *row, uint32_t w) {
+  const uint4 t = *reinterpret_cast<const uint4 *>(row);
+  const int m = (int)(w > t.x) + (int)(w > t.y) + (int)(w > t.z) + (int)(w > t.w);
+  return m < 4 ? m : count_below(row, 5, w);
 }
 
 // Exchange with the lane whose index differs in bit K (K = 0..5), for use in
@@ -131,7 +140,7 @@ struct Dyn {
 };
 
 template <int L, int P>
-__device__ void run_group(const SegDev &sg, const Dyn &dy, int group) {
+__device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int group, const uint32_t *tdw) {
   constexpr int SPW = 64 / L;
   constexpr int LOGL = (L == 4) ? 2 : (L == 8) ? 3 : (L == 16) ? 4 : (L == 32) ? 5 : 6;
   const ClassDev &C = *sg.cls;
@@ -161,17 +170,19 @@ __device__ void run_group(const SegDev &sg, const Dyn &dy, int group) {
   }
 
   // ---- state
-  float soc[P], erem[P], cap[P], plast[P];
+  double q[P];
+  float u[P], cap[P], icap[P], plast[P];
   int dw[P];
   const int64_t sofs = env * S;
 #pragma unroll
   for (int j = 0; j < P; ++j) {
     const int64_t i = sofs + j * L + l;
-    soc[j] = active ? sg.soc[i] : 0.f;
-    erem[j] = active ? sg.e_rem[i] : 0.f;
+    q[j] = active ? sg.q[i] : 0.0;
+    u[j] = active ? sg.u[i] : 0.f;
     cap[j] = active ? sg.cap[i] : 0.f;
     plast[j] = active ? sg.p_last[i] : 0.f;
     dw[j] = active ? (int)sg.dwell[i] : 0;
+    icap[j] = frcp(cap[j]);
   }
   double ret = active ? sg.ret[env] : 0.0;
 
@@ -200,7 +211,7 @@ __device__ void run_group(const SegDev &sg, const Dyn &dy, int group) {
       int td = t_day + l;
       while (td >= steps_ep) td -= steps_ep;
       const U4 w = philox(env_id, g + (uint32_t)l, 0u, kDomEnv, k0, k1);
-      bM = active ? count_below(C.tpois + td * kPoisStride, 5, w.x) : 0;
+      bM = active ? arrivals(C.tpois + td * kPoisStride, w.x) : 0;
       const float u1 = (float)((w.y >> 8) + 1u) * 0x1p-24f;
       const float u2 = u24(w.z);
       const float z = __builtin_amdgcn_sqrtf(-2.0f * __logf(u1)) * __builtin_amdgcn_cosf(u2);
@@ -239,51 +250,56 @@ __device__ void run_group(const SegDev &sg, const Dyn &dy, int group) {
     float pw[P];
 #pragma unroll
     for (int j = 0; j < P; ++j) {
-      const float one_m = 1.0f - soc[j];
+      const float qf = (float)q[j];
       const float req = (float)k[j] * C.inv_n_levels * pmax[j];
-      const float rhat = pmax[j] * fminf(1.0f, one_m * C.inv_1mtau);
-      const float room = one_m * cap[j] * C.inv_dt;
+      const float rhat = pmax[j] * fminf(1.0f, qf * C.inv_1mtau);
+      const float room = qf * cap[j] * C.inv_dt;
       pw[j] = dw[j] > 0 ? fminf(fminf(req, rhat), room) : 0.0f;
     }
 
     // ---- projection onto the capacity tree, deepest level first
-    for (int d = 0; d < D; ++d) {
-      float s[P];
 #pragma unroll
-      for (int j = 0; j < P; ++j) s[j] = block_sum_lanes<L>(pw[j], (int)((lbp[j] >> (8 * d)) & 0xFF));
-      // blocks wider than a row of L slots span whole registers: add across them
-      if constexpr (P >= 2) {
-        const int lb0 = (int)((lbp[0] >> (8 * d)) & 0xFF);
-        const int lb2 = (int)((lbp[P - 1] >> (8 * d)) & 0xFF);
-        if (lb0 > LOGL) {  // registers 0,1 pair up (lb uniform over the block)
-          const float a = s[0] + s[1];
-          s[0] = a; s[1] = a;
-        }
-        if constexpr (P == 4) {
-          if (lb2 > LOGL) {
-            const float a = s[2] + s[3];
-            s[2] = a; s[3] = a;
-          }
-          if (lb0 > LOGL + 1) {
-            const float a = s[0] + s[2];
-            s[0] = a; s[1] = a; s[2] = a; s[3] = a;
-          }
-        }
-      }
+    for (int d = 0; d < kMaxLevels; ++d) {
+      if (d < D) {
+        float s[P];
 #pragma unroll
-      for (int j = 0; j < P; ++j) {
-        const float c = lcap[d][j];
-        pw[j] = s[j] > c ? pw[j] * (c * frcp(s[j])) : pw[j];
+        for (int j = 0; j < P; ++j) s[j] = block_sum_lanes<L>(pw[j], (int)((lbp[j] >> (8 * d)) & 0xFF));
+        // blocks wider than a row of L slots span whole registers: add across them
+        if constexpr (P >= 2) {
+          const int lb0 = (int)((lbp[0] >> (8 * d)) & 0xFF);
+          if (lb0 > LOGL) {
+            const float a = s[0] + s[1];
+            s[0] = a;
+            s[1] = a;
+          }
+          if constexpr (P == 4) {
+            const int lb2 = (int)((lbp[2] >> (8 * d)) & 0xFF);
+            if (lb2 > LOGL) {
+              const float a = s[2] + s[3];
+              s[2] = a;
+              s[3] = a;
+            }
+            if (lb0 > LOGL + 1) {
+              const float a = s[0] + s[2];
+              s[0] = a; s[1] = a; s[2] = a; s[3] = a;
+            }
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+          const float c = lcap[d][j];
+          pw[j] = s[j] > c ? pw[j] * (c * frcp(s[j])) : pw[j];
+        }
       }
     }
-    // delivered energy and grid energy of the step (App. A.3, charging only)
+
+    // ---- delivered energy and grid energy (App. A.3, charging only)
     float e_net, e_grid;
     {
       float tot = 0.f;
 #pragma unroll
       for (int j = 0; j < P; ++j) tot += pw[j];
-      tot = station_sum<L>(tot);
-      e_net = C.dt * tot;
+      e_net = C.dt * station_sum<L>(tot);
       if (C.uniform_eta) {
         e_grid = e_net * C.inv_eta_uniform;
       } else {
@@ -300,13 +316,13 @@ __device__ void run_group(const SegDev &sg, const Dyn &dy, int group) {
     for (int j = 0; j < P; ++j) {
       if (dw[j] > 0) {
         const float e = C.dt * pw[j];
-        soc[j] = fminf(1.0f, soc[j] + e * frcp(cap[j]));
-        erem[j] -= e;
+        const double nq = q[j] - (double)(e * icap[j]);
+        q[j] = nq > 0.0 ? nq : 0.0;
         plast[j] = pw[j];
         dw[j] -= 1;
         if (dw[j] == 0) {
-          csat += fmaxf(0.0f, erem[j]);
-          soc[j] = 0.f; erem[j] = 0.f; cap[j] = 0.f; plast[j] = 0.f;
+          csat += fmaxf(0.0f, (float)((q[j] - (double)u[j]) * (double)cap[j]));
+          q[j] = 0.0; u[j] = 0.f; cap[j] = 0.f; icap[j] = 0.f; plast[j] = 0.f;
         }
       }
     }
@@ -336,10 +352,11 @@ __device__ void run_group(const SegDev &sg, const Dyn &dy, int group) {
           const float cp = C.cap_lo + C.cap_span * u24(b.x);
           const float s0 = C.soc_lo + C.soc_span * u24(b.y);
           const float tg = C.tgt_lo + C.tgt_span * u24(b.z);
-          dw[j] = 1 + count_below(C.tdwell, C.dwell_log2, b.w);
+          dw[j] = 1 + count_below(tdw, C.dwell_log2, b.w);
           cap[j] = cp;
-          soc[j] = s0;
-          erem[j] = (tg - s0) * cp;
+          icap[j] = frcp(cp);
+          q[j] = 1.0 - (double)s0;
+          u[j] = 1.0f - tg;
           plast[j] = 0.f;
         }
         run += cnt[j];
@@ -359,7 +376,7 @@ __device__ void run_group(const SegDev &sg, const Dyn &dy, int group) {
       t_day = 0;
 #pragma unroll
       for (int j = 0; j < P; ++j) {
-        dw[j] = 0; soc[j] = 0.f; erem[j] = 0.f; cap[j] = 0.f; plast[j] = 0.f;
+        dw[j] = 0; q[j] = 0.0; u[j] = 0.f; cap[j] = 0.f; icap[j] = 0.f; plast[j] = 0.f;
       }
     }
 
@@ -373,10 +390,10 @@ __device__ void run_group(const SegDev &sg, const Dyn &dy, int group) {
             const bool occ = dw[j] > 0;
             const int p = port[j];
             o[0 * N + p] = occ ? 1.0f : 0.0f;
-            o[1 * N + p] = soc[j];
-            o[2 * N + p] = occ ? erem[j] * frcp(cap[j]) : 0.0f;
+            o[1 * N + p] = occ ? (float)(1.0 - q[j]) : 0.0f;
+            o[2 * N + p] = occ ? (float)(q[j] - (double)u[j]) : 0.0f;
             o[3 * N + p] = (float)dw[j] * C.inv_steps_ep;
-            o[4 * N + p] = occ ? fminf(1.0f, (1.0f - soc[j]) * C.inv_1mtau) : 0.0f;
+            o[4 * N + p] = occ ? fminf(1.0f, (float)q[j] * C.inv_1mtau) : 0.0f;
             o[5 * N + p] = plast[j] * inv_pmax[j];
           }
         }
@@ -404,8 +421,8 @@ __device__ void run_group(const SegDev &sg, const Dyn &dy, int group) {
 #pragma unroll
     for (int j = 0; j < P; ++j) {
       const int64_t i = sofs + j * L + l;
-      sg.soc[i] = soc[j];
-      sg.e_rem[i] = erem[j];
+      sg.q[i] = q[j];
+      sg.u[i] = u[j];
       sg.cap[i] = cap[j];
       sg.p_last[i] = plast[j];
       sg.dwell[i] = (int16_t)dw[j];
@@ -414,7 +431,11 @@ __device__ void run_group(const SegDev &sg, const Dyn &dy, int group) {
   }
 }
 
+// One kernel per slots-per-lane count P, so that each keeps its own register
+// budget; the lanes-per-station L is dispatched inside (uniform per block).
+template <int P>
 __global__ __launch_bounds__(512) void k_rollout(LaunchArgs a) {
+  extern __shared__ uint32_t lds_tdwell[];
   const int b = blockIdx.x;
   int lo = 0, hi = a.n_segs - 1;
   while (lo < hi) {
@@ -423,9 +444,6 @@ __global__ __launch_bounds__(512) void k_rollout(LaunchArgs a) {
     else hi = mid - 1;
   }
   const SegDev &sg = a.segs[lo];
-  const int W = blockDim.x >> 6;
-  const int group = __builtin_amdgcn_readfirstlane((b - sg.block_begin) * W + (int)(threadIdx.x >> 6));
-  if (group >= sg.n_groups) return;
   Dyn dy;
   if (a.per_segment) {
     dy = Dyn{sg.T, sg.t_day0, sg.g0, sg.mode, sg.out_mode, sg.obs, sg.act, sg.reward, sg.done, sg.act_in,
@@ -434,22 +452,24 @@ __global__ __launch_bounds__(512) void k_rollout(LaunchArgs a) {
     dy = Dyn{a.T, a.t_day0, a.g0, a.mode, a.out_mode, a.obs, a.act, a.reward, a.done, a.act_in,
              a.obs_stride, a.act_stride, a.env_stride};
   }
-  switch (sg.pack) {
-    case 0: run_group<4, 1>(sg, dy, group); break;
-    case 1: run_group<8, 1>(sg, dy, group); break;
-    case 2: run_group<16, 1>(sg, dy, group); break;
-    case 3: run_group<32, 1>(sg, dy, group); break;
-    case 4: run_group<64, 1>(sg, dy, group); break;
-    case 5: run_group<4, 2>(sg, dy, group); break;
-    case 6: run_group<8, 2>(sg, dy, group); break;
-    case 7: run_group<16, 2>(sg, dy, group); break;
-    case 8: run_group<32, 2>(sg, dy, group); break;
-    case 9: run_group<64, 2>(sg, dy, group); break;
-    case 10: run_group<4, 4>(sg, dy, group); break;
-    case 11: run_group<8, 4>(sg, dy, group); break;
-    case 12: run_group<16, 4>(sg, dy, group); break;
-    case 13: run_group<32, 4>(sg, dy, group); break;
-    case 14: run_group<64, 4>(sg, dy, group); break;
+  // stay-length thresholds in LDS for multi-step launches (every wave of the
+  // block helps load them before any wave may leave)
+  const uint32_t *tdw = sg.cls->tdwell;
+  if (a.lds_tdwell) {
+    const int n = 1 << sg.cls->dwell_log2;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) lds_tdwell[i] = tdw[i];
+    __syncthreads();
+    tdw = lds_tdwell;
+  }
+  const int W = blockDim.x >> 6;
+  const int group = __builtin_amdgcn_readfirstlane((b - sg.block_begin) * W + (int)(threadIdx.x >> 6));
+  if (group >= sg.n_groups) return;
+  switch (pack_lanes(sg.pack)) {
+    case 4: run_group<4, P>(sg, dy, group, tdw); break;
+    case 8: run_group<8, P>(sg, dy, group, tdw); break;
+    case 16: run_group<16, P>(sg, dy, group, tdw); break;
+    case 32: run_group<32, P>(sg, dy, group, tdw); break;
+    case 64: run_group<64, P>(sg, dy, group, tdw); break;
     default: break;
   }
 }
@@ -468,38 +488,89 @@ __global__ void k_reset_obs(const ClassDev *cls, int64_t n_envs, float *obs) {
   }
 }
 
-}  // namespace
-
-hipError_t launch_rollout(const LaunchArgs &a, int n_blocks, int waves_per_block, hipStream_t st) {
-  if (n_blocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_rollout, dim3(n_blocks), dim3(64 * waves_per_block), 0, st, a);
-  return hipGetLastError();
+void *kernel_for(int per_lane) {
+  switch (per_lane) {
+    case 1: return reinterpret_cast<void *>(&k_rollout<1>);
+    case 2: return reinterpret_cast<void *>(&k_rollout<2>);
+    default: return reinterpret_cast<void *>(&k_rollout<4>);
+  }
 }
 
-hipError_t graph_rollout(RolloutGraph &g, const LaunchArgs &a, int n_blocks, int waves_per_block,
+// Arguments of one group's launch: its slice of the segment table and its LDS.
+LaunchArgs group_args(const LaunchArgs &a, const LaunchGroup &g, size_t *lds) {
+  LaunchArgs b = a;
+  b.segs = a.segs + g.seg_begin;
+  b.n_segs = g.n_segs;
+  const int T = a.per_segment ? g.max_T : a.T;
+  b.lds_tdwell = T >= 8 ? 1 : 0;
+  *lds = b.lds_tdwell ? ((size_t)4 << g.max_dwell_log2) : 0;
+  return b;
+}
+
+}  // namespace
+
+hipError_t launch_groups(const LaunchArgs &a, const LaunchGroup *groups, int n_groups, int waves_per_block,
                          hipStream_t st) {
-  if (n_blocks <= 0) return hipSuccess;
-  LaunchArgs args = a;
-  void *params[1] = {&args};
-  hipKernelNodeParams p{};
-  p.func = reinterpret_cast<void *>(&k_rollout);
-  p.gridDim = dim3(n_blocks);
-  p.blockDim = dim3(64 * waves_per_block);
-  p.sharedMemBytes = 0;
-  p.kernelParams = params;
-  p.extra = nullptr;
-  hipError_t e;
-  if (!g.exec || g.blocks != n_blocks || g.waves != waves_per_block) {
-    graph_destroy(g);
-    if ((e = hipGraphCreate(&g.graph, 0)) != hipSuccess) return e;
-    if ((e = hipGraphAddKernelNode(&g.node, g.graph, nullptr, 0, &p)) != hipSuccess) return e;
-    if ((e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0)) != hipSuccess) return e;
-    g.blocks = n_blocks;
-    g.waves = waves_per_block;
-  } else if ((e = hipGraphExecKernelNodeSetParams(g.exec, g.node, &p)) != hipSuccess) {
-    return e;
+  for (int i = 0; i < n_groups; ++i) {
+    const LaunchGroup &g = groups[i];
+    if (g.n_blocks <= 0) continue;
+    size_t lds = 0;
+    const LaunchArgs b = group_args(a, g, &lds);
+    const dim3 grid(g.n_blocks), block(64 * waves_per_block);
+    if (g.per_lane == 1) hipLaunchKernelGGL(k_rollout<1>, grid, block, lds, st, b);
+    else if (g.per_lane == 2) hipLaunchKernelGGL(k_rollout<2>, grid, block, lds, st, b);
+    else hipLaunchKernelGGL(k_rollout<4>, grid, block, lds, st, b);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
   }
-  return hipGraphLaunch(g.exec, st);
+  return hipSuccess;
+}
+
+hipError_t graph_rollout(RolloutGraph &G, const LaunchArgs &a, const LaunchGroup *groups, int n_groups,
+                         int waves_per_block, hipStream_t st) {
+  LaunchArgs args[3];
+  void *params[3][1];
+  hipKernelNodeParams p[3];
+  int n = 0;
+  int shape[3][3] = {};
+  for (int i = 0; i < n_groups && n < 3; ++i) {
+    const LaunchGroup &g = groups[i];
+    if (g.n_blocks <= 0) continue;
+    size_t lds = 0;
+    args[n] = group_args(a, g, &lds);
+    params[n][0] = &args[n];
+    p[n] = hipKernelNodeParams{};
+    p[n].func = kernel_for(g.per_lane);
+    p[n].gridDim = dim3(g.n_blocks);
+    p[n].blockDim = dim3(64 * waves_per_block);
+    p[n].sharedMemBytes = (unsigned)lds;
+    p[n].kernelParams = params[n];
+    p[n].extra = nullptr;
+    shape[n][0] = g.per_lane;
+    shape[n][1] = g.n_blocks;
+    shape[n][2] = (int)lds;
+    ++n;
+  }
+  if (n == 0) return hipSuccess;
+  bool same = G.exec && G.n_nodes == n && G.waves == waves_per_block;
+  for (int i = 0; same && i < n; ++i)
+    for (int j = 0; j < 3; ++j) same = same && G.shape[i][j] == shape[i][j];
+  hipError_t e;
+  if (!same) {
+    graph_destroy(G);
+    if ((e = hipGraphCreate(&G.graph, 0)) != hipSuccess) return e;
+    for (int i = 0; i < n; ++i)
+      if ((e = hipGraphAddKernelNode(&G.node[i], G.graph, nullptr, 0, &p[i])) != hipSuccess) return e;
+    if ((e = hipGraphInstantiate(&G.exec, G.graph, nullptr, nullptr, 0)) != hipSuccess) return e;
+    G.n_nodes = n;
+    G.waves = waves_per_block;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < 3; ++j) G.shape[i][j] = shape[i][j];
+  } else {
+    for (int i = 0; i < n; ++i)
+      if ((e = hipGraphExecKernelNodeSetParams(G.exec, G.node[i], &p[i])) != hipSuccess) return e;
+  }
+  return hipGraphLaunch(G.exec, st);
 }
 
 void graph_destroy(RolloutGraph &g) {

@@ -10,7 +10,7 @@ namespace cx {
 
 static const uint64_t kMagic = 0x31305843ull;  // "CX01"
 static const size_t kHeader = 8 + 8 + 8 + 4 + 4;
-static const size_t kPortRec = 4 * 5;
+static const size_t kPortRec = 4 + 8 + 4 + 4 + 4;
 
 size_t state_blob_bytes(const cx_ctx *ctx) {
   return kHeader + kPortRec * (size_t)ctx->total_ports + 8 * (size_t)ctx->n_envs;
@@ -29,11 +29,12 @@ cx_status cx_get_state(cx_ctx *ctx, void *host, size_t bytes) {
   hipError_t e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "cx_get_state synchronize");
   const size_t ns = (size_t)ctx->total_slots;
-  std::vector<float> soc(ns), erem(ns), cap(ns), pl(ns);
+  std::vector<double> qv(ns);
+  std::vector<float> uv(ns), cap(ns), pl(ns);
   std::vector<int16_t> dw(ns);
   std::vector<double> ret((size_t)ctx->n_envs);
-  if ((e = hipMemcpy(soc.data(), ctx->soc, 4 * ns, hipMemcpyDeviceToHost)) != hipSuccess ||
-      (e = hipMemcpy(erem.data(), ctx->e_rem, 4 * ns, hipMemcpyDeviceToHost)) != hipSuccess ||
+  if ((e = hipMemcpy(qv.data(), ctx->q, 8 * ns, hipMemcpyDeviceToHost)) != hipSuccess ||
+      (e = hipMemcpy(uv.data(), ctx->u, 4 * ns, hipMemcpyDeviceToHost)) != hipSuccess ||
       (e = hipMemcpy(cap.data(), ctx->cap, 4 * ns, hipMemcpyDeviceToHost)) != hipSuccess ||
       (e = hipMemcpy(pl.data(), ctx->p_last, 4 * ns, hipMemcpyDeviceToHost)) != hipSuccess ||
       (e = hipMemcpy(dw.data(), ctx->dwell, 2 * ns, hipMemcpyDeviceToHost)) != hipSuccess ||
@@ -53,10 +54,10 @@ cx_status cx_get_state(cx_ctx *ctx, void *host, size_t bytes) {
         const size_t x = (size_t)(c.slot_off + e2 * c.comp.S + c.comp.port_slot[i]);
         const int32_t d = dw[x];
         std::memcpy(q, &d, 4);
-        std::memcpy(q + 4, &soc[x], 4);
-        std::memcpy(q + 8, &erem[x], 4);
-        std::memcpy(q + 12, &cap[x], 4);
-        std::memcpy(q + 16, &pl[x], 4);
+        std::memcpy(q + 4, &qv[x], 8);
+        std::memcpy(q + 12, &uv[x], 4);
+        std::memcpy(q + 16, &cap[x], 4);
+        std::memcpy(q + 20, &pl[x], 4);
         q += kPortRec;
       }
     }
@@ -83,7 +84,8 @@ cx_status cx_set_state(cx_ctx *ctx, const void *host, size_t bytes) {
     return fail_status(CX_E_INVALID, "snapshot does not match this context");
   if (t_day < 0 || t_day >= ctx->steps_ep) return fail_status(CX_E_INVALID, "snapshot t_day out of range");
   const size_t ns = (size_t)ctx->total_slots;
-  std::vector<float> soc(ns, 0.f), erem(ns, 0.f), cap(ns, 0.f), pl(ns, 0.f);
+  std::vector<double> qv(ns, 0.0);
+  std::vector<float> uv(ns, 0.f), cap(ns, 0.f), pl(ns, 0.f);
   std::vector<int16_t> dw(ns, 0);
   std::vector<double> ret((size_t)ctx->n_envs);
   const unsigned char *q = p + kHeader;
@@ -95,10 +97,10 @@ cx_status cx_set_state(cx_ctx *ctx, const void *host, size_t bytes) {
         std::memcpy(&d, q, 4);
         if (d < 0 || d > 32767) return fail_status(CX_E_INVALID, "snapshot dwell out of range");
         dw[x] = (int16_t)d;
-        std::memcpy(&soc[x], q + 4, 4);
-        std::memcpy(&erem[x], q + 8, 4);
-        std::memcpy(&cap[x], q + 12, 4);
-        std::memcpy(&pl[x], q + 16, 4);
+        std::memcpy(&qv[x], q + 4, 8);
+        std::memcpy(&uv[x], q + 12, 4);
+        std::memcpy(&cap[x], q + 16, 4);
+        std::memcpy(&pl[x], q + 20, 4);
         q += kPortRec;
       }
     }
@@ -106,8 +108,8 @@ cx_status cx_set_state(cx_ctx *ctx, const void *host, size_t bytes) {
   std::memcpy(ret.data(), q, 8 * ret.size());
   hipError_t e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "cx_set_state synchronize");
-  if ((e = hipMemcpy(ctx->soc, soc.data(), 4 * ns, hipMemcpyHostToDevice)) != hipSuccess ||
-      (e = hipMemcpy(ctx->e_rem, erem.data(), 4 * ns, hipMemcpyHostToDevice)) != hipSuccess ||
+  if ((e = hipMemcpy(ctx->q, qv.data(), 8 * ns, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(ctx->u, uv.data(), 4 * ns, hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(ctx->cap, cap.data(), 4 * ns, hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(ctx->p_last, pl.data(), 4 * ns, hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(ctx->dwell, dw.data(), 2 * ns, hipMemcpyHostToDevice)) != hipSuccess ||

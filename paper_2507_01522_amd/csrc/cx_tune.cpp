@@ -82,6 +82,8 @@ extern "C" cx_status cx_autotune(cx_ctx *ctx, int32_t T_probe, const char *cache
   hipError_t e;
   void *saved = nullptr, *scratch = nullptr;
   SegDev *seg1 = nullptr;
+  std::vector<SegDev> one_segs;
+  std::vector<LaunchGroup> one_groups;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   const size_t obs_b = sizeof(float) * (size_t)T_probe * ctx->obs_elems;
   const size_t act_b = (size_t)T_probe * ctx->total_ports;
@@ -123,16 +125,16 @@ extern "C" cx_status cx_autotune(cx_ctx *ctx, int32_t T_probe, const char *cache
   a.act = sb + obs_b;
   a.reward = reinterpret_cast<float *>(sb + ((obs_b + act_b + 255) & ~(size_t)255));
   a.done = sb + ((obs_b + act_b + 255) & ~(size_t)255) + sizeof(float) * env_b;
-  // time one launch of the given segments (min over 3 after a warm-up)
-  auto time_launch = [&](const SegDev *segs, int n_segs, int blocks, int wpb, float *best_ms) -> hipError_t {
+  // time one launch of the given segment table (min over 3 after a warm-up)
+  auto time_launch = [&](const SegDev *segs, const std::vector<LaunchGroup> &groups, int wpb,
+                         float *best_ms) -> hipError_t {
     LaunchArgs b = a;
     b.segs = segs;
-    b.n_segs = n_segs;
     float best = 1e30f;
     for (int rep = 0; rep < 4; ++rep) {
       hipError_t r;
       if ((r = hipEventRecord(ev0, ctx->stream)) != hipSuccess) return r;
-      if ((r = launch_rollout(b, blocks, wpb, ctx->stream)) != hipSuccess) return r;
+      if ((r = launch_groups(b, groups.data(), (int)groups.size(), wpb, ctx->stream)) != hipSuccess) return r;
       if ((r = hipEventRecord(ev1, ctx->stream)) != hipSuccess) return r;
       if ((r = hipEventSynchronize(ev1)) != hipSuccess) return r;
       float ms = 0.f;
@@ -160,14 +162,13 @@ extern "C" cx_status cx_autotune(cx_ctx *ctx, int32_t T_probe, const char *cache
       SegDev one{};
       for (const SegDev &sg : ctx->segs_host)
         if (sg.cls == c.dev) one = sg;
-      one.block_begin = 0;
-      if ((e = hipMemcpy(seg1, &one, sizeof one, hipMemcpyHostToDevice)) != hipSuccess) {
+      build_groups({one}, {c.tab.dwell_log2}, ctx->wpb, &one_segs, &one_groups);
+      if ((e = hipMemcpy(seg1, one_segs.data(), sizeof(SegDev), hipMemcpyHostToDevice)) != hipSuccess) {
         st = hip_fail(ctx, e, "cx_autotune segment upload");
         break;
       }
       float ms = 0.f;
-      const int blocks = (one.n_groups + ctx->wpb - 1) / ctx->wpb;
-      if ((e = time_launch(seg1, 1, blocks, ctx->wpb, &ms)) != hipSuccess) {
+      if ((e = time_launch(seg1, one_groups, ctx->wpb, &ms)) != hipSuccess) {
         st = hip_fail(ctx, e, "cx_autotune timing");
         break;
       }
@@ -191,7 +192,7 @@ extern "C" cx_status cx_autotune(cx_ctx *ctx, int32_t T_probe, const char *cache
         ctx->wpb = w;
         if ((st = rebuild_segments(ctx)) != CX_OK) break;
         float ms = 0.f;
-        if ((e = time_launch(ctx->segs_dev, (int)ctx->segs_host.size(), ctx->n_blocks, w, &ms)) != hipSuccess) {
+        if ((e = time_launch(ctx->segs_dev, ctx->groups, w, &ms)) != hipSuccess) {
           st = hip_fail(ctx, e, "cx_autotune timing");
           break;
         }

@@ -301,11 +301,14 @@ class Env:
         head = np.frombuffer(blob, dtype=np.uint8, count=32)
         g = int(head[24:28].view(np.uint32)[0])
         t_day = int(head[28:32].view(np.int32)[0])
-        rec = np.frombuffer(blob, dtype=np.dtype([("dwell", "<i4"), ("soc", "<f4"), ("e_rem", "<f4"),
+        rec = np.frombuffer(blob, dtype=np.dtype([("dwell", "<i4"), ("q", "<f8"), ("u", "<f4"),
                                                   ("cap", "<f4"), ("p_last", "<f4")]),
                             count=i.total_ports, offset=32)
-        ret = np.frombuffer(blob, dtype="<f8", count=i.n_envs, offset=32 + 20 * i.total_ports)
+        ret = np.frombuffer(blob, dtype="<f8", count=i.n_envs, offset=32 + 24 * i.total_ports)
         out = {k: np.array(rec[k]) for k in rec.dtype.names}
+        occ = out["dwell"] > 0
+        out["soc"] = np.where(occ, 1.0 - out["q"], 0.0)
+        out["e_rem"] = np.where(occ, (out["q"] - out["u"].astype(np.float64)) * out["cap"], 0.0)
         out["ret"] = np.array(ret)
         out["g"] = g
         out["t_day"] = t_day
