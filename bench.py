@@ -76,6 +76,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain per-step comparison")
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="first run a plain 2 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the rollout has no cross-GPU work; run with --gpus 1",
@@ -84,6 +86,15 @@ def main():
 
     import torch
     import paper_2507_01522_amd as cx
+
+    if args.calib_copy:
+        src = torch.empty(1 << 29, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        src.fill_(1.0)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     seed = 3
     specs, ec = workload()

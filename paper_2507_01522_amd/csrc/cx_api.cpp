@@ -61,6 +61,17 @@ static cx_status upload_class(cx_ctx *ctx, ClassRt &c) {
   d.tgt_lo = (float)s.tgt_lo; d.tgt_span = (float)(s.tgt_hi - s.tgt_lo);
   d.inv_steps_ep = (float)(1.0 / s.steps_per_episode); d.inv_n_levels = (float)(1.0 / s.n_levels);
   d.inv_eta_uniform = k.inv_eta_uniform;
+  d.dense = k.S == k.N ? 1 : 0;
+  d.lvl_lb_uniform = 0;
+  for (int lvl = 0; lvl < kMaxLevels; ++lvl) {
+    uint32_t v = 0xFF;
+    if (lvl < k.D) {
+      v = (k.slot_lb[0] >> (8 * lvl)) & 0xFF;
+      for (int x = 1; x < k.S; ++x)
+        if (((k.slot_lb[x] >> (8 * lvl)) & 0xFF) != v) v = 0xFF;
+    }
+    d.lvl_lb_uniform |= v << (8 * lvl);
+  }
   d.slot_port = reinterpret_cast<const int32_t *>(base + o_port);
   d.slot_pmax = reinterpret_cast<const float *>(base + o_pmax);
   d.slot_inv_pmax = reinterpret_cast<const float *>(base + o_ipmax);
@@ -96,24 +107,25 @@ bool legal_packing(int S, int lanes) {
 
 int default_lanes(int S) { return S <= 64 ? S : 64; }
 
-// Group segments by slots per lane (one kernel each); inside a group the
-// heaviest classes (most slots) come first so they start first.
+// Group segments by packing (one kernel each); groups with more slots per
+// station come first so the heaviest waves start first.
 void build_groups(const std::vector<SegDev> &in, const std::vector<int> &log2_dwell, int wpb,
                   std::vector<SegDev> *out, std::vector<LaunchGroup> *groups) {
   out->clear();
   groups->clear();
-  for (int P : {4, 2, 1}) {
+  std::vector<int> packs;
+  for (const SegDev &sg : in)
+    if (std::find(packs.begin(), packs.end(), sg.pack) == packs.end()) packs.push_back(sg.pack);
+  std::stable_sort(packs.begin(), packs.end(), [](int a, int b) {
+    return pack_lanes(a) * pack_per_lane(a) > pack_lanes(b) * pack_per_lane(b);
+  });
+  for (int pk : packs) {
     LaunchGroup g;
-    g.per_lane = P;
+    g.pack = pk;
     g.seg_begin = (int)out->size();
     int blocks = 0;
-    std::vector<int> idx;
-    for (size_t i = 0; i < in.size(); ++i)
-      if (pack_per_lane(in[i].pack) == P) idx.push_back((int)i);
-    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
-      return pack_lanes(in[a].pack) * P > pack_lanes(in[b].pack) * P;
-    });
-    for (int i : idx) {
+    for (size_t i = 0; i < in.size(); ++i) {
+      if (in[i].pack != pk) continue;
       SegDev sg = in[i];
       sg.block_begin = blocks;
       blocks += (sg.n_groups + wpb - 1) / wpb;
@@ -123,7 +135,7 @@ void build_groups(const std::vector<SegDev> &in, const std::vector<int> &log2_dw
     }
     g.n_segs = (int)out->size() - g.seg_begin;
     g.n_blocks = blocks;
-    if (g.n_segs > 0) groups->push_back(g);
+    groups->push_back(g);
   }
 }
 

@@ -41,7 +41,10 @@ struct ClassDev {
   float p_sell_grid, fixed_cost, alpha_sat, alpha_dec;
   float price_sigma, cap_lo, cap_span, soc_lo;
   float soc_span, tgt_lo, tgt_span, inv_steps_ep;
-  float inv_n_levels, inv_eta_uniform, pad0, pad1;
+  float inv_n_levels, inv_eta_uniform;
+  uint32_t lvl_lb_uniform;     // per level (8 bits, level 0 = deepest): the block size log2
+                               // shared by every slot of the level, 0xFF if they differ
+  int32_t dense;               // 1: no padding slots (slot s holds port s)
   const int32_t *slot_port;    // [S]
   const float *slot_pmax;      // [S]
   const float *slot_inv_pmax;  // [S]
@@ -104,10 +107,10 @@ struct LaunchArgs {
   int64_t obs_stride, act_stride, env_stride;
 };
 
-// One launch group: the segments whose packing has P slots per lane, launched
-// by the kernel instantiated for that P.
+// One launch group: the segments of one packing, launched by the kernel
+// instantiated for that packing.
 struct LaunchGroup {
-  int per_lane = 1;     // P
+  int pack = 0;         // packing id
   int seg_begin = 0;    // index of the first segment in the device segment table
   int n_segs = 0;
   int n_blocks = 0;
@@ -121,9 +124,9 @@ struct LaunchGroup {
 struct RolloutGraph {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  hipGraphNode_t node[3] = {nullptr, nullptr, nullptr};
+  hipGraphNode_t node[kNumPackings] = {};
   int n_nodes = 0;
-  int shape[3][3] = {};
+  int shape[kNumPackings][3] = {};
   int waves = -1;
 };
 

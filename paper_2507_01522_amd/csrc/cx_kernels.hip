@@ -25,6 +25,7 @@ namespace {
 struct U4 {
   uint32_t x, y, z, w;
 };
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 // Philox4x32-10 (Salmon et al., SC'11).  The key is wave-uniform, so its
 // schedule stays in scalar registers.
@@ -32,14 +33,13 @@ __device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint
                                      uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
-    const uint32_t hi0 = __umulhi(0xD2511F53u, c0);
-    const uint32_t lo0 = 0xD2511F53u * c0;
-    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
-    const uint32_t lo1 = 0xCD9E8D57u * c2;
-    c0 = hi1 ^ c1 ^ k0;
-    c1 = lo1;
-    c2 = hi0 ^ c3 ^ k1;
-    c3 = lo0;
+    // one 32x32->64 multiply per product gives both halves (v_mad_u64_u32)
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+    c0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    c1 = (uint32_t)p1;
+    c2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    c3 = (uint32_t)p0;
     k0 += 0x9E3779B9u;
     k1 += 0xBB67AE85u;
   }
@@ -48,22 +48,39 @@ __device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint
 
 __device__ __forceinline__ float u24(uint32_t w) { return (float)(w >> 8) * 0x1p-24f; }
 
-// Number of entries of a non-decreasing table (size 2^log2n, last entry
-// 0xFFFFFFFF) that are strictly below w.
-__device__ __forceinline__ int count_below(const uint32_t *tab, int log2n, uint32_t w) {
-  int pos = 0;
-  for (int s = 1 << (log2n - 1); s >= 1; s >>= 1)
-    if (tab[pos + s - 1] < w) pos += s;
-  return pos;
+// Loads through the global address space (the tables live in device memory;
+// plain pointers from a struct would be generic and compile to flat loads).
+template <class T>
+__device__ __forceinline__ T gld(const T *p, int64_t i) {
+  return ((const __attribute__((address_space(1))) T *)p)[i];
 }
 
 // Arrivals of one step: thresholds exceeded by w in a 32-entry row.  The
 // first four entries come in one 16-byte load; the full bisection runs only
 // when w exceeds all four (rare for the rates used here).
 __device__ __forceinline__ int arrivals(const uint32_t *row, uint32_t w) {
-  const uint4 t = *reinterpret_cast<const uint4 *>(row);
+  const u32x4 t = gld(reinterpret_cast<const u32x4 *>(row), 0);
   const int m = (int)(w > t.x) + (int)(w > t.y) + (int)(w > t.z) + (int)(w > t.w);
-  return m < 4 ? m : count_below(row, 5, w);
+  if (m < 4) return m;
+  int pos = 0;
+  for (int s = 16; s >= 1; s >>= 1)
+    if (gld(row, pos + s - 1) < w) pos += s;
+  return pos;
+}
+
+// Stay length of an arriving car: 1 + #{thresholds below w}, bisecting the
+// table in LDS (multi-step launches) or in device memory.
+__device__ __forceinline__ int stay_len(const uint32_t *tab, bool in_lds, int log2n, uint32_t w) {
+  int pos = 0;
+  if (in_lds) {
+    const __attribute__((address_space(3))) uint32_t *t = (const __attribute__((address_space(3))) uint32_t *)tab;
+    for (int s = 1 << (log2n - 1); s >= 1; s >>= 1)
+      if (t[pos + s - 1] < w) pos += s;
+  } else {
+    for (int s = 1 << (log2n - 1); s >= 1; s >>= 1)
+      if (gld(tab, pos + s - 1) < w) pos += s;
+  }
+  return 1 + pos;
 }
 
 // Exchange with the lane whose index differs in bit K (K = 0..5), for use in
@@ -103,6 +120,18 @@ __device__ __forceinline__ float masked_step(float v, int lb) {
   return v + xlane<K>(u);
 }
 
+// Unmasked butterfly over aligned groups of 2^lb lanes (lb wave-uniform).
+template <int L>
+__device__ __forceinline__ float group_sum_lanes(float v, int lb) {
+  if constexpr (L > 1) if (0 < lb) v += xlane<0>(v);
+  if constexpr (L > 2) if (1 < lb) v += xlane<1>(v);
+  if constexpr (L > 4) if (2 < lb) v += xlane<2>(v);
+  if constexpr (L > 8) if (3 < lb) v += xlane<3>(v);
+  if constexpr (L > 16) if (4 < lb) v += xlane<4>(v);
+  if constexpr (L > 32) if (5 < lb) v += xlane<5>(v);
+  return v;
+}
+
 template <int L>
 __device__ __forceinline__ float block_sum_lanes(float v, int lb) {
   if constexpr (L > 1) v = masked_step<0>(v, lb);
@@ -139,19 +168,34 @@ struct Dyn {
   int64_t obs_stride, act_stride, env_stride;
 };
 
-template <int L, int P>
-__device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int group, const uint32_t *tdw) {
+// Store / load at a wave-uniform base plus a per-lane 32-bit byte offset
+// (the global "saddr" form: no 64-bit address per lane).
+template <class T>
+__device__ __forceinline__ void st_at(T *base, uint32_t byte_off, T v) {
+  *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + byte_off) = v;
+}
+template <class T>
+__device__ __forceinline__ T ld_at(const T *base, uint32_t byte_off) {
+  return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + byte_off);
+}
+
+// DENSE: the class has no padding slots (slot s holds port s, N = L * P), so
+// port indices and record offsets are compile-time constants.
+template <int L, int P, bool DENSE>
+__device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int group, const uint32_t *tdw,
+                                          bool tdw_lds) {
   constexpr int SPW = 64 / L;
   constexpr int LOGL = (L == 4) ? 2 : (L == 8) ? 3 : (L == 16) ? 4 : (L == 32) ? 5 : 6;
-  const ClassDev &C = *sg.cls;
+  const ClassDev C = *sg.cls;  // by value: scalar loads once, kept in SGPRs
   const int lane = __lane_id();
   const int l = lane & (L - 1);
   const int sbase = lane & ~(L - 1);
-  const int64_t env = (int64_t)group * SPW + (lane >> LOGL);
+  const int env = group * SPW + (lane >> LOGL);     // env index inside the segment
   const bool active = env < sg.n_envs;
-  const int S = C.S;
+  const int S = DENSE ? L * P : C.S;
   const int D = C.D;
-  const int N = C.n_ports;
+  const int N = DENSE ? L * P : C.n_ports;
+  const int obs_dim = 6 * N + 4;
 
   // ---- per-slot constants
   int port[P];
@@ -160,7 +204,7 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
 #pragma unroll
   for (int j = 0; j < P; ++j) {
     const int s = j * L + l;
-    port[j] = C.slot_port[s];
+    port[j] = DENSE ? s : C.slot_port[s];
     pmax[j] = C.slot_pmax[s];
     inv_pmax[j] = C.slot_inv_pmax[s];
     inv_eta[j] = C.slot_inv_eta[s];
@@ -173,7 +217,7 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
   double q[P];
   float u[P], cap[P], icap[P], plast[P];
   int dw[P];
-  const int64_t sofs = env * S;
+  const int64_t sofs = (int64_t)env * S;
 #pragma unroll
   for (int j = 0; j < P; ++j) {
     const int64_t i = sofs + j * L + l;
@@ -192,30 +236,37 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
   const int n_levels = C.n_levels;
   int t_day = dy.t_day0;
   uint32_t g = dy.g0;
-  int bM = 0;
-  float bpb = 0.f;
+  int bM = 0, bdw = 1;
+  float bpb = 0.f, bcp = 0.f, bs0 = 0.f, btg = 0.f;
   U4 aw[P];
 #pragma unroll
   for (int j = 0; j < P; ++j) aw[j] = U4{0, 0, 0, 0};
-  const uint64_t smask = (L == 64) ? ~0ull : (((1ull << L) - 1ull) << sbase);
+  const uint64_t smask = (L == 64) ? ~0ull : (((1ull << (L & 63)) - 1ull) << sbase);
   const uint64_t below_mask = (1ull << lane) - 1ull;
 
-  float *obs_e = dy.obs ? dy.obs + sg.obs_off + env * C.obs_dim : nullptr;
-  uint8_t *act_e = dy.act ? dy.act + sg.act_off + env * N : nullptr;
-  const uint8_t *ain_e = dy.act_in ? dy.act_in + sg.act_off + env * N : nullptr;
-  const int64_t renv = sg.env_off + env;
+  // per-lane byte offsets of this env's records inside a step's segment block
+  const uint32_t obs_bo = (uint32_t)env * (uint32_t)obs_dim * 4u;
+  const uint32_t act_bo = (uint32_t)env * (uint32_t)N;
+  const uint32_t env_bo = (uint32_t)env;
 
   for (int t = 0; t < dy.T; ++t, ++g) {
-    // ---- exogenous draws for the next L steps, lane l -> step t + l
+    // ---- exogenous draws for the next L steps, lane l -> step t + l: the
+    // arrival count, the price noise and the first arriving car's profile
     if ((t & (L - 1)) == 0) {
       int td = t_day + l;
       while (td >= steps_ep) td -= steps_ep;
-      const U4 w = philox(env_id, g + (uint32_t)l, 0u, kDomEnv, k0, k1);
+      const uint32_t gl = g + (uint32_t)l;
+      const U4 w = philox(env_id, gl, 0u, kDomEnv, k0, k1);
       bM = active ? arrivals(C.tpois + td * kPoisStride, w.x) : 0;
       const float u1 = (float)((w.y >> 8) + 1u) * 0x1p-24f;
       const float u2 = u24(w.z);
       const float z = __builtin_amdgcn_sqrtf(-2.0f * __logf(u1)) * __builtin_amdgcn_cosf(u2);
-      bpb = C.glob[td * 4 + 2] + C.price_sigma * z;
+      bpb = gld(C.glob, td * 4 + 2) + C.price_sigma * z;
+      const U4 b = philox(env_id, gl, 0u, kDomCar, k0, k1);
+      bcp = C.cap_lo + C.cap_span * u24(b.x);
+      bs0 = C.soc_lo + C.soc_span * u24(b.y);
+      btg = C.tgt_lo + C.tgt_span * u24(b.z);
+      bdw = stay_len(tdw, tdw_lds, C.dwell_log2, b.w);
     }
     const int tb = t & (L - 1);
     const int M = bcast<L>(bM, tb);
@@ -241,7 +292,8 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
 #pragma unroll
       for (int j = 0; j < P; ++j) {
         int v = 0;
-        if (active && port[j] >= 0) v = ain_e[(int64_t)t * dy.act_stride + port[j]];
+        if (active && port[j] >= 0)
+          v = ld_at(dy.act_in + sg.act_off + (int64_t)t * dy.act_stride, act_bo + (uint32_t)port[j]);
         k[j] = v > n_levels ? n_levels : v;
       }
     }
@@ -262,8 +314,14 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
     for (int d = 0; d < kMaxLevels; ++d) {
       if (d < D) {
         float s[P];
+        const int lbu = (int)((C.lvl_lb_uniform >> (8 * d)) & 0xFF);
+        if (lbu != 0xFF) {  // every slot of the level sits in a block of 2^lbu slots
 #pragma unroll
-        for (int j = 0; j < P; ++j) s[j] = block_sum_lanes<L>(pw[j], (int)((lbp[j] >> (8 * d)) & 0xFF));
+          for (int j = 0; j < P; ++j) s[j] = group_sum_lanes<L>(pw[j], lbu);
+        } else {
+#pragma unroll
+          for (int j = 0; j < P; ++j) s[j] = block_sum_lanes<L>(pw[j], (int)((lbp[j] >> (8 * d)) & 0xFF));
+        }
         // blocks wider than a row of L slots span whole registers: add across them
         if constexpr (P >= 2) {
           const int lb0 = (int)((lbp[0] >> (8 * d)) & 0xFF);
@@ -334,7 +392,7 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
     int n_free = 0;
 #pragma unroll
     for (int j = 0; j < P; ++j) {
-      fr[j] = dw[j] == 0 && port[j] >= 0;
+      fr[j] = dw[j] == 0 && (DENSE || port[j] >= 0);
       const uint64_t m = __ballot(fr[j]) & smask;
       cnt[j] = __popcll(m);
       below[j] = __popcll(m & below_mask);
@@ -342,17 +400,25 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
     }
     const int acc = M < n_free ? M : n_free;
     const int rej = M - acc;
-    if (acc > 0) {
+    if (__ballot(acc > 0)) {
+      // the first car's profile was drawn ahead by lane tb of the station
+      const float f_cp = bcastf<L>(bcp, tb), f_s0 = bcastf<L>(bs0, tb), f_tg = bcastf<L>(btg, tb);
+      const int f_dw = bcast<L>(bdw, tb);
       int run = 0;
 #pragma unroll
       for (int j = 0; j < P; ++j) {
         const int rank = run + below[j];
         if (fr[j] && rank < acc) {
-          const U4 b = philox(env_id, g, (uint32_t)rank, kDomCar, k0, k1);
-          const float cp = C.cap_lo + C.cap_span * u24(b.x);
-          const float s0 = C.soc_lo + C.soc_span * u24(b.y);
-          const float tg = C.tgt_lo + C.tgt_span * u24(b.z);
-          dw[j] = 1 + count_below(tdw, C.dwell_log2, b.w);
+          float cp = f_cp, s0 = f_s0, tg = f_tg;
+          int dd = f_dw;
+          if (rank > 0) {
+            const U4 b = philox(env_id, g, (uint32_t)rank, kDomCar, k0, k1);
+            cp = C.cap_lo + C.cap_span * u24(b.x);
+            s0 = C.soc_lo + C.soc_span * u24(b.y);
+            tg = C.tgt_lo + C.tgt_span * u24(b.z);
+            dd = stay_len(tdw, tdw_lds, C.dwell_log2, b.w);
+          }
+          dw[j] = dd;
           cap[j] = cp;
           icap[j] = frcp(cp);
           q[j] = 1.0 - (double)s0;
@@ -382,36 +448,37 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
 
     // ---- records
     if (active) {
-      if (dy.out_mode == CX_OUT_FULL && obs_e) {
-        float *o = obs_e + (int64_t)t * dy.obs_stride;
+      if (dy.out_mode == CX_OUT_FULL && dy.obs) {
+        float *ob = dy.obs + sg.obs_off + (int64_t)t * dy.obs_stride;
 #pragma unroll
         for (int j = 0; j < P; ++j) {
-          if (port[j] >= 0) {
+          if (DENSE || port[j] >= 0) {
             const bool occ = dw[j] > 0;
-            const int p = port[j];
-            o[0 * N + p] = occ ? 1.0f : 0.0f;
-            o[1 * N + p] = occ ? (float)(1.0 - q[j]) : 0.0f;
-            o[2 * N + p] = occ ? (float)(q[j] - (double)u[j]) : 0.0f;
-            o[3 * N + p] = (float)dw[j] * C.inv_steps_ep;
-            o[4 * N + p] = occ ? fminf(1.0f, (float)q[j] * C.inv_1mtau) : 0.0f;
-            o[5 * N + p] = plast[j] * inv_pmax[j];
+            const uint32_t o = obs_bo + 4u * (uint32_t)port[j];
+            st_at(ob, o + 0u * 4u * N, occ ? 1.0f : 0.0f);
+            st_at(ob, o + 1u * 4u * N, occ ? (float)(1.0 - q[j]) : 0.0f);
+            st_at(ob, o + 2u * 4u * N, occ ? (float)(q[j] - (double)u[j]) : 0.0f);
+            st_at(ob, o + 3u * 4u * N, (float)dw[j] * C.inv_steps_ep);
+            st_at(ob, o + 4u * 4u * N, occ ? fminf(1.0f, (float)q[j] * C.inv_1mtau) : 0.0f);
+            st_at(ob, o + 5u * 4u * N, plast[j] * inv_pmax[j]);
           }
         }
         if (l < 4) {
           const int n_occ = done ? 0 : (N - n_free + acc);
-          const float gv = l == 3 ? (float)n_occ * (1.0f / (float)N) : C.glob[t_day * 4 + l];
-          o[6 * N + l] = gv;
+          const float gv = l == 3 ? (float)n_occ * (1.0f / (float)N) : gld(C.glob, t_day * 4 + l);
+          st_at(ob, obs_bo + 4u * (uint32_t)(6 * N + l), gv);
         }
       }
-      if ((dy.out_mode == CX_OUT_FULL || dy.out_mode == CX_OUT_ACT_REWARD) && act_e) {
-        uint8_t *a = act_e + (int64_t)t * dy.act_stride;
+      if ((dy.out_mode == CX_OUT_FULL || dy.out_mode == CX_OUT_ACT_REWARD) && dy.act) {
+        uint8_t *ab = dy.act + sg.act_off + (int64_t)t * dy.act_stride;
 #pragma unroll
         for (int j = 0; j < P; ++j)
-          if (port[j] >= 0) a[port[j]] = (uint8_t)k[j];
+          if (DENSE || port[j] >= 0) st_at(ab, act_bo + (uint32_t)port[j], (uint8_t)k[j]);
       }
       if (l == 0) {
-        if (dy.reward) dy.reward[(int64_t)t * dy.env_stride + renv] = r;
-        if (dy.done) dy.done[(int64_t)t * dy.env_stride + renv] = done ? 1 : 0;
+        const int64_t rb = sg.env_off + (int64_t)t * dy.env_stride;
+        if (dy.reward) st_at(dy.reward + rb, 4u * env_bo, r);
+        if (dy.done) st_at(dy.done + rb, env_bo, (uint8_t)(done ? 1 : 0));
       }
     }
   }
@@ -431,10 +498,11 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
   }
 }
 
-// One kernel per slots-per-lane count P, so that each keeps its own register
-// budget; the lanes-per-station L is dispatched inside (uniform per block).
-template <int P>
+// One kernel per packing (lanes per station L, slots per lane P), so that each
+// keeps its own register budget and occupancy.
+template <int L, int P>
 __global__ __launch_bounds__(512) void k_rollout(LaunchArgs a) {
+  constexpr bool kDenseOk = true;
   extern __shared__ uint32_t lds_tdwell[];
   const int b = blockIdx.x;
   int lo = 0, hi = a.n_segs - 1;
@@ -443,7 +511,9 @@ __global__ __launch_bounds__(512) void k_rollout(LaunchArgs a) {
     if (a.segs[mid].block_begin <= b) lo = mid;
     else hi = mid - 1;
   }
-  const SegDev &sg = a.segs[lo];
+  // the segment is block-uniform: say so, so its fields come in scalar loads
+  lo = __builtin_amdgcn_readfirstlane(lo);
+  const SegDev sg = a.segs[lo];
   Dyn dy;
   if (a.per_segment) {
     dy = Dyn{sg.T, sg.t_day0, sg.g0, sg.mode, sg.out_mode, sg.obs, sg.act, sg.reward, sg.done, sg.act_in,
@@ -455,23 +525,18 @@ __global__ __launch_bounds__(512) void k_rollout(LaunchArgs a) {
   // stay-length thresholds in LDS for multi-step launches (every wave of the
   // block helps load them before any wave may leave)
   const uint32_t *tdw = sg.cls->tdwell;
-  if (a.lds_tdwell) {
+  const bool tdw_lds = a.lds_tdwell != 0;
+  if (tdw_lds) {
     const int n = 1 << sg.cls->dwell_log2;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) lds_tdwell[i] = tdw[i];
+    for (int i = threadIdx.x; i < n; i += blockDim.x) lds_tdwell[i] = gld(tdw, i);
     __syncthreads();
     tdw = lds_tdwell;
   }
   const int W = blockDim.x >> 6;
   const int group = __builtin_amdgcn_readfirstlane((b - sg.block_begin) * W + (int)(threadIdx.x >> 6));
   if (group >= sg.n_groups) return;
-  switch (pack_lanes(sg.pack)) {
-    case 4: run_group<4, P>(sg, dy, group, tdw); break;
-    case 8: run_group<8, P>(sg, dy, group, tdw); break;
-    case 16: run_group<16, P>(sg, dy, group, tdw); break;
-    case 32: run_group<32, P>(sg, dy, group, tdw); break;
-    case 64: run_group<64, P>(sg, dy, group, tdw); break;
-    default: break;
-  }
+  if (sg.cls->dense) run_group<L, P, kDenseOk>(sg, dy, group, tdw, tdw_lds);
+  else run_group<L, P, false>(sg, dy, group, tdw, tdw_lds);
 }
 
 // Observation of empty stations at t_day = 0 for every env of one segment.
@@ -488,13 +553,18 @@ __global__ void k_reset_obs(const ClassDev *cls, int64_t n_envs, float *obs) {
   }
 }
 
-void *kernel_for(int per_lane) {
-  switch (per_lane) {
-    case 1: return reinterpret_cast<void *>(&k_rollout<1>);
-    case 2: return reinterpret_cast<void *>(&k_rollout<2>);
-    default: return reinterpret_cast<void *>(&k_rollout<4>);
-  }
+using KernelFn = void (*)(LaunchArgs);
+
+template <int L, int P>
+constexpr KernelFn kfn() {
+  return &k_rollout<L, P>;
 }
+
+// Kernel of each packing id (id = P index * 5 + L index, as pack_id()).
+const KernelFn kKernels[kNumPackings] = {
+    kfn<4, 1>(), kfn<8, 1>(), kfn<16, 1>(), kfn<32, 1>(), kfn<64, 1>(),
+    kfn<4, 2>(), kfn<8, 2>(), kfn<16, 2>(), kfn<32, 2>(), kfn<64, 2>(),
+    kfn<4, 4>(), kfn<8, 4>(), kfn<16, 4>(), kfn<32, 4>(), kfn<64, 4>()};
 
 // Arguments of one group's launch: its slice of the segment table and its LDS.
 LaunchArgs group_args(const LaunchArgs &a, const LaunchGroup &g, size_t *lds) {
@@ -515,12 +585,10 @@ hipError_t launch_groups(const LaunchArgs &a, const LaunchGroup *groups, int n_g
     const LaunchGroup &g = groups[i];
     if (g.n_blocks <= 0) continue;
     size_t lds = 0;
-    const LaunchArgs b = group_args(a, g, &lds);
-    const dim3 grid(g.n_blocks), block(64 * waves_per_block);
-    if (g.per_lane == 1) hipLaunchKernelGGL(k_rollout<1>, grid, block, lds, st, b);
-    else if (g.per_lane == 2) hipLaunchKernelGGL(k_rollout<2>, grid, block, lds, st, b);
-    else hipLaunchKernelGGL(k_rollout<4>, grid, block, lds, st, b);
-    const hipError_t e = hipGetLastError();
+    LaunchArgs b = group_args(a, g, &lds);
+    void *params[1] = {&b};
+    hipError_t e = hipLaunchKernel(reinterpret_cast<const void *>(kKernels[g.pack]), dim3(g.n_blocks),
+                                   dim3(64 * waves_per_block), params, lds, st);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -528,25 +596,25 @@ hipError_t launch_groups(const LaunchArgs &a, const LaunchGroup *groups, int n_g
 
 hipError_t graph_rollout(RolloutGraph &G, const LaunchArgs &a, const LaunchGroup *groups, int n_groups,
                          int waves_per_block, hipStream_t st) {
-  LaunchArgs args[3];
-  void *params[3][1];
-  hipKernelNodeParams p[3];
+  LaunchArgs args[kNumPackings];
+  void *params[kNumPackings][1];
+  hipKernelNodeParams p[kNumPackings];
+  int shape[kNumPackings][3] = {};
   int n = 0;
-  int shape[3][3] = {};
-  for (int i = 0; i < n_groups && n < 3; ++i) {
+  for (int i = 0; i < n_groups && n < kNumPackings; ++i) {
     const LaunchGroup &g = groups[i];
     if (g.n_blocks <= 0) continue;
     size_t lds = 0;
     args[n] = group_args(a, g, &lds);
     params[n][0] = &args[n];
     p[n] = hipKernelNodeParams{};
-    p[n].func = kernel_for(g.per_lane);
+    p[n].func = reinterpret_cast<void *>(kKernels[g.pack]);
     p[n].gridDim = dim3(g.n_blocks);
     p[n].blockDim = dim3(64 * waves_per_block);
     p[n].sharedMemBytes = (unsigned)lds;
     p[n].kernelParams = params[n];
     p[n].extra = nullptr;
-    shape[n][0] = g.per_lane;
+    shape[n][0] = g.pack;
     shape[n][1] = g.n_blocks;
     shape[n][2] = (int)lds;
     ++n;
