@@ -61,7 +61,6 @@ static cx_status upload_class(cx_ctx *ctx, ClassRt &c) {
   d.tgt_lo = (float)s.tgt_lo; d.tgt_span = (float)(s.tgt_hi - s.tgt_lo);
   d.inv_steps_ep = (float)(1.0 / s.steps_per_episode); d.inv_n_levels = (float)(1.0 / s.n_levels);
   d.inv_eta_uniform = k.inv_eta_uniform;
-  d.dense = k.S == k.N ? 1 : 0;
   d.lvl_lb_uniform = 0;
   for (int lvl = 0; lvl < kMaxLevels; ++lvl) {
     uint32_t v = 0xFF;
@@ -72,6 +71,22 @@ static cx_status upload_class(cx_ctx *ctx, ClassRt &c) {
     }
     d.lvl_lb_uniform |= v << (8 * lvl);
   }
+  // SIMPLE: dense, one port maximum and efficiency, one block size and limit per level
+  bool simple = k.S == k.N && k.uniform_eta;
+  for (int x = 1; x < k.S && simple; ++x) simple = k.slot_pmax[x] == k.slot_pmax[0];
+  for (int lvl = 0; lvl < kMaxLevels; ++lvl) {
+    float cu = std::numeric_limits<float>::infinity();
+    if (lvl < k.D) {
+      if (((d.lvl_lb_uniform >> (8 * lvl)) & 0xFF) == 0xFF) simple = false;
+      cu = k.slot_cap[(size_t)lvl * k.S];
+      for (int x = 1; x < k.S; ++x)
+        if (k.slot_cap[(size_t)lvl * k.S + x] != cu) simple = false;
+    }
+    d.lvl_cap_u[lvl] = cu;
+  }
+  d.simple = simple ? 1 : 0;
+  d.pmax_u = k.slot_pmax[0];
+  d.inv_pmax_u = k.slot_inv_pmax[0];
   d.slot_port = reinterpret_cast<const int32_t *>(base + o_port);
   d.slot_pmax = reinterpret_cast<const float *>(base + o_pmax);
   d.slot_inv_pmax = reinterpret_cast<const float *>(base + o_ipmax);
@@ -109,23 +124,28 @@ int default_lanes(int S) { return S <= 64 ? S : 64; }
 
 // Group segments by packing (one kernel each); groups with more slots per
 // station come first so the heaviest waves start first.
-void build_groups(const std::vector<SegDev> &in, const std::vector<int> &log2_dwell, int wpb,
-                  std::vector<SegDev> *out, std::vector<LaunchGroup> *groups) {
+void build_groups(const std::vector<SegDev> &in, const std::vector<int> &log2_dwell,
+                  const std::vector<bool> &simple, int wpb, std::vector<SegDev> *out,
+                  std::vector<LaunchGroup> *groups) {
   out->clear();
   groups->clear();
-  std::vector<int> packs;
-  for (const SegDev &sg : in)
-    if (std::find(packs.begin(), packs.end(), sg.pack) == packs.end()) packs.push_back(sg.pack);
-  std::stable_sort(packs.begin(), packs.end(), [](int a, int b) {
-    return pack_lanes(a) * pack_per_lane(a) > pack_lanes(b) * pack_per_lane(b);
+  // launch kind = 2 * packing + simple
+  std::vector<int> kinds;
+  for (size_t i = 0; i < in.size(); ++i) {
+    const int kd = 2 * in[i].pack + (simple[i] ? 1 : 0);
+    if (std::find(kinds.begin(), kinds.end(), kd) == kinds.end()) kinds.push_back(kd);
+  }
+  std::stable_sort(kinds.begin(), kinds.end(), [](int a, int b) {
+    return pack_lanes(a / 2) * pack_per_lane(a / 2) > pack_lanes(b / 2) * pack_per_lane(b / 2);
   });
-  for (int pk : packs) {
+  for (int kd : kinds) {
     LaunchGroup g;
-    g.pack = pk;
+    g.pack = kd / 2;
+    g.simple = (kd & 1) != 0;
     g.seg_begin = (int)out->size();
     int blocks = 0;
     for (size_t i = 0; i < in.size(); ++i) {
-      if (in[i].pack != pk) continue;
+      if (2 * in[i].pack + (simple[i] ? 1 : 0) != kd) continue;
       SegDev sg = in[i];
       sg.block_begin = blocks;
       blocks += (sg.n_groups + wpb - 1) / wpb;
@@ -142,6 +162,7 @@ void build_groups(const std::vector<SegDev> &in, const std::vector<int> &log2_dw
 cx_status rebuild_segments(cx_ctx *ctx) {
   std::vector<SegDev> segs;
   std::vector<int> dl;
+  std::vector<bool> simple;
   for (ClassRt &c : ctx->classes) {
     if (c.n_envs == 0) continue;
     SegDev sg{};
@@ -165,8 +186,9 @@ cx_status rebuild_segments(cx_ctx *ctx) {
     sg.env_off = c.env_begin;
     segs.push_back(sg);
     dl.push_back(c.tab.dwell_log2);
+    simple.push_back(c.host_view.simple != 0);
   }
-  build_groups(segs, dl, ctx->wpb, &ctx->segs_host, &ctx->groups);
+  build_groups(segs, dl, simple, ctx->wpb, &ctx->segs_host, &ctx->groups);
   if (!ctx->segs_dev) {
     hipError_t e = hipMalloc(&ctx->segs_dev, sizeof(SegDev) * std::max<size_t>(1, ctx->classes.size()));
     if (e != hipSuccess) return fail_status(CX_E_OOM, "hipMalloc of segment table failed");

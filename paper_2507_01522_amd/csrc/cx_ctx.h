@@ -58,8 +58,9 @@ extern thread_local std::string g_last_error;
 cx_status fail_status(cx_status st, const std::string &msg);
 cx_status hip_fail(cx_ctx *ctx, hipError_t e, const char *what);
 cx_status rebuild_segments(cx_ctx *ctx);
-void build_groups(const std::vector<SegDev> &in, const std::vector<int> &log2_dwell, int wpb,
-                  std::vector<SegDev> *out, std::vector<LaunchGroup> *groups);
+void build_groups(const std::vector<SegDev> &in, const std::vector<int> &log2_dwell,
+                  const std::vector<bool> &simple, int wpb, std::vector<SegDev> *out,
+                  std::vector<LaunchGroup> *groups);
 LaunchArgs base_args(const cx_ctx *ctx);
 void advance_clock(cx_ctx *ctx, int32_t T);
 bool legal_packing(int S, int lanes);

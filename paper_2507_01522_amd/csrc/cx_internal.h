@@ -44,7 +44,10 @@ struct ClassDev {
   float inv_n_levels, inv_eta_uniform;
   uint32_t lvl_lb_uniform;     // per level (8 bits, level 0 = deepest): the block size log2
                                // shared by every slot of the level, 0xFF if they differ
-  int32_t dense;               // 1: no padding slots (slot s holds port s)
+  int32_t simple;              // 1: no padding, one port maximum / efficiency, and per level
+                               // one block size and one limit (all per-slot constants uniform)
+  float pmax_u, inv_pmax_u;    // the port maximum of a simple class
+  float lvl_cap_u[kMaxLevels]; // per level: the limit of a simple class (+inf beyond D)
   const int32_t *slot_port;    // [S]
   const float *slot_pmax;      // [S]
   const float *slot_inv_pmax;  // [S]
@@ -111,6 +114,7 @@ struct LaunchArgs {
 // instantiated for that packing.
 struct LaunchGroup {
   int pack = 0;         // packing id
+  bool simple = false;  // SIMPLE classes (see ClassDev::simple)
   int seg_begin = 0;    // index of the first segment in the device segment table
   int n_segs = 0;
   int n_blocks = 0;
@@ -124,9 +128,9 @@ struct LaunchGroup {
 struct RolloutGraph {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  hipGraphNode_t node[kNumPackings] = {};
+  hipGraphNode_t node[2 * kNumPackings] = {};
   int n_nodes = 0;
-  int shape[kNumPackings][3] = {};
+  int shape[2 * kNumPackings][3] = {};
   int waves = -1;
 };
 

@@ -31,6 +31,9 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 // schedule stays in scalar registers.
 __device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
                                      uint32_t k1) {
+  // keep the round keys from being precomputed (and held in 20 scalar
+  // registers) outside the step loop: bumping them costs two scalar adds
+  asm volatile("" : "+s"(k0), "+s"(k1));
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
     // one 32x32->64 multiply per product gives both halves (v_mad_u64_u32)
@@ -84,9 +87,12 @@ __device__ __forceinline__ int stay_len(const uint32_t *tab, bool in_lds, int lo
 }
 
 // Exchange with the lane whose index differs in bit K (K = 0..5), for use in
-// butterfly all-reductions.  For K = 2, 3 the partner is the mirror lane of
-// the same half-row / row: after the steps below K every lane of an aligned
-// 2^K group holds the same value, so the mirror is as good as the XOR partner.
+// butterfly all-reductions.  K = 0, 1: DPP quad permutes.  K = 2, 3: DPP
+// mirrors of the half-row / row -- after the steps below K every lane of an
+// aligned 2^K group holds the same value, so the mirror lane is as good as the
+// XOR partner.  K = 4, 5: the gfx950 row-swap instructions (v_permlane16_swap /
+// v_permlane32_swap, plain VALU, no LDS round trip) followed by a select of the
+// half that came from the partner.
 template <int K>
 __device__ __forceinline__ float xlane(float v) {
   const int iv = __float_as_int(v);
@@ -94,14 +100,20 @@ __device__ __forceinline__ float xlane(float v) {
   if constexpr (K == 1) return __int_as_float(__builtin_amdgcn_update_dpp(0, iv, 0x4E, 0xF, 0xF, false));
   if constexpr (K == 2) return __int_as_float(__builtin_amdgcn_update_dpp(0, iv, 0x141, 0xF, 0xF, false));
   if constexpr (K == 3) return __int_as_float(__builtin_amdgcn_update_dpp(0, iv, 0x140, 0xF, 0xF, false));
-  if constexpr (K == 4) return __int_as_float(__builtin_amdgcn_ds_swizzle(iv, 0x401F));
+  if constexpr (K == 4) {
+    // rows (0,1,2,3): first result = (r0, r0, r2, r2), second = (r1, r1, r3, r3)
+    const auto r = __builtin_amdgcn_permlane16_swap(iv, iv, false, false);
+    return __int_as_float((__lane_id() & 16) ? r[0] : r[1]);
+  }
   if constexpr (K == 5) {
-    const int lane = __lane_id();
-    return __int_as_float(__builtin_amdgcn_ds_bpermute((lane ^ 32) << 2, iv));
+    // halves (0,1): first result = (h0, h0), second = (h1, h1)
+    const auto r = __builtin_amdgcn_permlane32_swap(iv, iv, false, false);
+    return __int_as_float((__lane_id() & 32) ? r[0] : r[1]);
   }
   return v;
 }
 
+// Sum over aligned groups of L lanes (every lane receives its group's sum).
 template <int L>
 __device__ __forceinline__ float station_sum(float v) {
   if constexpr (L > 1) v += xlane<0>(v);
@@ -113,25 +125,15 @@ __device__ __forceinline__ float station_sum(float v) {
   return v;
 }
 
-// Masked butterfly step: lanes whose block is smaller than 2^(K+1) send 0.
+// Masked butterfly step: lanes whose block is smaller than 2^(K+1) send 0
+// (a select, no branch; lb may vary per lane or be wave-uniform).
 template <int K>
 __device__ __forceinline__ float masked_step(float v, int lb) {
   const float u = (K < lb) ? v : 0.0f;
   return v + xlane<K>(u);
 }
 
-// Unmasked butterfly over aligned groups of 2^lb lanes (lb wave-uniform).
-template <int L>
-__device__ __forceinline__ float group_sum_lanes(float v, int lb) {
-  if constexpr (L > 1) if (0 < lb) v += xlane<0>(v);
-  if constexpr (L > 2) if (1 < lb) v += xlane<1>(v);
-  if constexpr (L > 4) if (2 < lb) v += xlane<2>(v);
-  if constexpr (L > 8) if (3 < lb) v += xlane<3>(v);
-  if constexpr (L > 16) if (4 < lb) v += xlane<4>(v);
-  if constexpr (L > 32) if (5 < lb) v += xlane<5>(v);
-  return v;
-}
-
+// Sums over aligned blocks of 2^lb lanes (a lane's block: lanes sharing the bits above lb).
 template <int L>
 __device__ __forceinline__ float block_sum_lanes(float v, int lb) {
   if constexpr (L > 1) v = masked_step<0>(v, lb);
@@ -179,13 +181,16 @@ __device__ __forceinline__ T ld_at(const T *base, uint32_t byte_off) {
   return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + byte_off);
 }
 
-// DENSE: the class has no padding slots (slot s holds port s, N = L * P), so
-// port indices and record offsets are compile-time constants.
-template <int L, int P, bool DENSE>
+// SIMPLE: the class has no padding slots (slot s holds port s, N = L * P), one
+// port maximum and efficiency, and per tree level one block size and one limit.
+// Port indices and record offsets are then compile-time constants and every
+// per-slot constant is wave-uniform (scalar registers).
+template <int L, int P, bool SIMPLE>
 __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int group, const uint32_t *tdw,
                                           bool tdw_lds) {
   constexpr int SPW = 64 / L;
   constexpr int LOGL = (L == 4) ? 2 : (L == 8) ? 3 : (L == 16) ? 4 : (L == 32) ? 5 : 6;
+  constexpr bool DENSE = SIMPLE;
   const ClassDev C = *sg.cls;  // by value: scalar loads once, kept in SGPRs
   const int lane = __lane_id();
   const int l = lane & (L - 1);
@@ -204,13 +209,22 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
 #pragma unroll
   for (int j = 0; j < P; ++j) {
     const int s = j * L + l;
-    port[j] = DENSE ? s : C.slot_port[s];
-    pmax[j] = C.slot_pmax[s];
-    inv_pmax[j] = C.slot_inv_pmax[s];
-    inv_eta[j] = C.slot_inv_eta[s];
-    lbp[j] = C.slot_lb[s];
+    port[j] = DENSE ? s : gld(C.slot_port, s);
+    if constexpr (SIMPLE) {
+      pmax[j] = C.pmax_u;
+      inv_pmax[j] = C.inv_pmax_u;
+      inv_eta[j] = C.inv_eta_uniform;
+      lbp[j] = C.lvl_lb_uniform;
 #pragma unroll
-    for (int d = 0; d < kMaxLevels; ++d) lcap[d][j] = d < D ? C.slot_cap[d * S + s] : __builtin_inff();
+      for (int d = 0; d < kMaxLevels; ++d) lcap[d][j] = C.lvl_cap_u[d];
+    } else {
+      pmax[j] = gld(C.slot_pmax, s);
+      inv_pmax[j] = gld(C.slot_inv_pmax, s);
+      inv_eta[j] = gld(C.slot_inv_eta, s);
+      lbp[j] = gld(C.slot_lb, s);
+#pragma unroll
+      for (int d = 0; d < kMaxLevels; ++d) lcap[d][j] = d < D ? gld(C.slot_cap, d * S + s) : __builtin_inff();
+    }
   }
 
   // ---- state
@@ -226,9 +240,11 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
     cap[j] = active ? sg.cap[i] : 0.f;
     plast[j] = active ? sg.p_last[i] : 0.f;
     dw[j] = active ? (int)sg.dwell[i] : 0;
-    icap[j] = frcp(cap[j]);
+    icap[j] = cap[j] > 0.f ? frcp(cap[j]) : 0.f;
   }
   double ret = active ? sg.ret[env] : 0.0;
+  // limit of the root (the whole station)
+  const float c_root = D == 1 ? lcap[0][0] : D == 2 ? lcap[1][0] : D == 3 ? lcap[2][0] : lcap[3][0];
 
   const uint32_t k0 = (uint32_t)sg.seed, k1 = (uint32_t)(sg.seed >> 32);
   const uint32_t env_id = (uint32_t)(sg.env0 + env);
@@ -248,6 +264,18 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
   const uint32_t obs_bo = (uint32_t)env * (uint32_t)obs_dim * 4u;
   const uint32_t act_bo = (uint32_t)env * (uint32_t)N;
   const uint32_t env_bo = (uint32_t)env;
+  // wave-uniform record pointers of the current step, advanced every step
+  // (a record that is not written keeps a NULL pointer and a zero stride)
+  const bool w_obs = dy.out_mode == CX_OUT_FULL && dy.obs != nullptr;
+  const bool w_act = (dy.out_mode == CX_OUT_FULL || dy.out_mode == CX_OUT_ACT_REWARD) && dy.act != nullptr;
+  float *ob_t = w_obs ? dy.obs + sg.obs_off : nullptr;
+  uint8_t *ab_t = w_act ? dy.act + sg.act_off : nullptr;
+  const uint8_t *ai_t = dy.act_in ? dy.act_in + sg.act_off : nullptr;
+  float *rw_t = dy.reward ? dy.reward + sg.env_off : nullptr;
+  uint8_t *dn_t = dy.done ? dy.done + sg.env_off : nullptr;
+  const int64_t obs_step = w_obs ? dy.obs_stride : 0;
+  const int64_t act_step = (w_act || ai_t) ? dy.act_stride : 0;
+  const int64_t env_step = (rw_t || dn_t) ? dy.env_stride : 0;
 
   for (int t = 0; t < dy.T; ++t, ++g) {
     // ---- exogenous draws for the next L steps, lane l -> step t + l: the
@@ -293,7 +321,7 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
       for (int j = 0; j < P; ++j) {
         int v = 0;
         if (active && port[j] >= 0)
-          v = ld_at(dy.act_in + sg.act_off + (int64_t)t * dy.act_stride, act_bo + (uint32_t)port[j]);
+          v = ld_at(ai_t, act_bo + (uint32_t)port[j]);
         k[j] = v > n_levels ? n_levels : v;
       }
     }
@@ -309,15 +337,16 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
       pw[j] = dw[j] > 0 ? fminf(fminf(req, rhat), room) : 0.0f;
     }
 
-    // ---- projection onto the capacity tree, deepest level first
+    // ---- projection onto the capacity tree (Eq. ArchConst), deepest level
+    // first; the root (level D-1) holds the whole station
 #pragma unroll
-    for (int d = 0; d < kMaxLevels; ++d) {
-      if (d < D) {
+    for (int d = 0; d < kMaxLevels - 1; ++d) {
+      if (d < D - 1) {
         float s[P];
         const int lbu = (int)((C.lvl_lb_uniform >> (8 * d)) & 0xFF);
-        if (lbu != 0xFF) {  // every slot of the level sits in a block of 2^lbu slots
+        if (SIMPLE || lbu != 0xFF) {  // every slot of the level sits in a block of 2^lbu slots
 #pragma unroll
-          for (int j = 0; j < P; ++j) s[j] = group_sum_lanes<L>(pw[j], lbu);
+          for (int j = 0; j < P; ++j) s[j] = block_sum_lanes<L>(pw[j], lbu);
         } else {
 #pragma unroll
           for (int j = 0; j < P; ++j) s[j] = block_sum_lanes<L>(pw[j], (int)((lbp[j] >> (8 * d)) & 0xFF));
@@ -350,15 +379,20 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
         }
       }
     }
-
-    // ---- delivered energy and grid energy (App. A.3, charging only)
+    // root: the station total before root scaling; the delivered energy is its
+    // scaled value (App. A.3, charging only)
     float e_net, e_grid;
     {
       float tot = 0.f;
 #pragma unroll
       for (int j = 0; j < P; ++j) tot += pw[j];
-      e_net = C.dt * station_sum<L>(tot);
-      if (C.uniform_eta) {
+      tot = station_sum<L>(tot);
+      const bool over = tot > c_root;
+      const float f = over ? c_root * frcp(tot) : 1.0f;
+#pragma unroll
+      for (int j = 0; j < P; ++j) pw[j] *= f;
+      e_net = C.dt * (over ? c_root : tot);
+      if (SIMPLE || C.uniform_eta) {
         e_grid = e_net * C.inv_eta_uniform;
       } else {
         float tg = 0.f;
@@ -368,21 +402,24 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
       }
     }
 
-    // ---- charge, departures
+    // ---- charge, departures (selects: no branches)
     float csat = 0.f;
 #pragma unroll
     for (int j = 0; j < P; ++j) {
-      if (dw[j] > 0) {
-        const float e = C.dt * pw[j];
-        const double nq = q[j] - (double)(e * icap[j]);
-        q[j] = nq > 0.0 ? nq : 0.0;
-        plast[j] = pw[j];
-        dw[j] -= 1;
-        if (dw[j] == 0) {
-          csat += fmaxf(0.0f, (float)((q[j] - (double)u[j]) * (double)cap[j]));
-          q[j] = 0.0; u[j] = 0.f; cap[j] = 0.f; icap[j] = 0.f; plast[j] = 0.f;
-        }
-      }
+      const bool occ = dw[j] > 0;                // pw = 0 and icap = 0 on empty slots
+      const float e = C.dt * pw[j];
+      const double nq = q[j] - (double)(e * icap[j]);
+      q[j] = nq > 0.0 ? nq : 0.0;
+      plast[j] = pw[j];
+      dw[j] -= occ ? 1 : 0;
+      const bool dep = occ && dw[j] == 0;
+      const float miss = fmaxf(0.0f, (float)((q[j] - (double)u[j]) * (double)cap[j]));
+      csat += dep ? miss : 0.0f;
+      q[j] = dep ? 0.0 : q[j];
+      u[j] = dep ? 0.f : u[j];
+      cap[j] = dep ? 0.f : cap[j];
+      icap[j] = dep ? 0.f : icap[j];
+      plast[j] = dep ? 0.f : plast[j];
     }
     if (C.alpha_sat != 0.0f) csat = station_sum<L>(csat);
 
@@ -448,8 +485,8 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
 
     // ---- records
     if (active) {
-      if (dy.out_mode == CX_OUT_FULL && dy.obs) {
-        float *ob = dy.obs + sg.obs_off + (int64_t)t * dy.obs_stride;
+      if (w_obs) {
+        float *ob = ob_t;
 #pragma unroll
         for (int j = 0; j < P; ++j) {
           if (DENSE || port[j] >= 0) {
@@ -469,18 +506,22 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
           st_at(ob, obs_bo + 4u * (uint32_t)(6 * N + l), gv);
         }
       }
-      if ((dy.out_mode == CX_OUT_FULL || dy.out_mode == CX_OUT_ACT_REWARD) && dy.act) {
-        uint8_t *ab = dy.act + sg.act_off + (int64_t)t * dy.act_stride;
+      if (w_act) {
+        uint8_t *ab = ab_t;
 #pragma unroll
         for (int j = 0; j < P; ++j)
           if (DENSE || port[j] >= 0) st_at(ab, act_bo + (uint32_t)port[j], (uint8_t)k[j]);
       }
       if (l == 0) {
-        const int64_t rb = sg.env_off + (int64_t)t * dy.env_stride;
-        if (dy.reward) st_at(dy.reward + rb, 4u * env_bo, r);
-        if (dy.done) st_at(dy.done + rb, env_bo, (uint8_t)(done ? 1 : 0));
+        if (rw_t) st_at(rw_t, 4u * env_bo, r);
+        if (dn_t) st_at(dn_t, env_bo, (uint8_t)(done ? 1 : 0));
       }
     }
+    ob_t += obs_step;
+    ab_t += act_step;
+    ai_t += act_step;
+    rw_t += env_step;
+    dn_t += env_step;
   }
 
   // ---- state back to HBM
@@ -498,11 +539,10 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
   }
 }
 
-// One kernel per packing (lanes per station L, slots per lane P), so that each
-// keeps its own register budget and occupancy.
-template <int L, int P>
+// One kernel per packing (lanes per station L, slots per lane P) and class
+// kind (SIMPLE or general), so that each keeps its own register budget.
+template <int L, int P, bool SIMPLE>
 __global__ __launch_bounds__(512) void k_rollout(LaunchArgs a) {
-  constexpr bool kDenseOk = true;
   extern __shared__ uint32_t lds_tdwell[];
   const int b = blockIdx.x;
   int lo = 0, hi = a.n_segs - 1;
@@ -535,8 +575,7 @@ __global__ __launch_bounds__(512) void k_rollout(LaunchArgs a) {
   const int W = blockDim.x >> 6;
   const int group = __builtin_amdgcn_readfirstlane((b - sg.block_begin) * W + (int)(threadIdx.x >> 6));
   if (group >= sg.n_groups) return;
-  if (sg.cls->dense) run_group<L, P, kDenseOk>(sg, dy, group, tdw, tdw_lds);
-  else run_group<L, P, false>(sg, dy, group, tdw, tdw_lds);
+  run_group<L, P, SIMPLE>(sg, dy, group, tdw, tdw_lds);
 }
 
 // Observation of empty stations at t_day = 0 for every env of one segment.
@@ -555,16 +594,22 @@ __global__ void k_reset_obs(const ClassDev *cls, int64_t n_envs, float *obs) {
 
 using KernelFn = void (*)(LaunchArgs);
 
-template <int L, int P>
+template <int L, int P, bool S>
 constexpr KernelFn kfn() {
-  return &k_rollout<L, P>;
+  return &k_rollout<L, P, S>;
 }
 
-// Kernel of each packing id (id = P index * 5 + L index, as pack_id()).
-const KernelFn kKernels[kNumPackings] = {
-    kfn<4, 1>(), kfn<8, 1>(), kfn<16, 1>(), kfn<32, 1>(), kfn<64, 1>(),
-    kfn<4, 2>(), kfn<8, 2>(), kfn<16, 2>(), kfn<32, 2>(), kfn<64, 2>(),
-    kfn<4, 4>(), kfn<8, 4>(), kfn<16, 4>(), kfn<32, 4>(), kfn<64, 4>()};
+// Kernel of each launch kind: packing id (P index * 5 + L index, as pack_id())
+// times 2, plus 1 for SIMPLE classes.
+const KernelFn kKernels[2 * kNumPackings] = {
+    kfn<4, 1, false>(),  kfn<4, 1, true>(),  kfn<8, 1, false>(),  kfn<8, 1, true>(),
+    kfn<16, 1, false>(), kfn<16, 1, true>(), kfn<32, 1, false>(), kfn<32, 1, true>(),
+    kfn<64, 1, false>(), kfn<64, 1, true>(), kfn<4, 2, false>(),  kfn<4, 2, true>(),
+    kfn<8, 2, false>(),  kfn<8, 2, true>(),  kfn<16, 2, false>(), kfn<16, 2, true>(),
+    kfn<32, 2, false>(), kfn<32, 2, true>(), kfn<64, 2, false>(), kfn<64, 2, true>(),
+    kfn<4, 4, false>(),  kfn<4, 4, true>(),  kfn<8, 4, false>(),  kfn<8, 4, true>(),
+    kfn<16, 4, false>(), kfn<16, 4, true>(), kfn<32, 4, false>(), kfn<32, 4, true>(),
+    kfn<64, 4, false>(), kfn<64, 4, true>()};
 
 // Arguments of one group's launch: its slice of the segment table and its LDS.
 LaunchArgs group_args(const LaunchArgs &a, const LaunchGroup &g, size_t *lds) {
@@ -587,7 +632,7 @@ hipError_t launch_groups(const LaunchArgs &a, const LaunchGroup *groups, int n_g
     size_t lds = 0;
     LaunchArgs b = group_args(a, g, &lds);
     void *params[1] = {&b};
-    hipError_t e = hipLaunchKernel(reinterpret_cast<const void *>(kKernels[g.pack]), dim3(g.n_blocks),
+    hipError_t e = hipLaunchKernel(reinterpret_cast<const void *>(kKernels[2 * g.pack + (g.simple ? 1 : 0)]), dim3(g.n_blocks),
                                    dim3(64 * waves_per_block), params, lds, st);
     if (e != hipSuccess) return e;
   }
@@ -596,25 +641,25 @@ hipError_t launch_groups(const LaunchArgs &a, const LaunchGroup *groups, int n_g
 
 hipError_t graph_rollout(RolloutGraph &G, const LaunchArgs &a, const LaunchGroup *groups, int n_groups,
                          int waves_per_block, hipStream_t st) {
-  LaunchArgs args[kNumPackings];
-  void *params[kNumPackings][1];
-  hipKernelNodeParams p[kNumPackings];
-  int shape[kNumPackings][3] = {};
+  LaunchArgs args[2 * kNumPackings];
+  void *params[2 * kNumPackings][1];
+  hipKernelNodeParams p[2 * kNumPackings];
+  int shape[2 * kNumPackings][3] = {};
   int n = 0;
-  for (int i = 0; i < n_groups && n < kNumPackings; ++i) {
+  for (int i = 0; i < n_groups && n < 2 * kNumPackings; ++i) {
     const LaunchGroup &g = groups[i];
     if (g.n_blocks <= 0) continue;
     size_t lds = 0;
     args[n] = group_args(a, g, &lds);
     params[n][0] = &args[n];
     p[n] = hipKernelNodeParams{};
-    p[n].func = reinterpret_cast<void *>(kKernels[g.pack]);
+    p[n].func = reinterpret_cast<void *>(kKernels[2 * g.pack + (g.simple ? 1 : 0)]);
     p[n].gridDim = dim3(g.n_blocks);
     p[n].blockDim = dim3(64 * waves_per_block);
     p[n].sharedMemBytes = (unsigned)lds;
     p[n].kernelParams = params[n];
     p[n].extra = nullptr;
-    shape[n][0] = g.pack;
+    shape[n][0] = 2 * g.pack + (g.simple ? 1 : 0);
     shape[n][1] = g.n_blocks;
     shape[n][2] = (int)lds;
     ++n;
