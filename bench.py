@@ -40,6 +40,20 @@ def state_bytes(n_ports: np.ndarray) -> np.ndarray:
     return 22 * n_ports + 8
 
 
+def measured_traffic():
+    """HBM bytes of one rollout from the committed counter profile, if it was taken
+    on the current kernel source (None otherwise)."""
+    import hashlib
+    try:
+        prof = json.load(open(os.path.join(ROOT, "profiles", "k_rollout_traffic.json")))
+        src = open(os.path.join(ROOT, "paper_2507_01522_amd", "csrc", "cx_kernels.hip"), "rb").read()
+    except OSError:
+        return None
+    if hashlib.sha256(src).hexdigest()[:16] != prof.get("kernel_sha256_prefix"):
+        return None
+    return float(prof["traffic_bytes"])
+
+
 def workload():
     import workloads as W
     classes = W.mixture_classes()
@@ -159,7 +173,7 @@ def main():
                    "packing": {f"N{c.n_ports}d{c.levels}": c.lanes_per_station for c in ci},
                    "waves_per_block": ci[0].waves_per_block},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": "k_rollout", "kernel_ms": kernel_ms, "algorithmic_bytes": alg_bytes},
         "plain": plain,
         "speedup_vs_plain": (value / plain["env_steps_per_s"]) if plain else None,

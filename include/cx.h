@@ -229,45 +229,65 @@ const char *cx_last_error(void);
 void cx_destroy(cx_ctx *ctx);
 
 /* ---- serving: continuous batching of rollout requests ---------------------
- * A server owns a memory budget on the current device.  Requests (one station
- * class, n_envs, horizon T, seed, out_mode) are admitted first-come-first-served
- * as soon as their state and output buffers fit the budget; the scheduler
- * thread advances all admitted requests together, chunk_steps steps per launch,
- * so requests that arrive while others run join the next chunk.  A request's
- * results are identical alone or in any mix. */
+ * A server owns a memory budget on the current device and a scheduler thread.
+ * A request is one station class, n_envs stations, a horizon of T steps, a
+ * seed, an action mode (RANDOM or MAX) and an output mode; its stations start
+ * empty at t_day = 0 with their own step counter g = 0, and its Philox counters
+ * use request-local env indices, so its results depend on nothing else that
+ * runs.  Requests are admitted first-come-first-served as soon as their state
+ * (and their outputs, when the server allocates them) fit the budget; every
+ * launch advances all admitted requests together by up to chunk_steps steps,
+ * so requests that arrive while others run join at the next chunk boundary.
+ * A request's results are bit-identical alone or in any mix. */
 typedef struct cx_server cx_server;
 
 typedef struct {
   int32_t chunk_steps;      /* steps per launch (default 32) */
   int32_t max_active;       /* cap on concurrently admitted requests (default 256) */
   int32_t waves_per_block;  /* default 4 */
+  int32_t simulate_ns;      /* 0: run on the GPU.  > 0: no device is touched and a chunk
+                               takes simulate_ns per env-step on a host clock -- for
+                               testing the scheduler without a GPU */
 } cx_server_opts;
 
 typedef struct {
-  cx_station_spec spec;     /* copied at submit */
-  int64_t n_envs;
-  int32_t T;
+  cx_station_spec spec;     /* copied at submit (validated there: CX_E_INVALID) */
+  int64_t n_envs;           /* >= 1 */
+  int32_t T;                /* >= 1 */
   uint64_t seed;
   cx_out_mode out_mode;
-  cx_action_mode act_mode;  /* RANDOM or MAX */
+  cx_action_mode act_mode;  /* CX_ACT_RANDOM or CX_ACT_MAX */
+  cx_traj out;              /* optional caller-owned device buffers (layouts of cx_traj with
+                               this request's n_envs and T); members left NULL that out_mode
+                               needs are allocated by the server and count against the budget */
 } cx_request;
 
 typedef struct {
-  cx_status status;
+  cx_status status;         /* CX_OK when finished, CX_E_CANCELLED, or CX_E_DEVICE */
   int64_t n_envs;
   int32_t T;
-  cx_traj traj;             /* device buffers owned by the server until cx_release */
-  double submit_s, admit_s, done_s;  /* server clock, seconds */
-  int64_t bytes;
+  cx_traj traj;             /* where the records are: caller buffers, or server buffers that
+                               stay valid until cx_release */
+  double submit_s, admit_s, done_s;  /* server clock (seconds since create) */
+  int64_t bytes;            /* device bytes held for the request */
 } cx_result;
 
+/* Budget: device bytes the server may hold for admitted requests.  A request
+ * that could never fit is refused at submit with CX_E_BUDGET. */
 cx_status cx_server_create(size_t hbm_budget_bytes, const cx_server_opts *opts, cx_server **out);
 cx_status cx_submit(cx_server *s, const cx_request *req, uint64_t *ticket);
 cx_status cx_poll(cx_server *s, uint64_t ticket, cx_result *res);   /* CX_E_BUSY while queued/running */
-cx_status cx_wait(cx_server *s, uint64_t ticket, cx_result *res);
+cx_status cx_wait(cx_server *s, uint64_t ticket, cx_result *res);   /* blocks until done/cancelled */
+/* Cancel: a queued request is dropped at once; a running one at its next chunk
+ * boundary.  Its result then has status CX_E_CANCELLED. */
 cx_status cx_cancel(cx_server *s, uint64_t ticket);
-cx_status cx_release(cx_server *s, uint64_t ticket);                /* frees the request's buffers */
-cx_status cx_server_stats(cx_server *s, double *busy_s, int64_t *env_steps, int64_t *launches);
+/* Release a finished or cancelled request: its device memory returns to the
+ * budget and the ticket becomes unknown (CX_E_NOTFOUND). */
+cx_status cx_release(cx_server *s, uint64_t ticket);
+/* Totals since create: GPU time of the launched chunks, env-steps completed,
+ * number of chunk launches, and the peak of concurrently admitted requests. */
+cx_status cx_server_stats(cx_server *s, double *busy_s, int64_t *env_steps, int64_t *launches,
+                          int32_t *peak_active);
 void cx_server_destroy(cx_server *s);
 
 #ifdef __cplusplus

@@ -28,11 +28,12 @@ cx_status hip_fail(cx_ctx *ctx, hipError_t e, const char *what) {
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// Upload one class's constants, per-slot arrays and tables into one device block.
-static cx_status upload_class(cx_ctx *ctx, ClassRt &c) {
-  const Compiled &k = c.comp;
-  const Tables &t = c.tab;
-  const cx_station_spec &s = c.spec.s;
+// Host image of one class's device block: ClassDev, per-slot arrays and tables,
+// with the struct's pointers resolved against dev_base.  Returns the block size;
+// with host == nullptr only the size (and *view, if given) is produced.
+size_t class_block(const SpecCopy &sc, const Compiled &k, const Tables &t, unsigned char *dev_base,
+                   std::vector<unsigned char> *host, ClassDev *view) {
+  const cx_station_spec &s = sc.s;
   size_t off = align256(sizeof(ClassDev));
   auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
   const size_t o_port = take(sizeof(int32_t) * k.S);
@@ -44,11 +45,7 @@ static cx_status upload_class(cx_ctx *ctx, ClassRt &c) {
   const size_t o_tp = take(sizeof(uint32_t) * t.tpois_dev.size());
   const size_t o_td = take(sizeof(uint32_t) * t.tdwell_dev.size());
   const size_t o_gl = take(sizeof(float) * t.glob.size());
-  std::vector<unsigned char> host(off, 0);
-  hipError_t e = hipMalloc(&c.dev_mem, off);
-  if (e != hipSuccess) return fail_status(CX_E_OOM, "hipMalloc of class constants failed");
-  ctx->device_bytes += (int64_t)off;
-  unsigned char *base = static_cast<unsigned char *>(c.dev_mem);
+  unsigned char *base = dev_base;
   ClassDev d{};
   d.n_ports = k.N; d.S = k.S; d.D = k.D; d.n_levels = s.n_levels;
   d.steps_ep = s.steps_per_episode; d.obs_dim = 6 * k.N + 4; d.dwell_log2 = t.dwell_log2;
@@ -96,20 +93,34 @@ static cx_status upload_class(cx_ctx *ctx, ClassRt &c) {
   d.tpois = reinterpret_cast<const uint32_t *>(base + o_tp);
   d.tdwell = reinterpret_cast<const uint32_t *>(base + o_td);
   d.glob = reinterpret_cast<const float *>(base + o_gl);
-  std::memcpy(host.data(), &d, sizeof d);
-  std::memcpy(host.data() + o_port, k.slot_port.data(), sizeof(int32_t) * k.S);
-  std::memcpy(host.data() + o_pmax, k.slot_pmax.data(), sizeof(float) * k.S);
-  std::memcpy(host.data() + o_ipmax, k.slot_inv_pmax.data(), sizeof(float) * k.S);
-  std::memcpy(host.data() + o_ieta, k.slot_inv_eta.data(), sizeof(float) * k.S);
-  std::memcpy(host.data() + o_lb, k.slot_lb.data(), sizeof(uint32_t) * k.S);
-  std::memcpy(host.data() + o_cap, k.slot_cap.data(), sizeof(float) * k.S * k.D);
-  std::memcpy(host.data() + o_tp, t.tpois_dev.data(), sizeof(uint32_t) * t.tpois_dev.size());
-  std::memcpy(host.data() + o_td, t.tdwell_dev.data(), sizeof(uint32_t) * t.tdwell_dev.size());
-  std::memcpy(host.data() + o_gl, t.glob.data(), sizeof(float) * t.glob.size());
-  e = hipMemcpy(c.dev_mem, host.data(), off, hipMemcpyHostToDevice);
+  if (view) *view = d;
+  if (host) {
+    host->assign(off, 0);
+    std::memcpy(host->data(), &d, sizeof d);
+    std::memcpy(host->data() + o_port, k.slot_port.data(), sizeof(int32_t) * k.S);
+    std::memcpy(host->data() + o_pmax, k.slot_pmax.data(), sizeof(float) * k.S);
+    std::memcpy(host->data() + o_ipmax, k.slot_inv_pmax.data(), sizeof(float) * k.S);
+    std::memcpy(host->data() + o_ieta, k.slot_inv_eta.data(), sizeof(float) * k.S);
+    std::memcpy(host->data() + o_lb, k.slot_lb.data(), sizeof(uint32_t) * k.S);
+    std::memcpy(host->data() + o_cap, k.slot_cap.data(), sizeof(float) * k.S * k.D);
+    std::memcpy(host->data() + o_tp, t.tpois_dev.data(), sizeof(uint32_t) * t.tpois_dev.size());
+    std::memcpy(host->data() + o_td, t.tdwell_dev.data(), sizeof(uint32_t) * t.tdwell_dev.size());
+    std::memcpy(host->data() + o_gl, t.glob.data(), sizeof(float) * t.glob.size());
+  }
+  return off;
+}
+
+// Upload one class's constants, per-slot arrays and tables into one device block.
+static cx_status upload_class(cx_ctx *ctx, ClassRt &c) {
+  const size_t bytes = class_block(c.spec, c.comp, c.tab, nullptr, nullptr, nullptr);
+  hipError_t e = hipMalloc(&c.dev_mem, bytes);
+  if (e != hipSuccess) return fail_status(CX_E_OOM, "hipMalloc of class constants failed");
+  ctx->device_bytes += (int64_t)bytes;
+  std::vector<unsigned char> host;
+  class_block(c.spec, c.comp, c.tab, static_cast<unsigned char *>(c.dev_mem), &host, &c.host_view);
+  e = hipMemcpy(c.dev_mem, host.data(), bytes, hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(ctx, e, "upload of class constants");
   c.dev = reinterpret_cast<ClassDev *>(c.dev_mem);
-  c.host_view = d;
   return CX_OK;
 }
 

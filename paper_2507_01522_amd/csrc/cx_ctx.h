@@ -66,6 +66,8 @@ void advance_clock(cx_ctx *ctx, int32_t T);
 bool legal_packing(int S, int lanes);
 int default_lanes(int S);
 size_t state_blob_bytes(const cx_ctx *ctx);
+size_t class_block(const SpecCopy &sc, const Compiled &k, const Tables &t, unsigned char *dev_base,
+                   std::vector<unsigned char> *host, ClassDev *view);
 
 // policy (cx_policy.hip)
 void free_policy(cx_ctx *ctx);

@@ -61,12 +61,13 @@ class ClassInfoC(C.Structure):
 
 
 class ServerOptsC(C.Structure):
-    _fields_ = [("chunk_steps", C.c_int32), ("max_active", C.c_int32), ("waves_per_block", C.c_int32)]
+    _fields_ = [("chunk_steps", C.c_int32), ("max_active", C.c_int32), ("waves_per_block", C.c_int32),
+                ("simulate_ns", C.c_int32)]
 
 
 class RequestC(C.Structure):
     _fields_ = [("spec", StationSpecC), ("n_envs", C.c_int64), ("T", C.c_int32), ("seed", C.c_uint64),
-                ("out_mode", C.c_int32), ("act_mode", C.c_int32)]
+                ("out_mode", C.c_int32), ("act_mode", C.c_int32), ("out", TrajC)]
 
 
 class ResultC(C.Structure):
@@ -106,7 +107,7 @@ def lib() -> C.CDLL:
         "cx_synchronize": [P], "cx_last_error": [], "cx_destroy": [P],
         "cx_server_create": [C.c_size_t, P, P], "cx_submit": [P, P, P], "cx_poll": [P, U64, P],
         "cx_wait": [P, U64, P], "cx_cancel": [P, U64], "cx_release": [P, U64],
-        "cx_server_stats": [P, P, P, P], "cx_server_destroy": [P],
+        "cx_server_stats": [P, P, P, P, P], "cx_server_destroy": [P],
         "cx_compile_layout": [P, P, P, P, P, P], "cx_build_tables": [P, P, P],
     }
     for name, args in sig.items():
@@ -326,3 +327,67 @@ class Env:
         logits = torch.empty((n, spec.n_ports * (spec.n_levels + 1)), dtype=torch.float32, device=self.device)
         check(lib().cx_policy_logits(self.h, _p(obs.contiguous()), n, _p(logits)))
         return logits
+
+
+class Server:
+    """Continuous-batching rollout server (cx_server_*): requests of differing
+    station class, size and horizon share every launch; results are identical
+    alone or in a mix.  simulate_ns > 0 runs the scheduler on a host clock only."""
+
+    def __init__(self, budget_bytes: int, chunk_steps: int = 32, max_active: int = 256,
+                 waves_per_block: int = 4, simulate_ns: int = 0):
+        if simulate_ns <= 0 and not torch.cuda.is_available():
+            raise CxError(-3, "no HIP device visible to torch")
+        o = ServerOptsC(chunk_steps, max_active, waves_per_block, simulate_ns)
+        h = C.c_void_p()
+        check(lib().cx_server_create(int(budget_bytes), C.byref(o), C.byref(h)))
+        self.h = h
+        self._keep = {}
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            lib().cx_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, spec, n_envs: int, T: int, seed: int, out_mode: int = OUT_FULL,
+               act_mode: int = ACT_RANDOM, out: Optional[Dict[str, torch.Tensor]] = None) -> int:
+        holder = _SpecHolder(spec)
+        traj = TrajC() if out is None else Env._traj(out)
+        req = RequestC(holder.c, int(n_envs), int(T), int(seed), out_mode, act_mode, traj)
+        t = C.c_uint64()
+        check(lib().cx_submit(self.h, C.byref(req), C.byref(t)))
+        self._keep[t.value] = (holder, out)
+        return t.value
+
+    def poll(self, ticket: int):
+        r = ResultC()
+        st = lib().cx_poll(self.h, ticket, C.byref(r))
+        if st == -4:
+            return None
+        check(st)
+        return r
+
+    def wait(self, ticket: int) -> ResultC:
+        r = ResultC()
+        check(lib().cx_wait(self.h, ticket, C.byref(r)))
+        return r
+
+    def cancel(self, ticket: int):
+        check(lib().cx_cancel(self.h, ticket))
+
+    def release(self, ticket: int):
+        check(lib().cx_release(self.h, ticket))
+        self._keep.pop(ticket, None)
+
+    def stats(self) -> Dict[str, float]:
+        b = C.c_double()
+        e, n = C.c_int64(), C.c_int64()
+        p = C.c_int32()
+        check(lib().cx_server_stats(self.h, C.byref(b), C.byref(e), C.byref(n), C.byref(p)))
+        return {"busy_s": b.value, "env_steps": e.value, "launches": n.value, "peak_active": p.value}
