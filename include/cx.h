@@ -197,6 +197,11 @@ cx_status cx_set_policy(cx_ctx *ctx, int32_t hidden, const uint16_t *w1_host, co
  * logits_dev [n][n_ports*(n_levels+1)] float: the policy's first half alone. */
 cx_status cx_policy_logits(cx_ctx *ctx, const float *obs_dev, int64_t n, float *logits_dev);
 
+/* Observation of the current state of every station (the record layout of
+ * cx_traj.obs for one step, Sec. 3 state features): what a policy sees before
+ * the next step.  obs_dev: obs_elems floats of device memory, caller-owned. */
+cx_status cx_observe(cx_ctx *ctx, float *obs_dev);
+
 /* Snapshot / restore of the whole state (all stations, returns, g, t_day) in a
  * packing-independent host format of cx_info.state_bytes bytes, bit-exact, so a
  * restored context continues exactly as the original.  Both calls synchronise

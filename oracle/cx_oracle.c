@@ -478,7 +478,7 @@ static double bf16_bits_to_double(uint16_t b) {
  * port drawn by the Gumbel-max rule with Philox noise. */
 void ox_policy(const ox_class *c, int32_t hidden, const uint16_t *w1, const uint16_t *b1,
                const uint16_t *w2, const uint16_t *b2, const double *obs, uint64_t seed,
-               uint32_t env, uint32_t g, double *logits, int32_t *k) {
+               uint32_t env, uint32_t g, double *logits, int32_t *k, double *margin) {
   const int32_t N = c->n_ports, L = c->ip[OXI_N_LEVELS];
   const int32_t in = 6 * N + 4, out = N * (L + 1);
   double *x = (double *)malloc(sizeof(double) * in);
@@ -498,7 +498,7 @@ void ox_policy(const ox_class *c, int32_t hidden, const uint16_t *w1, const uint
   const int32_t Q = (L + 1 + 3) / 4;
   for (int32_t i = 0; i < N; ++i) {
     int32_t best = 0;
-    double best_v = -INFINITY;
+    double best_v = -INFINITY, second_v = -INFINITY;
     for (int32_t q = 0; q < Q; ++q) {
       uint32_t w[4];
       philox_seeded(seed, env, g, (uint32_t)(i * Q + q), OX_DOM_GUM, w);
@@ -508,12 +508,16 @@ void ox_policy(const ox_class *c, int32_t hidden, const uint16_t *w1, const uint
         double u = ((double)(w[r] >> 8) + 0.5) * (1.0 / 16777216.0);
         double v = z[i * (L + 1) + lev] - log(-log(u));
         if (v > best_v) {
+          second_v = best_v;
           best_v = v;
           best = lev;
+        } else if (v > second_v) {
+          second_v = v;
         }
       }
     }
     k[i] = best;
+    if (margin) margin[i] = best_v - second_v;
   }
   if (logits)
     for (int32_t o = 0; o < out; ++o) logits[o] = z[o];

@@ -154,10 +154,13 @@ int32_t ox_rollout(ox_class *const *classes, const int32_t *env_class, const int
 /* ---- policy (observation -> MLP -> Gumbel-argmax levels) ----
  * Weights are BF16 bit patterns; W1 [in][hidden], W2 [hidden][n_ports*(L+1)].
  * The observation is rounded to BF16 first and the hidden activation after tanh;
- * both products are taken in FP64.  logits (n_ports*(L+1)) may be NULL. */
+ * both products are taken in FP64.  Level of port i: argmax over its logits
+ * plus Gumbel noise -ln(-ln u), u from Philox (env, g, i Q + q, GUMBEL) word r
+ * for level 4 q + r, Q = ceil((L+1)/4).  logits (n_ports*(L+1)) and margin
+ * (n_ports: best minus second-best perturbed logit) may be NULL. */
 void ox_policy(const ox_class *c, int32_t hidden, const uint16_t *w1, const uint16_t *b1,
                const uint16_t *w2, const uint16_t *b2, const double *obs, uint64_t seed,
-               uint32_t env, uint32_t g, double *logits, int32_t *k);
+               uint32_t env, uint32_t g, double *logits, int32_t *k, double *margin);
 double ox_bf16_round(double x);
 
 #ifdef __cplusplus

@@ -73,7 +73,7 @@ def lib():
         L.ox_rollout.restype = I
         L.ox_rollout.argtypes = [P, P, P, C.c_int64, C.c_uint64, P, P, I, I, P, P, P, P, P, P, P, P,
                                  P, P, P, P, I]
-        L.ox_policy.argtypes = [P, I, P, P, P, P, P, C.c_uint64, C.c_uint32, C.c_uint32, P, P]
+        L.ox_policy.argtypes = [P, I, P, P, P, P, P, C.c_uint64, C.c_uint32, C.c_uint32, P, P, P]
         L.ox_bf16_round.restype = C.c_double
         L.ox_bf16_round.argtypes = [C.c_double]
         _lib = L
@@ -180,15 +180,18 @@ class OracleClass:
         st.t_day = t_day.value
         return info, obs, P
 
-    def policy(self, hidden: int, weights, obs, seed: int, env: int, g: int):
+    def policy(self, hidden: int, weights, obs, seed: int, env: int, g: int, with_margin: bool = False):
+        """Logits and sampled levels of one observation; with_margin adds, per
+        port, the gap between the best and second-best perturbed logit."""
         w1, b1, w2, b2 = [np.ascontiguousarray(w, dtype=np.uint16) for w in weights]
         o = np.ascontiguousarray(obs, dtype=np.float64)
         L = self.spec.n_levels
         logits = np.zeros(self.n * (L + 1), dtype=np.float64)
         k = np.zeros(self.n, dtype=np.int32)
+        margin = np.zeros(self.n, dtype=np.float64)
         lib().ox_policy(self.h, hidden, _ptr(w1), _ptr(b1), _ptr(w2), _ptr(b2), _ptr(o), seed, env, g,
-                        _ptr(logits), _ptr(k))
-        return logits, k
+                        _ptr(logits), _ptr(k), _ptr(margin))
+        return (logits, k, margin) if with_margin else (logits, k)
 
 
 class EnvState:

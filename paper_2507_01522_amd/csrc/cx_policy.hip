@@ -1,15 +1,387 @@
-// cx_policy.hip -- policy-in-the-loop rollouts (MLP on the matrix cores).
+// cx_policy.hip -- policy-in-the-loop rollouts.  Each step runs two kernels:
+//   k_policy  obs -> BF16 -> W1 (tanh) -> W2 -> logits on the matrix cores
+//             (v_mfma_f32_16x16x32_bf16, FP32 accumulation), then per port
+//             argmax over its levels of logit + Gumbel noise from Philox;
+//   the library's one-step environment kernel with those levels as external
+//             actions, which writes the next observation.
+// A third kernel, k_observe, gives the observation of the state a rollout
+// starts from.
+//
+// Both products are computed transposed so that no operand is ever shuffled
+// between lanes: with D = A * B on 16 x 16 tiles, lane l holds column l % 16
+// and rows 4 (l / 16) + i (i < 4) of D, and the 8 K-values of lane group
+// l / 16 of A and B.
+//   h^T [hidden x env]  = W1^T [hidden x obs] * obs^T [obs x env]
+//   z^T [logit x env]   = W2^T [logit x hidden] * h^T [hidden x env]
+// A lane thus ends the first product holding 8 hidden units of one env --
+// exactly the B operand of the second product, provided the hidden units of a
+// K-step are ordered as the lanes hold them; the host stores W2 in that order.
+// The rows of W2^T are arranged so that a lane ends the second product holding
+// all levels of one port of one env (level 4 r + i of port 4 g + l / 16 in row
+// i of tile (g, r)), so the argmax needs no exchange between lanes.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
 #include "cx_ctx.h"
+#include "cx_device.h"
 
 namespace cx {
 
-void free_policy(cx_ctx *ctx) { (void)ctx; }
+constexpr int kPolK1 = 8;  // K-steps of 32 observation features (obs_dim <= 256)
+constexpr int kPolHP = 8;  // K-steps of 32 hidden units (hidden <= 256)
+constexpr int kPolR = 3;   // tiles of 4 levels per port (levels + 1 <= 12)
+constexpr int kPolNT = 2;  // 16-env column tiles per wave
+constexpr int kPolWaves = 4;
+
+struct PolicyRt {
+  int hidden = 0, in_dim = 0, N = 0, L1 = 0;
+  int K1 = 0, HP = 0, R = 0, G = 0;
+  void *mem = nullptr;  // weights in fragment order + FP32 biases
+  const u32x4 *w1f = nullptr;
+  const float *b1 = nullptr;
+  const u32x4 *w2f = nullptr;
+  const float *b2f = nullptr;
+  float *obs = nullptr;  // one step of observations (rollouts that do not return them)
+  uint8_t *act = nullptr;  // one step of levels (rollouts that do not return them)
+  int64_t scratch_envs = 0;
+};
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+struct PolicyArgs {
+  const float *obs;  // [n][in_dim]
+  int64_t n;
+  int32_t in_dim, K1, HP, R, G, N, L1;
+  uint32_t g;        // global step of the draws
+  const u32x4 *w1f;
+  const float *b1;
+  const u32x4 *w2f;
+  const float *b2f;
+  uint8_t *act;      // [n][N] or NULL
+  float *logits;     // [n][N * L1] or NULL
+  uint64_t seed;
+  int64_t env0;      // Philox index of env 0
+};
+
+// FP32 -> BF16, round to nearest even (finite inputs).
+__device__ __forceinline__ uint32_t bf16_rne(float f) {
+  const uint32_t u = __float_as_uint(f);
+  return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+}
+__device__ __forceinline__ uint32_t pack2(float lo, float hi) { return bf16_rne(lo) | (bf16_rne(hi) << 16); }
+
+__device__ __forceinline__ f32x4 mfma(u32x4 a, u32x4 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
+                                                 0, 0, 0);
+}
+
+// tanh a = 1 - 2 / (e^{2a} + 1); saturates correctly at both ends.
+__device__ __forceinline__ float tanh_f(float a) {
+  const float e = __builtin_amdgcn_exp2f(a * 2.88539008177792681f);  // 2 / ln 2
+  return 1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f);
+}
+
+// Gumbel noise -ln(-ln u) of u = (m + 1/2) 2^-24, m the top 24 bits of w.
+// For u >= 1/2, -ln u = -ln(1 - v) with v = 1 - u exact, through Kahan's
+// log1p identity ln(1 + x) = ln(y) x / (y - 1), y = fl(1 + x): the winning
+// draws are the ones with u near 1, where ln u itself has no relative accuracy.
+__device__ __forceinline__ float gumbel(uint32_t w) {
+  constexpr float kLn2 = 0.693147180559945309f;
+  const uint32_t m = w >> 8;
+  const bool hi = m >= (1u << 23);
+  const float v = ((float)((1u << 24) - 1u - m) + 0.5f) * 0x1p-24f;  // 1 - u (exact when hi)
+  const float ulo = ((float)m + 0.5f) * 0x1p-24f;                    // u (exact when !hi)
+  const float y = 1.0f - v;
+  const float arg = hi ? y : ulo;
+  const float lg = __builtin_amdgcn_logf(arg);  // log2
+  float nl = -kLn2 * lg;                         // -ln(arg)
+  if (hi) nl = (y == 1.0f) ? v : nl * v * __builtin_amdgcn_rcpf(1.0f - y);
+  return -kLn2 * __builtin_amdgcn_logf(nl);
+}
+
+__global__ __launch_bounds__(64 * kPolWaves) void k_policy(PolicyArgs a) {
+  const int lane = __lane_id();
+  const int col = lane & 15, lg = lane >> 4;
+  const int64_t wave = (int64_t)blockIdx.x * kPolWaves + (threadIdx.x >> 6);
+  const int64_t e_base = wave * 16 * kPolNT;
+  if (e_base >= a.n) return;
+
+  // ---- B operand of the first product: 8 consecutive features of one env
+  u32x4 ob[kPolK1][kPolNT];
+#pragma unroll
+  for (int s = 0; s < kPolK1; ++s) {
+#pragma unroll
+    for (int n = 0; n < kPolNT; ++n) {
+      u32x4 v = {0u, 0u, 0u, 0u};
+      const int64_t e = e_base + 16 * n + col;
+      const int f = 32 * s + 8 * lg;
+      if (s < a.K1 && e < a.n && f < a.in_dim) {
+        const float *row = a.obs + e * a.in_dim + f;
+        typedef float f4 __attribute__((ext_vector_type(4)));
+        const f4 x = gld(reinterpret_cast<const f4 *>(row), 0);
+        f4 y = {0.f, 0.f, 0.f, 0.f};
+        if (f + 4 < a.in_dim) y = gld(reinterpret_cast<const f4 *>(row + 4), 0);
+        v = u32x4{pack2(x.x, x.y), pack2(x.z, x.w), pack2(y.x, y.y), pack2(y.z, y.w)};
+      }
+      ob[s][n] = v;
+    }
+  }
+
+  // ---- first product, 32 hidden units (two 16-row tiles) at a time
+  u32x4 h[kPolHP][kPolNT];
+#pragma unroll
+  for (int mp = 0; mp < kPolHP; ++mp) {
+#pragma unroll
+    for (int n = 0; n < kPolNT; ++n) h[mp][n] = u32x4{0u, 0u, 0u, 0u};
+    if (mp < a.HP) {
+      f32x4 c0[kPolNT], c1[kPolNT];
+#pragma unroll
+      for (int n = 0; n < kPolNT; ++n) {
+        c0[n] = f32x4{0.f, 0.f, 0.f, 0.f};
+        c1[n] = f32x4{0.f, 0.f, 0.f, 0.f};
+      }
+#pragma unroll
+      for (int s = 0; s < kPolK1; ++s) {
+        if (s < a.K1) {
+          const u32x4 a0 = gld(a.w1f, ((int64_t)(2 * mp) * a.K1 + s) * 64 + lane);
+          const u32x4 a1 = gld(a.w1f, ((int64_t)(2 * mp + 1) * a.K1 + s) * 64 + lane);
+#pragma unroll
+          for (int n = 0; n < kPolNT; ++n) {
+            c0[n] = mfma(a0, ob[s][n], c0[n]);
+            c1[n] = mfma(a1, ob[s][n], c1[n]);
+          }
+        }
+      }
+      const f32x4 bA = gld(reinterpret_cast<const f32x4 *>(a.b1 + 32 * mp + 4 * lg), 0);
+      const f32x4 bB = gld(reinterpret_cast<const f32x4 *>(a.b1 + 32 * mp + 16 + 4 * lg), 0);
+#pragma unroll
+      for (int n = 0; n < kPolNT; ++n) {
+        h[mp][n] = u32x4{pack2(tanh_f(c0[n].x + bA.x), tanh_f(c0[n].y + bA.y)),
+                         pack2(tanh_f(c0[n].z + bA.z), tanh_f(c0[n].w + bA.w)),
+                         pack2(tanh_f(c1[n].x + bB.x), tanh_f(c1[n].y + bB.y)),
+                         pack2(tanh_f(c1[n].z + bB.z), tanh_f(c1[n].w + bB.w))};
+      }
+    }
+  }
+
+  // ---- second product per group of 4 ports, then Gumbel-max per port
+  const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
+  const int out_dim = a.N * a.L1;
+  for (int grp = 0; grp < a.G; ++grp) {
+    f32x4 c[kPolR][kPolNT];
+#pragma unroll
+    for (int r = 0; r < kPolR; ++r) {
+      f32x4 b = {0.f, 0.f, 0.f, 0.f};
+      if (r < a.R) b = gld(reinterpret_cast<const f32x4 *>(a.b2f + (int64_t)(grp * a.R + r) * 16 + 4 * lg), 0);
+#pragma unroll
+      for (int n = 0; n < kPolNT; ++n) c[r][n] = b;
+    }
+#pragma unroll
+    for (int s = 0; s < kPolHP; ++s) {
+      if (s < a.HP) {
+#pragma unroll
+        for (int r = 0; r < kPolR; ++r) {
+          if (r < a.R) {
+            const u32x4 w = gld(a.w2f, ((int64_t)(grp * a.R + r) * a.HP + s) * 64 + lane);
+#pragma unroll
+            for (int n = 0; n < kPolNT; ++n) c[r][n] = mfma(w, h[s][n], c[r][n]);
+          }
+        }
+      }
+    }
+    const int port = 4 * grp + lg;
+#pragma unroll
+    for (int n = 0; n < kPolNT; ++n) {
+      const int64_t e = e_base + 16 * n + col;
+      if (port >= a.N || e >= a.n) continue;
+      if (a.logits) {
+        float *z = a.logits + e * out_dim + (int64_t)port * a.L1;
+#pragma unroll
+        for (int r = 0; r < kPolR; ++r) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int lev = 4 * r + i;
+            if (r < a.R && lev < a.L1) z[lev] = c[r][n][i];
+          }
+        }
+      }
+      if (a.act) {
+        int best = 0;
+        float bv = -__builtin_inff();
+#pragma unroll
+        for (int r = 0; r < kPolR; ++r) {
+          if (r < a.R) {
+            const U4 w = philox((uint32_t)(a.env0 + e), a.g, (uint32_t)(port * a.R + r), kDomGum, k0, k1);
+            const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const int lev = 4 * r + i;
+              if (lev < a.L1) {
+                const float v = c[r][n][i] + gumbel(ws[i]);
+                if (v > bv) {
+                  bv = v;
+                  best = lev;
+                }
+              }
+            }
+          }
+        }
+        a.act[e * a.N + port] = (uint8_t)best;
+      }
+    }
+  }
+}
+
+// Observation of the current state (the features the step kernel records).
+__global__ void k_observe(const ClassDev *cls, int64_t n_envs, const double *q, const float *u,
+                          const float *p_last, const int16_t *dwell, int32_t t_day, float *obs) {
+  const ClassDev C = *cls;
+  const int S = C.S, N = C.n_ports, dim = C.obs_dim;
+  const int64_t total = n_envs * S;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t env = i / S;
+    const int s = (int)(i - env * S);
+    const int port = C.slot_port[s];
+    if (port < 0) continue;
+    const int dw = dwell[i];
+    const bool occ = dw > 0;
+    const double qq = q[i];
+    float *o = obs + env * dim + port;
+    o[0 * N] = occ ? 1.0f : 0.0f;
+    o[1 * N] = occ ? (float)(1.0 - qq) : 0.0f;
+    o[2 * N] = occ ? (float)(qq - (double)u[i]) : 0.0f;
+    o[3 * N] = (float)dw * C.inv_steps_ep;
+    o[4 * N] = occ ? fminf(1.0f, (float)qq * C.inv_1mtau) : 0.0f;
+    o[5 * N] = p_last[i] * C.slot_inv_pmax[s];
+  }
+  for (int64_t env = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; env < n_envs;
+       env += (int64_t)gridDim.x * blockDim.x) {
+    int n_occ = 0;
+    for (int s = 0; s < S; ++s) n_occ += dwell[env * S + s] > 0 ? 1 : 0;
+    float *o = obs + env * dim + 6 * N;
+    o[0] = C.glob[t_day * 4 + 0];
+    o[1] = C.glob[t_day * 4 + 1];
+    o[2] = C.glob[t_day * 4 + 2];
+    o[3] = (float)n_occ * (1.0f / (float)N);
+  }
+}
+
+hipError_t launch_policy(const PolicyArgs &a, hipStream_t st) {
+  const int64_t waves = (a.n + 16 * kPolNT - 1) / (16 * kPolNT);
+  const int64_t blocks = (waves + kPolWaves - 1) / kPolWaves;
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_policy, dim3((unsigned)blocks), dim3(64 * kPolWaves), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_observe(const cx_ctx *ctx, float *obs, hipStream_t st) {
+  for (const ClassRt &c : ctx->classes) {
+    if (c.n_envs == 0) continue;
+    const int64_t work = c.n_envs * c.comp.S;
+    const int blocks = (int)std::min<int64_t>(4096, (work + 255) / 256);
+    hipLaunchKernelGGL(k_observe, dim3(blocks), dim3(256), 0, st, c.dev, c.n_envs, ctx->q + c.slot_off,
+                       ctx->u + c.slot_off, ctx->p_last + c.slot_off, ctx->dwell + c.slot_off, ctx->t_day,
+                       obs + c.obs_off);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+PolicyArgs policy_args(const cx_ctx *ctx, const float *obs, int64_t n) {
+  const PolicyRt &p = *ctx->policy;
+  PolicyArgs a{};
+  a.obs = obs;
+  a.n = n;
+  a.in_dim = p.in_dim; a.K1 = p.K1; a.HP = p.HP; a.R = p.R; a.G = p.G; a.N = p.N; a.L1 = p.L1;
+  a.w1f = p.w1f; a.b1 = p.b1; a.w2f = p.w2f; a.b2f = p.b2f;
+  a.seed = ctx->seed;
+  a.env0 = ctx->classes[0].env_begin;
+  return a;
+}
+
+double bf16_to_double(uint16_t b) {
+  const uint32_t u = (uint32_t)b << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
+cx_status ensure_scratch(cx_ctx *ctx) {
+  PolicyRt &p = *ctx->policy;
+  if (p.scratch_envs >= ctx->n_envs) return CX_OK;
+  if (p.obs) (void)hipFree(p.obs);
+  if (p.act) (void)hipFree(p.act);
+  p.obs = nullptr;
+  p.act = nullptr;
+  p.scratch_envs = 0;
+  if (hipMalloc(&p.obs, sizeof(float) * ctx->obs_elems) != hipSuccess ||
+      hipMalloc(&p.act, (size_t)ctx->total_ports) != hipSuccess)
+    return fail_status(CX_E_OOM, "policy rollout: scratch allocation failed");
+  p.scratch_envs = ctx->n_envs;
+  return CX_OK;
+}
+
+}  // namespace
+
+void free_policy(cx_ctx *ctx) {
+  if (!ctx || !ctx->policy) return;
+  PolicyRt *p = ctx->policy;
+  if (p->mem) (void)hipFree(p->mem);
+  if (p->obs) (void)hipFree(p->obs);
+  if (p->act) (void)hipFree(p->act);
+  delete p;
+  ctx->policy = nullptr;
+}
 
 cx_status policy_step(cx_ctx *ctx, int32_t T, cx_out_mode out_mode, const cx_traj *out, bool graph) {
-  (void)ctx; (void)T; (void)out_mode; (void)out; (void)graph;
-  return fail_status(CX_E_INVALID, "no policy set (cx_set_policy)");
+  (void)graph;
+  if (!ctx->policy) return fail_status(CX_E_INVALID, "no policy set (cx_set_policy)");
+  cx_status st = ensure_scratch(ctx);
+  if (st != CX_OK) return st;
+  const bool ret_obs = out && out_mode == CX_OUT_FULL && out->obs;
+  const bool ret_act = out && out_mode != CX_OUT_REWARD && out->actions;
+  if (ret_obs && (reinterpret_cast<uintptr_t>(out->obs) & 15u) != 0)
+    return fail_status(CX_E_INVALID, "policy rollout: obs buffer must be 16-byte aligned");
+  PolicyRt &p = *ctx->policy;
+  hipError_t e = launch_observe(ctx, p.obs, ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "policy rollout: observation kernel");
+  const float *obs_prev = p.obs;
+  for (int32_t t = 0; t < T; ++t) {
+    float *obs_t = ret_obs ? out->obs + (int64_t)t * ctx->obs_elems : p.obs;
+    uint8_t *act_t = ret_act ? out->actions + (int64_t)t * ctx->total_ports : p.act;
+    PolicyArgs pa = policy_args(ctx, obs_prev, ctx->n_envs);
+    pa.g = ctx->g + (uint32_t)t;
+    pa.act = act_t;
+    if ((e = launch_policy(pa, ctx->stream)) != hipSuccess) return hip_fail(ctx, e, "policy kernel");
+    LaunchArgs a = base_args(ctx);
+    a.T = 1;
+    a.g0 = ctx->g + (uint32_t)t;
+    a.t_day0 = (int32_t)(((int64_t)ctx->t_day + t) % ctx->steps_ep);
+    a.mode = CX_ACT_EXTERNAL;
+    a.out_mode = CX_OUT_FULL;
+    a.act_in = act_t;
+    a.obs = obs_t;
+    a.act = nullptr;
+    a.reward = out && out->reward ? out->reward + (int64_t)t * ctx->n_envs : nullptr;
+    a.done = out && out->done ? out->done + (int64_t)t * ctx->n_envs : nullptr;
+    if ((e = launch_groups(a, ctx->groups.data(), (int)ctx->groups.size(), ctx->wpb, ctx->stream)) !=
+        hipSuccess)
+      return hip_fail(ctx, e, "policy rollout: step kernel");
+    obs_prev = obs_t;
+  }
+  // the next rollout starts from the observation kernel again (it does not
+  // read obs_prev), so the clock is the only state carried here
+  advance_clock(ctx, T);
+  return CX_OK;
 }
 
 }  // namespace cx
@@ -20,13 +392,117 @@ extern "C" {
 
 cx_status cx_set_policy(cx_ctx *ctx, int32_t hidden, const uint16_t *w1, const uint16_t *b1,
                         const uint16_t *w2, const uint16_t *b2) {
-  (void)ctx; (void)hidden; (void)w1; (void)b1; (void)w2; (void)b2;
-  return fail_status(CX_E_INVALID, "cx_set_policy: not available in this build");
+  if (!ctx) return fail_status(CX_E_INVALID, "context is NULL");
+  if (ctx->failed) return fail_status(CX_E_DEVICE, "context has a sticky device error");
+  if (!w1 || !b1 || !w2 || !b2) return fail_status(CX_E_INVALID, "cx_set_policy: NULL weight array");
+  if (ctx->classes.size() != 1) return fail_status(CX_E_INVALID, "cx_set_policy: single-class contexts only");
+  const ClassRt &c = ctx->classes[0];
+  const int N = c.comp.N, L1 = c.spec.s.n_levels + 1, in_dim = 6 * N + 4;
+  if (hidden < 32 || hidden > 32 * kPolHP || hidden % 32 != 0)
+    return fail_status(CX_E_INVALID, "cx_set_policy: hidden must be a multiple of 32 in 32..256");
+  if (in_dim > 32 * kPolK1)
+    return fail_status(CX_E_INVALID, "cx_set_policy: observations longer than 256 (more than 42 ports)");
+  if (L1 > 4 * kPolR) return fail_status(CX_E_INVALID, "cx_set_policy: at most 11 levels per port");
+  const int K1 = (in_dim + 31) / 32, HP = hidden / 32, R = (L1 + 3) / 4, G = (N + 3) / 4;
+  const int out_dim = N * L1;
+  // W1^T fragments: tile m (hidden 16m..16m+15), K-step s, lane l -> hidden
+  // 16m + l % 16, features 32s + 8 (l / 16) + j
+  std::vector<uint16_t> w1f((size_t)2 * HP * K1 * 64 * 8, 0);
+  for (int m = 0; m < 2 * HP; ++m)
+    for (int s = 0; s < K1; ++s)
+      for (int l = 0; l < 64; ++l)
+        for (int j = 0; j < 8; ++j) {
+          const int f = 32 * s + 8 * (l >> 4) + j, hu = 16 * m + (l & 15);
+          if (f < in_dim) w1f[(((size_t)m * K1 + s) * 64 + l) * 8 + j] = w1[(size_t)f * hidden + hu];
+        }
+  std::vector<float> b1f(hidden);
+  for (int j = 0; j < hidden; ++j) b1f[j] = (float)bf16_to_double(b1[j]);
+  // W2^T fragments: tile (grp, r), K-step s, lane l -> row l % 16 = port
+  // 4 grp + (l % 16) / 4, level 4 r + l % 4; slot j -> hidden unit in the
+  // order the first product leaves them in a lane
+  std::vector<uint16_t> w2f((size_t)G * R * HP * 64 * 8, 0);
+  std::vector<float> b2f((size_t)G * R * 16, 0.f);
+  for (int grp = 0; grp < G; ++grp)
+    for (int r = 0; r < R; ++r) {
+      const int tile = grp * R + r;
+      for (int row = 0; row < 16; ++row) {
+        const int port = 4 * grp + (row >> 2), lev = 4 * r + (row & 3);
+        if (port < N && lev < L1) b2f[(size_t)tile * 16 + row] = (float)bf16_to_double(b2[port * L1 + lev]);
+      }
+      for (int s = 0; s < HP; ++s)
+        for (int l = 0; l < 64; ++l) {
+          const int row = l & 15, q = l >> 4;
+          const int port = 4 * grp + (row >> 2), lev = 4 * r + (row & 3);
+          if (port >= N || lev >= L1) continue;
+          const int o = port * L1 + lev;
+          for (int j = 0; j < 8; ++j) {
+            const int hu = 32 * s + (j < 4 ? 4 * q + j : 16 + 4 * q + (j - 4));
+            w2f[((((size_t)tile * HP + s) * 64 + l) * 8) + j] = w2[(size_t)hu * out_dim + o];
+          }
+        }
+    }
+  const size_t s_w1 = w1f.size() * 2, s_b1 = (size_t)hidden * 4, s_w2 = w2f.size() * 2, s_b2 = b2f.size() * 4;
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  const size_t bytes = al(s_w1) + al(s_b1) + al(s_w2) + al(s_b2);
+  void *mem = nullptr;
+  if (hipMalloc(&mem, bytes) != hipSuccess) return fail_status(CX_E_OOM, "cx_set_policy: hipMalloc failed");
+  unsigned char *b = static_cast<unsigned char *>(mem);
+  hipError_t e;
+  if ((e = hipMemcpy(b, w1f.data(), s_w1, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(b + al(s_w1), b1f.data(), s_b1, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(b + al(s_w1) + al(s_b1), w2f.data(), s_w2, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(b + al(s_w1) + al(s_b1) + al(s_w2), b2f.data(), s_b2, hipMemcpyHostToDevice)) !=
+          hipSuccess) {
+    (void)hipFree(mem);
+    return hip_fail(ctx, e, "cx_set_policy upload");
+  }
+  // replacing a policy waits for work that may still read the old weights
+  if ((e = hipStreamSynchronize(ctx->stream)) != hipSuccess) {
+    (void)hipFree(mem);
+    return hip_fail(ctx, e, "cx_set_policy synchronize");
+  }
+  PolicyRt *old = ctx->policy;
+  PolicyRt *p = new PolicyRt();
+  p->hidden = hidden; p->in_dim = in_dim; p->N = N; p->L1 = L1;
+  p->K1 = K1; p->HP = HP; p->R = R; p->G = G;
+  p->mem = mem;
+  p->w1f = reinterpret_cast<const u32x4 *>(b);
+  p->b1 = reinterpret_cast<const float *>(b + al(s_w1));
+  p->w2f = reinterpret_cast<const u32x4 *>(b + al(s_w1) + al(s_b1));
+  p->b2f = reinterpret_cast<const float *>(b + al(s_w1) + al(s_b1) + al(s_w2));
+  if (old) {  // keep the scratch buffers
+    p->obs = old->obs; p->act = old->act; p->scratch_envs = old->scratch_envs;
+    old->obs = nullptr; old->act = nullptr;
+    ctx->policy = old;
+    free_policy(ctx);
+  }
+  ctx->policy = p;
+  return CX_OK;
 }
 
 cx_status cx_policy_logits(cx_ctx *ctx, const float *obs_dev, int64_t n, float *logits_dev) {
-  (void)ctx; (void)obs_dev; (void)n; (void)logits_dev;
-  return fail_status(CX_E_INVALID, "no policy set (cx_set_policy)");
+  if (!ctx) return fail_status(CX_E_INVALID, "context is NULL");
+  if (ctx->failed) return fail_status(CX_E_DEVICE, "context has a sticky device error");
+  if (!ctx->policy) return fail_status(CX_E_INVALID, "no policy set (cx_set_policy)");
+  if (n < 0) return fail_status(CX_E_INVALID, "cx_policy_logits: n < 0");
+  if (n > 0 && (!obs_dev || !logits_dev)) return fail_status(CX_E_INVALID, "cx_policy_logits: NULL buffer");
+  if (n > 0 && (reinterpret_cast<uintptr_t>(obs_dev) & 15u) != 0)
+    return fail_status(CX_E_INVALID, "cx_policy_logits: obs_dev must be 16-byte aligned");
+  if (n == 0) return CX_OK;
+  PolicyArgs a = policy_args(ctx, obs_dev, n);
+  a.logits = logits_dev;
+  hipError_t e = launch_policy(a, ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "cx_policy_logits launch");
+  return CX_OK;
+}
+
+cx_status cx_observe(cx_ctx *ctx, float *obs_dev) {
+  if (!ctx) return fail_status(CX_E_INVALID, "context is NULL");
+  if (ctx->failed) return fail_status(CX_E_DEVICE, "context has a sticky device error");
+  if (!obs_dev) return fail_status(CX_E_INVALID, "cx_observe: obs_dev is NULL");
+  hipError_t e = launch_observe(ctx, obs_dev, ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "cx_observe launch");
+  return CX_OK;
 }
 
 }  // extern "C"

@@ -77,7 +77,7 @@ class ResultC(C.Structure):
 
 
 EXPORTS = ["cx_create", "cx_create_multi", "cx_set_stream", "cx_get_info", "cx_get_class_info", "cx_reset",
-           "cx_step", "cx_step_ex", "cx_rollout", "cx_set_policy", "cx_policy_logits", "cx_get_state",
+           "cx_step", "cx_step_ex", "cx_rollout", "cx_set_policy", "cx_policy_logits", "cx_observe", "cx_get_state",
            "cx_set_state", "cx_get_tables", "cx_set_packing", "cx_autotune", "cx_synchronize",
            "cx_last_error", "cx_destroy", "cx_server_create", "cx_submit", "cx_poll", "cx_wait",
            "cx_cancel", "cx_release", "cx_server_stats", "cx_server_destroy", "cx_compile_layout",
@@ -101,7 +101,7 @@ def lib() -> C.CDLL:
         "cx_set_stream": [P, P], "cx_get_info": [P, P], "cx_get_class_info": [P, I32, P],
         "cx_reset": [P, P], "cx_step": [P, P, P, P, P], "cx_step_ex": [P, I32, P, P],
         "cx_rollout": [P, I32, I32, I32, P, P], "cx_set_policy": [P, I32, P, P, P, P],
-        "cx_policy_logits": [P, P, I64, P], "cx_get_state": [P, P, C.c_size_t],
+        "cx_policy_logits": [P, P, I64, P], "cx_observe": [P, P], "cx_get_state": [P, P, C.c_size_t],
         "cx_set_state": [P, P, C.c_size_t], "cx_get_tables": [P, I32, P, P],
         "cx_set_packing": [P, I32, I32, I32], "cx_autotune": [P, I32, C.c_char_p],
         "cx_synchronize": [P], "cx_last_error": [], "cx_destroy": [P],
@@ -320,6 +320,13 @@ class Env:
         w1, b1, w2, b2 = [np.ascontiguousarray(w, np.uint16) for w in weights]
         check(lib().cx_set_policy(self.h, hidden, w1.ctypes.data, b1.ctypes.data, w2.ctypes.data,
                                   b2.ctypes.data))
+
+    def observe(self, obs: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """Observation of the current state (one record of the obs layout)."""
+        if obs is None:
+            obs = torch.empty((self.info().obs_elems,), dtype=torch.float32, device=self.device)
+        check(lib().cx_observe(self.h, _p(obs)))
+        return obs
 
     def policy_logits(self, obs: torch.Tensor) -> torch.Tensor:
         spec = self.specs[0]
