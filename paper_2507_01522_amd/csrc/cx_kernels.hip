@@ -582,7 +582,7 @@ LaunchArgs group_args(const LaunchArgs &a, const LaunchGroup &g, size_t *lds) {
   b.segs = a.segs + g.seg_begin;
   b.n_segs = g.n_segs;
   const int T = a.per_segment ? g.max_T : a.T;
-  b.lds_tdwell = T >= 8 ? 1 : 0;
+  b.lds_tdwell = 1;
   *lds = b.lds_tdwell ? ((size_t)4 << g.max_dwell_log2) : 0;
   return b;
 }

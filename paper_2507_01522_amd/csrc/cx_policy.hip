@@ -35,7 +35,7 @@ constexpr int kPolK1 = 8;  // K-steps of 32 observation features (obs_dim <= 256
 constexpr int kPolHP = 8;  // K-steps of 32 hidden units (hidden <= 256)
 constexpr int kPolR = 3;   // tiles of 4 levels per port (levels + 1 <= 12)
 constexpr int kPolNT = 2;  // 16-env column tiles per wave
-constexpr int kPolWaves = 4;
+constexpr int kPolWaves = 8;  // waves per block sharing each staged weight chunk
 
 struct PolicyRt {
   int hidden = 0, in_dim = 0, N = 0, L1 = 0;
@@ -89,29 +89,72 @@ __device__ __forceinline__ float tanh_f(float a) {
 }
 
 // Gumbel noise -ln(-ln u) of u = (m + 1/2) 2^-24, m the top 24 bits of w.
-// For u >= 1/2, -ln u = -ln(1 - v) with v = 1 - u exact, through Kahan's
-// log1p identity ln(1 + x) = ln(y) x / (y - 1), y = fl(1 + x): the winning
-// draws are the ones with u near 1, where ln u itself has no relative accuracy.
+// The winning draws are those with u near 1, where ln u has no relative
+// accuracy in FP32; there -ln u = -ln(1 - v) with v = 1 - u exact, taken from
+// its series for v < 1/16 (truncation below 3e-6 relative) and from log2 of
+// 1 - v above.  Over all 2^24 inputs the result is within 4e-6 of the exact
+// value.
 __device__ __forceinline__ float gumbel(uint32_t w) {
   constexpr float kLn2 = 0.693147180559945309f;
   const uint32_t m = w >> 8;
   const bool hi = m >= (1u << 23);
   const float v = ((float)((1u << 24) - 1u - m) + 0.5f) * 0x1p-24f;  // 1 - u (exact when hi)
   const float ulo = ((float)m + 0.5f) * 0x1p-24f;                    // u (exact when !hi)
-  const float y = 1.0f - v;
-  const float arg = hi ? y : ulo;
-  const float lg = __builtin_amdgcn_logf(arg);  // log2
-  float nl = -kLn2 * lg;                         // -ln(arg)
-  if (hi) nl = (y == 1.0f) ? v : nl * v * __builtin_amdgcn_rcpf(1.0f - y);
-  return -kLn2 * __builtin_amdgcn_logf(nl);
+  const float e_log = -kLn2 * __builtin_amdgcn_logf(hi ? 1.0f - v : ulo);
+  const float e_ser = v * (1.0f + v * (0.5f + v * (0.333333343f + v * 0.25f)));
+  const float e = (hi && v < 0.0625f) ? e_ser : e_log;  // -ln u
+  return -kLn2 * __builtin_amdgcn_logf(e);
+}
+
+// Weight chunks pass through LDS, double-buffered: chunk c < HP holds the two
+// W1^T tiles of hidden units 32c..32c+31 (all K-steps), chunk HP + g the R
+// tiles of W2^T of port group g.  Every wave of the block reads each chunk, so
+// a weight byte leaves L2 once per 16 * kPolNT * kPolWaves envs.
+constexpr int kChunkMax = 3 * kPolHP * 64;  // u32x4 per chunk (R * HP or 2 * K1 tiles of 64 lanes)
+constexpr int kPerThread = kChunkMax / (64 * kPolWaves);
+
+__device__ __forceinline__ void chunk_src(const PolicyArgs &a, int c, const u32x4 *&src, int &cnt) {
+  if (c < a.HP) {
+    src = a.w1f + (int64_t)(2 * c) * a.K1 * 64;
+    cnt = 2 * a.K1 * 64;
+  } else {
+    src = a.w2f + (int64_t)(c - a.HP) * a.R * a.HP * 64;
+    cnt = a.R * a.HP * 64;
+  }
+}
+
+__device__ __forceinline__ void fetch_chunk(const PolicyArgs &a, int c, u32x4 (&r)[kPerThread]) {
+  const u32x4 *src;
+  int cnt;
+  chunk_src(a, c, src, cnt);
+#pragma unroll
+  for (int i = 0; i < kPerThread; ++i) {
+    const int idx = (int)threadIdx.x + i * 64 * kPolWaves;
+    if (idx < cnt) r[i] = gld(src, idx);
+  }
+}
+
+__device__ __forceinline__ void put_chunk(const PolicyArgs &a, int c, const u32x4 (&r)[kPerThread], u32x4 *buf) {
+  const u32x4 *src;
+  int cnt;
+  chunk_src(a, c, src, cnt);
+#pragma unroll
+  for (int i = 0; i < kPerThread; ++i) {
+    const int idx = (int)threadIdx.x + i * 64 * kPolWaves;
+    if (idx < cnt) buf[idx] = r[i];
+  }
 }
 
 __global__ __launch_bounds__(64 * kPolWaves) void k_policy(PolicyArgs a) {
+  __shared__ u32x4 wbuf[2][kChunkMax];
   const int lane = __lane_id();
   const int col = lane & 15, lg = lane >> 4;
   const int64_t wave = (int64_t)blockIdx.x * kPolWaves + (threadIdx.x >> 6);
-  const int64_t e_base = wave * 16 * kPolNT;
-  if (e_base >= a.n) return;
+  const int64_t e_base = wave * 16 * kPolNT;  // waves past the end still take part in the barriers
+  const int n_chunks = a.HP + a.G;
+  u32x4 pf[kPerThread];
+  fetch_chunk(a, 0, pf);
+  put_chunk(a, 0, pf, wbuf[0]);
 
   // ---- B operand of the first product: 8 consecutive features of one env
   u32x4 ob[kPolK1][kPolNT];
@@ -133,14 +176,17 @@ __global__ __launch_bounds__(64 * kPolWaves) void k_policy(PolicyArgs a) {
       ob[s][n] = v;
     }
   }
+  __syncthreads();
 
-  // ---- first product, 32 hidden units (two 16-row tiles) at a time
+  // ---- first product, 32 hidden units (two 16-row tiles, one chunk) at a time
   u32x4 h[kPolHP][kPolNT];
 #pragma unroll
   for (int mp = 0; mp < kPolHP; ++mp) {
 #pragma unroll
     for (int n = 0; n < kPolNT; ++n) h[mp][n] = u32x4{0u, 0u, 0u, 0u};
     if (mp < a.HP) {
+      if (mp + 1 < n_chunks) fetch_chunk(a, mp + 1, pf);
+      const u32x4 *w = wbuf[mp & 1];
       f32x4 c0[kPolNT], c1[kPolNT];
 #pragma unroll
       for (int n = 0; n < kPolNT; ++n) {
@@ -150,8 +196,8 @@ __global__ __launch_bounds__(64 * kPolWaves) void k_policy(PolicyArgs a) {
 #pragma unroll
       for (int s = 0; s < kPolK1; ++s) {
         if (s < a.K1) {
-          const u32x4 a0 = gld(a.w1f, ((int64_t)(2 * mp) * a.K1 + s) * 64 + lane);
-          const u32x4 a1 = gld(a.w1f, ((int64_t)(2 * mp + 1) * a.K1 + s) * 64 + lane);
+          const u32x4 a0 = w[s * 64 + lane];
+          const u32x4 a1 = w[(a.K1 + s) * 64 + lane];
 #pragma unroll
           for (int n = 0; n < kPolNT; ++n) {
             c0[n] = mfma(a0, ob[s][n], c0[n]);
@@ -159,6 +205,7 @@ __global__ __launch_bounds__(64 * kPolWaves) void k_policy(PolicyArgs a) {
           }
         }
       }
+      if (mp + 1 < n_chunks) put_chunk(a, mp + 1, pf, wbuf[(mp + 1) & 1]);
       const f32x4 bA = gld(reinterpret_cast<const f32x4 *>(a.b1 + 32 * mp + 4 * lg), 0);
       const f32x4 bB = gld(reinterpret_cast<const f32x4 *>(a.b1 + 32 * mp + 16 + 4 * lg), 0);
 #pragma unroll
@@ -168,13 +215,17 @@ __global__ __launch_bounds__(64 * kPolWaves) void k_policy(PolicyArgs a) {
                          pack2(tanh_f(c1[n].x + bB.x), tanh_f(c1[n].y + bB.y)),
                          pack2(tanh_f(c1[n].z + bB.z), tanh_f(c1[n].w + bB.w))};
       }
+      __syncthreads();
     }
   }
 
-  // ---- second product per group of 4 ports, then Gumbel-max per port
+  // ---- second product per group of 4 ports (one chunk each), then Gumbel-max
   const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
   const int out_dim = a.N * a.L1;
   for (int grp = 0; grp < a.G; ++grp) {
+    const int cidx = a.HP + grp;
+    if (cidx + 1 < n_chunks) fetch_chunk(a, cidx + 1, pf);
+    const u32x4 *w = wbuf[cidx & 1];
     f32x4 c[kPolR][kPolNT];
 #pragma unroll
     for (int r = 0; r < kPolR; ++r) {
@@ -189,13 +240,15 @@ __global__ __launch_bounds__(64 * kPolWaves) void k_policy(PolicyArgs a) {
 #pragma unroll
         for (int r = 0; r < kPolR; ++r) {
           if (r < a.R) {
-            const u32x4 w = gld(a.w2f, ((int64_t)(grp * a.R + r) * a.HP + s) * 64 + lane);
+            const u32x4 wf = w[(r * a.HP + s) * 64 + lane];
 #pragma unroll
-            for (int n = 0; n < kPolNT; ++n) c[r][n] = mfma(w, h[s][n], c[r][n]);
+            for (int n = 0; n < kPolNT; ++n) c[r][n] = mfma(wf, h[s][n], c[r][n]);
           }
         }
       }
     }
+    if (cidx + 1 < n_chunks) put_chunk(a, cidx + 1, pf, wbuf[(cidx + 1) & 1]);
+    __syncthreads();
     const int port = 4 * grp + lg;
 #pragma unroll
     for (int n = 0; n < kPolNT; ++n) {
@@ -218,8 +271,8 @@ __global__ __launch_bounds__(64 * kPolWaves) void k_policy(PolicyArgs a) {
 #pragma unroll
         for (int r = 0; r < kPolR; ++r) {
           if (r < a.R) {
-            const U4 w = philox((uint32_t)(a.env0 + e), a.g, (uint32_t)(port * a.R + r), kDomGum, k0, k1);
-            const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+            const U4 w4 = philox((uint32_t)(a.env0 + e), a.g, (uint32_t)(port * a.R + r), kDomGum, k0, k1);
+            const uint32_t ws[4] = {w4.x, w4.y, w4.z, w4.w};
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
               const int lev = 4 * r + i;

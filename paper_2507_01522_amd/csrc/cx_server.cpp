@@ -59,6 +59,7 @@ struct Req {
   bool cancel = false;
   int32_t launched = 0;          // steps handed to the GPU
   int32_t retired = 0;           // steps whose chunk finished
+  bool admitted = false;         // holds its bytes of the budget until released
   int inflight = 0;
   uint32_t g = 0;
   int32_t t_day = 0;
@@ -226,6 +227,7 @@ bool admit(cx_server *s) {
       class_block(r.spec, r.comp, r.tab, nullptr, nullptr, &r.view);
     }
     s->used += r.total;
+    r.admitted = true;
     r.state = RState::Active;
     r.admit_s = s->now();
     s->active.push_back(r.ticket);
@@ -497,10 +499,8 @@ cx_status cx_release(cx_server *s, uint64_t ticket) {
   if (it == s->reqs.end()) return fail(CX_E_NOTFOUND, "unknown ticket");
   Req &r = *it->second;
   if (!finished(r)) return fail(CX_E_BUSY, "request still queued or running");
-  if (r.admit_s > 0 || r.mem) {
-    if (r.mem) (void)hipFreeAsync(r.mem, s->stream);  // ordered after every chunk that used it
-    if (r.admit_s > 0) s->used -= r.total;
-  }
+  if (r.mem) (void)hipFreeAsync(r.mem, s->stream);  // ordered after every chunk that used it
+  if (r.admitted) s->used -= r.total;
   s->reqs.erase(it);
   s->cv_work.notify_all();
   return CX_OK;

@@ -126,6 +126,23 @@ def check(st: int):
         raise CxError(st, lib().cx_last_error().decode(errors="replace"))
 
 
+_hip = None
+
+
+def _hip_copy_to_host(dst: np.ndarray, src_ptr):
+    """Synchronous device-to-host copy of a raw device pointer (server-owned buffers)."""
+    global _hip
+    if _hip is None:
+        _hip = C.CDLL("libamdhip64.so")
+        _hip.hipMemcpy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
+        _hip.hipMemcpy.restype = C.c_int
+    if not src_ptr:
+        raise CxError(-1, "record not produced by this request")
+    st = _hip.hipMemcpy(dst.ctypes.data, src_ptr, dst.nbytes, 2)  # hipMemcpyDeviceToHost
+    if st != 0:
+        raise CxError(-3, f"hipMemcpy failed ({st})")
+
+
 def _p(t: Optional[torch.Tensor]):
     return None if t is None else C.c_void_p(t.data_ptr())
 
@@ -391,6 +408,23 @@ class Server:
     def release(self, ticket: int):
         check(lib().cx_release(self.h, ticket))
         self._keep.pop(ticket, None)
+
+    @staticmethod
+    def fetch(res: ResultC, out_mode: int, n_ports: int) -> Dict[str, np.ndarray]:
+        """Copy the records of a finished request (server-owned or caller buffers)
+        to host arrays shaped like Env.alloc_traj."""
+        E, T = int(res.n_envs), int(res.T)
+        want = {"reward": (np.float32, (T, E), res.traj.reward), "done": (np.uint8, (T, E), res.traj.done)}
+        if out_mode == OUT_FULL:
+            want["obs"] = (np.float32, (T, E * (6 * n_ports + 4)), res.traj.obs)
+        if out_mode in (OUT_FULL, OUT_ACT_REWARD):
+            want["actions"] = (np.uint8, (T, E * n_ports), res.traj.actions)
+        out = {}
+        for k, (dt, shape, ptr) in want.items():
+            a = np.empty(shape, dtype=dt)
+            _hip_copy_to_host(a, ptr)
+            out[k] = a
+        return out
 
     def stats(self) -> Dict[str, float]:
         b = C.c_double()
