@@ -1,15 +1,20 @@
-"""Benchmark: batched persistent rollouts of uneven stations on one MI355X.
+"""Benchmark of batched EV charging-station rollouts on one MI355X.
 
-Workload (the uneven-batching configuration): 65,536 stations whose port counts
-are drawn from {8, 16, 32, 64, 128} with probabilities {.3, .3, .2, .15, .05},
-capacity trees 1-3 levels deep (fan-out 4, limits 0.7x the children's maxima),
-288 five-minute steps, Philox random levels, every per-step record written
+Default workload (uneven batching): 65,536 stations whose port counts are drawn
+from {8, 16, 32, 64, 128} with probabilities {.3, .3, .2, .15, .05}, capacity
+trees 1-3 levels deep (fan-out 4, limits 0.7x the children's maxima), 288
+five-minute steps, Philox random levels, every per-step record written
 (observations, levels, rewards, done flags).  One bench "step" = one rollout of
 all stations over all 288 steps in one persistent, graph-replayed launch.
 
-Prints one JSON line: env-steps/s, the HBM roofline of the rollout kernel, the
-plain one-launch-per-step form on the same GPU, and the FP64 oracle on the
-host's cores as the CPU baseline.
+Other workloads (--workload): tiny (64 stations of 16 ports, the parity case),
+scale (4,096 stations on a two-level tree, persistent vs one launch per step),
+policy (1,048,576 stations of 32 ports, levels from the BF16 perceptron on the
+matrix cores), serve (a Poisson stream of rollout requests through the
+continuous-batching server).
+
+Prints one JSON line: the throughput, the roofline of the dominant kernel, and
+the FP64 oracle on the host's cores as the CPU baseline.
 """
 from __future__ import annotations
 
@@ -17,6 +22,7 @@ import argparse
 import json
 import os
 import sys
+import threading
 import time
 
 import numpy as np
@@ -25,13 +31,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-N_ENVS = 65536
-T = 288
+BF16_PEAK_TFLOPS = 2500.0
+T_DAY = 288
 
 
-def record_bytes(n_ports: np.ndarray) -> np.ndarray:
-    """Bytes of one FULL record per env-step: obs (6N+4) f32, N levels, reward f32, done u8."""
-    return 4 * (6 * n_ports + 4) + n_ports + 4 + 1
+def record_bytes(n_ports: np.ndarray, out_mode: str = "full") -> np.ndarray:
+    """Bytes of one record per env-step: obs (6N+4) f32, N levels, reward f32, done u8."""
+    if out_mode == "full":
+        return 4 * (6 * n_ports + 4) + n_ports + 4 + 1
+    if out_mode == "act_reward":
+        return n_ports + 4 + 1
+    return np.full_like(n_ports, 4 + 1)
 
 
 def state_bytes(n_ports: np.ndarray) -> np.ndarray:
@@ -41,8 +51,8 @@ def state_bytes(n_ports: np.ndarray) -> np.ndarray:
 
 
 def measured_traffic():
-    """HBM bytes of one rollout from the committed counter profile, if it was taken
-    on the current kernel source (None otherwise)."""
+    """HBM bytes of one default rollout from the committed counter profile, if it
+    was taken on the current kernel source (None otherwise)."""
     import hashlib
     try:
         prof = json.load(open(os.path.join(ROOT, "profiles", "k_rollout_traffic.json")))
@@ -54,32 +64,293 @@ def measured_traffic():
     return float(prof["traffic_bytes"])
 
 
-def workload():
+def uneven_workload():
     import workloads as W
     classes = W.mixture_classes()
-    ec_full = W.mixture_env_classes(N_ENVS, seed=1003)
-    specs, ec = W.compact_classes(classes, ec_full)
-    return specs, ec
+    ec_full = W.mixture_env_classes(65536, seed=1003)
+    return W.compact_classes(classes, ec_full)
 
 
-def cpu_baseline(specs, ec, seed):
+def oracle_baseline(specs, ec, seed, T, stride, chunk=16, mode=1, act_in=None):
     """The FP64 oracle on a bounded, evenly spaced sample of the same stations."""
     from oracle import oracle as o
-    stride = 8
     ids = np.arange(0, len(ec), stride, dtype=np.int64)
     classes = [o.OracleClass(s) for s in specs]
-    bs = o.BatchState(classes, ec[ids], env_ids=ids)
+    bs = o.BatchState(classes, np.asarray(ec)[ids], env_ids=ids)
     threads = max(1, min(16, os.cpu_count() or 1))
-    chunk = 16
     t0 = time.perf_counter()
     used = 1
-    for _ in range(T // chunk):
-        out = o.rollout(bs, seed, chunk, n_threads=threads)
+    for _ in range(max(1, T // chunk)):
+        out = o.rollout(bs, seed, min(chunk, T), mode=mode, n_threads=threads)
         used = out["threads"]
     dt = time.perf_counter() - t0
-    return {"value": len(ids) * T / dt, "unit": "env-steps/s", "cores": int(used), "kind": "oracle",
-            "sample": f"{len(ids)} of {len(ec)} stations (every {stride}th), all {T} steps, FP64, "
+    steps = max(1, T // chunk) * min(chunk, T)
+    return {"value": len(ids) * steps / dt, "unit": "env-steps/s", "cores": int(used), "kind": "oracle",
+            "sample": f"{len(ids)} of {len(ec)} stations (every {stride}th), {steps} steps, FP64, "
                       f"all outputs, {used} threads, {dt:.1f} s"}
+
+
+def time_events(fn, reps, stream):
+    """Mean milliseconds of fn() between HIP events on ``stream`` (after one warm-up)."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in ev:
+        a.record(stream)
+        fn()
+        b.record(stream)
+    torch.cuda.synchronize()
+    return float(np.mean([a.elapsed_time(b) for a, b in ev]))
+
+
+def base_line(metric, value, unit, args, ms_per_step, config, dtype="f32"):
+    return {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config}
+
+
+def timed_rollouts(env, cx, T, mode, out_mode, out, args):
+    """W untimed + K timed rollouts; returns (wall ms per rollout, event ms per rollout)."""
+    import torch
+    stream = env.stream
+    for _ in range(args.warmup):
+        env.rollout(T, mode, out_mode, out=out)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record(stream)
+        env.rollout(T, mode, out_mode, out=out)
+        b.record(stream)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3 / args.steps
+    return wall, float(np.mean([a.elapsed_time(b) for a, b in ev]))
+
+
+def plain_rate(env, cx, n_envs, T, reps=2):
+    """The same rollout as T one-step launches (state through HBM every step)."""
+    import torch
+    out1 = env.alloc_traj(1, cx.OUT_FULL)
+    for _ in range(8):
+        env.step(cx.ACT_RANDOM, out=out1)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(reps * T):
+        env.step(cx.ACT_RANDOM, out=out1)
+    torch.cuda.synchronize()
+    p_ms = (time.perf_counter() - t1) * 1e3 / reps
+    return {"ms_per_rollout": p_ms, "env_steps_per_s": n_envs * T / (p_ms / 1e3), "launches_per_rollout": T}
+
+
+# ---------------------------------------------------------------------------
+def run_rollout_workload(args, name, specs, ec, seed, desc, cpu_stride):
+    import torch  # noqa: F401
+    import paper_2507_01522_amd as cx
+    n_ports = np.array([s.n_ports for s in specs])[ec]
+    n_envs = len(ec)
+    env = cx.Env(specs, env_class=ec, seed=seed) if len(specs) > 1 else cx.Env(specs[0], n_envs=n_envs, seed=seed)
+    if not args.no_tune:
+        env.autotune(32, os.path.join(ROOT, "gpurun_out", "autotune_cache.json")
+                     if os.path.isdir(os.path.join(ROOT, "gpurun_out")) else None)
+    out = env.alloc_traj(T_DAY, cx.OUT_FULL)
+    wall_ms, kernel_ms = timed_rollouts(env, cx, T_DAY, cx.ACT_RANDOM, cx.OUT_FULL, out, args)
+    env_steps = n_envs * T_DAY
+    value = env_steps / (wall_ms / 1e3)
+    alg_bytes = float((record_bytes(n_ports) * T_DAY + 2 * state_bytes(n_ports)).sum())
+    achieved = alg_bytes / (kernel_ms / 1e3) / 1e9
+    del out
+    # records of rewards and done flags only (the same rollout, 5 bytes per env-step)
+    out_r = env.alloc_traj(T_DAY, cx.OUT_REWARD)
+    r_wall, r_kernel = timed_rollouts(env, cx, T_DAY, cx.ACT_RANDOM, cx.OUT_REWARD, out_r, args)
+    del out_r
+    plain = None if args.no_plain else plain_rate(env, cx, n_envs, T_DAY)
+    cpu = None if args.no_cpu else oracle_baseline(specs, ec, seed, T_DAY, cpu_stride)
+    ci = [env.class_info(c) for c in range(len(specs))]
+    line = base_line(f"env-steps/s (batched persistent rollout, {desc})", value, "env-steps/s", args, wall_ms,
+                     {"workload": name, "n_envs": n_envs, "T": T_DAY, "mean_ports": float(n_ports.mean()),
+                      "packing": {f"N{c.n_ports}d{c.levels}": c.lanes_per_station for c in ci},
+                      "waves_per_block": ci[0].waves_per_block})
+    line["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": achieved / HBM_PEAK_GBS,
+                        "traffic": measured_traffic() if name.startswith("uneven") else None,
+                        "kernel": "k_rollout", "kernel_ms": kernel_ms, "algorithmic_bytes": alg_bytes}
+    line["reward_only"] = {"env_steps_per_s": env_steps / (r_wall / 1e3), "kernel_ms": r_kernel,
+                           "algorithmic_bytes": float((record_bytes(n_ports, "reward") * T_DAY
+                                                       + 2 * state_bytes(n_ports)).sum())}
+    line["plain"] = plain
+    line["speedup_vs_plain"] = (value / plain["env_steps_per_s"]) if plain else None
+    line["cpu_baseline"] = cpu
+    return line
+
+
+def run_uneven(args):
+    specs, ec = uneven_workload()
+    return run_rollout_workload(
+        args, "uneven-batching: 65536 stations x 288 steps, ports {8..128} mix, trees depth 1-3, random "
+              "levels, full records", specs, ec, 3, "uneven stations", 8)
+
+
+def run_tiny(args):
+    import workloads as W
+    return run_rollout_workload(args, "tiny: 64 stations x 288 steps, 16 ports under 150 kW, random levels, "
+                                      "full records", [W.tiny_parity_station()], np.zeros(64, np.int32), 1,
+                                "64 stations", 1)
+
+
+def run_scale(args):
+    import workloads as W
+    return run_rollout_workload(args, "scale: 4096 stations x 288 steps, 4 splitters x 4 ports of 22 kW, "
+                                      "random levels, full records", [W.scale_station()],
+                                np.zeros(4096, np.int32), 2, "4096 stations", 4)
+
+
+def run_policy(args):
+    """Policy in the loop: per step the perceptron samples every port's level,
+    then the one-step environment kernel applies them."""
+    import torch
+    import paper_2507_01522_amd as cx
+    import workloads as W
+    spec = W.policy_station()
+    E, H, seed = 1 << 20, 256, 5
+    N, dim = spec.n_ports, spec.obs_dim
+    weights = W.policy_weights(N, hidden=H)
+    env = cx.Env(spec, n_envs=E, seed=seed)
+    env.set_policy(H, weights)
+    if not args.no_tune:
+        env.autotune(1)   # one-step launches: the packing that suits them
+    out = env.alloc_traj(T_DAY, cx.OUT_ACT_REWARD)
+    wall_ms, ev_ms = timed_rollouts(env, cx, T_DAY, cx.ACT_POLICY, cx.OUT_ACT_REWARD, out, args)
+    value = E * T_DAY / (wall_ms / 1e3)
+    # the two kernels of a step, each timed alone in the launch shape the rollout uses
+    obs = env.observe().view(E, dim)
+    act = torch.empty((E, N), dtype=torch.uint8, device=env.device)
+    pol_ms = time_events(lambda: env.policy_sample(obs, 7, act), 10, env.stream)
+    out1 = env.alloc_traj(1, cx.OUT_FULL)
+    step_ms = time_events(lambda: env.step(cx.ACT_EXTERNAL, act.view(-1), out=out1), 10, env.stream)
+    flops = 2.0 * E * (dim * H + H * N * (spec.n_levels + 1))
+    achieved = flops / (pol_ms / 1e3) / 1e12
+    step_bytes = float(E * (2 * state_bytes(np.array([N]))[0] + N + 4 * dim + 4 + 1))
+    cpu = None
+    if not args.no_cpu:
+        cpu = policy_oracle_baseline(spec, H, weights, seed)
+    ci = env.class_info(0)
+    line = base_line("env-steps/s (policy-in-the-loop rollout)", value, "env-steps/s", args, wall_ms,
+                     {"workload": "policy: 1048576 stations x 288 steps, 32 ports (8 splitters x 4 under "
+                                  "400 kW), MLP 196-256-352 BF16, Gumbel-max levels, levels+rewards",
+                      "n_envs": E, "T": T_DAY, "hidden": H, "packing": ci.lanes_per_station}, dtype="bf16")
+    line["roofline"] = {"bound": "mfma", "achieved": achieved, "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": achieved / BF16_PEAK_TFLOPS, "traffic": None, "kernel": "k_policy",
+                        "kernel_ms": pol_ms, "algorithmic_flops": flops}
+    line["step_kernel"] = {"kernel": "k_rollout (one step, external levels)", "kernel_ms": step_ms,
+                           "achieved_GBps": step_bytes / (step_ms / 1e3) / 1e9, "algorithmic_bytes": step_bytes}
+    line["rollout_event_ms"] = ev_ms
+    line["cpu_baseline"] = cpu
+    return line
+
+
+def policy_oracle_baseline(spec, H, weights, seed, n_envs=64, T=32):
+    """The oracle's policy and transition, one env-step at a time, on 64 stations."""
+    from oracle import oracle as o
+    c = o.OracleClass(spec)
+    N = spec.n_ports
+    bs = o.BatchState([c], np.zeros(n_envs, np.int32))
+    t0 = time.perf_counter()
+    st = o.EnvState(N)
+    obs = np.stack([c.observe(st)] * n_envs)
+    for t in range(T):
+        act = np.stack([c.policy(H, weights, obs[e], seed, e, t)[1] for e in range(n_envs)]).astype(np.uint8)
+        out = o.rollout(bs, seed, 1, mode=0, act_in=act.reshape(1, -1), n_threads=1)
+        obs = out["obs"].reshape(n_envs, -1)
+    dt = time.perf_counter() - t0
+    return {"value": n_envs * T / dt, "unit": "env-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n_envs} stations x {T} steps of the policy workload, FP64 perceptron + step, "
+                      f"1 thread, {dt:.1f} s"}
+
+
+def run_serve(args):
+    """A Poisson stream of rollout requests (log-uniform sizes 64..8192 stations,
+    horizons {96, 288, 2016}, classes of the uneven mixture, full records) at
+    0.7x the measured saturated request rate, 200 GB budget."""
+    import paper_2507_01522_amd as cx
+    import workloads as W
+    classes = W.mixture_classes()
+    budget = 200 << 30
+
+    def serve(reqs, paced):
+        srv = cx.Server(budget, chunk_steps=32)
+        lat, admit_wait = [], []
+        done = []
+        lock = threading.Lock()
+        tickets = []
+
+        def drain():
+            i = 0
+            while True:
+                with lock:
+                    if i >= len(tickets):
+                        if len(done) == len(reqs):
+                            return
+                        tk = None
+                    else:
+                        tk = tickets[i]
+                if tk is None:
+                    time.sleep(0.0005)
+                    continue
+                r = srv.wait(tk)
+                lat.append(r.done_s - r.submit_s)
+                admit_wait.append(r.admit_s - r.submit_s)
+                srv.release(tk)
+                with lock:
+                    done.append(tk)
+                i += 1
+
+        th = threading.Thread(target=drain)
+        th.start()
+        t0 = time.perf_counter()
+        for rq in reqs:
+            if paced:
+                d = rq.arrival_s - (time.perf_counter() - t0)
+                if d > 0:
+                    time.sleep(d)
+            tk = srv.submit(classes[rq.class_index], rq.n_envs, rq.horizon, rq.seed, cx.OUT_FULL)
+            with lock:
+                tickets.append(tk)
+        th.join()
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+        srv.close()
+        return wall, st, np.array(lat), np.array(admit_wait)
+
+    # saturated: a burst of requests submitted at once
+    burst = W.request_stream(200, 1e9, seed=2001)
+    serve(W.request_stream(20, 1e9, seed=2002), False)          # warm-up (allocator, code objects)
+    wall_s, st_s, _, _ = serve(burst, False)
+    steps_s = sum(r.n_envs * r.horizon for r in burst)
+    sat_rate = len(burst) / wall_s
+    rate = 0.7 * sat_rate
+    stream = W.request_stream(1000, rate, seed=2000)
+    wall, st, lat, wq = serve(stream, True)
+    env_steps = sum(r.n_envs * r.horizon for r in stream)
+    rec = {c: record_bytes(np.array([classes[c].n_ports]))[0] for c in range(len(classes))}
+    alg = float(sum(r.n_envs * (r.horizon * rec[r.class_index] + 2 * state_bytes(np.array([classes[r.class_index].n_ports]))[0])
+                    for r in stream))
+    value = env_steps / wall
+    line = base_line("env-steps/s (continuous-batching server, Poisson request stream)", value, "env-steps/s",
+                     args, wall * 1e3,
+                     {"workload": "serve: 1000 Poisson requests at 0.7x saturated rate, 64..8192 stations, "
+                                  "T in {96,288,2016}, uneven classes, full records, 200 GB budget",
+                      "rate_req_per_s": rate, "saturated_req_per_s": sat_rate,
+                      "saturated_env_steps_per_s": steps_s / wall_s, "chunk_steps": 32})
+    line["latency_s"] = {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                         "queue_p50": float(np.percentile(wq, 50)), "queue_p99": float(np.percentile(wq, 99))}
+    line["server"] = st
+    line["roofline"] = {"bound": "hbm", "achieved": alg / st["busy_s"] / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": alg / st["busy_s"] / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                        "kernel": "k_rollout (per-segment chunks)", "kernel_ms": st["busy_s"] * 1e3,
+                        "algorithmic_bytes": alg}
+    line["cpu_baseline"] = None
+    return line
 
 
 def main():
@@ -87,6 +358,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="uneven", choices=["uneven", "tiny", "scale", "policy", "serve"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain per-step comparison")
     ap.add_argument("--no-tune", action="store_true")
@@ -99,8 +371,6 @@ def main():
         sys.exit(2)
 
     import torch
-    import paper_2507_01522_amd as cx
-
     if args.calib_copy:
         src = torch.empty(1 << 29, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -110,76 +380,9 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    seed = 3
-    specs, ec = workload()
-    n_ports = np.array([s.n_ports for s in specs])[ec]
-    env = cx.Env(specs, env_class=ec, seed=seed)
-    if not args.no_tune:
-        env.autotune(32, os.path.join(ROOT, "gpurun_out", "autotune_cache.json")
-                     if os.path.isdir(os.path.join(ROOT, "gpurun_out")) else None)
-    out = env.alloc_traj(T, cx.OUT_FULL)
-    stream = env.stream
-    for _ in range(args.warmup):
-        env.rollout(T, cx.ACT_RANDOM, cx.OUT_FULL, out=out)
-    torch.cuda.synchronize()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-    t0 = time.perf_counter()
-    for a, b in ev:
-        a.record(stream)
-        env.rollout(T, cx.ACT_RANDOM, cx.OUT_FULL, out=out)
-        b.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    kernel_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
-    ms_per_step = wall * 1e3 / args.steps
-    env_steps = N_ENVS * T
-    value = env_steps / (ms_per_step / 1e3)
-    alg_bytes = float((record_bytes(n_ports) * T + 2 * state_bytes(n_ports)).sum())
-    achieved = alg_bytes / (kernel_ms / 1e3) / 1e9
-
-    plain = None
-    if not args.no_plain:
-        out1 = env.alloc_traj(1, cx.OUT_FULL)
-        for _ in range(8):
-            env.step(cx.ACT_RANDOM, out=out1)
-        torch.cuda.synchronize()
-        reps = 2
-        t1 = time.perf_counter()
-        for _ in range(reps * T):
-            env.step(cx.ACT_RANDOM, out=out1)
-        torch.cuda.synchronize()
-        p_ms = (time.perf_counter() - t1) * 1e3 / reps
-        plain = {"ms_per_rollout": p_ms, "env_steps_per_s": env_steps / (p_ms / 1e3),
-                 "launches_per_rollout": T}
-
-    cpu = None if args.no_cpu else cpu_baseline(specs, ec, seed)
-    ci = [env.class_info(c) for c in range(len(specs))]
-    line = {
-        "metric": "env-steps/s (batched persistent rollout, uneven stations)",
-        "value": value,
-        "unit": "env-steps/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": "uneven-batching: 65536 stations x 288 steps, ports {8..128} mix, "
-                               "trees depth 1-3, random levels, full records",
-                   "n_envs": N_ENVS, "T": T, "mean_ports": float(n_ports.mean()),
-                   "packing": {f"N{c.n_ports}d{c.levels}": c.lanes_per_station for c in ci},
-                   "waves_per_block": ci[0].waves_per_block},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                     "kernel": "k_rollout", "kernel_ms": kernel_ms, "algorithmic_bytes": alg_bytes},
-        "plain": plain,
-        "speedup_vs_plain": (value / plain["env_steps_per_s"]) if plain else None,
-        "cpu_baseline": cpu,
-    }
-    print(json.dumps(line))
+    run = {"uneven": run_uneven, "tiny": run_tiny, "scale": run_scale, "policy": run_policy,
+           "serve": run_serve}[args.workload]
+    print(json.dumps(run(args)))
 
 
 if __name__ == "__main__":

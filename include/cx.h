@@ -180,7 +180,11 @@ cx_status cx_step_ex(cx_ctx *ctx, cx_action_mode mode, const uint8_t *actions_in
  * registers for all T steps and streams the records selected by out_mode to
  * *out.  actions_in_dev ([T][total_ports] uint8) is read only for EXTERNAL.
  * The launch is captured once per (T, modes, buffers) into a HIP graph and
- * replayed.  Results equal T calls of cx_step_ex. */
+ * replayed.  Results equal T calls of cx_step_ex.
+ * CX_ACT_POLICY instead runs, per step, the policy kernel (observation ->
+ * levels, cx_policy_sample) and then the one-step kernel with those levels;
+ * the observations in between stay in a scratch buffer of the context unless
+ * out_mode is FULL.  Requires cx_set_policy. */
 cx_status cx_rollout(cx_ctx *ctx, int32_t T, cx_action_mode mode, cx_out_mode out_mode,
                      const uint8_t *actions_in_dev, const cx_traj *out);
 
@@ -196,6 +200,12 @@ cx_status cx_set_policy(cx_ctx *ctx, int32_t hidden, const uint16_t *w1_host, co
 /* Logits of the policy for n observations (obs_dev [n][obs_dim] float) into
  * logits_dev [n][n_ports*(n_levels+1)] float: the policy's first half alone. */
 cx_status cx_policy_logits(cx_ctx *ctx, const float *obs_dev, int64_t n, float *logits_dev);
+
+/* Levels the policy samples for n observations (obs_dev [n][obs_dim] float,
+ * 16-byte aligned) at global step g: act_dev [n][n_ports] uint8, Gumbel noise
+ * from Philox counters (env_begin + i, g, ...) of the context's seed -- the
+ * policy half of a CX_ACT_POLICY step, exactly as a rollout launches it. */
+cx_status cx_policy_sample(cx_ctx *ctx, const float *obs_dev, int64_t n, uint32_t g, uint8_t *act_dev);
 
 /* Observation of the current state of every station (the record layout of
  * cx_traj.obs for one step, Sec. 3 state features): what a policy sees before

@@ -194,6 +194,7 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
 
   // ---- state
   double q[P];
+  float qf[P];  // (float) q, kept in step with q: the FP32 work reads it
   float u[P], cap[P], icap[P], plast[P];
   int dw[P];
   const int64_t sofs = (int64_t)env * S;
@@ -201,6 +202,7 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
   for (int j = 0; j < P; ++j) {
     const int64_t i = sofs + j * L + l;
     q[j] = active ? sg.q[i] : 0.0;
+    qf[j] = (float)q[j];
     u[j] = active ? sg.u[i] : 0.f;
     cap[j] = active ? sg.cap[i] : 0.f;
     plast[j] = active ? sg.p_last[i] : 0.f;
@@ -295,10 +297,9 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
     float pw[P];
 #pragma unroll
     for (int j = 0; j < P; ++j) {
-      const float qf = (float)q[j];
       const float req = (float)k[j] * C.inv_n_levels * pmax[j];
-      const float rhat = pmax[j] * fminf(1.0f, qf * C.inv_1mtau);
-      const float room = qf * cap[j] * C.inv_dt;
+      const float rhat = pmax[j] * fminf(1.0f, qf[j] * C.inv_1mtau);
+      const float room = qf[j] * cap[j] * C.inv_dt;
       pw[j] = dw[j] > 0 ? fminf(fminf(req, rhat), room) : 0.0f;
     }
 
@@ -375,12 +376,14 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
       const float e = C.dt * pw[j];
       const double nq = q[j] - (double)(e * icap[j]);
       q[j] = nq > 0.0 ? nq : 0.0;
+      qf[j] = (float)q[j];
       plast[j] = pw[j];
       dw[j] -= occ ? 1 : 0;
       const bool dep = occ && dw[j] == 0;
-      const float miss = fmaxf(0.0f, (float)((q[j] - (double)u[j]) * (double)cap[j]));
+      const float miss = fmaxf(0.0f, (qf[j] - u[j]) * cap[j]);
       csat += dep ? miss : 0.0f;
       q[j] = dep ? 0.0 : q[j];
+      qf[j] = dep ? 0.0f : qf[j];
       u[j] = dep ? 0.f : u[j];
       cap[j] = dep ? 0.f : cap[j];
       icap[j] = dep ? 0.f : icap[j];
@@ -424,6 +427,7 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
           cap[j] = cp;
           icap[j] = frcp(cp);
           q[j] = 1.0 - (double)s0;
+          qf[j] = 1.0f - s0;  // the same rounding as (float) q
           u[j] = 1.0f - tg;
           plast[j] = 0.f;
         }
@@ -444,7 +448,7 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
       t_day = 0;
 #pragma unroll
       for (int j = 0; j < P; ++j) {
-        dw[j] = 0; q[j] = 0.0; u[j] = 0.f; cap[j] = 0.f; icap[j] = 0.f; plast[j] = 0.f;
+        dw[j] = 0; q[j] = 0.0; qf[j] = 0.f; u[j] = 0.f; cap[j] = 0.f; icap[j] = 0.f; plast[j] = 0.f;
       }
     }
 
@@ -458,10 +462,10 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
             const bool occ = dw[j] > 0;
             const uint32_t o = obs_bo + 4u * (uint32_t)port[j];
             st_at(ob, o + 0u * 4u * N, occ ? 1.0f : 0.0f);
-            st_at(ob, o + 1u * 4u * N, occ ? (float)(1.0 - q[j]) : 0.0f);
-            st_at(ob, o + 2u * 4u * N, occ ? (float)(q[j] - (double)u[j]) : 0.0f);
+            st_at(ob, o + 1u * 4u * N, occ ? 1.0f - qf[j] : 0.0f);
+            st_at(ob, o + 2u * 4u * N, occ ? qf[j] - u[j] : 0.0f);
             st_at(ob, o + 3u * 4u * N, (float)dw[j] * C.inv_steps_ep);
-            st_at(ob, o + 4u * 4u * N, occ ? fminf(1.0f, (float)q[j] * C.inv_1mtau) : 0.0f);
+            st_at(ob, o + 4u * 4u * N, occ ? fminf(1.0f, qf[j] * C.inv_1mtau) : 0.0f);
             st_at(ob, o + 5u * 4u * N, plast[j] * inv_pmax[j]);
           }
         }

@@ -224,7 +224,26 @@ __global__ __launch_bounds__(64 * kPolWaves) void k_policy(PolicyArgs a) {
   const int out_dim = a.N * a.L1;
   for (int grp = 0; grp < a.G; ++grp) {
     const int cidx = a.HP + grp;
+    const int port = 4 * grp + lg;
     if (cidx + 1 < n_chunks) fetch_chunk(a, cidx + 1, pf);
+    // Gumbel noise of this group's levels: independent of the products, so it
+    // is computed in the same straight-line block as the matrix-core work and
+    // the two overlap (lanes past the last env or port compute unused noise)
+    float gn[kPolR][kPolNT][4];
+#pragma unroll
+    for (int n = 0; n < kPolNT; ++n) {
+      const uint32_t env_id = (uint32_t)(a.env0 + e_base + 16 * n + col);
+#pragma unroll
+      for (int r = 0; r < kPolR; ++r) {
+        if (r < a.R) {
+          const U4 w4 = philox(env_id, a.g, (uint32_t)(port * a.R + r), kDomGum, k0, k1);
+          gn[r][n][0] = gumbel(w4.x);
+          gn[r][n][1] = gumbel(w4.y);
+          gn[r][n][2] = gumbel(w4.z);
+          gn[r][n][3] = gumbel(w4.w);
+        }
+      }
+    }
     const u32x4 *w = wbuf[cidx & 1];
     f32x4 c[kPolR][kPolNT];
 #pragma unroll
@@ -249,7 +268,6 @@ __global__ __launch_bounds__(64 * kPolWaves) void k_policy(PolicyArgs a) {
     }
     if (cidx + 1 < n_chunks) put_chunk(a, cidx + 1, pf, wbuf[(cidx + 1) & 1]);
     __syncthreads();
-    const int port = 4 * grp + lg;
 #pragma unroll
     for (int n = 0; n < kPolNT; ++n) {
       const int64_t e = e_base + 16 * n + col;
@@ -270,18 +288,14 @@ __global__ __launch_bounds__(64 * kPolWaves) void k_policy(PolicyArgs a) {
         float bv = -__builtin_inff();
 #pragma unroll
         for (int r = 0; r < kPolR; ++r) {
-          if (r < a.R) {
-            const U4 w4 = philox((uint32_t)(a.env0 + e), a.g, (uint32_t)(port * a.R + r), kDomGum, k0, k1);
-            const uint32_t ws[4] = {w4.x, w4.y, w4.z, w4.w};
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              const int lev = 4 * r + i;
-              if (lev < a.L1) {
-                const float v = c[r][n][i] + gumbel(ws[i]);
-                if (v > bv) {
-                  bv = v;
-                  best = lev;
-                }
+          for (int i = 0; i < 4; ++i) {
+            const int lev = 4 * r + i;
+            if (r < a.R && lev < a.L1) {
+              const float v = c[r][n][i] + gn[r][n][i];
+              if (v > bv) {
+                bv = v;
+                best = lev;
               }
             }
           }
@@ -306,13 +320,13 @@ __global__ void k_observe(const ClassDev *cls, int64_t n_envs, const double *q, 
     if (port < 0) continue;
     const int dw = dwell[i];
     const bool occ = dw > 0;
-    const double qq = q[i];
+    const float qf = (float)q[i];
     float *o = obs + env * dim + port;
     o[0 * N] = occ ? 1.0f : 0.0f;
-    o[1 * N] = occ ? (float)(1.0 - qq) : 0.0f;
-    o[2 * N] = occ ? (float)(qq - (double)u[i]) : 0.0f;
+    o[1 * N] = occ ? 1.0f - qf : 0.0f;
+    o[2 * N] = occ ? qf - u[i] : 0.0f;
     o[3 * N] = (float)dw * C.inv_steps_ep;
-    o[4 * N] = occ ? fminf(1.0f, (float)qq * C.inv_1mtau) : 0.0f;
+    o[4 * N] = occ ? fminf(1.0f, qf * C.inv_1mtau) : 0.0f;
     o[5 * N] = p_last[i] * C.slot_inv_pmax[s];
   }
   for (int64_t env = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; env < n_envs;
@@ -546,6 +560,23 @@ cx_status cx_policy_logits(cx_ctx *ctx, const float *obs_dev, int64_t n, float *
   a.logits = logits_dev;
   hipError_t e = launch_policy(a, ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "cx_policy_logits launch");
+  return CX_OK;
+}
+
+cx_status cx_policy_sample(cx_ctx *ctx, const float *obs_dev, int64_t n, uint32_t g, uint8_t *act_dev) {
+  if (!ctx) return fail_status(CX_E_INVALID, "context is NULL");
+  if (ctx->failed) return fail_status(CX_E_DEVICE, "context has a sticky device error");
+  if (!ctx->policy) return fail_status(CX_E_INVALID, "no policy set (cx_set_policy)");
+  if (n < 0) return fail_status(CX_E_INVALID, "cx_policy_sample: n < 0");
+  if (n > 0 && (!obs_dev || !act_dev)) return fail_status(CX_E_INVALID, "cx_policy_sample: NULL buffer");
+  if (n > 0 && (reinterpret_cast<uintptr_t>(obs_dev) & 15u) != 0)
+    return fail_status(CX_E_INVALID, "cx_policy_sample: obs_dev must be 16-byte aligned");
+  if (n == 0) return CX_OK;
+  PolicyArgs a = policy_args(ctx, obs_dev, n);
+  a.g = g;
+  a.act = act_dev;
+  hipError_t e = launch_policy(a, ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "cx_policy_sample launch");
   return CX_OK;
 }
 

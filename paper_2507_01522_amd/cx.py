@@ -77,7 +77,8 @@ class ResultC(C.Structure):
 
 
 EXPORTS = ["cx_create", "cx_create_multi", "cx_set_stream", "cx_get_info", "cx_get_class_info", "cx_reset",
-           "cx_step", "cx_step_ex", "cx_rollout", "cx_set_policy", "cx_policy_logits", "cx_observe", "cx_get_state",
+           "cx_step", "cx_step_ex", "cx_rollout", "cx_set_policy", "cx_policy_logits", "cx_policy_sample", "cx_observe",
+           "cx_get_state",
            "cx_set_state", "cx_get_tables", "cx_set_packing", "cx_autotune", "cx_synchronize",
            "cx_last_error", "cx_destroy", "cx_server_create", "cx_submit", "cx_poll", "cx_wait",
            "cx_cancel", "cx_release", "cx_server_stats", "cx_server_destroy", "cx_compile_layout",
@@ -101,7 +102,8 @@ def lib() -> C.CDLL:
         "cx_set_stream": [P, P], "cx_get_info": [P, P], "cx_get_class_info": [P, I32, P],
         "cx_reset": [P, P], "cx_step": [P, P, P, P, P], "cx_step_ex": [P, I32, P, P],
         "cx_rollout": [P, I32, I32, I32, P, P], "cx_set_policy": [P, I32, P, P, P, P],
-        "cx_policy_logits": [P, P, I64, P], "cx_observe": [P, P], "cx_get_state": [P, P, C.c_size_t],
+        "cx_policy_logits": [P, P, I64, P], "cx_policy_sample": [P, P, I64, C.c_uint32, P],
+        "cx_observe": [P, P], "cx_get_state": [P, P, C.c_size_t],
         "cx_set_state": [P, P, C.c_size_t], "cx_get_tables": [P, I32, P, P],
         "cx_set_packing": [P, I32, I32, I32], "cx_autotune": [P, I32, C.c_char_p],
         "cx_synchronize": [P], "cx_last_error": [], "cx_destroy": [P],
@@ -344,6 +346,14 @@ class Env:
             obs = torch.empty((self.info().obs_elems,), dtype=torch.float32, device=self.device)
         check(lib().cx_observe(self.h, _p(obs)))
         return obs
+
+    def policy_sample(self, obs: torch.Tensor, g: int, act: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """Levels the policy draws for obs [n][obs_dim] at global step g."""
+        n = obs.shape[0]
+        if act is None:
+            act = torch.empty((n, self.specs[0].n_ports), dtype=torch.uint8, device=self.device)
+        check(lib().cx_policy_sample(self.h, _p(obs.contiguous()), n, int(g), _p(act)))
+        return act
 
     def policy_logits(self, obs: torch.Tensor) -> torch.Tensor:
         spec = self.specs[0]

@@ -29,6 +29,7 @@ def direct(cxm, spec, n_envs, T, seed, out_mode, act_mode):
 def mixed_requests(cxm):
     A, M = cxm.ACT_RANDOM, cxm.ACT_MAX
     return [
+        (W.scale_station(), 4096, 1500, 10, cxm.OUT_REWARD, A),   # long: the others join it
         (W.tiny_parity_station(), 64, 100, 11, cxm.OUT_FULL, A),
         (W.scale_station(), 200, 77, 12, cxm.OUT_ACT_REWARD, A),
         (W.fanout4_tree(32, 2), 33, 300, 13, cxm.OUT_REWARD, A),
@@ -39,8 +40,8 @@ def mixed_requests(cxm):
 
 
 def test_served_equals_direct(cxm):
-    """Six requests of differing class, size, horizon, output and action mode run
-    together (chunks of 32 steps): each equals its own direct rollout."""
+    """Seven requests of differing class, size, horizon, output and action mode
+    run together (chunks of 32 steps): each equals its own direct rollout."""
     reqs = mixed_requests(cxm)
     srv = cxm.Server(8 << 30, chunk_steps=32)
     tickets = [srv.submit(s, n, T, seed, om, act_mode=am) for (s, n, T, seed, om, am) in reqs]
@@ -54,7 +55,7 @@ def test_served_equals_direct(cxm):
         srv.release(t)
     st = srv.stats()
     assert st["env_steps"] == sum(n * T for (_, n, T, _, _, _) in reqs)
-    assert st["peak_active"] == len(reqs)
+    assert st["peak_active"] >= 3          # the short requests ran alongside the long one
     srv.close()
 
 
@@ -72,7 +73,7 @@ def test_alone_equals_mixed_and_caller_buffers(cxm):
     assert r.status == 0 and r.traj.obs == out["obs"].data_ptr()
     alone = PY.to_np(out)
     srv.release(t)
-    others = [srv.submit(s, nn, TT, sd, om, act_mode=am) for (s, nn, TT, sd, om, am) in mixed_requests(cxm)[:3]]
+    others = [srv.submit(s, nn, TT, sd, om, act_mode=am) for (s, nn, TT, sd, om, am) in mixed_requests(cxm)[:4]]
     t2 = srv.submit(spec, n, T, seed, cxm.OUT_FULL)
     r2 = srv.wait(t2)
     mixed = srv.fetch(r2, cxm.OUT_FULL, spec.n_ports)
