@@ -277,33 +277,38 @@ def run_serve(args):
     classes = W.mixture_classes()
     budget = 200 << 30
 
+    srv = cx.Server(budget, chunk_steps=32)   # reserves the budget on the device once
+
     def serve(reqs, paced):
-        srv = cx.Server(budget, chunk_steps=32)
+        """Submit (paced by arrival times or all at once); a client thread polls
+        the outstanding tickets and releases each as soon as it finishes."""
+        st0 = srv.stats()
         lat, admit_wait = [], []
-        done = []
         lock = threading.Lock()
-        tickets = []
+        outstanding = []
+        submitted = [0]
 
         def drain():
-            i = 0
-            while True:
+            n_done = 0
+            while n_done < len(reqs):
                 with lock:
-                    if i >= len(tickets):
-                        if len(done) == len(reqs):
-                            return
-                        tk = None
-                    else:
-                        tk = tickets[i]
-                if tk is None:
+                    live = list(outstanding)
+                finished = []
+                for tk in live:
+                    r = srv.poll(tk)
+                    if r is None:
+                        continue
+                    lat.append(r.done_s - r.submit_s)
+                    admit_wait.append(r.admit_s - r.submit_s)
+                    srv.release(tk)
+                    finished.append(tk)
+                if finished:
+                    with lock:
+                        for tk in finished:
+                            outstanding.remove(tk)
+                    n_done += len(finished)
+                else:
                     time.sleep(0.0005)
-                    continue
-                r = srv.wait(tk)
-                lat.append(r.done_s - r.submit_s)
-                admit_wait.append(r.admit_s - r.submit_s)
-                srv.release(tk)
-                with lock:
-                    done.append(tk)
-                i += 1
 
         th = threading.Thread(target=drain)
         th.start()
@@ -315,11 +320,13 @@ def run_serve(args):
                     time.sleep(d)
             tk = srv.submit(classes[rq.class_index], rq.n_envs, rq.horizon, rq.seed, cx.OUT_FULL)
             with lock:
-                tickets.append(tk)
+                outstanding.append(tk)
+                submitted[0] += 1
         th.join()
         wall = time.perf_counter() - t0
-        st = srv.stats()
-        srv.close()
+        st1 = srv.stats()
+        st = {k: st1[k] - st0[k] for k in ("busy_s", "env_steps", "launches")}
+        st["peak_active"] = st1["peak_active"]
         return wall, st, np.array(lat), np.array(admit_wait)
 
     # saturated: a burst of requests submitted at once
@@ -331,6 +338,7 @@ def run_serve(args):
     rate = 0.7 * sat_rate
     stream = W.request_stream(1000, rate, seed=2000)
     wall, st, lat, wq = serve(stream, True)
+    srv.close()
     env_steps = sum(r.n_envs * r.horizon for r in stream)
     rec = {c: record_bytes(np.array([classes[c].n_ports]))[0] for c in range(len(classes))}
     alg = float(sum(r.n_envs * (r.horizon * rec[r.class_index] + 2 * state_bytes(np.array([classes[r.class_index].n_ports]))[0])

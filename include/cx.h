@@ -287,8 +287,10 @@ typedef struct {
   int64_t bytes;            /* device bytes held for the request */
 } cx_result;
 
-/* Budget: device bytes the server may hold for admitted requests.  A request
- * that could never fit is refused at submit with CX_E_BUDGET. */
+/* Budget: device bytes the server may hold for admitted requests, reserved on
+ * the device at create (CX_E_OOM if it cannot be) as one arena; each admitted
+ * request takes one contiguous block of it (first fit) until released.  A
+ * request that could never fit is refused at submit with CX_E_BUDGET. */
 cx_status cx_server_create(size_t hbm_budget_bytes, const cx_server_opts *opts, cx_server **out);
 cx_status cx_submit(cx_server *s, const cx_request *req, uint64_t *ticket);
 cx_status cx_poll(cx_server *s, uint64_t ticket, cx_result *res);   /* CX_E_BUSY while queued/running */

@@ -1,8 +1,11 @@
 // cx_server.cpp -- serving: continuous batching of rollout requests.
 //
-// One scheduler thread per server.  Each loop it retires finished chunks,
-// admits queued requests first-come-first-served while their device memory
-// fits the budget, and launches the next chunk: one per-segment launch of the
+// One scheduler thread per server.  The server reserves its whole memory
+// budget as one device arena at create; a request's block (class constants,
+// state, server-owned records) is carved from it first-fit and returned on
+// release, so admission makes no allocation call.  Each loop the scheduler
+// retires finished chunks, admits queued requests first-come-first-served while
+// a block fits, and launches the next chunk: one per-segment launch of the
 // rollout kernels in which every admitted request is one segment with its own
 // horizon, step counter, seed and output pointers.  Two chunks may be in flight,
 // so the GPU never idles while the host prepares the next one; a request that
@@ -59,7 +62,8 @@ struct Req {
   bool cancel = false;
   int32_t launched = 0;          // steps handed to the GPU
   int32_t retired = 0;           // steps whose chunk finished
-  bool admitted = false;         // holds its bytes of the budget until released
+  bool admitted = false;         // holds its block of the arena until released
+  size_t arena_off = 0;
   int inflight = 0;
   uint32_t g = 0;
   int32_t t_day = 0;
@@ -74,6 +78,44 @@ struct Chunk {
   double sim_done = 0;           // simulated completion time (host clock)
 };
 
+// First-fit allocator over [0, size): free ranges keyed by offset, coalesced
+// on release.
+struct Arena {
+  size_t size = 0;
+  std::map<size_t, size_t> free_ranges;  // offset -> length
+  void init(size_t n) {
+    size = n;
+    free_ranges.clear();
+    free_ranges[0] = n;
+  }
+  bool take(size_t n, size_t *off) {
+    for (auto it = free_ranges.begin(); it != free_ranges.end(); ++it) {
+      if (it->second < n) continue;
+      *off = it->first;
+      const size_t rest = it->second - n, at = it->first + n;
+      free_ranges.erase(it);
+      if (rest) free_ranges[at] = rest;
+      return true;
+    }
+    return false;
+  }
+  void give(size_t off, size_t n) {
+    auto next = free_ranges.lower_bound(off);
+    if (next != free_ranges.end() && off + n == next->first) {
+      n += next->second;
+      next = free_ranges.erase(next);
+    }
+    if (next != free_ranges.begin()) {
+      auto prev = std::prev(next);
+      if (prev->first + prev->second == off) {
+        prev->second += n;
+        return;
+      }
+    }
+    free_ranges[off] = n;
+  }
+};
+
 }  // namespace
 }  // namespace cx
 
@@ -83,6 +125,8 @@ struct cx_server {
   bool sim = false;
   int device = 0;
   hipStream_t stream = nullptr;
+  void *arena_mem = nullptr;   // the budget, reserved at create (none when simulating)
+  cx::Arena arena;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   std::thread th;
@@ -207,15 +251,15 @@ bool admit(cx_server *s) {
       continue;
     }
     Req &r = *it->second;
-    if (s->used + r.total > s->budget) break;   // first come, first served: no skipping ahead
+    if (!s->arena.take(r.total, &r.arena_off)) break;   // first come, first served: no skipping ahead
     if (!s->sim) {
-      if (hipMallocAsync(&r.mem, r.total, s->stream) != hipSuccess) break;
+      r.mem = static_cast<unsigned char *>(s->arena_mem) + r.arena_off;
       unsigned char *b = static_cast<unsigned char *>(r.mem);
       class_block(r.spec, r.comp, r.tab, b, &r.class_host, &r.view);
       if (hipMemcpyAsync(b, r.class_host.data(), r.class_host.size(), hipMemcpyHostToDevice, s->stream) !=
               hipSuccess ||
           hipMemsetAsync(b + r.class_bytes, 0, r.state_bytes, s->stream) != hipSuccess) {
-        (void)hipFreeAsync(r.mem, s->stream);
+        s->arena.give(r.arena_off, r.total);
         r.mem = nullptr;
         s->failed = true;
         finish(s, r, RState::Failed, CX_E_DEVICE);
@@ -392,12 +436,18 @@ cx_status cx_server_create(size_t hbm_budget_bytes, const cx_server_opts *opts, 
     return fail(CX_E_INVALID, "server options out of range");
   std::unique_ptr<cx_server> s(new cx_server());
   s->budget = hbm_budget_bytes;
+  s->arena.init(hbm_budget_bytes);
   s->opts = o;
   s->sim = o.simulate_ns > 0;
   if (!s->sim) {
     if (hipGetDevice(&s->device) != hipSuccess) return fail(CX_E_DEVICE, "no HIP device");
     if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess)
       return fail(CX_E_DEVICE, "stream creation failed");
+    if (hipMalloc(&s->arena_mem, hbm_budget_bytes) != hipSuccess) {
+      s->arena_mem = nullptr;
+      cx_server_destroy(s.release());
+      return fail(CX_E_OOM, "the memory budget could not be reserved on the device");
+    }
     const size_t tb = sizeof(SegDev) * (size_t)o.max_active;
     for (int i = 0; i < kRing; ++i) {
       if (hipHostMalloc(reinterpret_cast<void **>(&s->ring_host[i]), tb, hipHostMallocDefault) != hipSuccess ||
@@ -499,8 +549,11 @@ cx_status cx_release(cx_server *s, uint64_t ticket) {
   if (it == s->reqs.end()) return fail(CX_E_NOTFOUND, "unknown ticket");
   Req &r = *it->second;
   if (!finished(r)) return fail(CX_E_BUSY, "request still queued or running");
-  if (r.mem) (void)hipFreeAsync(r.mem, s->stream);  // ordered after every chunk that used it
-  if (r.admitted) s->used -= r.total;
+  // every chunk that used the block has retired, so it may be handed out again
+  if (r.admitted) {
+    s->arena.give(r.arena_off, r.total);
+    s->used -= r.total;
+  }
   s->reqs.erase(it);
   s->cv_work.notify_all();
   return CX_OK;
@@ -531,8 +584,7 @@ void cx_server_destroy(cx_server *s) {
       if (c.ev0) (void)hipEventDestroy(c.ev0);
       if (c.ev1) (void)hipEventDestroy(c.ev1);
     }
-    for (auto &kv : s->reqs)
-      if (kv.second->mem) (void)hipFree(kv.second->mem);
+    if (s->arena_mem) (void)hipFree(s->arena_mem);
     for (int i = 0; i < kRing; ++i) {
       if (s->ring_host[i]) (void)hipHostFree(s->ring_host[i]);
       if (s->ring_dev[i]) (void)hipFree(s->ring_dev[i]);

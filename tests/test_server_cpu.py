@@ -141,3 +141,25 @@ def test_max_active_bounds_concurrency(cxm):
     # with two slots, the third request starts only after one of the first two ended
     assert rs[2].admit_s >= min(rs[0].done_s, rs[1].done_s)
     s.close()
+
+
+def test_blocks_are_contiguous_and_coalesce(cxm):
+    """A request needs one contiguous block: two separate free ranges that add up
+    to enough do not admit it; releasing the block between them does."""
+    spec = W.tiny_parity_station()
+    X = request_bytes(cxm, spec, 64, 64, cxm.OUT_FULL)
+    D = request_bytes(cxm, spec, 96, 64, cxm.OUT_FULL)
+    assert X < D < 2 * X
+    s = cxm.Server(3 * X, chunk_steps=16, simulate_ns=NS)
+    a, b, c = (s.submit(spec, 64, 64, i, cxm.OUT_FULL) for i in range(3))
+    for t in (a, b, c):
+        assert s.wait(t).status == 0
+    s.release(a)
+    s.release(c)                                       # free: [0, X) and [2X, 3X)
+    d = s.submit(spec, 96, 64, 9, cxm.OUT_FULL)
+    time.sleep(0.05)
+    assert s.poll(d) is None                           # 2X free in total, no 1.5X range
+    s.release(b)                                       # coalesces into [0, 3X)
+    assert s.wait(d).status == 0
+    s.release(d)
+    s.close()
