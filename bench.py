@@ -151,7 +151,7 @@ def run_rollout_workload(args, name, specs, ec, seed, desc, cpu_stride):
     n_envs = len(ec)
     env = cx.Env(specs, env_class=ec, seed=seed) if len(specs) > 1 else cx.Env(specs[0], n_envs=n_envs, seed=seed)
     if not args.no_tune:
-        env.autotune(32, os.path.join(ROOT, "gpurun_out", "autotune_cache.json")
+        env.autotune(T_DAY, os.path.join(ROOT, "gpurun_out", "autotune_cache.json")
                      if os.path.isdir(os.path.join(ROOT, "gpurun_out")) else None)
     out = env.alloc_traj(T_DAY, cx.OUT_FULL)
     wall_ms, kernel_ms = timed_rollouts(env, cx, T_DAY, cx.ACT_RANDOM, cx.OUT_FULL, out, args)

@@ -91,7 +91,9 @@ extern "C" cx_status cx_autotune(cx_ctx *ctx, int32_t T_probe, const char *cache
   const uint32_t g_saved = ctx->g;
   const int32_t t_saved = ctx->t_day;
   cx_status st = CX_OK;
+  RolloutGraph *probe_ptr = nullptr;
   auto cleanup = [&]() {
+    if (probe_ptr) graph_destroy(*probe_ptr);
     if (saved) {
       (void)hipMemcpyAsync(ctx->state_mem, saved, ctx->state_bytes_dev, hipMemcpyDeviceToDevice, ctx->stream);
       (void)hipStreamSynchronize(ctx->stream);
@@ -125,7 +127,10 @@ extern "C" cx_status cx_autotune(cx_ctx *ctx, int32_t T_probe, const char *cache
   a.act = sb + obs_b;
   a.reward = reinterpret_cast<float *>(sb + ((obs_b + act_b + 255) & ~(size_t)255));
   a.done = sb + ((obs_b + act_b + 255) & ~(size_t)255) + sizeof(float) * env_b;
-  // time one launch of the given segment table (min over 3 after a warm-up)
+  // time a launch of the given segment table as rollouts run it (one graph,
+  // its kernels concurrent); min over 3 after a warm-up
+  RolloutGraph probe;
+  probe_ptr = &probe;
   auto time_launch = [&](const SegDev *segs, const std::vector<LaunchGroup> &groups, int wpb,
                          float *best_ms) -> hipError_t {
     LaunchArgs b = a;
@@ -134,7 +139,8 @@ extern "C" cx_status cx_autotune(cx_ctx *ctx, int32_t T_probe, const char *cache
     for (int rep = 0; rep < 4; ++rep) {
       hipError_t r;
       if ((r = hipEventRecord(ev0, ctx->stream)) != hipSuccess) return r;
-      if ((r = launch_groups(b, groups.data(), (int)groups.size(), wpb, ctx->stream)) != hipSuccess) return r;
+      if ((r = graph_rollout(probe, b, groups.data(), (int)groups.size(), wpb, ctx->stream)) != hipSuccess)
+        return r;
       if ((r = hipEventRecord(ev1, ctx->stream)) != hipSuccess) return r;
       if ((r = hipEventSynchronize(ev1)) != hipSuccess) return r;
       float ms = 0.f;
