@@ -491,6 +491,11 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
     ai_t += act_step;
     rw_t += env_step;
     dn_t += env_step;
+    // Keep the block's waves on the same step: their records for the step
+    // are then adjacent envs' blocks written together, which HBM takes
+    // noticeably faster (better row locality) than the same bytes spread over
+    // many steps.  Waves that left early (past the last env) do not count.
+    __syncthreads();
   }
 
   // ---- state back to HBM
