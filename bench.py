@@ -71,22 +71,27 @@ def uneven_workload():
     return W.compact_classes(classes, ec_full)
 
 
-def oracle_baseline(specs, ec, seed, T, stride, chunk=16, mode=1, act_in=None):
-    """The FP64 oracle on a bounded, evenly spaced sample of the same stations."""
+def oracle_baseline(specs, ec, seed, T, stride, chunk=16, mode=1, min_s=10.0):
+    """The FP64 oracle on an evenly spaced sample of the same stations, whole days
+    repeated until about min_s seconds of host time have passed."""
     from oracle import oracle as o
     ids = np.arange(0, len(ec), stride, dtype=np.int64)
     classes = [o.OracleClass(s) for s in specs]
-    bs = o.BatchState(classes, np.asarray(ec)[ids], env_ids=ids)
     threads = max(1, min(16, os.cpu_count() or 1))
+    used, steps, days = 1, 0, 0
     t0 = time.perf_counter()
-    used = 1
-    for _ in range(max(1, T // chunk)):
-        out = o.rollout(bs, seed, min(chunk, T), mode=mode, n_threads=threads)
-        used = out["threads"]
+    while True:
+        bs = o.BatchState(classes, np.asarray(ec)[ids], env_ids=ids)
+        for _ in range(max(1, T // chunk)):
+            out = o.rollout(bs, seed, min(chunk, T), mode=mode, n_threads=threads)
+            used = out["threads"]
+            steps += min(chunk, T)
+        days += 1
+        if time.perf_counter() - t0 >= min_s:
+            break
     dt = time.perf_counter() - t0
-    steps = max(1, T // chunk) * min(chunk, T)
     return {"value": len(ids) * steps / dt, "unit": "env-steps/s", "cores": int(used), "kind": "oracle",
-            "sample": f"{len(ids)} of {len(ec)} stations (every {stride}th), {steps} steps, FP64, "
+            "sample": f"{len(ids)} of {len(ec)} stations (every {stride}th), {days} x {T} steps, FP64, "
                       f"all outputs, {used} threads, {dt:.1f} s"}
 
 
@@ -249,8 +254,9 @@ def run_policy(args):
     return line
 
 
-def policy_oracle_baseline(spec, H, weights, seed, n_envs=64, T=32):
-    """The oracle's policy and transition, one env-step at a time, on 64 stations."""
+def policy_oracle_baseline(spec, H, weights, seed, n_envs=64, min_s=10.0):
+    """The oracle's policy and transition, one env-step at a time, on 64 stations,
+    steps repeated until about min_s seconds of host time have passed."""
     from oracle import oracle as o
     c = o.OracleClass(spec)
     N = spec.n_ports
@@ -258,13 +264,17 @@ def policy_oracle_baseline(spec, H, weights, seed, n_envs=64, T=32):
     t0 = time.perf_counter()
     st = o.EnvState(N)
     obs = np.stack([c.observe(st)] * n_envs)
-    for t in range(T):
+    t = 0
+    while True:
         act = np.stack([c.policy(H, weights, obs[e], seed, e, t)[1] for e in range(n_envs)]).astype(np.uint8)
         out = o.rollout(bs, seed, 1, mode=0, act_in=act.reshape(1, -1), n_threads=1)
         obs = out["obs"].reshape(n_envs, -1)
+        t += 1
+        if time.perf_counter() - t0 >= min_s:
+            break
     dt = time.perf_counter() - t0
-    return {"value": n_envs * T / dt, "unit": "env-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n_envs} stations x {T} steps of the policy workload, FP64 perceptron + step, "
+    return {"value": n_envs * t / dt, "unit": "env-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n_envs} stations x {t} steps of the policy workload, FP64 perceptron + step, "
                       f"1 thread, {dt:.1f} s"}
 
 
