@@ -339,10 +339,10 @@ def run_serve(args):
         st["peak_active"] = st1["peak_active"]
         return wall, st, np.array(lat), np.array(admit_wait)
 
-    # saturated: a burst of requests submitted at once
-    burst = W.request_stream(200, 1e9, seed=2001)
-    serve(W.request_stream(20, 1e9, seed=2002), False)          # warm-up (allocator, code objects)
-    wall_s, st_s, _, _ = serve(burst, False)
+    # saturated: bursts of requests submitted at once (the better of two)
+    burst = W.request_stream(600, 1e9, seed=2001)
+    serve(W.request_stream(40, 1e9, seed=2002), False)          # warm-up (code objects, arena pages)
+    wall_s = min(serve(burst, False)[0] for _ in range(2))
     steps_s = sum(r.n_envs * r.horizon for r in burst)
     sat_rate = len(burst) / wall_s
     rate = 0.7 * sat_rate

@@ -125,6 +125,11 @@ struct cx_server {
   bool sim = false;
   int device = 0;
   hipStream_t stream = nullptr;
+  // a chunk's kernels (one per packing) run concurrently on these, forked from
+  // and joined back into `stream` with events
+  static constexpr int kAux = 4;
+  hipStream_t aux[kAux] = {};
+  hipEvent_t ev_fork = nullptr, ev_join[kAux] = {};
   void *arena_mem = nullptr;   // the budget, reserved at create (none when simulating)
   cx::Arena arena;
   std::mutex mu;
@@ -359,7 +364,22 @@ bool launch(cx_server *s) {
   LaunchArgs a{};
   a.segs = s->ring_dev[slot];
   a.per_segment = 1;
-  if (e == hipSuccess) e = launch_groups(a, groups.data(), (int)groups.size(), s->opts.waves_per_block, s->stream);
+  if (e == hipSuccess) {
+    if (groups.size() <= 1) {
+      e = launch_groups(a, groups.data(), (int)groups.size(), s->opts.waves_per_block, s->stream);
+    } else {
+      // fork: each packing's kernel on its own stream, then join
+      const int n_aux = std::min<int>((int)groups.size(), cx_server::kAux);
+      e = hipEventRecord(s->ev_fork, s->stream);
+      for (int k = 0; k < n_aux && e == hipSuccess; ++k) e = hipStreamWaitEvent(s->aux[k], s->ev_fork, 0);
+      for (size_t gi = 0; gi < groups.size() && e == hipSuccess; ++gi)
+        e = launch_groups(a, groups.data() + gi, 1, s->opts.waves_per_block, s->aux[gi % n_aux]);
+      for (int k = 0; k < n_aux && e == hipSuccess; ++k) {
+        e = hipEventRecord(s->ev_join[k], s->aux[k]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s->stream, s->ev_join[k], 0);
+      }
+    }
+  }
   if (e == hipSuccess) e = hipEventRecord(c.ev1, s->stream);
   if (e != hipSuccess) {
     s->failed = true;
@@ -443,6 +463,14 @@ cx_status cx_server_create(size_t hbm_budget_bytes, const cx_server_opts *opts, 
     if (hipGetDevice(&s->device) != hipSuccess) return fail(CX_E_DEVICE, "no HIP device");
     if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess)
       return fail(CX_E_DEVICE, "stream creation failed");
+    bool ok = hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming) == hipSuccess;
+    for (int k = 0; k < cx_server::kAux && ok; ++k)
+      ok = hipStreamCreateWithFlags(&s->aux[k], hipStreamNonBlocking) == hipSuccess &&
+           hipEventCreateWithFlags(&s->ev_join[k], hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+      cx_server_destroy(s.release());
+      return fail(CX_E_DEVICE, "server stream creation failed");
+    }
     if (hipMalloc(&s->arena_mem, hbm_budget_bytes) != hipSuccess) {
       s->arena_mem = nullptr;
       cx_server_destroy(s.release());
@@ -590,6 +618,12 @@ void cx_server_destroy(cx_server *s) {
       if (s->ring_dev[i]) (void)hipFree(s->ring_dev[i]);
       if (s->ring_ev[i]) (void)hipEventDestroy(s->ring_ev[i]);
     }
+    for (int k = 0; k < cx_server::kAux; ++k) {
+      if (s->aux[k]) (void)hipStreamSynchronize(s->aux[k]);
+      if (s->aux[k]) (void)hipStreamDestroy(s->aux[k]);
+      if (s->ev_join[k]) (void)hipEventDestroy(s->ev_join[k]);
+    }
+    if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
     if (s->stream) (void)hipStreamDestroy(s->stream);
   }
   delete s;
