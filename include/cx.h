@@ -96,6 +96,15 @@ typedef struct {
   double tgt_lo, tgt_hi;        /* desired SoC ~ U[...)  */
   double dwell_mu, dwell_sigma; /* stay ~ round(lognormal(mu, sigma)) steps */
   int32_t dwell_max;            /* cap on the stay in steps (<= 4096) */
+  /* Optional time-of-day profiles (Sec. 3 "Exogenous State Space", Table 1: the
+   * arrival and price data are per step of the day), each steps_per_episode
+   * doubles of host memory copied at create, or NULL for the smooth defaults:
+   *   arrival_rate[t]  Poisson mean of arrivals at step t of the day, in [0, 8]
+   *                    (replaces arrival_peak's curve);
+   *   price_table[t]   base buying price per kWh at step t (replaces
+   *                    price_base + price_amp sin; the noise sigma z is still added). */
+  const double *arrival_rate;
+  const double *price_table;
 } cx_station_spec;
 
 typedef struct cx_ctx cx_ctx;

@@ -26,6 +26,8 @@ struct ox_class {
   double p[OXP_COUNT];
   int32_t ip[OXI_COUNT];
   uint32_t *tpois;           /* [steps_per_episode][24] */
+  double *lam;               /* [steps_per_episode] Poisson mean of arrivals per step of the day */
+  double *price;             /* [steps_per_episode] base buying price per step of the day */
   uint32_t *tdwell;          /* [dwell_max], entry 0 unused */
 };
 
@@ -73,14 +75,14 @@ static uint32_t threshold_u32(double cdf) {
   return (uint32_t)x;
 }
 
-/* Arrival counts, Supp. B.1: M(t) ~ Poisson(lambda(t)).  The synthetic average
- * lambda(t) = peak * (1 - cos(2 pi t / S)) / 2 replaces the bundled per-step
- * averages.  The CDF is accumulated with the pmf recurrence. */
+/* Arrival counts, Supp. B.1: M(t) ~ Poisson(lambda(t)), lambda(t) the mean of
+ * step t of the day (c->lam: the given per-step table, else the synthetic
+ * average peak * (1 - cos(2 pi t / S)) / 2 in place of the bundled data).  The
+ * CDF is accumulated with the pmf recurrence. */
 static void build_tpois(ox_class *c) {
   const int32_t S = c->ip[OXI_STEPS_PER_EPISODE];
-  const double peak = c->p[OXP_ARRIVAL_PEAK];
   for (int32_t t = 0; t < S; ++t) {
-    double lam = 0.5 * peak * (1.0 - cos(2.0 * M_PI * (double)t / (double)S));
+    double lam = c->lam[t];
     double pmf = exp(-lam);
     double cdf = pmf;
     for (int32_t k = 0; k < OX_K_POIS; ++k) {
@@ -139,6 +141,14 @@ ox_class *ox_class_new(int32_t n_ports, int32_t n_nodes, const int32_t *node_par
   }
   c->tpois = (uint32_t *)malloc(sizeof(uint32_t) * c->ip[OXI_STEPS_PER_EPISODE] * OX_K_POIS);
   c->tdwell = (uint32_t *)malloc(sizeof(uint32_t) * c->ip[OXI_DWELL_MAX]);
+  /* default time-of-day profiles: smooth arrival curve, sinusoidal base price */
+  const int32_t S = c->ip[OXI_STEPS_PER_EPISODE];
+  c->lam = (double *)malloc(sizeof(double) * S);
+  c->price = (double *)malloc(sizeof(double) * S);
+  for (int32_t t = 0; t < S; ++t) {
+    c->lam[t] = 0.5 * c->p[OXP_ARRIVAL_PEAK] * (1.0 - cos(2.0 * M_PI * (double)t / (double)S));
+    c->price[t] = c->p[OXP_PRICE_BASE] + c->p[OXP_PRICE_AMP] * sin(2.0 * M_PI * (double)t / (double)S);
+  }
   build_tpois(c);
   build_tdwell(c);
   return c;
@@ -147,8 +157,15 @@ ox_class *ox_class_new(int32_t n_ports, int32_t n_nodes, const int32_t *node_par
 void ox_class_free(ox_class *c) {
   if (!c) return;
   free(c->node_parent); free(c->node_depth); free(c->node_cap); free(c->anc);
-  free(c->pmax); free(c->peta); free(c->tpois); free(c->tdwell);
+  free(c->pmax); free(c->peta); free(c->tpois); free(c->tdwell); free(c->lam); free(c->price);
   free(c);
+}
+
+void ox_class_set_profiles(ox_class *c, const double *arrival_rate, const double *price_table) {
+  const int32_t S = c->ip[OXI_STEPS_PER_EPISODE];
+  if (arrival_rate) memcpy(c->lam, arrival_rate, sizeof(double) * S);
+  if (price_table) memcpy(c->price, price_table, sizeof(double) * S);
+  build_tpois(c);
 }
 
 int32_t ox_class_ports(const ox_class *c) { return c->n_ports; }
@@ -227,8 +244,7 @@ void ox_draw_exo(const ox_class *c, uint64_t seed, uint32_t env, uint32_t g, int
   double u1 = ((double)(w[1] >> 8) + 1.0) * (1.0 / 16777216.0);
   double u2 = ox_u24(w[2]);
   x->z = sqrt(-2.0 * log(u1)) * cos(2.0 * M_PI * u2);
-  x->p_buy = c->p[OXP_PRICE_BASE] + c->p[OXP_PRICE_AMP] * sin(2.0 * M_PI * (double)t_day / (double)S) +
-             c->p[OXP_PRICE_SIGMA] * x->z;
+  x->p_buy = c->price[t_day] + c->p[OXP_PRICE_SIGMA] * x->z;
   /* car and user profiles of every arriving car j (App. A.2 "Arrival of new Cars") */
   const int32_t D = c->ip[OXI_DWELL_MAX];
   for (int32_t j = 0; j < M; ++j) {
@@ -279,7 +295,7 @@ void ox_observe(const ox_class *c, const int32_t *dwell, const double *soc, cons
   double ang = 2.0 * M_PI * (double)t_day / (double)S;
   obs[6 * N + 0] = sin(ang);
   obs[6 * N + 1] = cos(ang);
-  obs[6 * N + 2] = c->p[OXP_PRICE_BASE] + c->p[OXP_PRICE_AMP] * sin(ang);
+  obs[6 * N + 2] = c->price[t_day];
   obs[6 * N + 3] = (double)n_occ / (double)N;
 }
 

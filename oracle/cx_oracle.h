@@ -102,6 +102,10 @@ ox_class *ox_class_new(int32_t n_ports, int32_t n_nodes, const int32_t *node_par
                        const int32_t *port_parent, const double *port_pmax,
                        const double *port_eta, const double *params, const int32_t *iparams);
 void ox_class_free(ox_class *c);
+/* Time-of-day profiles (Sec. 3 "Exogenous State Space", Table 1): per step of the
+ * day, the Poisson mean of arrivals and the base buying price; NULL keeps the
+ * default curves.  Rebuilds the arrival thresholds. */
+void ox_class_set_profiles(ox_class *c, const double *arrival_rate, const double *price_table);
 int32_t ox_class_ports(const ox_class *c);
 int32_t ox_obs_dim(const ox_class *c);
 /* copies of the class's integer sampling tables (steps_per_episode x 24, dwell_max) */

@@ -73,6 +73,7 @@ def lib():
         L.ox_rollout.restype = I
         L.ox_rollout.argtypes = [P, P, P, C.c_int64, C.c_uint64, P, P, I, I, P, P, P, P, P, P, P, P,
                                  P, P, P, P, I]
+        L.ox_class_set_profiles.argtypes = [P, P, P]
         L.ox_policy.argtypes = [P, I, P, P, P, P, P, C.c_uint64, C.c_uint32, C.c_uint32, P, P, P]
         L.ox_bf16_round.restype = C.c_double
         L.ox_bf16_round.argtypes = [C.c_double]
@@ -116,6 +117,14 @@ class OracleClass:
             raise ValueError("oracle rejected the station spec")
         self.h = C.c_void_p(h)
         self.n = spec.n_ports
+        rate, price = getattr(spec, "arrival_rate", None), getattr(spec, "price_table", None)
+        if rate is not None or price is not None:
+            prof = [None if a is None else np.ascontiguousarray(a, dtype=np.float64) for a in (rate, price)]
+            for a in prof:
+                if a is not None and a.shape != (spec.steps_per_episode,):
+                    raise ValueError("profiles need steps_per_episode entries")
+            self._keep += [a for a in prof if a is not None]
+            lib().ox_class_set_profiles(self.h, _ptr(prof[0]), _ptr(prof[1]))
 
     def __del__(self):
         try:

@@ -48,6 +48,15 @@ bool copy_spec(const cx_station_spec &in, SpecCopy *out, std::string *err) {
   out->s.port_parent = out->port_parent.data();
   out->s.port_pmax_kw = out->port_pmax.data();
   out->s.port_eta = out->port_eta.data();
+  const int S = in.steps_per_episode;
+  if ((in.arrival_rate || in.price_table) && (S < 1 || S > 100000))
+    return fail(err, "steps_per_episode must be in 1..100000");
+  out->arrival_rate.clear();
+  out->price_table.clear();
+  if (in.arrival_rate) out->arrival_rate.assign(in.arrival_rate, in.arrival_rate + S);
+  if (in.price_table) out->price_table.assign(in.price_table, in.price_table + S);
+  out->s.arrival_rate = in.arrival_rate ? out->arrival_rate.data() : nullptr;
+  out->s.price_table = in.price_table ? out->price_table.data() : nullptr;
   return true;
 }
 
@@ -73,6 +82,10 @@ bool compile_spec(const SpecCopy &sc, Compiled *c, std::string *err) {
   for (double v : {s.p_sell, s.p_sell_grid, s.fixed_cost, s.alpha_sat, s.alpha_declined, s.price_base,
                    s.price_amp, s.price_sigma})
     if (!std::isfinite(v)) return fail(err, "prices and penalty weights must be finite");
+  for (double v : sc.arrival_rate)
+    if (!(v >= 0.0 && v <= 8.0)) return fail(err, "arrival_rate entries must be in [0, 8]");
+  for (double v : sc.price_table)
+    if (!std::isfinite(v)) return fail(err, "price_table entries must be finite");
   // ---- tree
   if (sc.node_parent[0] != -1) return fail(err, "node 0 must be the root (parent -1)");
   for (int h = 1; h < H; ++h)
@@ -178,11 +191,14 @@ void build_tables(const SpecCopy &sc, Tables *t) {
   const cx_station_spec &s = sc.s;
   const int Sep = s.steps_per_episode;
   const double two_pi = 2.0 * 3.14159265358979323846;
-  // arrivals ~ Poisson(lambda(t)), lambda(t) = peak (1 - cos(2 pi t / S)) / 2, CDF by the pmf recurrence
+  // arrivals ~ Poisson(lambda(t)): the given per-step means, else
+  // lambda(t) = peak (1 - cos(2 pi t / S)) / 2; CDF by the pmf recurrence
   t->tpois.assign((size_t)Sep * kPoisK, 0u);
   t->tpois_dev.assign((size_t)Sep * kPoisStride, 0xFFFFFFFFu);
   for (int step = 0; step < Sep; ++step) {
-    const double lam = 0.5 * s.arrival_peak * (1.0 - std::cos(two_pi * (double)step / (double)Sep));
+    const double lam = sc.arrival_rate.empty()
+                           ? 0.5 * s.arrival_peak * (1.0 - std::cos(two_pi * (double)step / (double)Sep))
+                           : sc.arrival_rate[step];
     double p = std::exp(-lam), F = p;
     for (int k = 0; k < kPoisK; ++k) {
       if (k > 0) {
@@ -213,7 +229,8 @@ void build_tables(const SpecCopy &sc, Tables *t) {
     const double a = two_pi * (double)step / (double)Sep;
     t->glob[(size_t)step * 4 + 0] = (float)std::sin(a);
     t->glob[(size_t)step * 4 + 1] = (float)std::cos(a);
-    t->glob[(size_t)step * 4 + 2] = (float)(s.price_base + s.price_amp * std::sin(a));
+    t->glob[(size_t)step * 4 + 2] =
+        (float)(sc.price_table.empty() ? s.price_base + s.price_amp * std::sin(a) : sc.price_table[step]);
   }
 }
 

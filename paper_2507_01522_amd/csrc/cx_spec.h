@@ -13,6 +13,7 @@ struct SpecCopy {
   cx_station_spec s;
   std::vector<int32_t> node_parent, port_parent;
   std::vector<double> node_limit, node_eta, port_pmax, port_eta;
+  std::vector<double> arrival_rate, price_table;  // empty: the default curves
 };
 
 // The capacity tree in the kernels' layout.  Every node owns an aligned block of

@@ -39,7 +39,8 @@ class StationSpecC(C.Structure):
                 ("price_amp", C.c_double), ("price_sigma", C.c_double), ("arrival_peak", C.c_double),
                 ("cap_lo", C.c_double), ("cap_hi", C.c_double), ("soc0_lo", C.c_double),
                 ("soc0_hi", C.c_double), ("tgt_lo", C.c_double), ("tgt_hi", C.c_double),
-                ("dwell_mu", C.c_double), ("dwell_sigma", C.c_double), ("dwell_max", C.c_int32)]
+                ("dwell_mu", C.c_double), ("dwell_sigma", C.c_double), ("dwell_max", C.c_int32),
+                ("arrival_rate", C.c_void_p), ("price_table", C.c_void_p)]
 
 
 class TrajC(C.Structure):
@@ -159,6 +160,11 @@ class _SpecHolder:
                        np.ascontiguousarray(spec.port_parent, np.int32),
                        np.ascontiguousarray(spec.port_pmax_kw, np.float64),
                        np.ascontiguousarray(spec.port_eta, np.float64)]
+        self.profiles = [None if getattr(spec, k, None) is None else
+                         np.ascontiguousarray(getattr(spec, k), np.float64) for k in ("arrival_rate", "price_table")]
+        for arr in self.profiles:
+            if arr is not None and arr.shape != (spec.steps_per_episode,):
+                raise ValueError("arrival_rate / price_table need steps_per_episode entries")
         a = self.arrays
         self.c = StationSpecC(spec.n_ports, len(spec.node_parent), a[0].ctypes.data, a[1].ctypes.data,
                               a[2].ctypes.data, a[3].ctypes.data, a[4].ctypes.data, a[5].ctypes.data,
@@ -166,7 +172,8 @@ class _SpecHolder:
                               spec.alpha_sat, spec.alpha_declined, spec.steps_per_episode, spec.n_levels,
                               spec.price_base, spec.price_amp, spec.price_sigma, spec.arrival_peak,
                               spec.cap_lo, spec.cap_hi, spec.soc0_lo, spec.soc0_hi, spec.tgt_lo, spec.tgt_hi,
-                              spec.dwell_mu, spec.dwell_sigma, spec.dwell_max)
+                              spec.dwell_mu, spec.dwell_sigma, spec.dwell_max,
+                              *[None if arr is None else arr.ctypes.data for arr in self.profiles])
 
 
 def compile_layout(spec) -> Dict[str, np.ndarray]:

@@ -20,7 +20,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
-from typing import List, Sequence, Tuple
+from typing import List, Optional, Sequence, Tuple
 
 import numpy as np
 
@@ -67,6 +67,10 @@ class StationSpec:
     dwell_sigma: float = 0.5
     dwell_max: int = 1024
     name: str = ""
+    # optional per-step profiles of the day (steps_per_episode entries each):
+    # Poisson arrival means and base buying prices; None = the smooth defaults
+    arrival_rate: Optional[np.ndarray] = None
+    price_table: Optional[np.ndarray] = None
 
     @property
     def n_nodes(self) -> int:
@@ -143,6 +147,29 @@ def fanout4_tree(n_ports: int, depth: int, factor: float = 0.7, **kw) -> Station
     return StationSpec(n_ports, parents, limit, [1.0] * len(parents), port_parent,
                        [PMAX_KW] * n_ports, [1.0] * n_ports,
                        arrival_peak=0.3 * n_ports / 16.0, name=f"fan4_n{n_ports}_d{depth}", **kw)
+
+
+def commuter_arrivals(steps: int = STEPS_PER_DAY, morning: float = 0.9, evening: float = 0.6,
+                      night: float = 0.02) -> np.ndarray:
+    """Synthetic time-of-day arrival means (cars per step) with a morning and an
+    evening peak over a small night floor: the shape of a workplace / commuter
+    station's arrival data (the paper's data sets are not available)."""
+    h = 24.0 * np.arange(steps) / steps
+    bump = lambda c, w: np.exp(-0.5 * ((h - c) / w) ** 2)  # noqa: E731
+    return night + morning * bump(8.5, 1.2) + evening * bump(17.5, 1.6)
+
+
+def time_of_use_prices(steps: int = STEPS_PER_DAY, off_peak: float = 0.16, mid: float = 0.27,
+                       peak: float = 0.41) -> np.ndarray:
+    """Synthetic time-of-use tariff: off-peak 23-07 h, peak 17-21 h, mid otherwise."""
+    h = 24.0 * np.arange(steps) / steps
+    return np.where((h >= 23.0) | (h < 7.0), off_peak, np.where((h >= 17.0) & (h < 21.0), peak, mid))
+
+
+def profile_station() -> StationSpec:
+    """The two-charger-type station with commuter arrivals and a time-of-use tariff."""
+    return two_charger_types().replace(name="types10dc6ac_tou", arrival_rate=commuter_arrivals(),
+                                       price_table=time_of_use_prices())
 
 
 def two_charger_types(n_dc: int = 10, n_ac: int = 6, dc_kw: float = 150.0, ac_kw: float = 11.5,
