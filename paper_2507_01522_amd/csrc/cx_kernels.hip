@@ -37,7 +37,7 @@ __device__ __forceinline__ int arrivals(const uint32_t *row, uint32_t w) {
 }
 
 // Stay length of an arriving car: 1 + #{thresholds below w}, bisecting the
-// table in LDS (multi-step launches) or in device memory.
+// table in LDS (staged by the block) or in device memory.
 __device__ __forceinline__ int stay_len(const uint32_t *tab, bool in_lds, int log2n, uint32_t w) {
   int pos = 0;
   if (in_lds) {
@@ -536,8 +536,8 @@ __global__ __launch_bounds__(512) void k_rollout(LaunchArgs a) {
     dy = Dyn{a.T, a.t_day0, a.g0, a.mode, a.out_mode, a.obs, a.act, a.reward, a.done, a.act_in,
              a.obs_stride, a.act_stride, a.env_stride};
   }
-  // stay-length thresholds in LDS for multi-step launches (every wave of the
-  // block helps load them before any wave may leave)
+  // stay-length thresholds in LDS (every wave of the block helps load them
+  // before any wave may leave)
   const uint32_t *tdw = sg.cls->tdwell;
   const bool tdw_lds = a.lds_tdwell != 0;
   if (tdw_lds) {
@@ -590,8 +590,8 @@ LaunchArgs group_args(const LaunchArgs &a, const LaunchGroup &g, size_t *lds) {
   LaunchArgs b = a;
   b.segs = a.segs + g.seg_begin;
   b.n_segs = g.n_segs;
-  const int T = a.per_segment ? g.max_T : a.T;
-  b.lds_tdwell = 1;
+  b.lds_tdwell = 1;  // staging the table costs one load per thread and beats device-memory
+                     // bisection even for one-step launches
   *lds = b.lds_tdwell ? ((size_t)4 << g.max_dwell_log2) : 0;
   return b;
 }
