@@ -23,6 +23,9 @@ struct ox_class {
   double *node_cap;          /* eta_H * I_H: the right side of Eq. (ArchConst) times eta_H */
   unsigned char *anc;        /* anc[h * n_ports + i] = 1 iff node h lies on port i's path   */
   double *pmax, *peta;
+  double *pdis;              /* discharge maximum per port (V2G) */
+  int32_t v2g;               /* 1: ports take levels -L..L */
+  double b_cap, b_rate, b_tau, b_soc0, a_db, a_dc;  /* battery (b_cap = 0: none), degradation weights */
   double p[OXP_COUNT];
   int32_t ip[OXI_COUNT];
   uint32_t *tpois;           /* [steps_per_episode][24] */
@@ -125,6 +128,7 @@ ox_class *ox_class_new(int32_t n_ports, int32_t n_nodes, const int32_t *node_par
   c->anc = (unsigned char *)calloc((size_t)n_nodes * n_ports, 1);
   c->pmax = (double *)malloc(sizeof(double) * n_ports);
   c->peta = (double *)malloc(sizeof(double) * n_ports);
+  c->pdis = (double *)malloc(sizeof(double) * n_ports);
   c->max_depth = 0;
   for (int32_t h = 0; h < n_nodes; ++h) {
     c->node_parent[h] = node_parent[h];
@@ -136,6 +140,7 @@ ox_class *ox_class_new(int32_t n_ports, int32_t n_nodes, const int32_t *node_par
   }
   for (int32_t i = 0; i < n_ports; ++i) {
     c->pmax[i] = port_pmax[i];
+    c->pdis[i] = port_pmax[i];
     c->peta[i] = port_eta[i];
     for (int32_t a = port_parent[i]; a >= 0; a = node_parent[a]) c->anc[(size_t)a * n_ports + i] = 1;
   }
@@ -157,7 +162,7 @@ ox_class *ox_class_new(int32_t n_ports, int32_t n_nodes, const int32_t *node_par
 void ox_class_free(ox_class *c) {
   if (!c) return;
   free(c->node_parent); free(c->node_depth); free(c->node_cap); free(c->anc);
-  free(c->pmax); free(c->peta); free(c->tpois); free(c->tdwell); free(c->lam); free(c->price);
+  free(c->pmax); free(c->peta); free(c->pdis); free(c->tpois); free(c->tdwell); free(c->lam); free(c->price);
   free(c);
 }
 
@@ -168,8 +173,27 @@ void ox_class_set_profiles(ox_class *c, const double *arrival_rate, const double
   build_tpois(c);
 }
 
+void ox_class_set_v2g(ox_class *c, int32_t v2g, const double *pdis, const double *batt) {
+  c->v2g = v2g ? 1 : 0;
+  for (int32_t i = 0; i < c->n_ports; ++i) c->pdis[i] = pdis ? pdis[i] : c->pmax[i];
+  c->b_cap = batt[0]; c->b_rate = batt[1]; c->b_tau = batt[2]; c->b_soc0 = batt[3];
+  c->a_db = batt[4]; c->a_dc = batt[5];
+}
+
+static int32_t has_battery(const ox_class *c) { return c->b_cap > 0.0; }
+
 int32_t ox_class_ports(const ox_class *c) { return c->n_ports; }
-int32_t ox_obs_dim(const ox_class *c) { return 6 * c->n_ports + 4; }
+int32_t ox_class_actions(const ox_class *c) { return c->n_ports + has_battery(c); }
+int32_t ox_obs_dim(const ox_class *c) { return 6 * c->n_ports + 4 + 2 * has_battery(c); }
+
+/* Levels of action index i run from -lo(i) to L: ports of a V2G class and the
+ * battery also discharge (the battery is the (N+1)-th pole, Sec. 3 "Action
+ * Space").  The action byte is the level plus lo(i). */
+static int32_t neg_levels(const ox_class *c, int32_t i) {
+  return (i == c->n_ports || c->v2g) ? c->ip[OXI_N_LEVELS] : 0;
+}
+
+int32_t ox_action_code(const ox_class *c, int32_t i, int32_t k) { return k + neg_levels(c, i); }
 
 void ox_class_tables(const ox_class *c, uint32_t *tpois, uint32_t *tdwell) {
   if (tpois) memcpy(tpois, c->tpois, sizeof(uint32_t) * c->ip[OXI_STEPS_PER_EPISODE] * OX_K_POIS);
@@ -183,10 +207,44 @@ static double charge_rate(double pmax, double tau, double soc) {
   return (1.0 - soc) * pmax / (1.0 - tau);
 }
 
-/* Eq. (ArchConst): for every subtree H, sum of its leaves' powers <= eta_H I_H.
- * Violations are removed by rescaling the leaves of the violated subtree
- * proportionally, deepest subtrees first, so that a parent sees the already
- * rescaled loads of its children. */
+/* Discharging curve: the charging curve mirrored about SoC = 0.5 (App. A.1). */
+static double discharge_rate(double pmax, double tau, double soc) {
+  return charge_rate(pmax, tau, 1.0 - soc);
+}
+
+/* Power of one pole for signed level k (App. A.2 "Apply Actions"): charging
+ * asks for k/L of the charge maximum, clipped by the charging curve and by the
+ * room left in the battery; discharging asks for |k|/L of the discharge
+ * maximum, clipped by the mirrored curve and by the energy stored. */
+static double pole_power(int32_t k, int32_t L, double pmax, double pdis, double tau, double soc,
+                         double cap, double dt) {
+  if (k >= 0) {
+    double v = (double)k / (double)L * pmax;
+    double rhat = charge_rate(pmax, tau, soc);
+    double room = (1.0 - soc) * cap / dt;
+    if (rhat < v) v = rhat;
+    if (room < v) v = room;
+    return v;
+  }
+  double v = (double)(-k) / (double)L * pdis;
+  double rhat = discharge_rate(pmax, tau, soc);
+  double stored = soc * cap / dt;
+  if (rhat < v) v = rhat;
+  if (stored < v) v = stored;
+  return -v;
+}
+
+double ox_battery_power(const ox_class *c, double soc_b, int32_t kb) {
+  if (!has_battery(c)) return 0.0;
+  return pole_power(kb, c->ip[OXI_N_LEVELS], c->b_rate, c->b_rate, c->b_tau, soc_b, c->b_cap,
+                    c->p[OXP_DT]);
+}
+
+/* Eq. (ArchConst): for every subtree H, the magnitude of the sum of its leaves'
+ * powers <= eta_H I_H (a discharging subtree drives the same hardware in
+ * reverse).  Violations are removed by rescaling the leaves of the violated
+ * subtree proportionally, deepest subtrees first, so that a parent sees the
+ * already rescaled loads of its children. */
 void ox_project(const ox_class *c, double *P) {
   const int32_t N = c->n_ports;
   for (int32_t d = c->max_depth; d >= 0; --d) {
@@ -196,8 +254,8 @@ void ox_project(const ox_class *c, double *P) {
       double S = 0.0;
       for (int32_t i = 0; i < N; ++i)
         if (in[i]) S += P[i];
-      if (S > c->node_cap[h]) {
-        double f = c->node_cap[h] / S;
+      if (fabs(S) > c->node_cap[h]) {
+        double f = c->node_cap[h] / fabs(S);
         for (int32_t i = 0; i < N; ++i)
           if (in[i]) P[i] = P[i] * f;
       }
@@ -205,33 +263,21 @@ void ox_project(const ox_class *c, double *P) {
   }
 }
 
-/* App. A.2 "Apply Actions" with absolute discrete levels (Supp. B.1): the
- * requested power k/L * pmax is clipped by the car's current charge rate and by
- * the energy that would fill its battery within one step. */
+/* App. A.2 "Apply Actions" with absolute discrete levels (Supp. B.1): every
+ * occupied port's signed request is clipped (pole_power), then the tree's
+ * limits are enforced. */
 void ox_apply_actions(const ox_class *c, const int32_t *dwell, const double *soc,
                       const double *cap, const int32_t *k, double *P) {
   const double tau = c->p[OXP_TAU], dt = c->p[OXP_DT];
   const int32_t L = c->ip[OXI_N_LEVELS];
-  for (int32_t i = 0; i < c->n_ports; ++i) {
-    if (dwell[i] > 0) {
-      double req = (double)k[i] / (double)L * c->pmax[i];
-      double rhat = charge_rate(c->pmax[i], tau, soc[i]);
-      double room = (1.0 - soc[i]) * cap[i] / dt;
-      double v = req;
-      if (rhat < v) v = rhat;
-      if (room < v) v = room;
-      P[i] = v;
-    } else {
-      P[i] = 0.0;
-    }
-  }
+  for (int32_t i = 0; i < c->n_ports; ++i)
+    P[i] = dwell[i] > 0 ? pole_power(k[i], L, c->pmax[i], c->pdis[i], tau, soc[i], cap[i], dt) : 0.0;
   ox_project(c, P);
 }
 
 /* ------------------------------------------------------------------------- */
 void ox_draw_exo(const ox_class *c, uint64_t seed, uint32_t env, uint32_t g, int32_t t_day,
                  ox_exo *x) {
-  const int32_t S = c->ip[OXI_STEPS_PER_EPISODE];
   uint32_t w[4];
   philox_seeded(seed, env, g, 0u, OX_DOM_ENV, w);
   /* arrivals: M = number of thresholds the word exceeds */
@@ -260,25 +306,33 @@ void ox_draw_exo(const ox_class *c, uint64_t seed, uint32_t env, uint32_t g, int
   }
 }
 
+/* Levels of every action index.  RANDOM: uniform over the index's lo + L + 1
+ * levels from Philox word g & 3 of counter (env, g >> 2, i, ACT); MAX: level L;
+ * EXTERNAL: the given byte minus lo, bytes above lo + L taken as lo + L. */
 void ox_draw_actions(const ox_class *c, int32_t mode, uint64_t seed, uint32_t env, uint32_t g,
                      const uint8_t *ext, int32_t *k) {
   const int32_t L = c->ip[OXI_N_LEVELS];
-  for (int32_t i = 0; i < c->n_ports; ++i) {
+  const int32_t n_act = ox_class_actions(c);
+  for (int32_t i = 0; i < n_act; ++i) {
+    const int32_t lo = neg_levels(c, i);
+    int32_t code;
     if (mode == OX_ACT_RANDOM) {
       uint32_t w[4];
       philox_seeded(seed, env, g >> 2, (uint32_t)i, OX_DOM_ACT, w);
-      k[i] = (int32_t)(((uint64_t)w[g & 3u] * (uint64_t)(L + 1)) >> 32);
+      code = (int32_t)(((uint64_t)w[g & 3u] * (uint64_t)(lo + L + 1)) >> 32);
     } else if (mode == OX_ACT_MAX) {
-      k[i] = L;
+      code = lo + L;
     } else {
-      k[i] = ext[i] > L ? L : (int32_t)ext[i];
+      code = ext[i] > lo + L ? lo + L : (int32_t)ext[i];
     }
+    k[i] = code - lo;
   }
 }
 
 /* ------------------------------------------------------------------------- */
 void ox_observe(const ox_class *c, const int32_t *dwell, const double *soc, const double *e_rem,
-                const double *cap, const double *p_last, int32_t t_day, double *obs) {
+                const double *cap, const double *p_last, const double *batt, int32_t t_day,
+                double *obs) {
   const int32_t N = c->n_ports, S = c->ip[OXI_STEPS_PER_EPISODE];
   const double tau = c->p[OXP_TAU];
   int32_t n_occ = 0;
@@ -297,6 +351,10 @@ void ox_observe(const ox_class *c, const int32_t *dwell, const double *soc, cons
   obs[6 * N + 1] = cos(ang);
   obs[6 * N + 2] = c->price[t_day];
   obs[6 * N + 3] = (double)n_occ / (double)N;
+  if (has_battery(c)) {
+    obs[6 * N + 4] = batt[0];
+    obs[6 * N + 5] = batt[1] / c->b_rate;
+  }
 }
 
 static void clear_port(int32_t i, int32_t *dwell, double *soc, double *e_rem, double *cap,
@@ -307,7 +365,7 @@ static void clear_port(int32_t i, int32_t *dwell, double *soc, double *e_rem, do
 /* App. A.2: (i) apply actions, (ii) charge, (iii) departures, (iv) arrivals;
  * then the reward of App. A.3 and the day boundary of Supp. B.1. */
 void ox_transition(const ox_class *c, int32_t *dwell, double *soc, double *e_rem, double *cap,
-                   double *p_last, double *ret, int32_t *t_day, const int32_t *k,
+                   double *p_last, double *batt, double *ret, int32_t *t_day, const int32_t *k,
                    const ox_exo *x, ox_step_info *info, double *obs, double *P_out) {
   const int32_t N = c->n_ports;
   const double dt = c->p[OXP_DT];
@@ -319,20 +377,33 @@ void ox_transition(const ox_class *c, int32_t *dwell, double *soc, double *e_rem
   if (P_out)
     for (int32_t i = 0; i < N; ++i) P_out[i] = P[i];
 
-  /* (ii) charge stationed cars; energies of App. A.3 (charging only) */
-  double e_net = 0.0, e_grid = 0.0;
+  /* (ii) charge (or discharge) stationed cars; energies of App. A.3: into the
+   * cars (net), drawn from the grid for charging (losses 1/eta), fed back by
+   * discharging cars (losses eta, <= 0) */
+  double e_net = 0.0, e_from_grid = 0.0, e_to_grid = 0.0;
   for (int32_t i = 0; i < N; ++i) {
     was_occ[i] = dwell[i] > 0;
     if (!was_occ[i]) continue;
     double e = dt * P[i];
     double s = soc[i] + e / cap[i];
-    soc[i] = s > 1.0 ? 1.0 : s;
+    soc[i] = s > 1.0 ? 1.0 : (s < 0.0 ? 0.0 : s);
     e_rem[i] = e_rem[i] - e;
     e_net += e;
-    e_grid += e / c->peta[i];
+    if (e > 0.0) e_from_grid += e / c->peta[i];
+    if (e < 0.0) e_to_grid += c->peta[i] * e;
     p_last[i] = P[i];
     dwell[i] -= 1;
   }
+  /* the station battery: the (N+1)-th pole, at the grid connection */
+  double e_batt = 0.0;
+  if (has_battery(c)) {
+    double pb = ox_battery_power(c, batt[0], k[N]);
+    e_batt = dt * pb;
+    double s = batt[0] + e_batt / c->b_cap;
+    batt[0] = s > 1.0 ? 1.0 : (s < 0.0 ? 0.0 : s);
+    batt[1] = pb;
+  }
+  double e_grid = e_from_grid + e_to_grid + e_batt;
 
   /* (iii) departures of time-sensitive users; c_satisfaction,0 */
   double c_sat = 0.0;
@@ -361,17 +432,26 @@ void ox_transition(const ox_class *c, int32_t *dwell, double *soc, double *e_rem
     ++j;
   }
 
-  /* reward: profit minus penalties */
+  /* reward: profit minus penalties (satisfaction, declined cars, degradation
+   * of the station battery when it discharges and of discharged cars) */
   double price = e_grid > 0.0 ? x->p_buy : c->p[OXP_P_SELL_GRID];
   double profit = c->p[OXP_P_SELL] * e_net - price * e_grid - c->p[OXP_FIXED_COST];
-  double reward = profit - c->p[OXP_ALPHA_SAT] * c_sat - c->p[OXP_ALPHA_DEC] * (double)rej;
+  double c_db = e_batt < 0.0 ? -e_batt : 0.0;
+  double c_dc = -e_to_grid;
+  double reward = profit - c->p[OXP_ALPHA_SAT] * c_sat - c->p[OXP_ALPHA_DEC] * (double)rej -
+                  c->a_db * c_db - c->a_dc * c_dc;
   *ret += reward;
 
-  /* time and the end of the day */
+  /* time and the end of the day: every port empties, the battery starts the
+   * next day at its initial SoC */
   *t_day += 1;
   int32_t done = *t_day == c->ip[OXI_STEPS_PER_EPISODE];
   if (done) {
     for (int32_t i = 0; i < N; ++i) clear_port(i, dwell, soc, e_rem, cap, p_last);
+    if (has_battery(c)) {
+      batt[0] = c->b_soc0;
+      batt[1] = 0.0;
+    }
     *t_day = 0;
   }
   int32_t n_occ = 0;
@@ -380,9 +460,9 @@ void ox_transition(const ox_class *c, int32_t *dwell, double *soc, double *e_rem
   if (info) {
     info->reward = reward; info->profit = profit; info->e_net = e_net; info->e_grid = e_grid;
     info->c_sat = c_sat; info->M = x->M; info->acc = acc; info->rej = rej; info->n_dep = n_dep;
-    info->done = done; info->n_occ = n_occ;
+    info->done = done; info->n_occ = n_occ; info->e_to_grid = e_to_grid; info->e_batt = e_batt;
   }
-  if (obs) ox_observe(c, dwell, soc, e_rem, cap, p_last, *t_day, obs);
+  if (obs) ox_observe(c, dwell, soc, e_rem, cap, p_last, batt, *t_day, obs);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -390,40 +470,42 @@ typedef struct {
   ox_class *const *classes;
   const int32_t *env_class;
   const int64_t *env_ids;
-  const int64_t *port_off, *obs_off;
-  int64_t total_ports, total_obs, n_envs;
+  const int64_t *port_off, *act_off, *obs_off;
+  int64_t total_act, total_obs, n_envs;
   int64_t e_begin, e_end;
   uint64_t seed;
   uint32_t g0;
   int32_t t0, T, mode;
   const uint8_t *act_in;
   int32_t *dwell;
-  double *soc, *e_rem, *cap, *p_last, *ret, *obs, *reward;
+  double *soc, *e_rem, *cap, *p_last, *batt, *ret, *obs, *reward;
   uint8_t *act, *done;
   ox_step_info *info;
 } rollout_job;
 
 static void *rollout_worker(void *arg) {
   rollout_job *J = (rollout_job *)arg;
-  int32_t k[OX_MAX_PORTS];
+  int32_t k[OX_MAX_PORTS + 1];
   ox_exo x;
   for (int64_t e = J->e_begin; e < J->e_end; ++e) {
     const ox_class *c = J->classes[J->env_class[e]];
-    const int64_t po = J->port_off[e], oo = J->obs_off[e];
-    const int32_t N = c->n_ports;
+    const int64_t po = J->port_off[e], ao = J->act_off[e], oo = J->obs_off[e];
+    const int32_t n_act = ox_class_actions(c);
+    double *bt = J->batt ? J->batt + 2 * e : NULL;
     int32_t t_day = J->t0;
     const uint32_t eid = (uint32_t)(J->env_ids ? J->env_ids[e] : e);
     for (int32_t t = 0; t < J->T; ++t) {
       uint32_t g = J->g0 + (uint32_t)t;
-      const uint8_t *ext = J->act_in ? J->act_in + (size_t)t * J->total_ports + po : NULL;
+      const uint8_t *ext = J->act_in ? J->act_in + (size_t)t * J->total_act + ao : NULL;
       ox_draw_actions(c, J->mode, J->seed, eid, g, ext, k);
       ox_draw_exo(c, J->seed, eid, g, t_day, &x);
       ox_step_info inf;
       double *o = J->obs ? J->obs + (size_t)t * J->total_obs + oo : NULL;
-      ox_transition(c, J->dwell + po, J->soc + po, J->e_rem + po, J->cap + po, J->p_last + po,
+      ox_transition(c, J->dwell + po, J->soc + po, J->e_rem + po, J->cap + po, J->p_last + po, bt,
                     J->ret + e, &t_day, k, &x, &inf, o, NULL);
       if (J->act)
-        for (int32_t i = 0; i < N; ++i) J->act[(size_t)t * J->total_ports + po + i] = (uint8_t)k[i];
+        for (int32_t i = 0; i < n_act; ++i)
+          J->act[(size_t)t * J->total_act + ao + i] = (uint8_t)ox_action_code(c, i, k[i]);
       if (J->reward) J->reward[(size_t)t * J->n_envs + e] = inf.reward;
       if (J->done) J->done[(size_t)t * J->n_envs + e] = (uint8_t)inf.done;
       if (J->info) J->info[(size_t)t * J->n_envs + e] = inf;
@@ -435,15 +517,17 @@ static void *rollout_worker(void *arg) {
 int32_t ox_rollout(ox_class *const *classes, const int32_t *env_class, const int64_t *env_ids,
                    int64_t n_envs, uint64_t seed, uint32_t *g, int32_t *t_day, int32_t T, int32_t mode,
                    const uint8_t *act_in, int32_t *dwell, double *soc, double *e_rem,
-                   double *cap, double *p_last, double *ret, double *obs, uint8_t *act,
+                   double *cap, double *p_last, double *batt, double *ret, double *obs, uint8_t *act,
                    double *reward, uint8_t *done, ox_step_info *info, int32_t n_threads) {
   int64_t *port_off = (int64_t *)malloc(sizeof(int64_t) * (n_envs + 1));
+  int64_t *act_off = (int64_t *)malloc(sizeof(int64_t) * (n_envs + 1));
   int64_t *obs_off = (int64_t *)malloc(sizeof(int64_t) * (n_envs + 1));
-  port_off[0] = obs_off[0] = 0;
+  port_off[0] = act_off[0] = obs_off[0] = 0;
   for (int64_t e = 0; e < n_envs; ++e) {
     const ox_class *c = classes[env_class[e]];
     port_off[e + 1] = port_off[e] + c->n_ports;
-    obs_off[e + 1] = obs_off[e] + 6 * c->n_ports + 4;
+    act_off[e + 1] = act_off[e] + ox_class_actions(c);
+    obs_off[e + 1] = obs_off[e] + ox_obs_dim(c);
   }
   if (n_threads < 1) n_threads = 1;
   if (n_threads > n_envs) n_threads = n_envs > 0 ? (int32_t)n_envs : 1;
@@ -451,11 +535,12 @@ int32_t ox_rollout(ox_class *const *classes, const int32_t *env_class, const int
   pthread_t *th = (pthread_t *)calloc((size_t)n_threads, sizeof(pthread_t));
   for (int32_t w = 0; w < n_threads; ++w) {
     rollout_job *J = &jobs[w];
-    J->classes = classes; J->env_class = env_class; J->env_ids = env_ids; J->port_off = port_off; J->obs_off = obs_off;
-    J->total_ports = port_off[n_envs]; J->total_obs = obs_off[n_envs]; J->n_envs = n_envs;
+    J->classes = classes; J->env_class = env_class; J->env_ids = env_ids; J->port_off = port_off;
+    J->act_off = act_off; J->obs_off = obs_off;
+    J->total_act = act_off[n_envs]; J->total_obs = obs_off[n_envs]; J->n_envs = n_envs;
     J->e_begin = n_envs * w / n_threads; J->e_end = n_envs * (w + 1) / n_threads;
     J->seed = seed; J->g0 = *g; J->t0 = *t_day; J->T = T; J->mode = mode; J->act_in = act_in;
-    J->dwell = dwell; J->soc = soc; J->e_rem = e_rem; J->cap = cap; J->p_last = p_last;
+    J->dwell = dwell; J->soc = soc; J->e_rem = e_rem; J->cap = cap; J->p_last = p_last; J->batt = batt;
     J->ret = ret; J->obs = obs; J->act = act; J->reward = reward; J->done = done; J->info = info;
   }
   if (n_threads == 1) {
@@ -466,7 +551,7 @@ int32_t ox_rollout(ox_class *const *classes, const int32_t *env_class, const int
   }
   *g += (uint32_t)T;
   *t_day = (int32_t)(((int64_t)*t_day + T) % classes[env_class[0]]->ip[OXI_STEPS_PER_EPISODE]);
-  free(jobs); free(th); free(port_off); free(obs_off);
+  free(jobs); free(th); free(port_off); free(act_off); free(obs_off);
   return n_threads;
 }
 

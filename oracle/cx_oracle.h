@@ -39,6 +39,12 @@
  *   ox_policy         -- numpy FP64 products on the decoded BF16 operands;
  *                        Gumbel-max frequencies equal softmax (chi-square);
  *                        BF16 rounding equal to torch's
+ *   V2G / battery     -- (tests/test_oracle_v2g.py) mirror symmetry: a mirrored
+ *                        state (SoC -> 1 - SoC) under negated levels draws exactly
+ *                        the negated powers through clip and projection;
+ *                        hand-worked discharge, projection and energy cases;
+ *                        the battery equals a V2G port holding a car of the
+ *                        battery's size; uniform signed levels (chi-square)
  *
  * All quantities: power in kW, energy in kWh, time step dt in hours.  The fixed
  * EVSE voltage of Sec. 3 cancels, so currents and powers are interchangeable.
@@ -90,10 +96,13 @@ typedef struct {
   int32_t car_dwell[OX_K_POIS];   /* dwell time of car j in steps, >= 1         */
 } ox_exo;
 
-/* Everything one transition reports besides the new state. */
+/* Everything one transition reports besides the new state.  e_grid is the net
+ * grid energy (grid -> cars + cars -> grid + battery), e_to_grid the (<= 0)
+ * energy discharged cars feed back, e_batt the battery's (signed) energy. */
 typedef struct {
   double reward, profit, e_net, e_grid, c_sat;
   int32_t M, acc, rej, n_dep, done, n_occ;
+  double e_to_grid, e_batt;
 } ox_step_info;
 
 /* ---- class (one station architecture + parameters) ---- */
@@ -106,8 +115,18 @@ void ox_class_free(ox_class *c);
  * day, the Poisson mean of arrivals and the base buying price; NULL keeps the
  * default curves.  Rebuilds the arrival thresholds. */
 void ox_class_set_profiles(ox_class *c, const double *arrival_rate, const double *price_table);
+/* V2G and the station battery (App. A.1 "Endogenous state space", App. A.2
+ * "Apply Actions", App. A.3).  v2g = 1 lets ports discharge: levels -L..L, a
+ * negative level asking for |k|/L of the port's discharge maximum pdis[i]
+ * (NULL = the port maximum).  batt = {capacity kWh (0 = no battery), maximum
+ * rate kW, tau, SoC at the start of a day, alpha_degrad_battery,
+ * alpha_degrad_cars}. */
+void ox_class_set_v2g(ox_class *c, int32_t v2g, const double *pdis, const double *batt);
 int32_t ox_class_ports(const ox_class *c);
-int32_t ox_obs_dim(const ox_class *c);
+int32_t ox_class_actions(const ox_class *c);  /* ports + 1 with a battery */
+int32_t ox_obs_dim(const ox_class *c);        /* 6 N + 4, + 2 with a battery */
+/* The action byte of level k at action index i (i = n_ports: the battery). */
+int32_t ox_action_code(const ox_class *c, int32_t i, int32_t k);
 /* copies of the class's integer sampling tables (steps_per_episode x 24, dwell_max) */
 void ox_class_tables(const ox_class *c, uint32_t *tpois, uint32_t *tdwell);
 
@@ -122,26 +141,35 @@ void ox_apply_actions(const ox_class *c, const int32_t *dwell, const double *soc
 /* The projection of Eq. (ArchConst) alone, in place on P. */
 void ox_project(const ox_class *c, double *P);
 
+/* The battery's power for level kb at state-of-charge soc_b (0 without one). */
+double ox_battery_power(const ox_class *c, double soc_b, int32_t kb);
+
 void ox_draw_exo(const ox_class *c, uint64_t seed, uint32_t env, uint32_t g, int32_t t_day,
                  ox_exo *x);
+/* Signed levels of every action index (ox_class_actions entries: the ports,
+ * then the battery).  ext holds action bytes (EXTERNAL). */
 void ox_draw_actions(const ox_class *c, int32_t mode, uint64_t seed, uint32_t env, uint32_t g,
                      const uint8_t *ext, int32_t *k);
 
-/* One transition of one env, state in place.  obs (obs_dim) may be NULL; P_out
+/* One transition of one env, state in place.  batt = {SoC, last power} of the
+ * station battery (NULL without one).  obs (obs_dim) may be NULL; P_out
  * (n_ports) receives the applied powers and may be NULL. */
 void ox_transition(const ox_class *c, int32_t *dwell, double *soc, double *e_rem, double *cap,
-                   double *p_last, double *ret, int32_t *t_day, const int32_t *k,
+                   double *p_last, double *batt, double *ret, int32_t *t_day, const int32_t *k,
                    const ox_exo *x, ox_step_info *info, double *obs, double *P_out);
 /* Observation of the current state (used after reset and by the policy). */
 void ox_observe(const ox_class *c, const int32_t *dwell, const double *soc, const double *e_rem,
-                const double *cap, const double *p_last, int32_t t_day, double *obs);
+                const double *cap, const double *p_last, const double *batt, int32_t t_day,
+                double *obs);
 
 /* ---- batched rollout over many envs (threads over env ranges) ----
  * env_class[n_envs] indexes classes[]; envs may be in any class order.  State
  * arrays are port-major per env, envs concatenated (port offset = prefix sum of
- * the envs' port counts).  Outputs are time-major:
+ * the envs' port counts); batt holds {SoC, last power} per env (2 n_envs
+ * doubles, used by battery classes only; may be NULL if no class has one).
+ * Outputs are time-major:
  *   obs    [T][sum_e obs_dim(e)]   (may be NULL)
- *   act    [T][sum_e n_ports(e)]   (may be NULL)
+ *   act    [T][sum_e actions(e)]   action bytes (may be NULL)
  *   reward [T][n_envs], done [T][n_envs]  (may be NULL)
  *   info   [T][n_envs] (may be NULL)
  * act_in (EXTERNAL mode) has the act layout.  g and t_day are common to all envs
@@ -152,7 +180,7 @@ int32_t ox_rollout(ox_class *const *classes, const int32_t *env_class, const int
                    int64_t n_envs,
                    uint64_t seed, uint32_t *g, int32_t *t_day, int32_t T, int32_t mode,
                    const uint8_t *act_in, int32_t *dwell, double *soc, double *e_rem,
-                   double *cap, double *p_last, double *ret, double *obs, uint8_t *act,
+                   double *cap, double *p_last, double *batt, double *ret, double *obs, uint8_t *act,
                    double *reward, uint8_t *done, ox_step_info *info, int32_t n_threads);
 
 /* ---- policy (observation -> MLP -> Gumbel-argmax levels) ----

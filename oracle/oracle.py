@@ -38,7 +38,8 @@ def build(force: bool = True) -> str:
 class StepInfo(C.Structure):
     _fields_ = [("reward", C.c_double), ("profit", C.c_double), ("e_net", C.c_double),
                 ("e_grid", C.c_double), ("c_sat", C.c_double), ("M", C.c_int32), ("acc", C.c_int32),
-                ("rej", C.c_int32), ("n_dep", C.c_int32), ("done", C.c_int32), ("n_occ", C.c_int32)]
+                ("rej", C.c_int32), ("n_dep", C.c_int32), ("done", C.c_int32), ("n_occ", C.c_int32),
+                ("e_to_grid", C.c_double), ("e_batt", C.c_double)]
 
 
 class Exo(C.Structure):
@@ -68,11 +69,20 @@ def lib():
         L.ox_apply_actions.argtypes = [P, P, P, P, P, P]
         L.ox_draw_exo.argtypes = [P, C.c_uint64, C.c_uint32, C.c_uint32, I, P]
         L.ox_draw_actions.argtypes = [P, I, C.c_uint64, C.c_uint32, C.c_uint32, P, P]
-        L.ox_transition.argtypes = [P] * 13
-        L.ox_observe.argtypes = [P, P, P, P, P, P, I, P]
+        L.ox_transition.argtypes = [P] * 14
+        L.ox_observe.argtypes = [P, P, P, P, P, P, P, I, P]
         L.ox_rollout.restype = I
         L.ox_rollout.argtypes = [P, P, P, C.c_int64, C.c_uint64, P, P, I, I, P, P, P, P, P, P, P, P,
-                                 P, P, P, P, I]
+                                 P, P, P, P, P, I]
+        L.ox_class_set_v2g.argtypes = [P, I, P, P]
+        L.ox_class_actions.restype = I
+        L.ox_class_actions.argtypes = [P]
+        L.ox_obs_dim.restype = I
+        L.ox_obs_dim.argtypes = [P]
+        L.ox_action_code.restype = I
+        L.ox_action_code.argtypes = [P, I, I]
+        L.ox_battery_power.restype = C.c_double
+        L.ox_battery_power.argtypes = [P, C.c_double, I]
         L.ox_class_set_profiles.argtypes = [P, P, P]
         L.ox_policy.argtypes = [P, I, P, P, P, P, P, C.c_uint64, C.c_uint32, C.c_uint32, P, P, P]
         L.ox_bf16_round.restype = C.c_double
@@ -125,6 +135,15 @@ class OracleClass:
                     raise ValueError("profiles need steps_per_episode entries")
             self._keep += [a for a in prof if a is not None]
             lib().ox_class_set_profiles(self.h, _ptr(prof[0]), _ptr(prof[1]))
+        if getattr(spec, "v2g", 0) or getattr(spec, "battery_kwh", 0.0) > 0.0:
+            pdis = getattr(spec, "port_pdis_kw", None)
+            pd = None if pdis is None else np.ascontiguousarray(pdis, dtype=np.float64)
+            bp = np.array([spec.battery_kwh, spec.battery_kw, spec.battery_tau, spec.battery_soc0,
+                           spec.alpha_degrad_battery, spec.alpha_degrad_cars], dtype=np.float64)
+            self._keep += [a for a in (pd, bp) if a is not None]
+            lib().ox_class_set_v2g(self.h, int(spec.v2g), _ptr(pd), _ptr(bp))
+        self.n_act = lib().ox_class_actions(self.h)
+        self.has_battery = self.n_act > self.n
 
     def __del__(self):
         try:
@@ -135,7 +154,18 @@ class OracleClass:
 
     @property
     def obs_dim(self) -> int:
-        return 6 * self.n + 4
+        return lib().ox_obs_dim(self.h)
+
+    def action_code(self, i: int, k: int) -> int:
+        """The action byte of signed level k at action index i (n_ports = the battery)."""
+        return lib().ox_action_code(self.h, i, k)
+
+    def battery_power(self, soc_b: float, kb: int) -> float:
+        return lib().ox_battery_power(self.h, float(soc_b), int(kb))
+
+    def new_state(self) -> "EnvState":
+        """An empty station at t_day 0 (battery at its initial SoC)."""
+        return EnvState(self.n, self.spec.battery_soc0 if self.has_battery else 0.0)
 
     def tables(self):
         tp = np.zeros((self.spec.steps_per_episode, K_POIS), dtype=np.uint32)
@@ -163,7 +193,8 @@ class OracleClass:
         return x
 
     def draw_actions(self, mode: int, seed: int, env: int, g: int, ext=None) -> np.ndarray:
-        k = np.zeros(self.n, dtype=np.int32)
+        """Signed levels of the ports (and the battery, last)."""
+        k = np.zeros(self.n_act, dtype=np.int32)
         e = None if ext is None else np.ascontiguousarray(ext, dtype=np.uint8)
         lib().ox_draw_actions(self.h, mode, seed, env, g, _ptr(e), _ptr(k))
         return k
@@ -171,7 +202,7 @@ class OracleClass:
     def observe(self, st: "EnvState") -> np.ndarray:
         obs = np.zeros(self.obs_dim, dtype=np.float64)
         lib().ox_observe(self.h, _ptr(st.dwell), _ptr(st.soc), _ptr(st.e_rem), _ptr(st.cap),
-                         _ptr(st.p_last), st.t_day, _ptr(obs))
+                         _ptr(st.p_last), _ptr(st.batt), st.t_day, _ptr(obs))
         return obs
 
     def transition(self, st: "EnvState", k, exo: Exo):
@@ -183,7 +214,8 @@ class OracleClass:
         ret = C.c_double(st.ret)
         t_day = C.c_int32(st.t_day)
         lib().ox_transition(self.h, _ptr(st.dwell), _ptr(st.soc), _ptr(st.e_rem), _ptr(st.cap),
-                            _ptr(st.p_last), C.byref(ret), C.byref(t_day), _ptr(kk), C.byref(exo),
+                            _ptr(st.p_last), _ptr(st.batt), C.byref(ret), C.byref(t_day), _ptr(kk),
+                            C.byref(exo),
                             C.byref(info), _ptr(obs), _ptr(P))
         st.ret = ret.value
         st.t_day = t_day.value
@@ -206,7 +238,8 @@ class OracleClass:
 class EnvState:
     """Mutable state of one env (port-major arrays) for single-env tests."""
 
-    def __init__(self, n_ports: int):
+    def __init__(self, n_ports: int, battery_soc: float = 0.0):
+        self.batt = np.array([battery_soc, 0.0])   # station battery: SoC, last power
         self.dwell = np.zeros(n_ports, dtype=np.int32)
         self.soc = np.zeros(n_ports, dtype=np.float64)
         self.e_rem = np.zeros(n_ports, dtype=np.float64)
@@ -242,12 +275,18 @@ class BatchState:
         self.env_ids = None if env_ids is None else np.ascontiguousarray(env_ids, dtype=np.int64)
         ports = np.array([c.n for c in self.classes], dtype=np.int64)[self.env_class]
         self.port_off = np.concatenate([[0], np.cumsum(ports)])
-        obs = 6 * ports + 4
+        acts = np.array([c.n_act for c in self.classes], dtype=np.int64)[self.env_class]
+        self.act_off = np.concatenate([[0], np.cumsum(acts)])
+        obs = np.array([c.obs_dim for c in self.classes], dtype=np.int64)[self.env_class]
         self.obs_off = np.concatenate([[0], np.cumsum(obs)])
         P = int(self.port_off[-1])
         self.n_envs = len(self.env_class)
         self.total_ports = P
+        self.total_act = int(self.act_off[-1])
         self.total_obs = int(self.obs_off[-1])
+        soc0 = np.array([c.spec.battery_soc0 if c.has_battery else 0.0 for c in self.classes])
+        self.batt = np.zeros(2 * self.n_envs)          # per env: battery SoC, last power
+        self.batt[0::2] = soc0[self.env_class]
         self.dwell = np.zeros(P, dtype=np.int32)
         self.soc = np.zeros(P)
         self.e_rem = np.zeros(P)
@@ -266,7 +305,7 @@ def rollout(bs: BatchState, seed: int, T: int, mode: int = ACT_RANDOM, act_in=No
         n_threads = max(1, min(16, os.cpu_count() or 1))
     handles = (C.c_void_p * len(bs.classes))(*[c.h.value for c in bs.classes])
     obs = np.zeros((T, bs.total_obs)) if want_obs else None
-    act = np.zeros((T, bs.total_ports), dtype=np.uint8) if want_act else None
+    act = np.zeros((T, bs.total_act), dtype=np.uint8) if want_act else None
     rew = np.zeros((T, bs.n_envs))
     done = np.zeros((T, bs.n_envs), dtype=np.uint8)
     info = (StepInfo * (T * bs.n_envs))() if want_info else None
@@ -275,7 +314,7 @@ def rollout(bs: BatchState, seed: int, T: int, mode: int = ACT_RANDOM, act_in=No
     t_day = C.c_int32(bs.t_day)
     used = lib().ox_rollout(handles, _ptr(bs.env_class), _ptr(bs.env_ids), bs.n_envs, seed, C.byref(g), C.byref(t_day),
                             T, mode, _ptr(ain), _ptr(bs.dwell), _ptr(bs.soc), _ptr(bs.e_rem),
-                            _ptr(bs.cap), _ptr(bs.p_last), _ptr(bs.ret), _ptr(obs), _ptr(act),
+                            _ptr(bs.cap), _ptr(bs.p_last), _ptr(bs.batt), _ptr(bs.ret), _ptr(obs), _ptr(act),
                             _ptr(rew), _ptr(done), None if info is None else C.cast(info, C.c_void_p),
                             n_threads)
     bs.g = g.value

@@ -86,6 +86,7 @@ def _env_state(bs, e, N):
     s.e_rem = np.ascontiguousarray(bs.e_rem[sl])
     s.cap = np.ascontiguousarray(bs.cap[sl])
     s.p_last = np.ascontiguousarray(bs.p_last[sl])
+    s.batt = np.ascontiguousarray(bs.batt[2 * e:2 * e + 2])
     s.t_day = bs.t_day
     return s
 

@@ -71,14 +71,33 @@ class StationSpec:
     # Poisson arrival means and base buying prices; None = the smooth defaults
     arrival_rate: Optional[np.ndarray] = None
     price_table: Optional[np.ndarray] = None
+    # V2G: ports also discharge (levels -n_levels..n_levels, the negative ones a
+    # share of port_pdis_kw, default port_pmax_kw); station battery (0 kWh = none)
+    v2g: int = 0
+    port_pdis_kw: Optional[List[float]] = None
+    battery_kwh: float = 0.0
+    battery_kw: float = 0.0
+    battery_tau: float = 0.8
+    battery_soc0: float = 0.5
+    alpha_degrad_battery: float = 0.0
+    alpha_degrad_cars: float = 0.0
 
     @property
     def n_nodes(self) -> int:
         return len(self.node_parent)
 
     @property
+    def has_battery(self) -> bool:
+        return self.battery_kwh > 0.0
+
+    @property
+    def n_actions(self) -> int:
+        """Action bytes per env: one per port, plus one for the battery."""
+        return self.n_ports + (1 if self.has_battery else 0)
+
+    @property
     def obs_dim(self) -> int:
-        return 6 * self.n_ports + 4
+        return 6 * self.n_ports + 4 + (2 if self.has_battery else 0)
 
     def replace(self, **kw) -> "StationSpec":
         return dataclasses.replace(self, **kw)
@@ -181,6 +200,31 @@ def two_charger_types(n_dc: int = 10, n_ac: int = 6, dc_kw: float = 150.0, ac_kw
     pm = [dc_kw] * n_dc + [ac_kw] * n_ac
     return StationSpec(n, [-1, 0, 0], [root_kw, dc_split_kw, ac_split_kw], [1.0, 1.0, 1.0], pp, pm,
                        [1.0] * n, arrival_peak=0.3 * n / 16.0, name=f"types{n_dc}dc{n_ac}ac", **kw)
+
+
+def v2g_station(battery: bool = True, **kw) -> StationSpec:
+    """A 16-port V2G station: 4 splitters of 60 kW x 4 bidirectional 22 kW ports
+    under a 200 kW transformer, with (by default) a 200 kWh / 50 kW station
+    battery; the synthetic stand-in for the paper's V2G and battery scenarios."""
+    s = splitter_tree(4, 4, 60.0, 200.0).replace(v2g=1, name="v2g_split4x4" + ("_batt" if battery else ""))
+    if battery:
+        s = s.replace(battery_kwh=200.0, battery_kw=50.0, battery_tau=0.8, battery_soc0=0.5)
+    return s.replace(**kw) if kw else s
+
+
+def v2g_mixture() -> List[StationSpec]:
+    """V2G classes of several shapes: flat and padded trees, uneven discharge
+    maxima and efficiencies, with and without a battery, plus one charging-only
+    class with a battery."""
+    a = v2g_station(alpha_degrad_battery=0.02, alpha_degrad_cars=0.03, alpha_sat=0.1, alpha_declined=0.5)
+    b = fanout4_tree(12, 2).replace(v2g=1, port_pdis_kw=[11.0] * 6 + [22.0] * 6,
+                                    port_eta=[0.95] * 4 + [0.9] * 8, name="v2g_fan12_d2")
+    c = two_charger_types().replace(v2g=1, battery_kwh=80.0, battery_kw=120.0, battery_tau=0.7,
+                                    battery_soc0=0.3, alpha_degrad_cars=0.05, name="v2g_types_batt")
+    d = fanout4_tree(40, 3).replace(v2g=1, name="v2g_fan40_d3")
+    e = single_transformer(8, 120.0).replace(battery_kwh=60.0, battery_kw=30.0, battery_soc0=0.9,
+                                             alpha_degrad_battery=0.01, name="flat8_batt")
+    return [a, b, c, d, e]
 
 
 # ---- the five workloads ------------------------------------------------------
