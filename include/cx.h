@@ -49,11 +49,16 @@ typedef enum {
 } cx_status;
 
 /* Where the per-port power levels come from.  A level k in 0..n_levels asks for
- * k / n_levels of the port's maximum power (Supp. B.1: discretisation 10). */
+ * k / n_levels of the port's maximum power (Supp. B.1: discretisation 10).
+ * Ports of a V2G class, and the station battery, also take negative levels
+ * -n_levels..-1, asking to discharge |k| / n_levels of the discharge maximum.
+ * Levels travel as action bytes: byte = k + lo, where lo = n_levels for a V2G
+ * port or the battery and 0 otherwise; a class with a battery has one more
+ * action byte per env, after its ports. */
 typedef enum {
-  CX_ACT_EXTERNAL = 0, /* caller-provided uint8 levels (values above n_levels are clamped) */
-  CX_ACT_RANDOM = 1,   /* uniform levels from Philox: k = (w * (n_levels + 1)) >> 32      */
-  CX_ACT_MAX = 2,      /* every port asks for its maximum (the paper's baseline policy)   */
+  CX_ACT_EXTERNAL = 0, /* caller-provided action bytes (above lo + n_levels: clamped)     */
+  CX_ACT_RANDOM = 1,   /* uniform bytes from Philox: (w * (lo + n_levels + 1)) >> 32      */
+  CX_ACT_MAX = 2,      /* every port (and the battery) asks for its maximum charge        */
   CX_ACT_POLICY = 3    /* the MLP set by cx_set_policy, Gumbel-max sampled               */
 } cx_action_mode;
 
@@ -105,6 +110,22 @@ typedef struct {
    *                    price_base + price_amp sin; the noise sigma z is still added). */
   const double *arrival_rate;
   const double *price_table;
+  /* V2G and the station battery (App. A.1 "Endogenous state space", App. A.2
+   * "Apply Actions", App. A.3 energy terms and "Battery Degradation").  A V2G
+   * port discharges along the charging curve mirrored about SoC = 0.5, never
+   * below SoC 0; Eq. (ArchConst) then bounds the magnitude of each node's net
+   * power.  The battery is the (N+1)-th pole, at the grid connection outside
+   * the capacity tree, with the same (mirrored) curves; it starts every day at
+   * battery_soc0.  Grid energy = sum over charging ports of e/eta + sum over
+   * discharging ports of eta e + the battery's e. */
+  int32_t v2g;                  /* 1: ports also discharge (levels -n_levels..-1)      */
+  const double *port_pdis_kw;   /* [n_ports] > 0 discharge maxima, NULL = port_pmax_kw  */
+  double battery_kwh;           /* capacity; 0 = no battery                           */
+  double battery_kw;            /* its maximum (dis)charging rate r_bar (> 0 if any)   */
+  double battery_tau;           /* its charging-curve knee, in (0,1)                   */
+  double battery_soc0;          /* its SoC at the start of every day, in [0,1]         */
+  double alpha_degrad_battery;  /* weight of c_degrad,battery (energy it discharges)   */
+  double alpha_degrad_cars;     /* weight of c_degrad,cars (energy cars feed back)     */
 } cx_station_spec;
 
 typedef struct cx_ctx cx_ctx;
@@ -114,8 +135,11 @@ typedef struct cx_ctx cx_ctx;
  *   obs     float [T][obs_elems]   FULL only; env e at obs_offset(e), 6N+4 floats:
  *           [occupied, SoC, e_rem/C, dwell/S, r_hat/pmax, p_last/pmax] x N ports
  *           (feature-major: feature f of port p at f*N + p), then
- *           [sin 2 pi t/S, cos 2 pi t/S, base price(t), occupied ports / N].
- *   actions uint8 [T][total_ports] FULL and ACT_REWARD: the level applied per port.
+ *           [sin 2 pi t/S, cos 2 pi t/S, base price(t), occupied ports / N],
+ *           then, with a battery, [battery SoC, battery power / battery_kw].
+ *           p_last is negative while a port discharges.
+ *   actions uint8 [T][total_ports] FULL and ACT_REWARD: the action byte applied per
+ *           port (and battery: total_ports counts action bytes).
  *   reward  float [T][n_envs]
  *   done    uint8 [T][n_envs]       1 when the step ended the day (the obs is then the
  *                                   observation of the reset station).
@@ -149,6 +173,7 @@ typedef struct {
   int32_t levels;                /* depth of the capacity tree (levels incl. root) */
   int32_t lanes_per_station;     /* current packing: lanes per station */
   int32_t waves_per_block;
+  int32_t n_actions;             /* action bytes per env: n_ports (+1 with a battery) */
 } cx_class_info;
 
 /* Create a context of n_envs stations of one class, state = empty stations at
@@ -174,7 +199,7 @@ cx_status cx_get_class_info(const cx_ctx *ctx, int32_t cls, cx_class_info *info)
 cx_status cx_reset(cx_ctx *ctx, float *obs_dev);
 
 /* One environment step, one kernel launch, state read from and written back to
- * HBM (the plain form).  actions_dev: uint8 levels [total_ports] (EXTERNAL).
+ * HBM (the plain form).  actions_dev: action bytes [total_ports] (EXTERNAL).
  * obs/reward/done receive one record each (layouts of cx_traj with T = 1);
  * obs_dev may be NULL. */
 cx_status cx_step(cx_ctx *ctx, const uint8_t *actions_dev, float *obs_dev, float *reward_dev,
@@ -202,7 +227,7 @@ cx_status cx_rollout(cx_ctx *ctx, int32_t T, cx_action_mode mode, cx_out_mode ou
  * w1 [obs_dim][hidden], b1 [hidden], w2 [hidden][n_ports*(n_levels+1)], b2.
  * Products run on the matrix cores in BF16 with FP32 accumulation; the level of
  * each port is argmax over its logits plus Gumbel noise from Philox.
- * Only single-class contexts. */
+ * Only single-class contexts of charging-only stations (no V2G, no battery). */
 cx_status cx_set_policy(cx_ctx *ctx, int32_t hidden, const uint16_t *w1_host, const uint16_t *b1_host,
                         const uint16_t *w2_host, const uint16_t *b2_host);
 
@@ -225,11 +250,13 @@ cx_status cx_observe(cx_ctx *ctx, float *obs_dev);
  * packing-independent host format of cx_info.state_bytes bytes, bit-exact, so a
  * restored context continues exactly as the original.  Both calls synchronise
  * the context's stream.  Format (little endian):
- *   u64 magic 0x31305843 ('CX01'), i64 n_envs, i64 total_ports, u32 g, i32 t_day,
+ *   u64 magic 0x31305843 ('CX01'), i64 n_envs, i64 ports (sum of n_ports over
+ *   the envs), u32 g, i32 t_day,
  *   then per port in env/port order (24 bytes): i32 dwell (steps left, 0 = empty),
  *   f64 1 - SoC, f32 1 - target SoC, f32 battery capacity C, f32 last power;
- *   then per env: f64 return.  The energy still wanted is (target - SoC) * C.
- *   An empty port is all zeros. */
+ *   then per env: f64 return; then per env of a class with a station battery,
+ *   in env order (12 bytes): f64 battery SoC, f32 battery last power.
+ *   The energy still wanted is (target - SoC) * C.  An empty port is all zeros. */
 cx_status cx_get_state(cx_ctx *ctx, void *host, size_t bytes);
 cx_status cx_set_state(cx_ctx *ctx, const void *host, size_t bytes);
 

@@ -45,10 +45,12 @@ size_t class_block(const SpecCopy &sc, const Compiled &k, const Tables &t, unsig
   const size_t o_tp = take(sizeof(uint32_t) * t.tpois_dev.size());
   const size_t o_td = take(sizeof(uint32_t) * t.tdwell_dev.size());
   const size_t o_gl = take(sizeof(float) * t.glob.size());
+  const size_t o_pdis = take(sizeof(float) * k.S);
+  const size_t o_eta = take(sizeof(float) * k.S);
   unsigned char *base = dev_base;
   ClassDev d{};
   d.n_ports = k.N; d.S = k.S; d.D = k.D; d.n_levels = s.n_levels;
-  d.steps_ep = s.steps_per_episode; d.obs_dim = 6 * k.N + 4; d.dwell_log2 = t.dwell_log2;
+  d.steps_ep = s.steps_per_episode; d.obs_dim = k.obs_dim; d.dwell_log2 = t.dwell_log2;
   d.uniform_eta = k.uniform_eta ? 1 : 0;
   d.dt = (float)s.dt_hours; d.inv_dt = (float)(1.0 / s.dt_hours); d.inv_1mtau = (float)(1.0 / (1.0 - s.tau));
   d.p_sell = (float)s.p_sell; d.p_sell_grid = (float)s.p_sell_grid; d.fixed_cost = (float)s.fixed_cost;
@@ -81,7 +83,19 @@ size_t class_block(const SpecCopy &sc, const Compiled &k, const Tables &t, unsig
     }
     d.lvl_cap_u[lvl] = cu;
   }
-  d.simple = simple ? 1 : 0;
+  d.kind = k.bidirectional() ? kKindBidir : simple ? kKindSimple : kKindGeneral;
+  d.simple = d.kind == kKindSimple ? 1 : 0;
+  d.n_neg = k.v2g ? s.n_levels : 0;
+  d.has_batt = k.battery ? 1 : 0;
+  d.n_act = k.n_act;
+  d.alpha_db = (float)s.alpha_degrad_battery;
+  d.alpha_dc = (float)s.alpha_degrad_cars;
+  if (k.battery) {
+    d.b_cap = s.battery_kwh; d.b_inv_cap = 1.0 / s.battery_kwh;
+    d.b_rate = s.battery_kw; d.b_inv_1mtau = 1.0 / (1.0 - s.battery_tau);
+    d.b_soc0 = s.battery_soc0; d.b_inv_rate = (float)(1.0 / s.battery_kw);
+  }
+  d.dt_d = s.dt_hours; d.inv_dt_d = 1.0 / s.dt_hours; d.inv_n_d = 1.0 / s.n_levels;
   d.pmax_u = k.slot_pmax[0];
   d.inv_pmax_u = k.slot_inv_pmax[0];
   d.slot_port = reinterpret_cast<const int32_t *>(base + o_port);
@@ -93,6 +107,8 @@ size_t class_block(const SpecCopy &sc, const Compiled &k, const Tables &t, unsig
   d.tpois = reinterpret_cast<const uint32_t *>(base + o_tp);
   d.tdwell = reinterpret_cast<const uint32_t *>(base + o_td);
   d.glob = reinterpret_cast<const float *>(base + o_gl);
+  d.slot_pdis = reinterpret_cast<const float *>(base + o_pdis);
+  d.slot_eta = reinterpret_cast<const float *>(base + o_eta);
   if (view) *view = d;
   if (host) {
     host->assign(off, 0);
@@ -106,6 +122,8 @@ size_t class_block(const SpecCopy &sc, const Compiled &k, const Tables &t, unsig
     std::memcpy(host->data() + o_tp, t.tpois_dev.data(), sizeof(uint32_t) * t.tpois_dev.size());
     std::memcpy(host->data() + o_td, t.tdwell_dev.data(), sizeof(uint32_t) * t.tdwell_dev.size());
     std::memcpy(host->data() + o_gl, t.glob.data(), sizeof(float) * t.glob.size());
+    std::memcpy(host->data() + o_pdis, k.slot_pdis.data(), sizeof(float) * k.S);
+    std::memcpy(host->data() + o_eta, k.slot_eta.data(), sizeof(float) * k.S);
   }
   return off;
 }
@@ -136,27 +154,28 @@ int default_lanes(int S) { return S <= 64 ? S : 64; }
 // Group segments by packing (one kernel each); groups with more slots per
 // station come first so the heaviest waves start first.
 void build_groups(const std::vector<SegDev> &in, const std::vector<int> &log2_dwell,
-                  const std::vector<bool> &simple, int wpb, std::vector<SegDev> *out,
+                  const std::vector<int> &kind, int wpb, std::vector<SegDev> *out,
                   std::vector<LaunchGroup> *groups) {
   out->clear();
   groups->clear();
-  // launch kind = 2 * packing + simple
+  // launch kind = kNumKinds * packing + kernel kind
   std::vector<int> kinds;
   for (size_t i = 0; i < in.size(); ++i) {
-    const int kd = 2 * in[i].pack + (simple[i] ? 1 : 0);
+    const int kd = kNumKinds * in[i].pack + kind[i];
     if (std::find(kinds.begin(), kinds.end(), kd) == kinds.end()) kinds.push_back(kd);
   }
   std::stable_sort(kinds.begin(), kinds.end(), [](int a, int b) {
-    return pack_lanes(a / 2) * pack_per_lane(a / 2) > pack_lanes(b / 2) * pack_per_lane(b / 2);
+    const int pa = a / kNumKinds, pb = b / kNumKinds;
+    return pack_lanes(pa) * pack_per_lane(pa) > pack_lanes(pb) * pack_per_lane(pb);
   });
   for (int kd : kinds) {
     LaunchGroup g;
-    g.pack = kd / 2;
-    g.simple = (kd & 1) != 0;
+    g.pack = kd / kNumKinds;
+    g.kind = kd % kNumKinds;
     g.seg_begin = (int)out->size();
     int blocks = 0;
     for (size_t i = 0; i < in.size(); ++i) {
-      if (2 * in[i].pack + (simple[i] ? 1 : 0) != kd) continue;
+      if (kNumKinds * in[i].pack + kind[i] != kd) continue;
       SegDev sg = in[i];
       sg.block_begin = blocks;
       blocks += (sg.n_groups + wpb - 1) / wpb;
@@ -173,39 +192,60 @@ void build_groups(const std::vector<SegDev> &in, const std::vector<int> &log2_dw
 cx_status rebuild_segments(cx_ctx *ctx) {
   std::vector<SegDev> segs;
   std::vector<int> dl;
-  std::vector<bool> simple;
+  std::vector<int> kind;
   for (ClassRt &c : ctx->classes) {
     if (c.n_envs == 0) continue;
-    SegDev sg{};
     const int L = c.lanes, P = c.comp.S / c.lanes;
     const int spw = 64 / L;
-    sg.cls = c.dev;
-    sg.env0 = c.env_begin;
-    sg.n_envs = c.n_envs;
-    sg.n_groups = (int32_t)((c.n_envs + spw - 1) / spw);
-    sg.pack = pack_id(L, P);
-    sg.seed = ctx->seed;
-    const int64_t so = c.slot_off;
-    sg.q = ctx->q + so;
-    sg.u = ctx->u + so;
-    sg.cap = ctx->cap + so;
-    sg.p_last = ctx->p_last + so;
-    sg.dwell = ctx->dwell + so;
-    sg.ret = ctx->ret + c.env_begin;
-    sg.obs_off = c.obs_off;
-    sg.act_off = c.port_off;
-    sg.env_off = c.env_begin;
-    segs.push_back(sg);
-    dl.push_back(c.tab.dwell_log2);
-    simple.push_back(c.host_view.simple != 0);
+    // the kernels address a segment's records with 32-bit per-lane byte offsets:
+    // a class whose observation block would reach 4 GiB per step is cut into
+    // several segments (whole waves each)
+    int64_t chunk = (int64_t)(((1ull << 32) - 1) / (4ull * (uint64_t)c.comp.obs_dim));
+    chunk -= chunk % 64;
+    for (int64_t e0 = 0; e0 < c.n_envs; e0 += chunk) {
+      const int64_t n = std::min<int64_t>(chunk, c.n_envs - e0);
+      SegDev sg{};
+      sg.cls = c.dev;
+      sg.env0 = c.env_begin + e0;
+      sg.n_envs = n;
+      sg.n_groups = (int32_t)((n + spw - 1) / spw);
+      sg.pack = pack_id(L, P);
+      sg.seed = ctx->seed;
+      const int64_t so = c.slot_off + e0 * c.comp.S;
+      sg.q = ctx->q + so;
+      sg.u = ctx->u + so;
+      sg.cap = ctx->cap + so;
+      sg.p_last = ctx->p_last + so;
+      sg.dwell = ctx->dwell + so;
+      sg.ret = ctx->ret + c.env_begin + e0;
+      sg.bsoc = ctx->bsoc + c.env_begin + e0;
+      sg.bp = ctx->bp + c.env_begin + e0;
+      sg.obs_off = c.obs_off + e0 * c.comp.obs_dim;
+      sg.act_off = c.port_off + e0 * c.comp.n_act;
+      sg.env_off = c.env_begin + e0;
+      segs.push_back(sg);
+      dl.push_back(c.tab.dwell_log2);
+      kind.push_back(c.host_view.kind);
+    }
   }
-  build_groups(segs, dl, simple, ctx->wpb, &ctx->segs_host, &ctx->groups);
-  if (!ctx->segs_dev) {
-    hipError_t e = hipMalloc(&ctx->segs_dev, sizeof(SegDev) * std::max<size_t>(1, ctx->classes.size()));
+  build_groups(segs, dl, kind, ctx->wpb, &ctx->segs_host, &ctx->groups);
+  if (!ctx->segs_dev || ctx->segs_host.size() > ctx->segs_cap) {
+    if (ctx->segs_dev) {
+      hipError_t e = hipStreamSynchronize(ctx->stream);  // launches in flight may still read the old table
+      if (e != hipSuccess) return hip_fail(ctx, e, "segment table resize synchronize");
+      (void)hipFree(ctx->segs_dev);
+      ctx->segs_dev = nullptr;
+    }
+    const size_t cap = std::max<size_t>(ctx->segs_host.size(), ctx->classes.size());
+    hipError_t e = hipMalloc(&ctx->segs_dev, sizeof(SegDev) * std::max<size_t>(1, cap));
     if (e != hipSuccess) return fail_status(CX_E_OOM, "hipMalloc of segment table failed");
+    ctx->segs_cap = cap;
   }
   if (!ctx->segs_host.empty()) {
-    hipError_t e = hipMemcpy(ctx->segs_dev, ctx->segs_host.data(), sizeof(SegDev) * ctx->segs_host.size(),
+    // work still queued on the context's stream reads the current table
+    hipError_t e = ctx->segs_cap ? hipStreamSynchronize(ctx->stream) : hipSuccess;
+    if (e != hipSuccess) return hip_fail(ctx, e, "segment table synchronize");
+    e = hipMemcpy(ctx->segs_dev, ctx->segs_host.data(), sizeof(SegDev) * ctx->segs_host.size(),
                              hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(ctx, e, "upload of segment table");
   }
@@ -260,7 +300,7 @@ static cx_status create_impl(const cx_station_spec *specs, int32_t n_specs, cons
   ctx->seed = seed;
   ctx->n_envs = n_envs;
   ctx->classes.resize(n_specs);
-  int64_t env_begin = 0, port_off = 0, obs_off = 0, slot_off = 0;
+  int64_t env_begin = 0, port_off = 0, obs_off = 0, slot_off = 0, port_count = 0;
   for (int i = 0; i < n_specs; ++i) {
     ClassRt &c = ctx->classes[i];
     std::string err;
@@ -284,9 +324,10 @@ static cx_status create_impl(const cx_station_spec *specs, int32_t n_specs, cons
     c.slot_off = slot_off;
     c.lanes = default_lanes(c.comp.S);
     env_begin += c.n_envs;
-    port_off += c.n_envs * c.comp.N;
-    obs_off += c.n_envs * (6 * c.comp.N + 4);
+    port_off += c.n_envs * c.comp.n_act;
+    obs_off += c.n_envs * c.comp.obs_dim;
     slot_off += c.n_envs * c.comp.S;
+    port_count += c.n_envs * c.comp.N;
   }
   if (hipGetDevice(&ctx->device) != hipSuccess) {
     free_ctx(ctx);
@@ -296,12 +337,15 @@ static cx_status create_impl(const cx_station_spec *specs, int32_t n_specs, cons
   ctx->total_ports = port_off;
   ctx->obs_elems = obs_off;
   ctx->total_slots = slot_off;
-  // state: q (double), u / cap / p_last (float), dwell (int16) over all slots; return per env
+  ctx->port_count = port_count;
+  // state: q (double), u / cap / p_last (float), dwell (int16) over all slots; return,
+  // battery SoC (double) and battery power (float) per env
   const size_t qbytes = align256(sizeof(double) * (size_t)slot_off);
   const size_t fbytes = align256(sizeof(float) * (size_t)slot_off);
   const size_t dbytes = align256(sizeof(int16_t) * (size_t)slot_off);
   const size_t rbytes = align256(sizeof(double) * (size_t)n_envs);
-  const size_t total = qbytes + 3 * fbytes + dbytes + rbytes;
+  const size_t bbytes = align256(sizeof(float) * (size_t)n_envs);
+  const size_t total = qbytes + 3 * fbytes + dbytes + 2 * rbytes + bbytes;
   if (hipMalloc(&ctx->state_mem, total) != hipSuccess) {
     free_ctx(ctx);
     return fail_status(CX_E_OOM, "hipMalloc of station state failed");
@@ -315,9 +359,20 @@ static cx_status create_impl(const cx_station_spec *specs, int32_t n_specs, cons
   ctx->p_last = reinterpret_cast<float *>(b + qbytes + 2 * fbytes);
   ctx->dwell = reinterpret_cast<int16_t *>(b + qbytes + 3 * fbytes);
   ctx->ret = reinterpret_cast<double *>(b + qbytes + 3 * fbytes + dbytes);
+  ctx->bsoc = reinterpret_cast<double *>(b + qbytes + 3 * fbytes + dbytes + rbytes);
+  ctx->bp = reinterpret_cast<float *>(b + qbytes + 3 * fbytes + dbytes + 2 * rbytes);
   if (hipMemset(ctx->state_mem, 0, total) != hipSuccess) {
     free_ctx(ctx);
     return fail_status(CX_E_DEVICE, "hipMemset of station state failed");
+  }
+  // station batteries start at their initial SoC
+  for (const ClassRt &c : ctx->classes) {
+    if (!c.comp.battery || c.n_envs == 0) continue;
+    std::vector<double> v((size_t)c.n_envs, c.spec.s.battery_soc0);
+    if (hipMemcpy(ctx->bsoc + c.env_begin, v.data(), 8 * v.size(), hipMemcpyHostToDevice) != hipSuccess) {
+      free_ctx(ctx);
+      return fail_status(CX_E_DEVICE, "upload of battery state failed");
+    }
   }
   for (auto &c : ctx->classes) {
     cx_status st = upload_class(ctx, c);
@@ -387,11 +442,12 @@ cx_status cx_get_class_info(const cx_ctx *ctx, int32_t cls, cx_class_info *info)
   info->port_offset = c.port_off;
   info->obs_offset = c.obs_off;
   info->n_ports = c.comp.N;
-  info->obs_dim = 6 * c.comp.N + 4;
+  info->obs_dim = c.comp.obs_dim;
   info->slots = c.comp.S;
   info->levels = c.comp.D;
   info->lanes_per_station = c.lanes;
   info->waves_per_block = ctx->wpb;
+  info->n_actions = c.comp.n_act;
   return CX_OK;
 }
 
@@ -399,6 +455,11 @@ cx_status cx_reset(cx_ctx *ctx, float *obs_dev) {
   CTX_CHECK(ctx);
   hipError_t e = hipMemsetAsync(ctx->state_mem, 0, ctx->state_bytes_dev, ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "cx_reset memset");
+  for (const ClassRt &c : ctx->classes) {
+    if (!c.comp.battery || c.n_envs == 0) continue;
+    e = launch_fill_f64(ctx->bsoc + c.env_begin, c.n_envs, c.spec.s.battery_soc0, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "cx_reset battery fill");
+  }
   ctx->t_day = 0;
   if (obs_dev) {
     for (auto &c : ctx->classes) {

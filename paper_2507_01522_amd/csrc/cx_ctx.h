@@ -32,6 +32,7 @@ struct cx_ctx {
   int32_t t_day = 0;
   int32_t steps_ep = 288;
   int64_t n_envs = 0, total_ports = 0, obs_elems = 0, total_slots = 0;
+  int64_t port_count = 0;         // sum of n_ports over the envs (total_ports counts action bytes)
   std::vector<cx::ClassRt> classes;
   // state, env-major slot layout: q = 1 - SoC (double), u = 1 - target SoC,
   // capacity and last power (float), dwell (int16); return per env (double)
@@ -41,8 +42,11 @@ struct cx_ctx {
   float *u = nullptr, *cap = nullptr, *p_last = nullptr;
   int16_t *dwell = nullptr;
   double *ret = nullptr;
+  double *bsoc = nullptr;         // station battery SoC per env (battery classes)
+  float *bp = nullptr;            // station battery last power per env
   // launch layout: segments grouped by slots per lane, one kernel per group
   cx::SegDev *segs_dev = nullptr;
+  size_t segs_cap = 0;            // entries allocated at segs_dev
   std::vector<cx::SegDev> segs_host;
   std::vector<cx::LaunchGroup> groups;
   int wpb = 4;
@@ -59,7 +63,7 @@ cx_status fail_status(cx_status st, const std::string &msg);
 cx_status hip_fail(cx_ctx *ctx, hipError_t e, const char *what);
 cx_status rebuild_segments(cx_ctx *ctx);
 void build_groups(const std::vector<SegDev> &in, const std::vector<int> &log2_dwell,
-                  const std::vector<bool> &simple, int wpb, std::vector<SegDev> *out,
+                  const std::vector<int> &kind, int wpb, std::vector<SegDev> *out,
                   std::vector<LaunchGroup> *groups);
 LaunchArgs base_args(const cx_ctx *ctx);
 void advance_clock(cx_ctx *ctx, int32_t T);

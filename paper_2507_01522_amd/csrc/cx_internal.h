@@ -22,6 +22,9 @@ enum : uint32_t { kDomEnv = 0, kDomAct = 1, kDomCar = 2, kDomGum = 3 };
 // Packings: lanes per station L in {4,...,64} and slots per lane P in {1,2,4};
 // L * P = padded slots of the class.
 constexpr int kNumPackings = 15;
+// Kernel kinds per packing: general classes, SIMPLE classes (every per-slot
+// constant uniform), and bidirectional classes (V2G ports or a station battery).
+enum : int { kKindGeneral = 0, kKindSimple = 1, kKindBidir = 2, kNumKinds = 3 };
 __host__ __device__ constexpr int pack_lanes(int id) { return 4 << (id % 5); }
 __host__ __device__ constexpr int pack_per_lane(int id) { return 1 << (id / 5); }
 inline int pack_id(int lanes, int per_lane) {
@@ -57,6 +60,18 @@ struct ClassDev {
   const uint32_t *tpois;       // [steps_ep][32]
   const uint32_t *tdwell;      // [1 << dwell_log2]: thresholds for stays of 2, 3, ... steps
   const float *glob;           // [steps_ep][4]: sin, cos, base price, 0
+  // bidirectional classes: V2G ports and the station battery (FP64 constants:
+  // the battery is one scalar per station, its arithmetic is kept in FP64)
+  int32_t n_neg;               // discharge levels of a port: n_levels (V2G) or 0
+  int32_t has_batt;            // 1: a station battery (the (N+1)-th action byte)
+  int32_t n_act;               // action bytes per env
+  int32_t kind;                // kKind* of the class
+  float alpha_db, alpha_dc;    // degradation weights: battery discharge, car discharge
+  float b_inv_rate, pad_f;     // 1 / battery maximum rate
+  double b_cap, b_inv_cap, b_rate, b_inv_1mtau, b_soc0;
+  double dt_d, inv_dt_d, inv_n_d;  // dt, 1/dt, 1/n_levels in FP64
+  const float *slot_pdis;      // [S]: discharge maxima
+  const float *slot_eta;       // [S]: efficiencies
 };
 
 // One class's env range inside a launch.  Static fields are set when the
@@ -91,6 +106,9 @@ struct SegDev {
   uint8_t *done;
   const uint8_t *act_in;
   int64_t obs_stride, act_stride, env_stride;
+  // station battery state per env (battery classes): SoC (FP64) and last power
+  double *bsoc;
+  float *bp;
 };
 
 // Launch-wide arguments (by value).
@@ -114,7 +132,7 @@ struct LaunchArgs {
 // instantiated for that packing.
 struct LaunchGroup {
   int pack = 0;         // packing id
-  bool simple = false;  // SIMPLE classes (see ClassDev::simple)
+  int kind = kKindGeneral;  // kernel kind (kKind*)
   int seg_begin = 0;    // index of the first segment in the device segment table
   int n_segs = 0;
   int n_blocks = 0;
@@ -128,9 +146,9 @@ struct LaunchGroup {
 struct RolloutGraph {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  hipGraphNode_t node[2 * kNumPackings] = {};
+  hipGraphNode_t node[kNumKinds * kNumPackings] = {};
   int n_nodes = 0;
-  int shape[2 * kNumPackings][3] = {};
+  int shape[kNumKinds * kNumPackings][3] = {};
   int waves = -1;
 };
 
@@ -142,5 +160,7 @@ hipError_t graph_rollout(RolloutGraph &g, const LaunchArgs &a, const LaunchGroup
                          int waves_per_block, hipStream_t st);
 void graph_destroy(RolloutGraph &g);
 hipError_t launch_reset_obs_one(const ClassDev *cls_dev, int64_t n_envs, float *obs, hipStream_t st);
+// Sets n doubles at p to v (battery SoC at the start of a day).
+hipError_t launch_fill_f64(double *p, int64_t n, double v, hipStream_t st);
 
 }  // namespace cx

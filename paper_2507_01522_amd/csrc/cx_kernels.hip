@@ -15,7 +15,13 @@
 //                     ds_swizzle / bpermute across rows, adds across registers)
 //   charge, departures, arrivals (ballot + popcount ranks), reward, day end,
 //   records.
+// Bidirectional classes (V2G ports, a station battery) run their own kernels:
+// signed levels, the mirrored discharge curve, two-sided limits, the split of
+// the grid energy, and the battery as one FP64 scalar per station that every
+// lane of the station updates alike.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "cx_device.h"
 #include "cx_internal.h"
@@ -150,7 +156,8 @@ __device__ __forceinline__ T ld_at(const T *base, uint32_t byte_off) {
 // port maximum and efficiency, and per tree level one block size and one limit.
 // Port indices and record offsets are then compile-time constants and every
 // per-slot constant is wave-uniform (scalar registers).
-template <int L, int P, bool SIMPLE>
+// BIDIR: V2G ports and / or a station battery (never SIMPLE).
+template <int L, int P, bool SIMPLE, bool BIDIR>
 __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int group, const uint32_t *tdw,
                                           bool tdw_lds) {
   constexpr int SPW = 64 / L;
@@ -165,11 +172,15 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
   const int S = DENSE ? L * P : C.S;
   const int D = C.D;
   const int N = DENSE ? L * P : C.n_ports;
-  const int obs_dim = 6 * N + 4;
+  const int obs_dim = BIDIR ? C.obs_dim : 6 * N + 4;
+  const int n_act = BIDIR ? C.n_act : N;      // action bytes per env
+  const int n_neg = BIDIR ? C.n_neg : 0;      // discharge levels of a port
+  const bool batt = BIDIR && C.has_batt != 0;
 
   // ---- per-slot constants
   int port[P];
   float pmax[P], inv_pmax[P], inv_eta[P], lcap[kMaxLevels][P];
+  float pdis[P], eta[P];  // BIDIR only
   uint32_t lbp[P];
 #pragma unroll
   for (int j = 0; j < P; ++j) {
@@ -189,6 +200,10 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
       lbp[j] = gld(C.slot_lb, s);
 #pragma unroll
       for (int d = 0; d < kMaxLevels; ++d) lcap[d][j] = d < D ? gld(C.slot_cap, d * S + s) : __builtin_inff();
+    }
+    if constexpr (BIDIR) {
+      pdis[j] = gld(C.slot_pdis, s);
+      eta[j] = gld(C.slot_eta, s);
     }
   }
 
@@ -210,6 +225,16 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
     icap[j] = cap[j] > 0.f ? frcp(cap[j]) : 0.f;
   }
   double ret = active ? sg.ret[env] : 0.0;
+  // station battery (BIDIR): SoC in FP64 and last power, alike in every lane of the station
+  double bsoc = 0.0;
+  float bpw = 0.f;
+  if constexpr (BIDIR) {
+    if (batt && active) {
+      bsoc = sg.bsoc[env];
+      bpw = sg.bp[env];
+    }
+  }
+  U4 bw = U4{0, 0, 0, 0};
   // limit of the root (the whole station)
   const float c_root = D == 1 ? lcap[0][0] : D == 2 ? lcap[1][0] : D == 3 ? lcap[2][0] : lcap[3][0];
 
@@ -229,7 +254,7 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
 
   // per-lane byte offsets of this env's records inside a step's segment block
   const uint32_t obs_bo = (uint32_t)env * (uint32_t)obs_dim * 4u;
-  const uint32_t act_bo = (uint32_t)env * (uint32_t)N;
+  const uint32_t act_bo = (uint32_t)env * (uint32_t)n_act;
   const uint32_t env_bo = (uint32_t)env;
   // wave-uniform record pointers of the current step, advanced every step
   // (a record that is not written keeps a NULL pointer and a zero stride)
@@ -267,40 +292,67 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
     const int M = bcast<L>(bM, tb);
     const float pbuy = bcastf<L>(bpb, tb);
 
-    // ---- actions
+    // ---- actions: action bytes k (level + n_neg)
     int k[P];
+    int kb = 0;  // the battery's action byte (level + n_levels)
     if (dy.mode == CX_ACT_RANDOM) {
       if (t == 0 || (g & 3u) == 0) {
 #pragma unroll
         for (int j = 0; j < P; ++j) aw[j] = philox(env_id, g >> 2, (uint32_t)port[j], kDomAct, k0, k1);
+        if constexpr (BIDIR) {
+          if (batt) bw = philox(env_id, g >> 2, (uint32_t)N, kDomAct, k0, k1);
+        }
       }
       const uint32_t sel = g & 3u;
 #pragma unroll
       for (int j = 0; j < P; ++j) {
         const uint32_t w = sel == 0 ? aw[j].x : sel == 1 ? aw[j].y : sel == 2 ? aw[j].z : aw[j].w;
-        k[j] = (int)__umulhi(w, (uint32_t)(n_levels + 1));
+        k[j] = (int)__umulhi(w, (uint32_t)(n_levels + n_neg + 1));
+      }
+      if constexpr (BIDIR) {
+        const uint32_t w = sel == 0 ? bw.x : sel == 1 ? bw.y : sel == 2 ? bw.z : bw.w;
+        kb = (int)__umulhi(w, (uint32_t)(2 * n_levels + 1));
       }
     } else if (dy.mode == CX_ACT_MAX) {
 #pragma unroll
-      for (int j = 0; j < P; ++j) k[j] = n_levels;
+      for (int j = 0; j < P; ++j) k[j] = n_levels + n_neg;
+      kb = 2 * n_levels;
     } else {
 #pragma unroll
       for (int j = 0; j < P; ++j) {
         int v = 0;
         if (active && port[j] >= 0)
           v = ld_at(ai_t, act_bo + (uint32_t)port[j]);
-        k[j] = v > n_levels ? n_levels : v;
+        k[j] = v > n_levels + n_neg ? n_levels + n_neg : v;
+      }
+      if constexpr (BIDIR) {
+        int v = 0;
+        if (batt && active) v = ld_at(ai_t, act_bo + (uint32_t)N);
+        kb = v > 2 * n_levels ? 2 * n_levels : v;
       }
     }
 
-    // ---- apply actions: clip by request, charge curve, battery room
+    // ---- apply actions: clip by request, charge curve, battery room; a
+    // discharging port (BIDIR) by its discharge maximum, the charging curve
+    // mirrored about SoC 1/2 and the energy stored
     float pw[P];
 #pragma unroll
     for (int j = 0; j < P; ++j) {
       const float req = (float)k[j] * C.inv_n_levels * pmax[j];
       const float rhat = pmax[j] * fminf(1.0f, qf[j] * C.inv_1mtau);
       const float room = qf[j] * cap[j] * C.inv_dt;
-      pw[j] = dw[j] > 0 ? fminf(fminf(req, rhat), room) : 0.0f;
+      if constexpr (BIDIR) {
+        const int lev = k[j] - n_neg;
+        const float soc = (float)(1.0 - q[j]);
+        const float creq = (float)lev * C.inv_n_levels * pmax[j];
+        const float dreq = (float)(-lev) * C.inv_n_levels * pdis[j];
+        const float drate = pmax[j] * fminf(1.0f, soc * C.inv_1mtau);
+        const float stored = soc * cap[j] * C.inv_dt;
+        const float p = lev >= 0 ? fminf(fminf(creq, rhat), room) : -fminf(fminf(dreq, drate), stored);
+        pw[j] = dw[j] > 0 ? p : 0.0f;
+      } else {
+        pw[j] = dw[j] > 0 ? fminf(fminf(req, rhat), room) : 0.0f;
+      }
     }
 
     // ---- projection onto the capacity tree (Eq. ArchConst), deepest level
@@ -341,14 +393,39 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
 #pragma unroll
         for (int j = 0; j < P; ++j) {
           const float c = lcap[d][j];
-          pw[j] = s[j] > c ? pw[j] * (c * frcp(s[j])) : pw[j];
+          if constexpr (BIDIR) {
+            const float a = fabsf(s[j]);   // the limit bounds the magnitude of the net power
+            pw[j] = a > c ? pw[j] * (c * frcp(a)) : pw[j];
+          } else {
+            pw[j] = s[j] > c ? pw[j] * (c * frcp(s[j])) : pw[j];
+          }
         }
       }
     }
     // root: the station total before root scaling; the delivered energy is its
     // scaled value (App. A.3, charging only)
-    float e_net, e_grid;
-    {
+    float e_net, e_grid, e_out = 0.f;
+    if constexpr (BIDIR) {
+      float tot = 0.f;
+#pragma unroll
+      for (int j = 0; j < P; ++j) tot += pw[j];
+      tot = station_sum<L>(tot);
+      const float a = fabsf(tot);
+      const bool over = a > c_root;
+      const float f = over ? c_root * frcp(a) : 1.0f;
+#pragma unroll
+      for (int j = 0; j < P; ++j) pw[j] *= f;
+      e_net = C.dt * (over ? copysignf(c_root, tot) : tot);
+      // grid energy: charging ports draw e / eta, discharging ports return eta e
+      float tg = 0.f, to = 0.f;
+#pragma unroll
+      for (int j = 0; j < P; ++j) {
+        tg += pw[j] > 0.f ? pw[j] * inv_eta[j] : pw[j] * eta[j];
+        to += pw[j] < 0.f ? pw[j] * eta[j] : 0.f;
+      }
+      e_grid = C.dt * station_sum<L>(tg);
+      if (C.alpha_dc != 0.0f) e_out = C.dt * station_sum<L>(to);
+    } else {
       float tot = 0.f;
 #pragma unroll
       for (int j = 0; j < P; ++j) tot += pw[j];
@@ -368,6 +445,33 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
       }
     }
 
+    // ---- the station battery (BIDIR): the (N+1)-th pole at the grid
+    // connection, same curves, FP64 like the cars' q
+    float e_b = 0.f;
+    if constexpr (BIDIR) {
+      if (batt) {
+        const int lev = kb - n_levels;
+        const double sb = bsoc;
+        double pb;
+        if (lev >= 0) {
+          const double req = (double)lev * C.inv_n_d * C.b_rate;
+          const double rhat = C.b_rate * fmin(1.0, (1.0 - sb) * C.b_inv_1mtau);
+          const double room = (1.0 - sb) * C.b_cap * C.inv_dt_d;
+          pb = fmin(fmin(req, rhat), room);
+        } else {
+          const double req = (double)(-lev) * C.inv_n_d * C.b_rate;
+          const double rhat = C.b_rate * fmin(1.0, sb * C.b_inv_1mtau);
+          const double stored = sb * C.b_cap * C.inv_dt_d;
+          pb = -fmin(fmin(req, rhat), stored);
+        }
+        const double eb = C.dt_d * pb;
+        const double ns = sb + eb * C.b_inv_cap;
+        bsoc = ns > 1.0 ? 1.0 : (ns < 0.0 ? 0.0 : ns);
+        bpw = (float)pb;
+        e_b = (float)eb;
+      }
+    }
+
     // ---- charge, departures (selects: no branches)
     float csat = 0.f;
 #pragma unroll
@@ -376,6 +480,7 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
       const float e = C.dt * pw[j];
       const double nq = q[j] - (double)(e * icap[j]);
       q[j] = nq > 0.0 ? nq : 0.0;
+      if constexpr (BIDIR) q[j] = q[j] < 1.0 ? q[j] : 1.0;  // discharging never below SoC 0
       qf[j] = (float)q[j];
       plast[j] = pw[j];
       dw[j] -= occ ? 1 : 0;
@@ -436,9 +541,16 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
     }
 
     // ---- reward (App. A.3)
-    const float price = e_grid > 0.0f ? pbuy : C.p_sell_grid;
-    const float r = C.p_sell * e_net - price * e_grid - C.fixed_cost - C.alpha_sat * csat -
-                    C.alpha_dec * (float)rej;
+    float r;
+    if constexpr (BIDIR) {
+      const float e_gn = e_grid + e_b;
+      const float price = e_gn > 0.0f ? pbuy : C.p_sell_grid;
+      r = C.p_sell * e_net - price * e_gn - C.fixed_cost - C.alpha_sat * csat - C.alpha_dec * (float)rej -
+          C.alpha_db * fmaxf(0.0f, -e_b) + C.alpha_dc * e_out;
+    } else {
+      const float price = e_grid > 0.0f ? pbuy : C.p_sell_grid;
+      r = C.p_sell * e_net - price * e_grid - C.fixed_cost - C.alpha_sat * csat - C.alpha_dec * (float)rej;
+    }
     ret += (double)r;
 
     // ---- end of day
@@ -449,6 +561,12 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
 #pragma unroll
       for (int j = 0; j < P; ++j) {
         dw[j] = 0; q[j] = 0.0; qf[j] = 0.f; u[j] = 0.f; cap[j] = 0.f; icap[j] = 0.f; plast[j] = 0.f;
+      }
+      if constexpr (BIDIR) {
+        if (batt) {
+          bsoc = C.b_soc0;
+          bpw = 0.f;
+        }
       }
     }
 
@@ -474,12 +592,19 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
           const float gv = l == 3 ? (float)n_occ * (1.0f / (float)N) : gld(C.glob, t_day * 4 + l);
           st_at(ob, obs_bo + 4u * (uint32_t)(6 * N + l), gv);
         }
+        if constexpr (BIDIR) {
+          if (batt && l < 2)
+            st_at(ob, obs_bo + 4u * (uint32_t)(6 * N + 4 + l), l == 0 ? (float)bsoc : bpw * C.b_inv_rate);
+        }
       }
       if (w_act) {
         uint8_t *ab = ab_t;
 #pragma unroll
         for (int j = 0; j < P; ++j)
           if (DENSE || port[j] >= 0) st_at(ab, act_bo + (uint32_t)port[j], (uint8_t)k[j]);
+        if constexpr (BIDIR) {
+          if (batt && l == 0) st_at(ab, act_bo + (uint32_t)N, (uint8_t)kb);
+        }
       }
       if (l == 0) {
         if (rw_t) st_at(rw_t, 4u * env_bo, r);
@@ -510,12 +635,18 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
       sg.dwell[i] = (int16_t)dw[j];
     }
     if (l == 0) sg.ret[env] = ret;
+    if constexpr (BIDIR) {
+      if (batt && l == 0) {
+        sg.bsoc[env] = bsoc;
+        sg.bp[env] = bpw;
+      }
+    }
   }
 }
 
 // One kernel per packing (lanes per station L, slots per lane P) and class
-// kind (SIMPLE or general), so that each keeps its own register budget.
-template <int L, int P, bool SIMPLE>
+// kind (general, SIMPLE, bidirectional), so that each keeps its own register budget.
+template <int L, int P, bool SIMPLE, bool BIDIR>
 __global__ __launch_bounds__(512) void k_rollout(LaunchArgs a) {
   extern __shared__ uint32_t lds_tdwell[];
   const int b = blockIdx.x;
@@ -549,7 +680,7 @@ __global__ __launch_bounds__(512) void k_rollout(LaunchArgs a) {
   const int W = blockDim.x >> 6;
   const int group = __builtin_amdgcn_readfirstlane((b - sg.block_begin) * W + (int)(threadIdx.x >> 6));
   if (group >= sg.n_groups) return;
-  run_group<L, P, SIMPLE>(sg, dy, group, tdw, tdw_lds);
+  run_group<L, P, SIMPLE, BIDIR>(sg, dy, group, tdw, tdw_lds);
 }
 
 // Observation of empty stations at t_day = 0 for every env of one segment.
@@ -562,28 +693,28 @@ __global__ void k_reset_obs(const ClassDev *cls, int64_t n_envs, float *obs) {
     const int64_t f = i % dim;
     float v = 0.f;
     if (f >= 6 * N && f < 6 * N + 3) v = cls->glob[f - 6 * N];
+    if (f == 6 * N + 4) v = (float)cls->b_soc0;  // a battery starts the day at its initial SoC
     obs[i] = v;
   }
 }
 
-using KernelFn = void (*)(LaunchArgs);
-
-template <int L, int P, bool S>
-constexpr KernelFn kfn() {
-  return &k_rollout<L, P, S>;
+__global__ void k_fill_f64(double *p, int64_t n, double v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
 }
 
+using KernelFn = void (*)(LaunchArgs);
+
+// The three kernels of one packing: general, SIMPLE, bidirectional.
+#define CX_KINDS(L, P) &k_rollout<L, P, false, false>, &k_rollout<L, P, true, false>, &k_rollout<L, P, false, true>
+
 // Kernel of each launch kind: packing id (P index * 5 + L index, as pack_id())
-// times 2, plus 1 for SIMPLE classes.
-const KernelFn kKernels[2 * kNumPackings] = {
-    kfn<4, 1, false>(),  kfn<4, 1, true>(),  kfn<8, 1, false>(),  kfn<8, 1, true>(),
-    kfn<16, 1, false>(), kfn<16, 1, true>(), kfn<32, 1, false>(), kfn<32, 1, true>(),
-    kfn<64, 1, false>(), kfn<64, 1, true>(), kfn<4, 2, false>(),  kfn<4, 2, true>(),
-    kfn<8, 2, false>(),  kfn<8, 2, true>(),  kfn<16, 2, false>(), kfn<16, 2, true>(),
-    kfn<32, 2, false>(), kfn<32, 2, true>(), kfn<64, 2, false>(), kfn<64, 2, true>(),
-    kfn<4, 4, false>(),  kfn<4, 4, true>(),  kfn<8, 4, false>(),  kfn<8, 4, true>(),
-    kfn<16, 4, false>(), kfn<16, 4, true>(), kfn<32, 4, false>(), kfn<32, 4, true>(),
-    kfn<64, 4, false>(), kfn<64, 4, true>()};
+// times kNumKinds, plus the kernel kind (kKind*).
+const KernelFn kKernels[kNumKinds * kNumPackings] = {
+    CX_KINDS(4, 1), CX_KINDS(8, 1), CX_KINDS(16, 1), CX_KINDS(32, 1), CX_KINDS(64, 1),
+    CX_KINDS(4, 2), CX_KINDS(8, 2), CX_KINDS(16, 2), CX_KINDS(32, 2), CX_KINDS(64, 2),
+    CX_KINDS(4, 4), CX_KINDS(8, 4), CX_KINDS(16, 4), CX_KINDS(32, 4), CX_KINDS(64, 4)};
+#undef CX_KINDS
 
 // Arguments of one group's launch: its slice of the segment table and its LDS.
 LaunchArgs group_args(const LaunchArgs &a, const LaunchGroup &g, size_t *lds) {
@@ -606,7 +737,7 @@ hipError_t launch_groups(const LaunchArgs &a, const LaunchGroup *groups, int n_g
     size_t lds = 0;
     LaunchArgs b = group_args(a, g, &lds);
     void *params[1] = {&b};
-    hipError_t e = hipLaunchKernel(reinterpret_cast<const void *>(kKernels[2 * g.pack + (g.simple ? 1 : 0)]), dim3(g.n_blocks),
+    hipError_t e = hipLaunchKernel(reinterpret_cast<const void *>(kKernels[kNumKinds * g.pack + g.kind]), dim3(g.n_blocks),
                                    dim3(64 * waves_per_block), params, lds, st);
     if (e != hipSuccess) return e;
   }
@@ -615,25 +746,25 @@ hipError_t launch_groups(const LaunchArgs &a, const LaunchGroup *groups, int n_g
 
 hipError_t graph_rollout(RolloutGraph &G, const LaunchArgs &a, const LaunchGroup *groups, int n_groups,
                          int waves_per_block, hipStream_t st) {
-  LaunchArgs args[2 * kNumPackings];
-  void *params[2 * kNumPackings][1];
-  hipKernelNodeParams p[2 * kNumPackings];
-  int shape[2 * kNumPackings][3] = {};
+  LaunchArgs args[kNumKinds * kNumPackings];
+  void *params[kNumKinds * kNumPackings][1];
+  hipKernelNodeParams p[kNumKinds * kNumPackings];
+  int shape[kNumKinds * kNumPackings][3] = {};
   int n = 0;
-  for (int i = 0; i < n_groups && n < 2 * kNumPackings; ++i) {
+  for (int i = 0; i < n_groups && n < kNumKinds * kNumPackings; ++i) {
     const LaunchGroup &g = groups[i];
     if (g.n_blocks <= 0) continue;
     size_t lds = 0;
     args[n] = group_args(a, g, &lds);
     params[n][0] = &args[n];
     p[n] = hipKernelNodeParams{};
-    p[n].func = reinterpret_cast<void *>(kKernels[2 * g.pack + (g.simple ? 1 : 0)]);
+    p[n].func = reinterpret_cast<void *>(kKernels[kNumKinds * g.pack + g.kind]);
     p[n].gridDim = dim3(g.n_blocks);
     p[n].blockDim = dim3(64 * waves_per_block);
     p[n].sharedMemBytes = (unsigned)lds;
     p[n].kernelParams = params[n];
     p[n].extra = nullptr;
-    shape[n][0] = 2 * g.pack + (g.simple ? 1 : 0);
+    shape[n][0] = kNumKinds * g.pack + g.kind;
     shape[n][1] = g.n_blocks;
     shape[n][2] = (int)lds;
     ++n;
@@ -669,6 +800,13 @@ void graph_destroy(RolloutGraph &g) {
 hipError_t launch_reset_obs_one(const ClassDev *cls_dev, int64_t n_envs, float *obs, hipStream_t st) {
   if (n_envs <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_reset_obs, dim3(256), dim3(256), 0, st, cls_dev, n_envs, obs);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_f64(double *p, int64_t n, double v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int blocks = (int)std::min<int64_t>(1024, (n + 255) / 256);
+  hipLaunchKernelGGL(k_fill_f64, dim3(blocks), dim3(256), 0, st, p, n, v);
   return hipGetLastError();
 }
 

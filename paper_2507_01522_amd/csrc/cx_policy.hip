@@ -308,7 +308,8 @@ __global__ __launch_bounds__(64 * kPolWaves) void k_policy(PolicyArgs a) {
 
 // Observation of the current state (the features the step kernel records).
 __global__ void k_observe(const ClassDev *cls, int64_t n_envs, const double *q, const float *u,
-                          const float *p_last, const int16_t *dwell, int32_t t_day, float *obs) {
+                          const float *p_last, const int16_t *dwell, const double *bsoc, const float *bp,
+                          int32_t t_day, float *obs) {
   const ClassDev C = *cls;
   const int S = C.S, N = C.n_ports, dim = C.obs_dim;
   const int64_t total = n_envs * S;
@@ -338,6 +339,10 @@ __global__ void k_observe(const ClassDev *cls, int64_t n_envs, const double *q, 
     o[1] = C.glob[t_day * 4 + 1];
     o[2] = C.glob[t_day * 4 + 2];
     o[3] = (float)n_occ * (1.0f / (float)N);
+    if (C.has_batt) {
+      o[4] = (float)bsoc[env];
+      o[5] = bp[env] * C.b_inv_rate;
+    }
   }
 }
 
@@ -355,8 +360,8 @@ hipError_t launch_observe(const cx_ctx *ctx, float *obs, hipStream_t st) {
     const int64_t work = c.n_envs * c.comp.S;
     const int blocks = (int)std::min<int64_t>(4096, (work + 255) / 256);
     hipLaunchKernelGGL(k_observe, dim3(blocks), dim3(256), 0, st, c.dev, c.n_envs, ctx->q + c.slot_off,
-                       ctx->u + c.slot_off, ctx->p_last + c.slot_off, ctx->dwell + c.slot_off, ctx->t_day,
-                       obs + c.obs_off);
+                       ctx->u + c.slot_off, ctx->p_last + c.slot_off, ctx->dwell + c.slot_off,
+                       ctx->bsoc + c.env_begin, ctx->bp + c.env_begin, ctx->t_day, obs + c.obs_off);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -464,6 +469,8 @@ cx_status cx_set_policy(cx_ctx *ctx, int32_t hidden, const uint16_t *w1, const u
   if (!w1 || !b1 || !w2 || !b2) return fail_status(CX_E_INVALID, "cx_set_policy: NULL weight array");
   if (ctx->classes.size() != 1) return fail_status(CX_E_INVALID, "cx_set_policy: single-class contexts only");
   const ClassRt &c = ctx->classes[0];
+  if (c.comp.bidirectional())
+    return fail_status(CX_E_INVALID, "cx_set_policy: charging-only stations only (no V2G, no battery)");
   const int N = c.comp.N, L1 = c.spec.s.n_levels + 1, in_dim = 6 * N + 4;
   if (hidden < 32 || hidden > 32 * kPolHP || hidden % 32 != 0)
     return fail_status(CX_E_INVALID, "cx_set_policy: hidden must be a multiple of 32 in 32..256");

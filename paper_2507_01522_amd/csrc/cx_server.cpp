@@ -51,7 +51,7 @@ struct Req {
   cx_traj traj{};                // effective output buffers
   // device layout: [class block | state | server-owned outputs]
   size_t class_bytes = 0, state_bytes = 0, out_bytes = 0, total = 0;
-  size_t off_q = 0, off_u = 0, off_cap = 0, off_pl = 0, off_dw = 0, off_ret = 0;
+  size_t off_q = 0, off_u = 0, off_cap = 0, off_pl = 0, off_dw = 0, off_ret = 0, off_bsoc = 0, off_bp = 0;
   size_t off_obs = 0, off_act = 0, off_rew = 0, off_done = 0;
   std::vector<unsigned char> class_host;  // kept until the request ends (async upload source)
   ClassDev view{};
@@ -162,8 +162,8 @@ namespace {
 
 // Byte sizes and offsets of a request's device block.
 void plan(Req &r) {
-  const int64_t E = r.n_envs, S = r.comp.S, N = r.comp.N, T = r.T;
-  const int64_t od = 6 * N + 4;
+  const int64_t E = r.n_envs, S = r.comp.S, A = r.comp.n_act, T = r.T;
+  const int64_t od = r.comp.obs_dim;
   r.class_bytes = a256(class_block(r.spec, r.comp, r.tab, nullptr, nullptr, nullptr));
   size_t o = r.class_bytes;
   r.off_q = o; o = a256(o + 8 * (size_t)(E * S));
@@ -172,13 +172,15 @@ void plan(Req &r) {
   r.off_pl = o; o = a256(o + 4 * (size_t)(E * S));
   r.off_dw = o; o = a256(o + 2 * (size_t)(E * S));
   r.off_ret = o; o = a256(o + 8 * (size_t)E);
+  r.off_bsoc = o; o = a256(o + (r.comp.battery ? 8 * (size_t)E : 0));
+  r.off_bp = o; o = a256(o + (r.comp.battery ? 4 * (size_t)E : 0));
   r.state_bytes = o - r.class_bytes;
   const size_t out0 = o;
   const bool want_obs = r.out_mode == CX_OUT_FULL;
   const bool want_act = r.out_mode != CX_OUT_REWARD;
   r.off_obs = r.off_act = r.off_rew = r.off_done = 0;
   if (want_obs && !r.user.obs) { r.off_obs = o; o = a256(o + 4 * (size_t)(T * E * od)); }
-  if (want_act && !r.user.actions) { r.off_act = o; o = a256(o + (size_t)(T * E * N)); }
+  if (want_act && !r.user.actions) { r.off_act = o; o = a256(o + (size_t)(T * E * A)); }
   if (!r.user.reward) { r.off_rew = o; o = a256(o + 4 * (size_t)(T * E)); }
   if (!r.user.done) { r.off_done = o; o = a256(o + (size_t)(T * E)); }
   r.out_bytes = o - out0;
@@ -263,7 +265,9 @@ bool admit(cx_server *s) {
       class_block(r.spec, r.comp, r.tab, b, &r.class_host, &r.view);
       if (hipMemcpyAsync(b, r.class_host.data(), r.class_host.size(), hipMemcpyHostToDevice, s->stream) !=
               hipSuccess ||
-          hipMemsetAsync(b + r.class_bytes, 0, r.state_bytes, s->stream) != hipSuccess) {
+          hipMemsetAsync(b + r.class_bytes, 0, r.state_bytes, s->stream) != hipSuccess ||
+          (r.comp.battery && launch_fill_f64(reinterpret_cast<double *>(b + r.off_bsoc), r.n_envs,
+                                             r.spec.s.battery_soc0, s->stream) != hipSuccess)) {
         s->arena.give(r.arena_off, r.total);
         r.mem = nullptr;
         s->failed = true;
@@ -292,7 +296,7 @@ bool launch(cx_server *s) {
   if ((int)s->inflight.size() >= kMaxInflight) return false;
   std::vector<SegDev> segs;
   std::vector<int> dl;
-  std::vector<bool> simple;
+  std::vector<int> kind;
   Chunk c;
   for (uint64_t tk : s->active) {
     Req &r = *s->reqs[tk];
@@ -301,7 +305,7 @@ bool launch(cx_server *s) {
     SegDev sg{};
     const int L = r.lanes, P = r.comp.S / r.lanes, spw = 64 / L;
     unsigned char *b = static_cast<unsigned char *>(r.mem);
-    const int64_t E = r.n_envs, N = r.comp.N, od = 6 * N + 4, t = r.launched;
+    const int64_t E = r.n_envs, A = r.comp.n_act, od = r.comp.obs_dim, t = r.launched;
     sg.cls = reinterpret_cast<const ClassDev *>(b);
     sg.env0 = 0;
     sg.n_envs = E;
@@ -315,8 +319,10 @@ bool launch(cx_server *s) {
       sg.p_last = reinterpret_cast<float *>(b + r.off_pl);
       sg.dwell = reinterpret_cast<int16_t *>(b + r.off_dw);
       sg.ret = reinterpret_cast<double *>(b + r.off_ret);
+      sg.bsoc = reinterpret_cast<double *>(b + r.off_bsoc);
+      sg.bp = reinterpret_cast<float *>(b + r.off_bp);
       sg.obs = r.traj.obs ? r.traj.obs + t * E * od : nullptr;
-      sg.act = r.traj.actions ? r.traj.actions + t * E * N : nullptr;
+      sg.act = r.traj.actions ? r.traj.actions + t * E * A : nullptr;
       sg.reward = r.traj.reward + t * E;
       sg.done = r.traj.done + t * E;
     }
@@ -326,11 +332,11 @@ bool launch(cx_server *s) {
     sg.mode = r.act_mode;
     sg.out_mode = r.out_mode;
     sg.obs_stride = E * od;
-    sg.act_stride = E * N;
+    sg.act_stride = E * A;
     sg.env_stride = E;
     segs.push_back(sg);
     dl.push_back(r.tab.dwell_log2);
-    simple.push_back(r.view.simple != 0);
+    kind.push_back(r.view.kind);
     c.members.push_back({tk, n});
     c.env_steps += E * n;
     r.launched += n;
@@ -349,7 +355,7 @@ bool launch(cx_server *s) {
   }
   std::vector<SegDev> ordered;
   std::vector<LaunchGroup> groups;
-  build_groups(segs, dl, simple, s->opts.waves_per_block, &ordered, &groups);
+  build_groups(segs, dl, kind, s->opts.waves_per_block, &ordered, &groups);
   const int slot = s->ring_next;
   s->ring_next = (s->ring_next + 1) % kRing;
   if (s->ring_used[slot]) (void)hipEventSynchronize(s->ring_ev[slot]);  // earlier copy out of this buffer done
@@ -505,7 +511,7 @@ cx_status cx_submit(cx_server *s, const cx_request *req, uint64_t *ticket) {
     return fail_status(CX_E_INVALID, "station spec: " + err);
   build_tables(r->spec, &r->tab);
   if (!tables_monotone(r->tab)) return fail(CX_E_INVALID, "sampling tables are not monotone");
-  if ((uint64_t)req->n_envs * (uint64_t)(6 * r->comp.N + 4) * 4 >= (1ull << 32))
+  if ((uint64_t)req->n_envs * (uint64_t)r->comp.obs_dim * 4 >= (1ull << 32))
     return fail(CX_E_INVALID, "request too large for one segment (n_envs * obs_dim * 4 >= 2^32)");
   r->n_envs = req->n_envs;
   r->T = req->T;

@@ -57,6 +57,9 @@ bool copy_spec(const cx_station_spec &in, SpecCopy *out, std::string *err) {
   if (in.price_table) out->price_table.assign(in.price_table, in.price_table + S);
   out->s.arrival_rate = in.arrival_rate ? out->arrival_rate.data() : nullptr;
   out->s.price_table = in.price_table ? out->price_table.data() : nullptr;
+  if (in.port_pdis_kw) out->port_pdis.assign(in.port_pdis_kw, in.port_pdis_kw + in.n_ports);
+  else out->port_pdis = out->port_pmax;
+  out->s.port_pdis_kw = out->port_pdis.data();
   return true;
 }
 
@@ -86,6 +89,19 @@ bool compile_spec(const SpecCopy &sc, Compiled *c, std::string *err) {
     if (!(v >= 0.0 && v <= 8.0)) return fail(err, "arrival_rate entries must be in [0, 8]");
   for (double v : sc.price_table)
     if (!std::isfinite(v)) return fail(err, "price_table entries must be finite");
+  if (s.v2g != 0 && s.v2g != 1) return fail(err, "v2g must be 0 or 1");
+  if ((s.v2g || s.battery_kwh > 0.0) && s.n_levels > 127)
+    return fail(err, "n_levels must be at most 127 with discharging (signed levels fit an action byte)");
+  for (double v : sc.port_pdis)
+    if (!finite_pos(v)) return fail(err, "port_pdis_kw must be > 0");
+  if (!(s.battery_kwh >= 0.0) || !std::isfinite(s.battery_kwh)) return fail(err, "battery_kwh must be >= 0");
+  if (s.battery_kwh > 0.0) {
+    if (!finite_pos(s.battery_kw)) return fail(err, "battery_kw must be > 0");
+    if (!(s.battery_tau > 0.0 && s.battery_tau < 1.0)) return fail(err, "battery_tau must be in (0,1)");
+    if (!(s.battery_soc0 >= 0.0 && s.battery_soc0 <= 1.0)) return fail(err, "battery_soc0 must be in [0,1]");
+  }
+  if (!std::isfinite(s.alpha_degrad_battery) || !std::isfinite(s.alpha_degrad_cars))
+    return fail(err, "degradation weights must be finite");
   // ---- tree
   if (sc.node_parent[0] != -1) return fail(err, "node 0 must be the root (parent -1)");
   for (int h = 1; h < H; ++h)
@@ -166,16 +182,24 @@ bool compile_spec(const SpecCopy &sc, Compiled *c, std::string *err) {
   c->slot_pmax.assign(S, 0.f);
   c->slot_inv_pmax.assign(S, 0.f);
   c->slot_inv_eta.assign(S, 1.f);
+  c->slot_pdis.assign(S, 0.f);
+  c->slot_eta.assign(S, 1.f);
   bool uni = true;
   for (int i = 0; i < N; ++i) {
     const int x = c->port_slot[i];
     c->slot_pmax[x] = (float)sc.port_pmax[i];
     c->slot_inv_pmax[x] = (float)(1.0 / sc.port_pmax[i]);
     c->slot_inv_eta[x] = (float)(1.0 / sc.port_eta[i]);
+    c->slot_pdis[x] = (float)sc.port_pdis[i];
+    c->slot_eta[x] = (float)sc.port_eta[i];
     if (sc.port_eta[i] != sc.port_eta[0]) uni = false;
   }
   c->uniform_eta = uni;
   c->inv_eta_uniform = (float)(1.0 / sc.port_eta[0]);
+  c->v2g = s.v2g == 1;
+  c->battery = s.battery_kwh > 0.0;
+  c->n_act = N + (c->battery ? 1 : 0);
+  c->obs_dim = 6 * N + 4 + (c->battery ? 2 : 0);
   return true;
 }
 

@@ -14,6 +14,7 @@ struct SpecCopy {
   std::vector<int32_t> node_parent, port_parent;
   std::vector<double> node_limit, node_eta, port_pmax, port_eta;
   std::vector<double> arrival_rate, price_table;  // empty: the default curves
+  std::vector<double> port_pdis;                  // discharge maxima (port maxima if not given)
 };
 
 // The capacity tree in the kernels' layout.  Every node owns an aligned block of
@@ -27,8 +28,12 @@ struct Compiled {
   std::vector<uint32_t> slot_lb;    // [S], 8 bits per level
   std::vector<float> slot_cap;      // [D][S]
   std::vector<float> slot_pmax, slot_inv_pmax, slot_inv_eta;
+  std::vector<float> slot_pdis, slot_eta;  // discharge maxima and efficiencies (V2G)
   bool uniform_eta = true;
   float inv_eta_uniform = 1.f;
+  bool v2g = false, battery = false;       // ports discharge / a station battery
+  int n_act = 0, obs_dim = 0;              // action bytes and observation floats per env
+  bool bidirectional() const { return v2g || battery; }  // needs the V2G kernels
 };
 
 struct Tables {

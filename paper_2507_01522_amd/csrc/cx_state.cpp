@@ -11,9 +11,17 @@ namespace cx {
 static const uint64_t kMagic = 0x31305843ull;  // "CX01"
 static const size_t kHeader = 8 + 8 + 8 + 4 + 4;
 static const size_t kPortRec = 4 + 8 + 4 + 4 + 4;
+static const size_t kBattRec = 8 + 4;
+
+static size_t battery_envs(const cx_ctx *ctx) {
+  size_t n = 0;
+  for (const ClassRt &c : ctx->classes)
+    if (c.comp.battery) n += (size_t)c.n_envs;
+  return n;
+}
 
 size_t state_blob_bytes(const cx_ctx *ctx) {
-  return kHeader + kPortRec * (size_t)ctx->total_ports + 8 * (size_t)ctx->n_envs;
+  return kHeader + kPortRec * (size_t)ctx->port_count + 8 * (size_t)ctx->n_envs + kBattRec * battery_envs(ctx);
 }
 
 }  // namespace cx
@@ -32,8 +40,11 @@ cx_status cx_get_state(cx_ctx *ctx, void *host, size_t bytes) {
   std::vector<double> qv(ns);
   std::vector<float> uv(ns), cap(ns), pl(ns);
   std::vector<int16_t> dw(ns);
-  std::vector<double> ret((size_t)ctx->n_envs);
+  std::vector<double> ret((size_t)ctx->n_envs), bsoc((size_t)ctx->n_envs);
+  std::vector<float> bp((size_t)ctx->n_envs);
   if ((e = hipMemcpy(qv.data(), ctx->q, 8 * ns, hipMemcpyDeviceToHost)) != hipSuccess ||
+      (e = hipMemcpy(bsoc.data(), ctx->bsoc, 8 * bsoc.size(), hipMemcpyDeviceToHost)) != hipSuccess ||
+      (e = hipMemcpy(bp.data(), ctx->bp, 4 * bp.size(), hipMemcpyDeviceToHost)) != hipSuccess ||
       (e = hipMemcpy(uv.data(), ctx->u, 4 * ns, hipMemcpyDeviceToHost)) != hipSuccess ||
       (e = hipMemcpy(cap.data(), ctx->cap, 4 * ns, hipMemcpyDeviceToHost)) != hipSuccess ||
       (e = hipMemcpy(pl.data(), ctx->p_last, 4 * ns, hipMemcpyDeviceToHost)) != hipSuccess ||
@@ -41,7 +52,7 @@ cx_status cx_get_state(cx_ctx *ctx, void *host, size_t bytes) {
       (e = hipMemcpy(ret.data(), ctx->ret, 8 * ret.size(), hipMemcpyDeviceToHost)) != hipSuccess)
     return hip_fail(ctx, e, "cx_get_state copy");
   unsigned char *p = static_cast<unsigned char *>(host);
-  const int64_t ne = ctx->n_envs, np = ctx->total_ports;
+  const int64_t ne = ctx->n_envs, np = ctx->port_count;
   std::memcpy(p, &kMagic, 8);
   std::memcpy(p + 8, &ne, 8);
   std::memcpy(p + 16, &np, 8);
@@ -63,6 +74,15 @@ cx_status cx_get_state(cx_ctx *ctx, void *host, size_t bytes) {
     }
   }
   std::memcpy(q, ret.data(), 8 * ret.size());
+  q += 8 * ret.size();
+  for (const ClassRt &c : ctx->classes) {
+    if (!c.comp.battery) continue;
+    for (int64_t e2 = 0; e2 < c.n_envs; ++e2) {
+      std::memcpy(q, &bsoc[(size_t)(c.env_begin + e2)], 8);
+      std::memcpy(q + 8, &bp[(size_t)(c.env_begin + e2)], 4);
+      q += kBattRec;
+    }
+  }
   return CX_OK;
 }
 
@@ -80,7 +100,7 @@ cx_status cx_set_state(cx_ctx *ctx, const void *host, size_t bytes) {
   std::memcpy(&np, p + 16, 8);
   std::memcpy(&g, p + 24, 4);
   std::memcpy(&t_day, p + 28, 4);
-  if (magic != kMagic || ne != ctx->n_envs || np != ctx->total_ports)
+  if (magic != kMagic || ne != ctx->n_envs || np != ctx->port_count)
     return fail_status(CX_E_INVALID, "snapshot does not match this context");
   if (t_day < 0 || t_day >= ctx->steps_ep) return fail_status(CX_E_INVALID, "snapshot t_day out of range");
   const size_t ns = (size_t)ctx->total_slots;
@@ -106,6 +126,20 @@ cx_status cx_set_state(cx_ctx *ctx, const void *host, size_t bytes) {
     }
   }
   std::memcpy(ret.data(), q, 8 * ret.size());
+  q += 8 * ret.size();
+  std::vector<double> bsoc((size_t)ctx->n_envs, 0.0);
+  std::vector<float> bp((size_t)ctx->n_envs, 0.f);
+  for (const ClassRt &c : ctx->classes) {
+    if (!c.comp.battery) continue;
+    for (int64_t e2 = 0; e2 < c.n_envs; ++e2) {
+      double v;
+      std::memcpy(&v, q, 8);
+      if (!(v >= 0.0 && v <= 1.0)) return fail_status(CX_E_INVALID, "snapshot battery SoC out of [0,1]");
+      bsoc[(size_t)(c.env_begin + e2)] = v;
+      std::memcpy(&bp[(size_t)(c.env_begin + e2)], q + 8, 4);
+      q += kBattRec;
+    }
+  }
   hipError_t e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "cx_set_state synchronize");
   if ((e = hipMemcpy(ctx->q, qv.data(), 8 * ns, hipMemcpyHostToDevice)) != hipSuccess ||
@@ -113,7 +147,9 @@ cx_status cx_set_state(cx_ctx *ctx, const void *host, size_t bytes) {
       (e = hipMemcpy(ctx->cap, cap.data(), 4 * ns, hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(ctx->p_last, pl.data(), 4 * ns, hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(ctx->dwell, dw.data(), 2 * ns, hipMemcpyHostToDevice)) != hipSuccess ||
-      (e = hipMemcpy(ctx->ret, ret.data(), 8 * ret.size(), hipMemcpyHostToDevice)) != hipSuccess)
+      (e = hipMemcpy(ctx->ret, ret.data(), 8 * ret.size(), hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(ctx->bsoc, bsoc.data(), 8 * bsoc.size(), hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(ctx->bp, bp.data(), 4 * bp.size(), hipMemcpyHostToDevice)) != hipSuccess)
     return hip_fail(ctx, e, "cx_set_state copy");
   ctx->g = g;
   ctx->t_day = t_day;

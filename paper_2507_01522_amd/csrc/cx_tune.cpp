@@ -167,8 +167,8 @@ extern "C" cx_status cx_autotune(cx_ctx *ctx, int32_t T_probe, const char *cache
       if ((st = rebuild_segments(ctx)) != CX_OK) break;
       SegDev one{};
       for (const SegDev &sg : ctx->segs_host)
-        if (sg.cls == c.dev) one = sg;
-      build_groups({one}, {c.tab.dwell_log2}, {c.host_view.simple != 0}, ctx->wpb, &one_segs, &one_groups);
+        if (sg.cls == c.dev && one.cls == nullptr) one = sg;   // the class's first (largest) segment
+      build_groups({one}, {c.tab.dwell_log2}, {c.host_view.kind}, ctx->wpb, &one_segs, &one_groups);
       if ((e = hipMemcpy(seg1, one_segs.data(), sizeof(SegDev), hipMemcpyHostToDevice)) != hipSuccess) {
         st = hip_fail(ctx, e, "cx_autotune segment upload");
         break;

@@ -40,7 +40,10 @@ class StationSpecC(C.Structure):
                 ("cap_lo", C.c_double), ("cap_hi", C.c_double), ("soc0_lo", C.c_double),
                 ("soc0_hi", C.c_double), ("tgt_lo", C.c_double), ("tgt_hi", C.c_double),
                 ("dwell_mu", C.c_double), ("dwell_sigma", C.c_double), ("dwell_max", C.c_int32),
-                ("arrival_rate", C.c_void_p), ("price_table", C.c_void_p)]
+                ("arrival_rate", C.c_void_p), ("price_table", C.c_void_p), ("v2g", C.c_int32),
+                ("port_pdis_kw", C.c_void_p), ("battery_kwh", C.c_double), ("battery_kw", C.c_double),
+                ("battery_tau", C.c_double), ("battery_soc0", C.c_double),
+                ("alpha_degrad_battery", C.c_double), ("alpha_degrad_cars", C.c_double)]
 
 
 class TrajC(C.Structure):
@@ -58,7 +61,7 @@ class ClassInfoC(C.Structure):
     _fields_ = [("env_begin", C.c_int64), ("n_envs", C.c_int64), ("port_offset", C.c_int64),
                 ("obs_offset", C.c_int64), ("n_ports", C.c_int32), ("obs_dim", C.c_int32),
                 ("slots", C.c_int32), ("levels", C.c_int32), ("lanes_per_station", C.c_int32),
-                ("waves_per_block", C.c_int32)]
+                ("waves_per_block", C.c_int32), ("n_actions", C.c_int32)]
 
 
 class ServerOptsC(C.Structure):
@@ -165,6 +168,10 @@ class _SpecHolder:
         for arr in self.profiles:
             if arr is not None and arr.shape != (spec.steps_per_episode,):
                 raise ValueError("arrival_rate / price_table need steps_per_episode entries")
+        pdis = getattr(spec, "port_pdis_kw", None)
+        self.pdis = None if pdis is None else np.ascontiguousarray(pdis, np.float64)
+        if self.pdis is not None and self.pdis.shape != (spec.n_ports,):
+            raise ValueError("port_pdis_kw needs n_ports entries")
         a = self.arrays
         self.c = StationSpecC(spec.n_ports, len(spec.node_parent), a[0].ctypes.data, a[1].ctypes.data,
                               a[2].ctypes.data, a[3].ctypes.data, a[4].ctypes.data, a[5].ctypes.data,
@@ -173,7 +180,13 @@ class _SpecHolder:
                               spec.price_base, spec.price_amp, spec.price_sigma, spec.arrival_peak,
                               spec.cap_lo, spec.cap_hi, spec.soc0_lo, spec.soc0_hi, spec.tgt_lo, spec.tgt_hi,
                               spec.dwell_mu, spec.dwell_sigma, spec.dwell_max,
-                              *[None if arr is None else arr.ctypes.data for arr in self.profiles])
+                              *[None if arr is None else arr.ctypes.data for arr in self.profiles],
+                              int(getattr(spec, "v2g", 0)),
+                              None if self.pdis is None else self.pdis.ctypes.data,
+                              float(getattr(spec, "battery_kwh", 0.0)), float(getattr(spec, "battery_kw", 0.0)),
+                              float(getattr(spec, "battery_tau", 0.8)), float(getattr(spec, "battery_soc0", 0.5)),
+                              float(getattr(spec, "alpha_degrad_battery", 0.0)),
+                              float(getattr(spec, "alpha_degrad_cars", 0.0)))
 
 
 def compile_layout(spec) -> Dict[str, np.ndarray]:
@@ -322,21 +335,38 @@ class Env:
         check(lib().cx_set_state(self.h, buf, len(blob)))
 
     def state_arrays(self) -> Dict[str, np.ndarray]:
-        """Decode get_state(): per-port dwell/soc/e_rem/cap/p_last (env-major port order), returns."""
+        """Decode get_state(): per-port dwell/soc/e_rem/cap/p_last (env-major port order),
+        returns, and per env the station battery's SoC and last power (battery
+        classes; other envs read as 0)."""
         blob = self.get_state()
         i = self.info()
         head = np.frombuffer(blob, dtype=np.uint8, count=32)
+        n_ports = int(head[16:24].view(np.int64)[0])
         g = int(head[24:28].view(np.uint32)[0])
         t_day = int(head[28:32].view(np.int32)[0])
         rec = np.frombuffer(blob, dtype=np.dtype([("dwell", "<i4"), ("q", "<f8"), ("u", "<f4"),
                                                   ("cap", "<f4"), ("p_last", "<f4")]),
-                            count=i.total_ports, offset=32)
-        ret = np.frombuffer(blob, dtype="<f8", count=i.n_envs, offset=32 + 24 * i.total_ports)
+                            count=n_ports, offset=32)
+        off = 32 + 24 * n_ports
+        ret = np.frombuffer(blob, dtype="<f8", count=i.n_envs, offset=off)
+        off += 8 * i.n_envs
+        bsoc = np.zeros(i.n_envs)
+        bp = np.zeros(i.n_envs, np.float32)
+        for c in range(i.n_classes):
+            ci = self.class_info(c)
+            if ci.n_actions == ci.n_ports:
+                continue
+            b = np.frombuffer(blob, dtype=np.dtype([("soc", "<f8"), ("p", "<f4")]), count=ci.n_envs, offset=off)
+            bsoc[ci.env_begin:ci.env_begin + ci.n_envs] = b["soc"]
+            bp[ci.env_begin:ci.env_begin + ci.n_envs] = b["p"]
+            off += 12 * ci.n_envs
         out = {k: np.array(rec[k]) for k in rec.dtype.names}
         occ = out["dwell"] > 0
         out["soc"] = np.where(occ, 1.0 - out["q"], 0.0)
         out["e_rem"] = np.where(occ, (out["q"] - out["u"].astype(np.float64)) * out["cap"], 0.0)
         out["ret"] = np.array(ret)
+        out["batt_soc"] = bsoc
+        out["batt_p"] = bp
         out["g"] = g
         out["t_day"] = t_day
         return out
@@ -427,15 +457,20 @@ class Server:
         self._keep.pop(ticket, None)
 
     @staticmethod
-    def fetch(res: ResultC, out_mode: int, n_ports: int) -> Dict[str, np.ndarray]:
+    def fetch(res: ResultC, out_mode: int, spec) -> Dict[str, np.ndarray]:
         """Copy the records of a finished request (server-owned or caller buffers)
-        to host arrays shaped like Env.alloc_traj."""
+        to host arrays shaped like Env.alloc_traj.  spec: the request's station
+        spec (or, for a charging-only station, its port count)."""
         E, T = int(res.n_envs), int(res.T)
+        if isinstance(spec, (int, np.integer)):
+            obs_dim, n_act = 6 * int(spec) + 4, int(spec)
+        else:
+            obs_dim, n_act = spec.obs_dim, spec.n_actions
         want = {"reward": (np.float32, (T, E), res.traj.reward), "done": (np.uint8, (T, E), res.traj.done)}
         if out_mode == OUT_FULL:
-            want["obs"] = (np.float32, (T, E * (6 * n_ports + 4)), res.traj.obs)
+            want["obs"] = (np.float32, (T, E * obs_dim), res.traj.obs)
         if out_mode in (OUT_FULL, OUT_ACT_REWARD):
-            want["actions"] = (np.uint8, (T, E * n_ports), res.traj.actions)
+            want["actions"] = (np.uint8, (T, E * n_act), res.traj.actions)
         out = {}
         for k, (dt, shape, ptr) in want.items():
             a = np.empty(shape, dtype=dt)

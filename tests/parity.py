@@ -15,9 +15,10 @@ REL = 1e-5
 
 
 def env_layout(specs, env_class):
-    ports = np.array([s.n_ports for s in specs])[env_class]
-    obs_dim = 6 * ports + 4
-    return (np.concatenate([[0], np.cumsum(ports)]).astype(np.int64),
+    """Per-env offsets of the action bytes and of the observation floats."""
+    acts = np.array([s.n_actions for s in specs])[env_class]
+    obs_dim = np.array([s.obs_dim for s in specs])[env_class]
+    return (np.concatenate([[0], np.cumsum(acts)]).astype(np.int64),
             np.concatenate([[0], np.cumsum(obs_dim)]).astype(np.int64))
 
 
@@ -39,7 +40,11 @@ def obs_masks(specs, env_class):
 
 
 def reward_floor(specs, env_class):
-    f = np.array([s.p_sell * s.node_limit_kw[0] * s.node_eta[0] * s.dt_hours for s in specs])
+    """The largest profit of one step: the sell price times the root's energy
+    (plus the battery's, at the larger of the buy and sell prices)."""
+    f = np.array([s.p_sell * s.node_limit_kw[0] * s.node_eta[0] * s.dt_hours +
+                  max(s.p_sell, s.price_base + s.price_amp) * getattr(s, "battery_kw", 0.0) * s.dt_hours
+                  for s in specs])
     return f[env_class]
 
 
@@ -94,6 +99,11 @@ def compare_state(st, bs, specs, env_class):
     pmax = np.concatenate([specs[c].port_pmax_kw for c in env_class])
     check_close("p_last", st["p_last"], bs.p_last, pmax)
     check_close("return", st["ret"], bs.ret, reward_floor(specs, env_class))
+    has_b = np.array([specs[c].has_battery for c in env_class])
+    if has_b.any():
+        check_close("battery soc", st["batt_soc"][has_b], bs.batt[0::2][has_b], 1.0)
+        bkw = np.array([specs[c].battery_kw for c in env_class])[has_b]
+        check_close("battery power", st["batt_p"][has_b], bs.batt[1::2][has_b], bkw)
 
 
 def to_np(out):

@@ -43,7 +43,7 @@ def test_library_exports_every_declared_symbol(cxm):
 SPECS = [W.tiny_parity_station(), W.scale_station(), W.policy_station(), W.two_charger_types(),
          W.tiny_parity_station().replace(arrival_peak=0.0, dwell_max=1),
          W.fanout4_tree(32, 2).replace(steps_per_episode=96, dwell_max=300, dwell_mu=math.log(12.0)),
-         W.fanout4_tree(128, 3).replace(arrival_peak=8.0)] + W.mixture_classes()
+         W.fanout4_tree(128, 3).replace(arrival_peak=8.0)] + W.mixture_classes() + W.v2g_mixture()
 
 
 @pytest.mark.parametrize("spec", SPECS, ids=[s.name or str(i) for i, s in enumerate(SPECS)])
@@ -66,7 +66,7 @@ def leaves_of(spec, h):
     return out
 
 
-@pytest.mark.parametrize("spec", SPECS[:4] + W.mixture_classes(), ids=lambda s: s.name)
+@pytest.mark.parametrize("spec", SPECS[:4] + W.mixture_classes() + W.v2g_mixture(), ids=lambda s: s.name)
 def test_layout_is_aligned_and_order_preserving(cxm, spec):
     lay = cxm.compile_layout(spec)
     S, D = lay["slots"], lay["levels"]
@@ -105,6 +105,13 @@ BAD = [
     ("eta", dict(port_eta=[0.0] * 16)),
     ("dfs", None),
     ("depth", None),
+    ("v2g_flag", dict(v2g=2)),
+    ("pdis", dict(v2g=1, port_pdis_kw=[0.0] * 16)),
+    ("v2g_levels", dict(v2g=1, n_levels=200)),
+    ("battery_rate", dict(battery_kwh=50.0, battery_kw=0.0)),
+    ("battery_tau", dict(battery_kwh=50.0, battery_kw=10.0, battery_tau=1.0)),
+    ("battery_soc0", dict(battery_kwh=50.0, battery_kw=10.0, battery_soc0=1.5)),
+    ("battery_kwh", dict(battery_kwh=float("nan"))),
 ]
 
 
