@@ -9,6 +9,7 @@ all stations over all 288 steps in one persistent, graph-replayed launch.
 
 Other workloads (--workload): tiny (64 stations of 16 ports, the parity case),
 scale (4,096 stations on a two-level tree, persistent vs one launch per step),
+v2g (65,536 stations with bidirectional ports and a station battery),
 policy (1,048,576 stations of 32 ports, levels from the BF16 perceptron on the
 matrix cores), serve (a Poisson stream of rollout requests through the
 continuous-batching server).
@@ -35,19 +36,21 @@ BF16_PEAK_TFLOPS = 2500.0
 T_DAY = 288
 
 
-def record_bytes(n_ports: np.ndarray, out_mode: str = "full") -> np.ndarray:
-    """Bytes of one record per env-step: obs (6N+4) f32, N levels, reward f32, done u8."""
+def record_bytes(n_ports: np.ndarray, out_mode: str = "full", battery=0) -> np.ndarray:
+    """Bytes of one record per env-step: obs (6N+4, +2 with a station battery) f32,
+    one action byte per port (+1 for the battery), reward f32, done u8."""
+    b = np.asarray(battery, dtype=np.int64)
     if out_mode == "full":
-        return 4 * (6 * n_ports + 4) + n_ports + 4 + 1
+        return 4 * (6 * n_ports + 4 + 2 * b) + n_ports + b + 4 + 1
     if out_mode == "act_reward":
-        return n_ports + 4 + 1
+        return n_ports + b + 4 + 1
     return np.full_like(n_ports, 4 + 1)
 
 
-def state_bytes(n_ports: np.ndarray) -> np.ndarray:
+def state_bytes(n_ports: np.ndarray, battery=0) -> np.ndarray:
     """Per env: 1 - SoC (f64), 1 - target, capacity, last power (f32) and dwell (i16)
-    per port, plus the f64 return."""
-    return 22 * n_ports + 8
+    per port, plus the f64 return (and the battery's f64 SoC and f32 power)."""
+    return 22 * n_ports + 8 + 12 * np.asarray(battery, dtype=np.int64)
 
 
 def measured_traffic():
@@ -153,6 +156,7 @@ def run_rollout_workload(args, name, specs, ec, seed, desc, cpu_stride):
     import torch  # noqa: F401
     import paper_2507_01522_amd as cx
     n_ports = np.array([s.n_ports for s in specs])[ec]
+    batt = np.array([1 if getattr(s, "has_battery", False) else 0 for s in specs])[ec]
     n_envs = len(ec)
     env = cx.Env(specs, env_class=ec, seed=seed) if len(specs) > 1 else cx.Env(specs[0], n_envs=n_envs, seed=seed)
     if not args.no_tune:
@@ -162,7 +166,7 @@ def run_rollout_workload(args, name, specs, ec, seed, desc, cpu_stride):
     wall_ms, kernel_ms = timed_rollouts(env, cx, T_DAY, cx.ACT_RANDOM, cx.OUT_FULL, out, args)
     env_steps = n_envs * T_DAY
     value = env_steps / (wall_ms / 1e3)
-    alg_bytes = float((record_bytes(n_ports) * T_DAY + 2 * state_bytes(n_ports)).sum())
+    alg_bytes = float((record_bytes(n_ports, "full", batt) * T_DAY + 2 * state_bytes(n_ports, batt)).sum())
     achieved = alg_bytes / (kernel_ms / 1e3) / 1e9
     del out
     # records of rewards and done flags only (the same rollout, 5 bytes per env-step)
@@ -182,7 +186,7 @@ def run_rollout_workload(args, name, specs, ec, seed, desc, cpu_stride):
                         "kernel": "k_rollout", "kernel_ms": kernel_ms, "algorithmic_bytes": alg_bytes}
     line["reward_only"] = {"env_steps_per_s": env_steps / (r_wall / 1e3), "kernel_ms": r_kernel,
                            "algorithmic_bytes": float((record_bytes(n_ports, "reward") * T_DAY
-                                                       + 2 * state_bytes(n_ports)).sum())}
+                                                       + 2 * state_bytes(n_ports, batt)).sum())}
     line["plain"] = plain
     line["speedup_vs_plain"] = (value / plain["env_steps_per_s"]) if plain else None
     line["cpu_baseline"] = cpu
@@ -208,6 +212,14 @@ def run_scale(args):
     return run_rollout_workload(args, "scale: 4096 stations x 288 steps, 4 splitters x 4 ports of 22 kW, "
                                       "random levels, full records", [W.scale_station()],
                                 np.zeros(4096, np.int32), 2, "4096 stations", 4)
+
+
+def run_v2g(args):
+    import workloads as W
+    return run_rollout_workload(args, "v2g: 65536 stations x 288 steps, 4 splitters x 4 bidirectional 22 kW "
+                                      "ports, 200 kWh / 50 kW station battery, random signed levels, full "
+                                      "records", [W.v2g_station()], np.zeros(65536, np.int32), 3,
+                                "V2G stations with batteries", 64)
 
 
 def run_policy(args):
@@ -376,7 +388,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="uneven", choices=["uneven", "tiny", "scale", "policy", "serve"])
+    ap.add_argument("--workload", default="uneven", choices=["uneven", "tiny", "scale", "v2g", "policy", "serve"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain per-step comparison")
     ap.add_argument("--no-tune", action="store_true")
@@ -398,7 +410,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    run = {"uneven": run_uneven, "tiny": run_tiny, "scale": run_scale, "policy": run_policy,
+    run = {"uneven": run_uneven, "tiny": run_tiny, "scale": run_scale, "v2g": run_v2g, "policy": run_policy,
            "serve": run_serve}[args.workload]
     print(json.dumps(run(args)))
 
