@@ -26,6 +26,8 @@ struct ox_class {
   double *pdis;              /* discharge maximum per port (V2G) */
   int32_t v2g;               /* 1: ports take levels -L..L */
   double b_cap, b_rate, b_tau, b_soc0, a_db, a_dc;  /* battery (b_cap = 0: none), degradation weights */
+  double cs_share, a_sat1, beta1;  /* charge-sensitive users: share of arrivals, weight, beta */
+  uint32_t cs_thresh;        /* a car's user is charge-sensitive iff its word <= cs_thresh (share > 0) */
   double p[OXP_COUNT];
   int32_t ip[OXI_COUNT];
   uint32_t *tpois;           /* [steps_per_episode][24] */
@@ -96,6 +98,13 @@ static void build_tpois(ox_class *c) {
       c->tpois[t * OX_K_POIS + k] = threshold_u32(cdf);
     }
   }
+}
+
+void ox_class_set_users(ox_class *c, double share, double alpha, double beta) {
+  c->cs_share = share;
+  c->a_sat1 = alpha;
+  c->beta1 = beta;
+  c->cs_thresh = threshold_u32(share);
 }
 
 /* Dwell time, App. A.1 "User Profiles": the lognormal stay length rounded to
@@ -181,10 +190,13 @@ void ox_class_set_v2g(ox_class *c, int32_t v2g, const double *pdis, const double
 }
 
 static int32_t has_battery(const ox_class *c) { return c->b_cap > 0.0; }
+static int32_t has_users(const ox_class *c) { return c->cs_share > 0.0; }
 
 int32_t ox_class_ports(const ox_class *c) { return c->n_ports; }
 int32_t ox_class_actions(const ox_class *c) { return c->n_ports + has_battery(c); }
-int32_t ox_obs_dim(const ox_class *c) { return 6 * c->n_ports + 4 + 2 * has_battery(c); }
+int32_t ox_obs_dim(const ox_class *c) {
+  return 6 * c->n_ports + 4 + 2 * has_battery(c) + (has_users(c) ? c->n_ports : 0);
+}
 
 /* Levels of action index i run from -lo(i) to L: ports of a V2G class and the
  * battery also discharge (the battery is the (N+1)-th pole, Sec. 3 "Action
@@ -266,12 +278,17 @@ void ox_project(const ox_class *c, double *P) {
 /* App. A.2 "Apply Actions" with absolute discrete levels (Supp. B.1): every
  * occupied port's signed request is clipped (pole_power), then the tree's
  * limits are enforced. */
-void ox_apply_actions(const ox_class *c, const int32_t *dwell, const double *soc,
+static int32_t occupied(const int32_t *dwell, const int32_t *user, int32_t i) {
+  return dwell[i] > 0 || (user && user[i] == 1);
+}
+
+void ox_apply_actions(const ox_class *c, const int32_t *dwell, const int32_t *user, const double *soc,
                       const double *cap, const int32_t *k, double *P) {
   const double tau = c->p[OXP_TAU], dt = c->p[OXP_DT];
   const int32_t L = c->ip[OXI_N_LEVELS];
   for (int32_t i = 0; i < c->n_ports; ++i)
-    P[i] = dwell[i] > 0 ? pole_power(k[i], L, c->pmax[i], c->pdis[i], tau, soc[i], cap[i], dt) : 0.0;
+    P[i] = occupied(dwell, user, i) ? pole_power(k[i], L, c->pmax[i], c->pdis[i], tau, soc[i], cap[i], dt)
+                                    : 0.0;
   ox_project(c, P);
 }
 
@@ -303,6 +320,14 @@ void ox_draw_exo(const ox_class *c, uint64_t seed, uint32_t env, uint32_t g, int
     for (int32_t k = 1; k < D; ++k)
       if (b[3] > c->tdwell[k]) ++d;
     x->car_dwell[j] = d;
+    /* the user's preference u (App. A.1 "User Profiles"): charge-sensitive with
+     * probability cs_share */
+    x->car_user[j] = 0;
+    if (has_users(c)) {
+      uint32_t w[4];
+      philox_seeded(seed, env, g, (uint32_t)j, OX_DOM_USER, w);
+      x->car_user[j] = w[0] <= c->cs_thresh;
+    }
   }
 }
 
@@ -330,14 +355,14 @@ void ox_draw_actions(const ox_class *c, int32_t mode, uint64_t seed, uint32_t en
 }
 
 /* ------------------------------------------------------------------------- */
-void ox_observe(const ox_class *c, const int32_t *dwell, const double *soc, const double *e_rem,
-                const double *cap, const double *p_last, const double *batt, int32_t t_day,
-                double *obs) {
+void ox_observe(const ox_class *c, const int32_t *dwell, const int32_t *user, const double *soc,
+                const double *e_rem, const double *cap, const double *p_last, const double *batt,
+                int32_t t_day, double *obs) {
   const int32_t N = c->n_ports, S = c->ip[OXI_STEPS_PER_EPISODE];
   const double tau = c->p[OXP_TAU];
   int32_t n_occ = 0;
   for (int32_t i = 0; i < N; ++i) {
-    int32_t occ = dwell[i] > 0;
+    int32_t occ = occupied(dwell, user, i);
     n_occ += occ;
     obs[0 * N + i] = occ ? 1.0 : 0.0;
     obs[1 * N + i] = occ ? soc[i] : 0.0;
@@ -355,25 +380,29 @@ void ox_observe(const ox_class *c, const int32_t *dwell, const double *soc, cons
     obs[6 * N + 4] = batt[0];
     obs[6 * N + 5] = batt[1] / c->b_rate;
   }
+  if (has_users(c)) {  /* the user preference u of every port (0 when empty) */
+    double *o = obs + 6 * N + 4 + 2 * has_battery(c);
+    for (int32_t i = 0; i < N; ++i) o[i] = user[i] == 1 ? 1.0 : 0.0;
+  }
 }
 
-static void clear_port(int32_t i, int32_t *dwell, double *soc, double *e_rem, double *cap,
+static void clear_port(int32_t i, int32_t *dwell, int32_t *user, double *soc, double *e_rem, double *cap,
                        double *p_last) {
-  dwell[i] = 0; soc[i] = 0.0; e_rem[i] = 0.0; cap[i] = 0.0; p_last[i] = 0.0;
+  dwell[i] = 0; user[i] = 0; soc[i] = 0.0; e_rem[i] = 0.0; cap[i] = 0.0; p_last[i] = 0.0;
 }
 
 /* App. A.2: (i) apply actions, (ii) charge, (iii) departures, (iv) arrivals;
  * then the reward of App. A.3 and the day boundary of Supp. B.1. */
-void ox_transition(const ox_class *c, int32_t *dwell, double *soc, double *e_rem, double *cap,
-                   double *p_last, double *batt, double *ret, int32_t *t_day, const int32_t *k,
-                   const ox_exo *x, ox_step_info *info, double *obs, double *P_out) {
+void ox_transition(const ox_class *c, int32_t *dwell, int32_t *user, double *soc, double *e_rem,
+                   double *cap, double *p_last, double *batt, double *ret, int32_t *t_day,
+                   const int32_t *k, const ox_exo *x, ox_step_info *info, double *obs, double *P_out) {
   const int32_t N = c->n_ports;
   const double dt = c->p[OXP_DT];
   double P[OX_MAX_PORTS];
   unsigned char was_occ[OX_MAX_PORTS];
 
   /* (i) apply actions */
-  ox_apply_actions(c, dwell, soc, cap, k, P);
+  ox_apply_actions(c, dwell, user, soc, cap, k, P);
   if (P_out)
     for (int32_t i = 0; i < N; ++i) P_out[i] = P[i];
 
@@ -382,7 +411,7 @@ void ox_transition(const ox_class *c, int32_t *dwell, double *soc, double *e_rem
    * discharging cars (losses eta, <= 0) */
   double e_net = 0.0, e_from_grid = 0.0, e_to_grid = 0.0;
   for (int32_t i = 0; i < N; ++i) {
-    was_occ[i] = dwell[i] > 0;
+    was_occ[i] = occupied(dwell, user, i);
     if (!was_occ[i]) continue;
     double e = dt * P[i];
     double s = soc[i] + e / cap[i];
@@ -405,26 +434,38 @@ void ox_transition(const ox_class *c, int32_t *dwell, double *soc, double *e_rem
   }
   double e_grid = e_from_grid + e_to_grid + e_batt;
 
-  /* (iii) departures of time-sensitive users; c_satisfaction,0 */
-  double c_sat = 0.0;
+  /* (iii) departures: time-sensitive users when no time remains
+   * (c_satisfaction,0: the energy still wanted), charge-sensitive users when no
+   * energy remains (c_satisfaction,1: hours past the planned departure, minus
+   * beta times the hours left early) */
+  double c_sat = 0.0, c_sat1 = 0.0;
   int32_t n_dep = 0;
   for (int32_t i = 0; i < N; ++i) {
-    if (was_occ[i] && dwell[i] == 0) {
+    if (!was_occ[i]) continue;
+    if (user[i] == 1) {
+      if (e_rem[i] <= 0.0) {
+        double t_left = (double)dwell[i] * dt;
+        c_sat1 += (t_left < 0.0 ? -t_left : 0.0) - c->beta1 * (t_left > 0.0 ? t_left : 0.0);
+        ++n_dep;
+        clear_port(i, dwell, user, soc, e_rem, cap, p_last);
+      }
+    } else if (dwell[i] == 0) {
       c_sat += e_rem[i] > 0.0 ? e_rem[i] : 0.0;
       ++n_dep;
-      clear_port(i, dwell, soc, e_rem, cap, p_last);
+      clear_port(i, dwell, user, soc, e_rem, cap, p_last);
     }
   }
 
   /* (iv) arrivals: clip by free spots, first free ports in port order */
   int32_t n_free = 0;
-  for (int32_t i = 0; i < N; ++i) n_free += dwell[i] == 0;
+  for (int32_t i = 0; i < N; ++i) n_free += !occupied(dwell, user, i);
   int32_t acc = x->M < n_free ? x->M : n_free;
   int32_t rej = x->M - acc;
   int32_t j = 0;
   for (int32_t i = 0; i < N && j < acc; ++i) {
-    if (dwell[i] != 0) continue;
+    if (occupied(dwell, user, i)) continue;
     dwell[i] = x->car_dwell[j];
+    user[i] = x->car_user[j];
     soc[i] = x->car_soc[j];
     cap[i] = x->car_cap[j];
     e_rem[i] = (x->car_tgt[j] - x->car_soc[j]) * x->car_cap[j];
@@ -439,7 +480,7 @@ void ox_transition(const ox_class *c, int32_t *dwell, double *soc, double *e_rem
   double c_db = e_batt < 0.0 ? -e_batt : 0.0;
   double c_dc = -e_to_grid;
   double reward = profit - c->p[OXP_ALPHA_SAT] * c_sat - c->p[OXP_ALPHA_DEC] * (double)rej -
-                  c->a_db * c_db - c->a_dc * c_dc;
+                  c->a_db * c_db - c->a_dc * c_dc - c->a_sat1 * c_sat1;
   *ret += reward;
 
   /* time and the end of the day: every port empties, the battery starts the
@@ -447,7 +488,7 @@ void ox_transition(const ox_class *c, int32_t *dwell, double *soc, double *e_rem
   *t_day += 1;
   int32_t done = *t_day == c->ip[OXI_STEPS_PER_EPISODE];
   if (done) {
-    for (int32_t i = 0; i < N; ++i) clear_port(i, dwell, soc, e_rem, cap, p_last);
+    for (int32_t i = 0; i < N; ++i) clear_port(i, dwell, user, soc, e_rem, cap, p_last);
     if (has_battery(c)) {
       batt[0] = c->b_soc0;
       batt[1] = 0.0;
@@ -455,14 +496,15 @@ void ox_transition(const ox_class *c, int32_t *dwell, double *soc, double *e_rem
     *t_day = 0;
   }
   int32_t n_occ = 0;
-  for (int32_t i = 0; i < N; ++i) n_occ += dwell[i] > 0;
+  for (int32_t i = 0; i < N; ++i) n_occ += occupied(dwell, user, i);
 
   if (info) {
     info->reward = reward; info->profit = profit; info->e_net = e_net; info->e_grid = e_grid;
     info->c_sat = c_sat; info->M = x->M; info->acc = acc; info->rej = rej; info->n_dep = n_dep;
     info->done = done; info->n_occ = n_occ; info->e_to_grid = e_to_grid; info->e_batt = e_batt;
+    info->c_sat1 = c_sat1;
   }
-  if (obs) ox_observe(c, dwell, soc, e_rem, cap, p_last, batt, *t_day, obs);
+  if (obs) ox_observe(c, dwell, user, soc, e_rem, cap, p_last, batt, *t_day, obs);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -477,7 +519,7 @@ typedef struct {
   uint32_t g0;
   int32_t t0, T, mode;
   const uint8_t *act_in;
-  int32_t *dwell;
+  int32_t *dwell, *user;
   double *soc, *e_rem, *cap, *p_last, *batt, *ret, *obs, *reward;
   uint8_t *act, *done;
   ox_step_info *info;
@@ -501,8 +543,8 @@ static void *rollout_worker(void *arg) {
       ox_draw_exo(c, J->seed, eid, g, t_day, &x);
       ox_step_info inf;
       double *o = J->obs ? J->obs + (size_t)t * J->total_obs + oo : NULL;
-      ox_transition(c, J->dwell + po, J->soc + po, J->e_rem + po, J->cap + po, J->p_last + po, bt,
-                    J->ret + e, &t_day, k, &x, &inf, o, NULL);
+      ox_transition(c, J->dwell + po, J->user + po, J->soc + po, J->e_rem + po, J->cap + po,
+                    J->p_last + po, bt, J->ret + e, &t_day, k, &x, &inf, o, NULL);
       if (J->act)
         for (int32_t i = 0; i < n_act; ++i)
           J->act[(size_t)t * J->total_act + ao + i] = (uint8_t)ox_action_code(c, i, k[i]);
@@ -516,7 +558,7 @@ static void *rollout_worker(void *arg) {
 
 int32_t ox_rollout(ox_class *const *classes, const int32_t *env_class, const int64_t *env_ids,
                    int64_t n_envs, uint64_t seed, uint32_t *g, int32_t *t_day, int32_t T, int32_t mode,
-                   const uint8_t *act_in, int32_t *dwell, double *soc, double *e_rem,
+                   const uint8_t *act_in, int32_t *dwell, int32_t *user, double *soc, double *e_rem,
                    double *cap, double *p_last, double *batt, double *ret, double *obs, uint8_t *act,
                    double *reward, uint8_t *done, ox_step_info *info, int32_t n_threads) {
   int64_t *port_off = (int64_t *)malloc(sizeof(int64_t) * (n_envs + 1));
@@ -540,7 +582,8 @@ int32_t ox_rollout(ox_class *const *classes, const int32_t *env_class, const int
     J->total_act = act_off[n_envs]; J->total_obs = obs_off[n_envs]; J->n_envs = n_envs;
     J->e_begin = n_envs * w / n_threads; J->e_end = n_envs * (w + 1) / n_threads;
     J->seed = seed; J->g0 = *g; J->t0 = *t_day; J->T = T; J->mode = mode; J->act_in = act_in;
-    J->dwell = dwell; J->soc = soc; J->e_rem = e_rem; J->cap = cap; J->p_last = p_last; J->batt = batt;
+    J->dwell = dwell; J->user = user; J->soc = soc; J->e_rem = e_rem; J->cap = cap; J->p_last = p_last;
+    J->batt = batt;
     J->ret = ret; J->obs = obs; J->act = act; J->reward = reward; J->done = done; J->info = info;
   }
   if (n_threads == 1) {

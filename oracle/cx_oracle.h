@@ -39,6 +39,10 @@
  *   ox_policy         -- numpy FP64 products on the decoded BF16 operands;
  *                        Gumbel-max frequencies equal softmax (chi-square);
  *                        BF16 rounding equal to torch's
+ *   charge-sensitive  -- (tests/test_oracle_users.py) hand-worked departures on
+ *   users (u = 1)        reaching the target, overstay and early-leave terms of
+ *                        c_satisfaction,1, share of drawn users (binomial), the
+ *                        all-time-sensitive special case equal to the base model
  *   V2G / battery     -- (tests/test_oracle_v2g.py) mirror symmetry: a mirrored
  *                        state (SoC -> 1 - SoC) under negated levels draws exactly
  *                        the negated powers through clip and projection;
@@ -67,6 +71,7 @@ extern "C" {
 #define OX_DOM_ACT 1u       /* ctr = (env, g >> 2, port, 1): word g & 3          */
 #define OX_DOM_CAR 2u       /* ctr = (env, g, j, 2): j-th arriving car of step g */
 #define OX_DOM_GUM 3u       /* ctr = (env, g, 3*port + q, 3): Gumbel noise       */
+#define OX_DOM_USER 4u      /* ctr = (env, g, j, 4): user type of car j, word 0  */
 
 /* action modes */
 #define OX_ACT_EXTERNAL 0
@@ -94,6 +99,7 @@ typedef struct {
   double car_soc[OX_K_POIS];      /* arrival SoC_0 of car j                     */
   double car_tgt[OX_K_POIS];      /* desired SoC of car j                       */
   int32_t car_dwell[OX_K_POIS];   /* dwell time of car j in steps, >= 1         */
+  int32_t car_user[OX_K_POIS];    /* 1: charge-sensitive user (u = 1), else 0   */
 } ox_exo;
 
 /* Everything one transition reports besides the new state.  e_grid is the net
@@ -102,7 +108,7 @@ typedef struct {
 typedef struct {
   double reward, profit, e_net, e_grid, c_sat;
   int32_t M, acc, rej, n_dep, done, n_occ;
-  double e_to_grid, e_batt;
+  double e_to_grid, e_batt, c_sat1;
 } ox_step_info;
 
 /* ---- class (one station architecture + parameters) ---- */
@@ -122,9 +128,15 @@ void ox_class_set_profiles(ox_class *c, const double *arrival_rate, const double
  * rate kW, tau, SoC at the start of a day, alpha_degrad_battery,
  * alpha_degrad_cars}. */
 void ox_class_set_v2g(ox_class *c, int32_t v2g, const double *pdis, const double *batt);
+/* Charge-sensitive users (App. A.1 "User Profiles", App. A.2 "Departure of
+ * Cars", App. A.3 c_satisfaction,1): each arriving car's user is charge-
+ * sensitive with probability share; such a user leaves when the energy still
+ * wanted reaches zero, and c_satisfaction,1 (weight alpha) charges the hours
+ * stayed past the planned departure minus beta times the hours left early. */
+void ox_class_set_users(ox_class *c, double share, double alpha, double beta);
 int32_t ox_class_ports(const ox_class *c);
 int32_t ox_class_actions(const ox_class *c);  /* ports + 1 with a battery */
-int32_t ox_obs_dim(const ox_class *c);        /* 6 N + 4, + 2 with a battery */
+int32_t ox_obs_dim(const ox_class *c);        /* 6 N + 4, + 2 with a battery, + N with u = 1 users */
 /* The action byte of level k at action index i (i = n_ports: the battery). */
 int32_t ox_action_code(const ox_class *c, int32_t i, int32_t k);
 /* copies of the class's integer sampling tables (steps_per_episode x 24, dwell_max) */
@@ -135,8 +147,10 @@ void ox_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out
 double ox_u24(uint32_t w);  /* (w >> 8) * 2^-24 */
 
 /* Apply-actions step: clip by port maximum, charging curve and remaining capacity,
- * then project onto the architecture constraints.  P (n_ports) is written. */
-void ox_apply_actions(const ox_class *c, const int32_t *dwell, const double *soc,
+ * then project onto the architecture constraints.  P (n_ports) is written.
+ * A port is occupied when dwell > 0 or it holds a charge-sensitive user
+ * (user[i] = 1; user may be NULL: all time-sensitive). */
+void ox_apply_actions(const ox_class *c, const int32_t *dwell, const int32_t *user, const double *soc,
                       const double *cap, const int32_t *k, double *P);
 /* The projection of Eq. (ArchConst) alone, in place on P. */
 void ox_project(const ox_class *c, double *P);
@@ -151,16 +165,18 @@ void ox_draw_exo(const ox_class *c, uint64_t seed, uint32_t env, uint32_t g, int
 void ox_draw_actions(const ox_class *c, int32_t mode, uint64_t seed, uint32_t env, uint32_t g,
                      const uint8_t *ext, int32_t *k);
 
-/* One transition of one env, state in place.  batt = {SoC, last power} of the
- * station battery (NULL without one).  obs (obs_dim) may be NULL; P_out
- * (n_ports) receives the applied powers and may be NULL. */
-void ox_transition(const ox_class *c, int32_t *dwell, double *soc, double *e_rem, double *cap,
-                   double *p_last, double *batt, double *ret, int32_t *t_day, const int32_t *k,
-                   const ox_exo *x, ox_step_info *info, double *obs, double *P_out);
+/* One transition of one env, state in place.  user[i] = 1 marks a charge-
+ * sensitive user at port i (dwell may then be <= 0: time past the planned
+ * departure).  batt = {SoC, last power} of the station battery (NULL without
+ * one).  obs (obs_dim) may be NULL; P_out (n_ports) receives the applied powers
+ * and may be NULL. */
+void ox_transition(const ox_class *c, int32_t *dwell, int32_t *user, double *soc, double *e_rem,
+                   double *cap, double *p_last, double *batt, double *ret, int32_t *t_day,
+                   const int32_t *k, const ox_exo *x, ox_step_info *info, double *obs, double *P_out);
 /* Observation of the current state (used after reset and by the policy). */
-void ox_observe(const ox_class *c, const int32_t *dwell, const double *soc, const double *e_rem,
-                const double *cap, const double *p_last, const double *batt, int32_t t_day,
-                double *obs);
+void ox_observe(const ox_class *c, const int32_t *dwell, const int32_t *user, const double *soc,
+                const double *e_rem, const double *cap, const double *p_last, const double *batt,
+                int32_t t_day, double *obs);
 
 /* ---- batched rollout over many envs (threads over env ranges) ----
  * env_class[n_envs] indexes classes[]; envs may be in any class order.  State
@@ -179,7 +195,7 @@ void ox_observe(const ox_class *c, const int32_t *dwell, const double *soc, cons
 int32_t ox_rollout(ox_class *const *classes, const int32_t *env_class, const int64_t *env_ids,
                    int64_t n_envs,
                    uint64_t seed, uint32_t *g, int32_t *t_day, int32_t T, int32_t mode,
-                   const uint8_t *act_in, int32_t *dwell, double *soc, double *e_rem,
+                   const uint8_t *act_in, int32_t *dwell, int32_t *user, double *soc, double *e_rem,
                    double *cap, double *p_last, double *batt, double *ret, double *obs, uint8_t *act,
                    double *reward, uint8_t *done, ox_step_info *info, int32_t n_threads);
 

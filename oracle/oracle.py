@@ -39,13 +39,14 @@ class StepInfo(C.Structure):
     _fields_ = [("reward", C.c_double), ("profit", C.c_double), ("e_net", C.c_double),
                 ("e_grid", C.c_double), ("c_sat", C.c_double), ("M", C.c_int32), ("acc", C.c_int32),
                 ("rej", C.c_int32), ("n_dep", C.c_int32), ("done", C.c_int32), ("n_occ", C.c_int32),
-                ("e_to_grid", C.c_double), ("e_batt", C.c_double)]
+                ("e_to_grid", C.c_double), ("e_batt", C.c_double), ("c_sat1", C.c_double)]
 
 
 class Exo(C.Structure):
     _fields_ = [("M", C.c_int32), ("z", C.c_double), ("p_buy", C.c_double),
                 ("car_cap", C.c_double * K_POIS), ("car_soc", C.c_double * K_POIS),
-                ("car_tgt", C.c_double * K_POIS), ("car_dwell", C.c_int32 * K_POIS)]
+                ("car_tgt", C.c_double * K_POIS), ("car_dwell", C.c_int32 * K_POIS),
+                ("car_user", C.c_int32 * K_POIS)]
 
 
 _lib = None
@@ -66,14 +67,15 @@ def lib():
         L.ox_u24.restype = C.c_double
         L.ox_u24.argtypes = [C.c_uint32]
         L.ox_project.argtypes = [P, P]
-        L.ox_apply_actions.argtypes = [P, P, P, P, P, P]
+        L.ox_apply_actions.argtypes = [P, P, P, P, P, P, P]
         L.ox_draw_exo.argtypes = [P, C.c_uint64, C.c_uint32, C.c_uint32, I, P]
         L.ox_draw_actions.argtypes = [P, I, C.c_uint64, C.c_uint32, C.c_uint32, P, P]
-        L.ox_transition.argtypes = [P] * 14
-        L.ox_observe.argtypes = [P, P, P, P, P, P, P, I, P]
+        L.ox_transition.argtypes = [P] * 15
+        L.ox_observe.argtypes = [P, P, P, P, P, P, P, P, I, P]
         L.ox_rollout.restype = I
         L.ox_rollout.argtypes = [P, P, P, C.c_int64, C.c_uint64, P, P, I, I, P, P, P, P, P, P, P, P,
-                                 P, P, P, P, P, I]
+                                 P, P, P, P, P, P, I]
+        L.ox_class_set_users.argtypes = [P, C.c_double, C.c_double, C.c_double]
         L.ox_class_set_v2g.argtypes = [P, I, P, P]
         L.ox_class_actions.restype = I
         L.ox_class_actions.argtypes = [P]
@@ -142,6 +144,9 @@ class OracleClass:
                            spec.alpha_degrad_battery, spec.alpha_degrad_cars], dtype=np.float64)
             self._keep += [a for a in (pd, bp) if a is not None]
             lib().ox_class_set_v2g(self.h, int(spec.v2g), _ptr(pd), _ptr(bp))
+        if getattr(spec, "charge_sensitive_share", 0.0) > 0.0:
+            lib().ox_class_set_users(self.h, float(spec.charge_sensitive_share), float(spec.alpha_sat1),
+                                     float(spec.beta_sat1))
         self.n_act = lib().ox_class_actions(self.h)
         self.has_battery = self.n_act > self.n
 
@@ -178,13 +183,14 @@ class OracleClass:
         lib().ox_project(self.h, _ptr(P))
         return P
 
-    def apply_actions(self, dwell, soc, cap, k) -> np.ndarray:
+    def apply_actions(self, dwell, soc, cap, k, user=None) -> np.ndarray:
         d = np.ascontiguousarray(dwell, dtype=np.int32)
+        u = None if user is None else np.ascontiguousarray(user, dtype=np.int32)
         s = np.ascontiguousarray(soc, dtype=np.float64)
         c = np.ascontiguousarray(cap, dtype=np.float64)
         kk = np.ascontiguousarray(k, dtype=np.int32)
         P = np.zeros(self.n, dtype=np.float64)
-        lib().ox_apply_actions(self.h, _ptr(d), _ptr(s), _ptr(c), _ptr(kk), _ptr(P))
+        lib().ox_apply_actions(self.h, _ptr(d), _ptr(u), _ptr(s), _ptr(c), _ptr(kk), _ptr(P))
         return P
 
     def draw_exo(self, seed: int, env: int, g: int, t_day: int) -> Exo:
@@ -201,7 +207,7 @@ class OracleClass:
 
     def observe(self, st: "EnvState") -> np.ndarray:
         obs = np.zeros(self.obs_dim, dtype=np.float64)
-        lib().ox_observe(self.h, _ptr(st.dwell), _ptr(st.soc), _ptr(st.e_rem), _ptr(st.cap),
+        lib().ox_observe(self.h, _ptr(st.dwell), _ptr(st.user), _ptr(st.soc), _ptr(st.e_rem), _ptr(st.cap),
                          _ptr(st.p_last), _ptr(st.batt), st.t_day, _ptr(obs))
         return obs
 
@@ -213,9 +219,9 @@ class OracleClass:
         P = np.zeros(self.n, dtype=np.float64)
         ret = C.c_double(st.ret)
         t_day = C.c_int32(st.t_day)
-        lib().ox_transition(self.h, _ptr(st.dwell), _ptr(st.soc), _ptr(st.e_rem), _ptr(st.cap),
-                            _ptr(st.p_last), _ptr(st.batt), C.byref(ret), C.byref(t_day), _ptr(kk),
-                            C.byref(exo),
+        lib().ox_transition(self.h, _ptr(st.dwell), _ptr(st.user), _ptr(st.soc), _ptr(st.e_rem),
+                            _ptr(st.cap), _ptr(st.p_last), _ptr(st.batt), C.byref(ret), C.byref(t_day),
+                            _ptr(kk), C.byref(exo),
                             C.byref(info), _ptr(obs), _ptr(P))
         st.ret = ret.value
         st.t_day = t_day.value
@@ -241,6 +247,7 @@ class EnvState:
     def __init__(self, n_ports: int, battery_soc: float = 0.0):
         self.batt = np.array([battery_soc, 0.0])   # station battery: SoC, last power
         self.dwell = np.zeros(n_ports, dtype=np.int32)
+        self.user = np.zeros(n_ports, dtype=np.int32)   # 1: charge-sensitive user
         self.soc = np.zeros(n_ports, dtype=np.float64)
         self.e_rem = np.zeros(n_ports, dtype=np.float64)
         self.cap = np.zeros(n_ports, dtype=np.float64)
@@ -248,21 +255,24 @@ class EnvState:
         self.ret = 0.0
         self.t_day = 0
 
-    def put_car(self, port: int, soc: float, cap: float, dwell: int, e_rem: float):
+    def put_car(self, port: int, soc: float, cap: float, dwell: int, e_rem: float, user: int = 0):
         self.dwell[port] = dwell
+        self.user[port] = user
         self.soc[port] = soc
         self.cap[port] = cap
         self.e_rem[port] = e_rem
 
 
 def exo(M: int = 0, p_buy: float = 0.25, cars=()) -> Exo:
-    """Hand-built exogenous input: cars = [(cap, soc0, tgt, dwell), ...]."""
+    """Hand-built exogenous input: cars = [(cap, soc0, tgt, dwell[, user]), ...]."""
     x = Exo()
     x.M = M
     x.z = 0.0
     x.p_buy = p_buy
-    for j, (cap, soc0, tgt, dwell) in enumerate(cars):
+    for j, car in enumerate(cars):
+        cap, soc0, tgt, dwell = car[:4]
         x.car_cap[j], x.car_soc[j], x.car_tgt[j], x.car_dwell[j] = cap, soc0, tgt, dwell
+        x.car_user[j] = car[4] if len(car) > 4 else 0
     return x
 
 
@@ -288,6 +298,7 @@ class BatchState:
         self.batt = np.zeros(2 * self.n_envs)          # per env: battery SoC, last power
         self.batt[0::2] = soc0[self.env_class]
         self.dwell = np.zeros(P, dtype=np.int32)
+        self.user = np.zeros(P, dtype=np.int32)
         self.soc = np.zeros(P)
         self.e_rem = np.zeros(P)
         self.cap = np.zeros(P)
@@ -313,7 +324,7 @@ def rollout(bs: BatchState, seed: int, T: int, mode: int = ACT_RANDOM, act_in=No
     g = C.c_uint32(bs.g)
     t_day = C.c_int32(bs.t_day)
     used = lib().ox_rollout(handles, _ptr(bs.env_class), _ptr(bs.env_ids), bs.n_envs, seed, C.byref(g), C.byref(t_day),
-                            T, mode, _ptr(ain), _ptr(bs.dwell), _ptr(bs.soc), _ptr(bs.e_rem),
+                            T, mode, _ptr(ain), _ptr(bs.dwell), _ptr(bs.user), _ptr(bs.soc), _ptr(bs.e_rem),
                             _ptr(bs.cap), _ptr(bs.p_last), _ptr(bs.batt), _ptr(bs.ret), _ptr(obs), _ptr(act),
                             _ptr(rew), _ptr(done), None if info is None else C.cast(info, C.c_void_p),
                             n_threads)

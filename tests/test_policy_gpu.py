@@ -87,6 +87,7 @@ def _env_state(bs, e, N):
     s.cap = np.ascontiguousarray(bs.cap[sl])
     s.p_last = np.ascontiguousarray(bs.p_last[sl])
     s.batt = np.ascontiguousarray(bs.batt[2 * e:2 * e + 2])
+    s.user = np.ascontiguousarray(bs.user[sl])
     s.t_day = bs.t_day
     return s
 

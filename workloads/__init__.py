@@ -81,6 +81,11 @@ class StationSpec:
     battery_soc0: float = 0.5
     alpha_degrad_battery: float = 0.0
     alpha_degrad_cars: float = 0.0
+    # charge-sensitive users (u = 1): share of arriving users, weight of
+    # c_satisfaction,1 and its beta (weight of the hours left early)
+    charge_sensitive_share: float = 0.0
+    alpha_sat1: float = 0.0
+    beta_sat1: float = 0.0
 
     @property
     def n_nodes(self) -> int:
@@ -96,8 +101,14 @@ class StationSpec:
         return self.n_ports + (1 if self.has_battery else 0)
 
     @property
+    def has_users(self) -> bool:
+        """Some arriving users are charge-sensitive (u = 1)."""
+        return self.charge_sensitive_share > 0.0
+
+    @property
     def obs_dim(self) -> int:
-        return 6 * self.n_ports + 4 + (2 if self.has_battery else 0)
+        return (6 * self.n_ports + 4 + (2 if self.has_battery else 0) +
+                (self.n_ports if self.has_users else 0))
 
     def replace(self, **kw) -> "StationSpec":
         return dataclasses.replace(self, **kw)
