@@ -9,7 +9,8 @@ all stations over all 288 steps in one persistent, graph-replayed launch.
 
 Other workloads (--workload): tiny (64 stations of 16 ports, the parity case),
 scale (4,096 stations on a two-level tree, persistent vs one launch per step),
-v2g (65,536 stations with bidirectional ports and a station battery),
+v2g (65,536 stations with bidirectional ports and a station battery), users
+(65,536 stations where half the users are charge-sensitive),
 policy (1,048,576 stations of 32 ports, levels from the BF16 perceptron on the
 matrix cores), serve (a Poisson stream of rollout requests through the
 continuous-batching server).
@@ -157,6 +158,7 @@ def run_rollout_workload(args, name, specs, ec, seed, desc, cpu_stride):
     import paper_2507_01522_amd as cx
     n_ports = np.array([s.n_ports for s in specs])[ec]
     batt = np.array([1 if getattr(s, "has_battery", False) else 0 for s in specs])[ec]
+    users = np.array([1 if getattr(s, "has_users", False) else 0 for s in specs])[ec]
     n_envs = len(ec)
     env = cx.Env(specs, env_class=ec, seed=seed) if len(specs) > 1 else cx.Env(specs[0], n_envs=n_envs, seed=seed)
     if not args.no_tune:
@@ -166,7 +168,9 @@ def run_rollout_workload(args, name, specs, ec, seed, desc, cpu_stride):
     wall_ms, kernel_ms = timed_rollouts(env, cx, T_DAY, cx.ACT_RANDOM, cx.OUT_FULL, out, args)
     env_steps = n_envs * T_DAY
     value = env_steps / (wall_ms / 1e3)
-    alg_bytes = float((record_bytes(n_ports, "full", batt) * T_DAY + 2 * state_bytes(n_ports, batt)).sum())
+    # records (+ the user flags, 4 bytes per port) and the state in and out (+ a user byte per port)
+    alg_bytes = float(((record_bytes(n_ports, "full", batt) + 4 * n_ports * users) * T_DAY
+                       + 2 * (state_bytes(n_ports, batt) + n_ports * users)).sum())
     achieved = alg_bytes / (kernel_ms / 1e3) / 1e9
     del out
     # records of rewards and done flags only (the same rollout, 5 bytes per env-step)
@@ -186,7 +190,7 @@ def run_rollout_workload(args, name, specs, ec, seed, desc, cpu_stride):
                         "kernel": "k_rollout", "kernel_ms": kernel_ms, "algorithmic_bytes": alg_bytes}
     line["reward_only"] = {"env_steps_per_s": env_steps / (r_wall / 1e3), "kernel_ms": r_kernel,
                            "algorithmic_bytes": float((record_bytes(n_ports, "reward") * T_DAY
-                                                       + 2 * state_bytes(n_ports, batt)).sum())}
+                                                       + 2 * (state_bytes(n_ports, batt) + n_ports * users)).sum())}
     line["plain"] = plain
     line["speedup_vs_plain"] = (value / plain["env_steps_per_s"]) if plain else None
     line["cpu_baseline"] = cpu
@@ -220,6 +224,14 @@ def run_v2g(args):
                                       "ports, 200 kWh / 50 kW station battery, random signed levels, full "
                                       "records", [W.v2g_station()], np.zeros(65536, np.int32), 3,
                                 "V2G stations with batteries", 64)
+
+
+def run_users(args):
+    import workloads as W
+    return run_rollout_workload(args, "users: 65536 stations x 288 steps, 4 splitters x 4 ports of 22 kW, half "
+                                      "the users charge-sensitive (leave when charged), random levels, full "
+                                      "records", [W.user_station()], np.zeros(65536, np.int32), 4,
+                                "stations with charge-sensitive users", 64)
 
 
 def run_policy(args):
@@ -388,7 +400,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="uneven", choices=["uneven", "tiny", "scale", "v2g", "policy", "serve"])
+    ap.add_argument("--workload", default="uneven", choices=["uneven", "tiny", "scale", "v2g", "users", "policy", "serve"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain per-step comparison")
     ap.add_argument("--no-tune", action="store_true")
@@ -410,7 +422,8 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    run = {"uneven": run_uneven, "tiny": run_tiny, "scale": run_scale, "v2g": run_v2g, "policy": run_policy,
+    run = {"uneven": run_uneven, "tiny": run_tiny, "scale": run_scale, "v2g": run_v2g, "users": run_users,
+           "policy": run_policy,
            "serve": run_serve}[args.workload]
     print(json.dumps(run(args)))
 

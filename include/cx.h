@@ -126,6 +126,18 @@ typedef struct {
   double battery_soc0;          /* its SoC at the start of every day, in [0,1]         */
   double alpha_degrad_battery;  /* weight of c_degrad,battery (energy it discharges)   */
   double alpha_degrad_cars;     /* weight of c_degrad,cars (energy cars feed back)     */
+  /* Charge-sensitive users (App. A.1 "User Profiles", App. A.2 "Departure of
+   * Cars", App. A.3 c_satisfaction,1): each arriving car's user is charge-
+   * sensitive (u = 1) with probability charge_sensitive_share, drawn from
+   * Philox (env, g, j, 4) word 0 against an integer threshold.  Such a user
+   * leaves at the end of the step in which the energy still wanted reaches zero
+   * (e_rem <= 0), not when its planned stay ends: its steps left go negative
+   * while it overstays.  On leaving it adds (hours overstayed) - beta_sat1 x
+   * (hours left early) to c_satisfaction,1, weighted by alpha_sat1.
+   * steps_per_episode must be <= 30000 when the share is > 0. */
+  double charge_sensitive_share;  /* in [0,1]; 0 = every user time-sensitive        */
+  double alpha_sat1;              /* weight of c_satisfaction,1                      */
+  double beta_sat1;               /* its weight of the hours left early              */
 } cx_station_spec;
 
 typedef struct cx_ctx cx_ctx;
@@ -136,8 +148,10 @@ typedef struct cx_ctx cx_ctx;
  *           [occupied, SoC, e_rem/C, dwell/S, r_hat/pmax, p_last/pmax] x N ports
  *           (feature-major: feature f of port p at f*N + p), then
  *           [sin 2 pi t/S, cos 2 pi t/S, base price(t), occupied ports / N],
- *           then, with a battery, [battery SoC, battery power / battery_kw].
- *           p_last is negative while a port discharges.
+ *           then, with a battery, [battery SoC, battery power / battery_kw],
+ *           then, with charge-sensitive users, [u] x N ports (1 = charge-sensitive).
+ *           p_last is negative while a port discharges; dwell/S is negative while a
+ *           charge-sensitive user overstays.
  *   actions uint8 [T][total_ports] FULL and ACT_REWARD: the action byte applied per
  *           port (and battery: total_ports counts action bytes).
  *   reward  float [T][n_envs]
@@ -250,10 +264,12 @@ cx_status cx_observe(cx_ctx *ctx, float *obs_dev);
  * packing-independent host format of cx_info.state_bytes bytes, bit-exact, so a
  * restored context continues exactly as the original.  Both calls synchronise
  * the context's stream.  Format (little endian):
- *   u64 magic 0x31305843 ('CX01'), i64 n_envs, i64 ports (sum of n_ports over
+ *   u64 magic 0x32305843 ('CX02'), i64 n_envs, i64 ports (sum of n_ports over
  *   the envs), u32 g, i32 t_day,
- *   then per port in env/port order (24 bytes): i32 dwell (steps left, 0 = empty),
- *   f64 1 - SoC, f32 1 - target SoC, f32 battery capacity C, f32 last power;
+ *   then per port in env/port order (25 bytes): i32 dwell (steps left; <= 0 only
+ *   for a charge-sensitive user), f64 1 - SoC, f32 1 - target SoC, f32 battery
+ *   capacity C, f32 last power, u8 user (1 = charge-sensitive; a port is empty
+ *   when dwell <= 0 and user = 0);
  *   then per env: f64 return; then per env of a class with a station battery,
  *   in env order (12 bytes): f64 battery SoC, f32 battery last power.
  *   The energy still wanted is (target - SoC) * C.  An empty port is all zeros. */

@@ -83,7 +83,7 @@ size_t class_block(const SpecCopy &sc, const Compiled &k, const Tables &t, unsig
     }
     d.lvl_cap_u[lvl] = cu;
   }
-  d.kind = k.bidirectional() ? kKindBidir : simple ? kKindSimple : kKindGeneral;
+  d.kind = k.extended() ? kKindExt : simple ? kKindSimple : kKindGeneral;
   d.simple = d.kind == kKindSimple ? 1 : 0;
   d.n_neg = k.v2g ? s.n_levels : 0;
   d.has_batt = k.battery ? 1 : 0;
@@ -96,6 +96,11 @@ size_t class_block(const SpecCopy &sc, const Compiled &k, const Tables &t, unsig
     d.b_soc0 = s.battery_soc0; d.b_inv_rate = (float)(1.0 / s.battery_kw);
   }
   d.dt_d = s.dt_hours; d.inv_dt_d = 1.0 / s.dt_hours; d.inv_n_d = 1.0 / s.n_levels;
+  d.has_users = k.users ? 1 : 0;
+  d.cs_thresh = k.cs_thresh;
+  d.user_obs = k.user_obs;
+  d.alpha_sat1 = (float)s.alpha_sat1;
+  d.beta_sat1 = (float)s.beta_sat1;
   d.pmax_u = k.slot_pmax[0];
   d.inv_pmax_u = k.slot_inv_pmax[0];
   d.slot_port = reinterpret_cast<const int32_t *>(base + o_port);
@@ -220,6 +225,7 @@ cx_status rebuild_segments(cx_ctx *ctx) {
       sg.ret = ctx->ret + c.env_begin + e0;
       sg.bsoc = ctx->bsoc + c.env_begin + e0;
       sg.bp = ctx->bp + c.env_begin + e0;
+      sg.utype = ctx->utype + so;
       sg.obs_off = c.obs_off + e0 * c.comp.obs_dim;
       sg.act_off = c.port_off + e0 * c.comp.n_act;
       sg.env_off = c.env_begin + e0;
@@ -345,7 +351,8 @@ static cx_status create_impl(const cx_station_spec *specs, int32_t n_specs, cons
   const size_t dbytes = align256(sizeof(int16_t) * (size_t)slot_off);
   const size_t rbytes = align256(sizeof(double) * (size_t)n_envs);
   const size_t bbytes = align256(sizeof(float) * (size_t)n_envs);
-  const size_t total = qbytes + 3 * fbytes + dbytes + 2 * rbytes + bbytes;
+  const size_t ubytes = align256((size_t)slot_off);
+  const size_t total = qbytes + 3 * fbytes + dbytes + 2 * rbytes + bbytes + ubytes;
   if (hipMalloc(&ctx->state_mem, total) != hipSuccess) {
     free_ctx(ctx);
     return fail_status(CX_E_OOM, "hipMalloc of station state failed");
@@ -361,6 +368,7 @@ static cx_status create_impl(const cx_station_spec *specs, int32_t n_specs, cons
   ctx->ret = reinterpret_cast<double *>(b + qbytes + 3 * fbytes + dbytes);
   ctx->bsoc = reinterpret_cast<double *>(b + qbytes + 3 * fbytes + dbytes + rbytes);
   ctx->bp = reinterpret_cast<float *>(b + qbytes + 3 * fbytes + dbytes + 2 * rbytes);
+  ctx->utype = reinterpret_cast<uint8_t *>(b + qbytes + 3 * fbytes + dbytes + 2 * rbytes + bbytes);
   if (hipMemset(ctx->state_mem, 0, total) != hipSuccess) {
     free_ctx(ctx);
     return fail_status(CX_E_DEVICE, "hipMemset of station state failed");

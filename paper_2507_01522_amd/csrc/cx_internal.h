@@ -17,14 +17,15 @@ constexpr int kMaxWaves = 8;     // waves per block
 
 // Philox counter domains (word 3 of the counter); see the action / arrival
 // / noise derivations in the kernels.
-enum : uint32_t { kDomEnv = 0, kDomAct = 1, kDomCar = 2, kDomGum = 3 };
+enum : uint32_t { kDomEnv = 0, kDomAct = 1, kDomCar = 2, kDomGum = 3, kDomUser = 4 };
 
 // Packings: lanes per station L in {4,...,64} and slots per lane P in {1,2,4};
 // L * P = padded slots of the class.
 constexpr int kNumPackings = 15;
 // Kernel kinds per packing: general classes, SIMPLE classes (every per-slot
-// constant uniform), and bidirectional classes (V2G ports or a station battery).
-enum : int { kKindGeneral = 0, kKindSimple = 1, kKindBidir = 2, kNumKinds = 3 };
+// constant uniform), and extended classes (V2G ports, a station battery or
+// charge-sensitive users).
+enum : int { kKindGeneral = 0, kKindSimple = 1, kKindExt = 2, kNumKinds = 3 };
 __host__ __device__ constexpr int pack_lanes(int id) { return 4 << (id % 5); }
 __host__ __device__ constexpr int pack_per_lane(int id) { return 1 << (id / 5); }
 inline int pack_id(int lanes, int per_lane) {
@@ -60,8 +61,9 @@ struct ClassDev {
   const uint32_t *tpois;       // [steps_ep][32]
   const uint32_t *tdwell;      // [1 << dwell_log2]: thresholds for stays of 2, 3, ... steps
   const float *glob;           // [steps_ep][4]: sin, cos, base price, 0
-  // bidirectional classes: V2G ports and the station battery (FP64 constants:
-  // the battery is one scalar per station, its arithmetic is kept in FP64)
+  // extended classes: V2G ports and the station battery (FP64 constants: the
+  // battery is one scalar per station, its arithmetic is kept in FP64), and
+  // charge-sensitive users
   int32_t n_neg;               // discharge levels of a port: n_levels (V2G) or 0
   int32_t has_batt;            // 1: a station battery (the (N+1)-th action byte)
   int32_t n_act;               // action bytes per env
@@ -72,6 +74,11 @@ struct ClassDev {
   double dt_d, inv_dt_d, inv_n_d;  // dt, 1/dt, 1/n_levels in FP64
   const float *slot_pdis;      // [S]: discharge maxima
   const float *slot_eta;       // [S]: efficiencies
+  int32_t has_users;           // 1: some users are charge-sensitive
+  uint32_t cs_thresh;          // a user is charge-sensitive iff its Philox word <= cs_thresh
+  int32_t user_obs;            // observation offset of the per-port user flags
+  float alpha_sat1, beta_sat1; // c_satisfaction,1 weight and its early-leave weight
+  float pad_u;
 };
 
 // One class's env range inside a launch.  Static fields are set when the
@@ -109,6 +116,8 @@ struct SegDev {
   // station battery state per env (battery classes): SoC (FP64) and last power
   double *bsoc;
   float *bp;
+  // user type per slot (classes with charge-sensitive users): 1 = charge-sensitive
+  uint8_t *utype;
 };
 
 // Launch-wide arguments (by value).

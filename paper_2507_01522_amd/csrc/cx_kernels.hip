@@ -156,8 +156,8 @@ __device__ __forceinline__ T ld_at(const T *base, uint32_t byte_off) {
 // port maximum and efficiency, and per tree level one block size and one limit.
 // Port indices and record offsets are then compile-time constants and every
 // per-slot constant is wave-uniform (scalar registers).
-// BIDIR: V2G ports and / or a station battery (never SIMPLE).
-template <int L, int P, bool SIMPLE, bool BIDIR>
+// EXT: V2G ports and / or a station battery (never SIMPLE).
+template <int L, int P, bool SIMPLE, bool EXT>
 __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int group, const uint32_t *tdw,
                                           bool tdw_lds) {
   constexpr int SPW = 64 / L;
@@ -172,15 +172,16 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
   const int S = DENSE ? L * P : C.S;
   const int D = C.D;
   const int N = DENSE ? L * P : C.n_ports;
-  const int obs_dim = BIDIR ? C.obs_dim : 6 * N + 4;
-  const int n_act = BIDIR ? C.n_act : N;      // action bytes per env
-  const int n_neg = BIDIR ? C.n_neg : 0;      // discharge levels of a port
-  const bool batt = BIDIR && C.has_batt != 0;
+  const int obs_dim = EXT ? C.obs_dim : 6 * N + 4;
+  const int n_act = EXT ? C.n_act : N;      // action bytes per env
+  const int n_neg = EXT ? C.n_neg : 0;      // discharge levels of a port
+  const bool batt = EXT && C.has_batt != 0;
+  const bool users = EXT && C.has_users != 0;  // some users are charge-sensitive
 
   // ---- per-slot constants
   int port[P];
   float pmax[P], inv_pmax[P], inv_eta[P], lcap[kMaxLevels][P];
-  float pdis[P], eta[P];  // BIDIR only
+  float pdis[P], eta[P];  // EXT only
   uint32_t lbp[P];
 #pragma unroll
   for (int j = 0; j < P; ++j) {
@@ -201,7 +202,7 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
 #pragma unroll
       for (int d = 0; d < kMaxLevels; ++d) lcap[d][j] = d < D ? gld(C.slot_cap, d * S + s) : __builtin_inff();
     }
-    if constexpr (BIDIR) {
+    if constexpr (EXT) {
       pdis[j] = gld(C.slot_pdis, s);
       eta[j] = gld(C.slot_eta, s);
     }
@@ -212,6 +213,7 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
   float qf[P];  // (float) q, kept in step with q: the FP32 work reads it
   float u[P], cap[P], icap[P], plast[P];
   int dw[P];
+  int cs[P];  // EXT: 1 = a charge-sensitive user holds the slot (its dw may be <= 0)
   const int64_t sofs = (int64_t)env * S;
 #pragma unroll
   for (int j = 0; j < P; ++j) {
@@ -222,13 +224,17 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
     cap[j] = active ? sg.cap[i] : 0.f;
     plast[j] = active ? sg.p_last[i] : 0.f;
     dw[j] = active ? (int)sg.dwell[i] : 0;
+    cs[j] = (users && active) ? (int)sg.utype[i] : 0;
     icap[j] = cap[j] > 0.f ? frcp(cap[j]) : 0.f;
   }
+  // a slot is occupied while its car's stay runs, or while a charge-sensitive
+  // user waits to be charged
+#define CX_OCCUPIED(j) (EXT ? (dw[j] > 0 || cs[j] != 0) : dw[j] > 0)
   double ret = active ? sg.ret[env] : 0.0;
-  // station battery (BIDIR): SoC in FP64 and last power, alike in every lane of the station
+  // station battery (EXT): SoC in FP64 and last power, alike in every lane of the station
   double bsoc = 0.0;
   float bpw = 0.f;
-  if constexpr (BIDIR) {
+  if constexpr (EXT) {
     if (batt && active) {
       bsoc = sg.bsoc[env];
       bpw = sg.bp[env];
@@ -244,7 +250,7 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
   const int n_levels = C.n_levels;
   int t_day = dy.t_day0;
   uint32_t g = dy.g0;
-  int bM = 0, bdw = 1;
+  int bM = 0, bdw = 1, bus = 0;
   float bpb = 0.f, bcp = 0.f, bs0 = 0.f, btg = 0.f;
   U4 aw[P];
 #pragma unroll
@@ -287,6 +293,9 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
       bs0 = C.soc_lo + C.soc_span * u24(b.y);
       btg = C.tgt_lo + C.tgt_span * u24(b.z);
       bdw = stay_len(tdw, tdw_lds, C.dwell_log2, b.w);
+      if constexpr (EXT) {
+        if (users) bus = philox(env_id, gl, 0u, kDomUser, k0, k1).x <= C.cs_thresh ? 1 : 0;
+      }
     }
     const int tb = t & (L - 1);
     const int M = bcast<L>(bM, tb);
@@ -299,7 +308,7 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
       if (t == 0 || (g & 3u) == 0) {
 #pragma unroll
         for (int j = 0; j < P; ++j) aw[j] = philox(env_id, g >> 2, (uint32_t)port[j], kDomAct, k0, k1);
-        if constexpr (BIDIR) {
+        if constexpr (EXT) {
           if (batt) bw = philox(env_id, g >> 2, (uint32_t)N, kDomAct, k0, k1);
         }
       }
@@ -309,7 +318,7 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
         const uint32_t w = sel == 0 ? aw[j].x : sel == 1 ? aw[j].y : sel == 2 ? aw[j].z : aw[j].w;
         k[j] = (int)__umulhi(w, (uint32_t)(n_levels + n_neg + 1));
       }
-      if constexpr (BIDIR) {
+      if constexpr (EXT) {
         const uint32_t w = sel == 0 ? bw.x : sel == 1 ? bw.y : sel == 2 ? bw.z : bw.w;
         kb = (int)__umulhi(w, (uint32_t)(2 * n_levels + 1));
       }
@@ -325,7 +334,7 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
           v = ld_at(ai_t, act_bo + (uint32_t)port[j]);
         k[j] = v > n_levels + n_neg ? n_levels + n_neg : v;
       }
-      if constexpr (BIDIR) {
+      if constexpr (EXT) {
         int v = 0;
         if (batt && active) v = ld_at(ai_t, act_bo + (uint32_t)N);
         kb = v > 2 * n_levels ? 2 * n_levels : v;
@@ -333,7 +342,7 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
     }
 
     // ---- apply actions: clip by request, charge curve, battery room; a
-    // discharging port (BIDIR) by its discharge maximum, the charging curve
+    // discharging port (EXT) by its discharge maximum, the charging curve
     // mirrored about SoC 1/2 and the energy stored
     float pw[P];
 #pragma unroll
@@ -341,7 +350,7 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
       const float req = (float)k[j] * C.inv_n_levels * pmax[j];
       const float rhat = pmax[j] * fminf(1.0f, qf[j] * C.inv_1mtau);
       const float room = qf[j] * cap[j] * C.inv_dt;
-      if constexpr (BIDIR) {
+      if constexpr (EXT) {
         const int lev = k[j] - n_neg;
         const float soc = (float)(1.0 - q[j]);
         const float creq = (float)lev * C.inv_n_levels * pmax[j];
@@ -349,7 +358,7 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
         const float drate = pmax[j] * fminf(1.0f, soc * C.inv_1mtau);
         const float stored = soc * cap[j] * C.inv_dt;
         const float p = lev >= 0 ? fminf(fminf(creq, rhat), room) : -fminf(fminf(dreq, drate), stored);
-        pw[j] = dw[j] > 0 ? p : 0.0f;
+        pw[j] = CX_OCCUPIED(j) ? p : 0.0f;
       } else {
         pw[j] = dw[j] > 0 ? fminf(fminf(req, rhat), room) : 0.0f;
       }
@@ -393,7 +402,7 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
 #pragma unroll
         for (int j = 0; j < P; ++j) {
           const float c = lcap[d][j];
-          if constexpr (BIDIR) {
+          if constexpr (EXT) {
             const float a = fabsf(s[j]);   // the limit bounds the magnitude of the net power
             pw[j] = a > c ? pw[j] * (c * frcp(a)) : pw[j];
           } else {
@@ -405,7 +414,7 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
     // root: the station total before root scaling; the delivered energy is its
     // scaled value (App. A.3, charging only)
     float e_net, e_grid, e_out = 0.f;
-    if constexpr (BIDIR) {
+    if constexpr (EXT) {
       float tot = 0.f;
 #pragma unroll
       for (int j = 0; j < P; ++j) tot += pw[j];
@@ -445,10 +454,10 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
       }
     }
 
-    // ---- the station battery (BIDIR): the (N+1)-th pole at the grid
+    // ---- the station battery (EXT): the (N+1)-th pole at the grid
     // connection, same curves, FP64 like the cars' q
     float e_b = 0.f;
-    if constexpr (BIDIR) {
+    if constexpr (EXT) {
       if (batt) {
         const int lev = kb - n_levels;
         const double sb = bsoc;
@@ -472,21 +481,36 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
       }
     }
 
-    // ---- charge, departures (selects: no branches)
-    float csat = 0.f;
+    // ---- charge, departures (selects: no branches): a time-sensitive user
+    // leaves when its stay ends (c_satisfaction,0: energy still wanted), a
+    // charge-sensitive one (EXT) when no energy is wanted any more
+    // (c_satisfaction,1: hours overstayed - beta x hours left early)
+    float csat = 0.f, csat1 = 0.f;
 #pragma unroll
     for (int j = 0; j < P; ++j) {
-      const bool occ = dw[j] > 0;                // pw = 0 and icap = 0 on empty slots
+      const bool occ = CX_OCCUPIED(j);              // pw = 0 and icap = 0 on empty slots
       const float e = C.dt * pw[j];
       const double nq = q[j] - (double)(e * icap[j]);
       q[j] = nq > 0.0 ? nq : 0.0;
-      if constexpr (BIDIR) q[j] = q[j] < 1.0 ? q[j] : 1.0;  // discharging never below SoC 0
+      if constexpr (EXT) q[j] = q[j] < 1.0 ? q[j] : 1.0;  // discharging never below SoC 0
       qf[j] = (float)q[j];
       plast[j] = pw[j];
       dw[j] -= occ ? 1 : 0;
-      const bool dep = occ && dw[j] == 0;
+      bool dep = occ && dw[j] == 0;
+      bool dep0 = dep;  // a time-sensitive user leaves
+      if constexpr (EXT) {
+        if (users) {
+          const bool csu = cs[j] != 0;
+          dep = occ && (csu ? q[j] <= (double)u[j] : dw[j] == 0);
+          dep0 = dep && !csu;
+          const float tl = (float)dw[j] * C.dt;
+          csat1 += (dep && csu) ? fmaxf(0.0f, -tl) - C.beta_sat1 * fmaxf(0.0f, tl) : 0.0f;
+          cs[j] = dep ? 0 : cs[j];
+          dw[j] = dep ? 0 : dw[j];   // a charged user may leave with steps of its stay left
+        }
+      }
       const float miss = fmaxf(0.0f, (qf[j] - u[j]) * cap[j]);
-      csat += dep ? miss : 0.0f;
+      csat += dep0 ? miss : 0.0f;
       q[j] = dep ? 0.0 : q[j];
       qf[j] = dep ? 0.0f : qf[j];
       u[j] = dep ? 0.f : u[j];
@@ -495,6 +519,9 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
       plast[j] = dep ? 0.f : plast[j];
     }
     if (C.alpha_sat != 0.0f) csat = station_sum<L>(csat);
+    if constexpr (EXT) {
+      if (users && C.alpha_sat1 != 0.0f) csat1 = station_sum<L>(csat1);
+    }
 
     // ---- arrivals: first free ports in port order take the accepted cars
     int cnt[P], below[P];
@@ -502,7 +529,7 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
     int n_free = 0;
 #pragma unroll
     for (int j = 0; j < P; ++j) {
-      fr[j] = dw[j] == 0 && (DENSE || port[j] >= 0);
+      fr[j] = (EXT ? !CX_OCCUPIED(j) : dw[j] == 0) && (DENSE || port[j] >= 0);
       const uint64_t m = __ballot(fr[j]) & smask;
       cnt[j] = __popcll(m);
       below[j] = __popcll(m & below_mask);
@@ -514,6 +541,7 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
       // the first car's profile was drawn ahead by lane tb of the station
       const float f_cp = bcastf<L>(bcp, tb), f_s0 = bcastf<L>(bs0, tb), f_tg = bcastf<L>(btg, tb);
       const int f_dw = bcast<L>(bdw, tb);
+      const int f_us = EXT ? bcast<L>(bus, tb) : 0;
       int run = 0;
 #pragma unroll
       for (int j = 0; j < P; ++j) {
@@ -521,14 +549,19 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
         if (fr[j] && rank < acc) {
           float cp = f_cp, s0 = f_s0, tg = f_tg;
           int dd = f_dw;
+          int us = f_us;
           if (rank > 0) {
             const U4 b = philox(env_id, g, (uint32_t)rank, kDomCar, k0, k1);
             cp = C.cap_lo + C.cap_span * u24(b.x);
             s0 = C.soc_lo + C.soc_span * u24(b.y);
             tg = C.tgt_lo + C.tgt_span * u24(b.z);
             dd = stay_len(tdw, tdw_lds, C.dwell_log2, b.w);
+            if constexpr (EXT) {
+              if (users) us = philox(env_id, g, (uint32_t)rank, kDomUser, k0, k1).x <= C.cs_thresh ? 1 : 0;
+            }
           }
           dw[j] = dd;
+          if constexpr (EXT) cs[j] = us;
           cap[j] = cp;
           icap[j] = frcp(cp);
           q[j] = 1.0 - (double)s0;
@@ -542,11 +575,11 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
 
     // ---- reward (App. A.3)
     float r;
-    if constexpr (BIDIR) {
+    if constexpr (EXT) {
       const float e_gn = e_grid + e_b;
       const float price = e_gn > 0.0f ? pbuy : C.p_sell_grid;
       r = C.p_sell * e_net - price * e_gn - C.fixed_cost - C.alpha_sat * csat - C.alpha_dec * (float)rej -
-          C.alpha_db * fmaxf(0.0f, -e_b) + C.alpha_dc * e_out;
+          C.alpha_db * fmaxf(0.0f, -e_b) + C.alpha_dc * e_out - C.alpha_sat1 * csat1;
     } else {
       const float price = e_grid > 0.0f ? pbuy : C.p_sell_grid;
       r = C.p_sell * e_net - price * e_grid - C.fixed_cost - C.alpha_sat * csat - C.alpha_dec * (float)rej;
@@ -561,8 +594,9 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
 #pragma unroll
       for (int j = 0; j < P; ++j) {
         dw[j] = 0; q[j] = 0.0; qf[j] = 0.f; u[j] = 0.f; cap[j] = 0.f; icap[j] = 0.f; plast[j] = 0.f;
+        if constexpr (EXT) cs[j] = 0;
       }
-      if constexpr (BIDIR) {
+      if constexpr (EXT) {
         if (batt) {
           bsoc = C.b_soc0;
           bpw = 0.f;
@@ -577,7 +611,7 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
 #pragma unroll
         for (int j = 0; j < P; ++j) {
           if (DENSE || port[j] >= 0) {
-            const bool occ = dw[j] > 0;
+            const bool occ = CX_OCCUPIED(j);
             const uint32_t o = obs_bo + 4u * (uint32_t)port[j];
             st_at(ob, o + 0u * 4u * N, occ ? 1.0f : 0.0f);
             st_at(ob, o + 1u * 4u * N, occ ? 1.0f - qf[j] : 0.0f);
@@ -585,6 +619,9 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
             st_at(ob, o + 3u * 4u * N, (float)dw[j] * C.inv_steps_ep);
             st_at(ob, o + 4u * 4u * N, occ ? fminf(1.0f, qf[j] * C.inv_1mtau) : 0.0f);
             st_at(ob, o + 5u * 4u * N, plast[j] * inv_pmax[j]);
+            if constexpr (EXT) {
+              if (users) st_at(ob, obs_bo + 4u * (uint32_t)(C.user_obs + port[j]), cs[j] ? 1.0f : 0.0f);
+            }
           }
         }
         if (l < 4) {
@@ -592,7 +629,7 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
           const float gv = l == 3 ? (float)n_occ * (1.0f / (float)N) : gld(C.glob, t_day * 4 + l);
           st_at(ob, obs_bo + 4u * (uint32_t)(6 * N + l), gv);
         }
-        if constexpr (BIDIR) {
+        if constexpr (EXT) {
           if (batt && l < 2)
             st_at(ob, obs_bo + 4u * (uint32_t)(6 * N + 4 + l), l == 0 ? (float)bsoc : bpw * C.b_inv_rate);
         }
@@ -602,7 +639,7 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
 #pragma unroll
         for (int j = 0; j < P; ++j)
           if (DENSE || port[j] >= 0) st_at(ab, act_bo + (uint32_t)port[j], (uint8_t)k[j]);
-        if constexpr (BIDIR) {
+        if constexpr (EXT) {
           if (batt && l == 0) st_at(ab, act_bo + (uint32_t)N, (uint8_t)kb);
         }
       }
@@ -633,9 +670,12 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
       sg.cap[i] = cap[j];
       sg.p_last[i] = plast[j];
       sg.dwell[i] = (int16_t)dw[j];
+      if constexpr (EXT) {
+        if (users) sg.utype[i] = (uint8_t)cs[j];
+      }
     }
     if (l == 0) sg.ret[env] = ret;
-    if constexpr (BIDIR) {
+    if constexpr (EXT) {
       if (batt && l == 0) {
         sg.bsoc[env] = bsoc;
         sg.bp[env] = bpw;
@@ -644,9 +684,11 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
   }
 }
 
+#undef CX_OCCUPIED
+
 // One kernel per packing (lanes per station L, slots per lane P) and class
 // kind (general, SIMPLE, bidirectional), so that each keeps its own register budget.
-template <int L, int P, bool SIMPLE, bool BIDIR>
+template <int L, int P, bool SIMPLE, bool EXT>
 __global__ __launch_bounds__(512) void k_rollout(LaunchArgs a) {
   extern __shared__ uint32_t lds_tdwell[];
   const int b = blockIdx.x;
@@ -680,7 +722,7 @@ __global__ __launch_bounds__(512) void k_rollout(LaunchArgs a) {
   const int W = blockDim.x >> 6;
   const int group = __builtin_amdgcn_readfirstlane((b - sg.block_begin) * W + (int)(threadIdx.x >> 6));
   if (group >= sg.n_groups) return;
-  run_group<L, P, SIMPLE, BIDIR>(sg, dy, group, tdw, tdw_lds);
+  run_group<L, P, SIMPLE, EXT>(sg, dy, group, tdw, tdw_lds);
 }
 
 // Observation of empty stations at t_day = 0 for every env of one segment.

@@ -308,8 +308,8 @@ __global__ __launch_bounds__(64 * kPolWaves) void k_policy(PolicyArgs a) {
 
 // Observation of the current state (the features the step kernel records).
 __global__ void k_observe(const ClassDev *cls, int64_t n_envs, const double *q, const float *u,
-                          const float *p_last, const int16_t *dwell, const double *bsoc, const float *bp,
-                          int32_t t_day, float *obs) {
+                          const float *p_last, const int16_t *dwell, const uint8_t *utype, const double *bsoc,
+                          const float *bp, int32_t t_day, float *obs) {
   const ClassDev C = *cls;
   const int S = C.S, N = C.n_ports, dim = C.obs_dim;
   const int64_t total = n_envs * S;
@@ -320,7 +320,8 @@ __global__ void k_observe(const ClassDev *cls, int64_t n_envs, const double *q, 
     const int port = C.slot_port[s];
     if (port < 0) continue;
     const int dw = dwell[i];
-    const bool occ = dw > 0;
+    const bool cs = C.has_users && utype[i] != 0;
+    const bool occ = dw > 0 || cs;
     const float qf = (float)q[i];
     float *o = obs + env * dim + port;
     o[0 * N] = occ ? 1.0f : 0.0f;
@@ -329,11 +330,13 @@ __global__ void k_observe(const ClassDev *cls, int64_t n_envs, const double *q, 
     o[3 * N] = (float)dw * C.inv_steps_ep;
     o[4 * N] = occ ? fminf(1.0f, qf * C.inv_1mtau) : 0.0f;
     o[5 * N] = p_last[i] * C.slot_inv_pmax[s];
+    if (C.has_users) obs[env * dim + C.user_obs + port] = cs ? 1.0f : 0.0f;
   }
   for (int64_t env = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; env < n_envs;
        env += (int64_t)gridDim.x * blockDim.x) {
     int n_occ = 0;
-    for (int s = 0; s < S; ++s) n_occ += dwell[env * S + s] > 0 ? 1 : 0;
+    for (int s = 0; s < S; ++s)
+      n_occ += (dwell[env * S + s] > 0 || (C.has_users && utype[env * S + s] != 0)) ? 1 : 0;
     float *o = obs + env * dim + 6 * N;
     o[0] = C.glob[t_day * 4 + 0];
     o[1] = C.glob[t_day * 4 + 1];
@@ -361,7 +364,8 @@ hipError_t launch_observe(const cx_ctx *ctx, float *obs, hipStream_t st) {
     const int blocks = (int)std::min<int64_t>(4096, (work + 255) / 256);
     hipLaunchKernelGGL(k_observe, dim3(blocks), dim3(256), 0, st, c.dev, c.n_envs, ctx->q + c.slot_off,
                        ctx->u + c.slot_off, ctx->p_last + c.slot_off, ctx->dwell + c.slot_off,
-                       ctx->bsoc + c.env_begin, ctx->bp + c.env_begin, ctx->t_day, obs + c.obs_off);
+                       ctx->utype + c.slot_off, ctx->bsoc + c.env_begin, ctx->bp + c.env_begin, ctx->t_day,
+                       obs + c.obs_off);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -469,7 +473,7 @@ cx_status cx_set_policy(cx_ctx *ctx, int32_t hidden, const uint16_t *w1, const u
   if (!w1 || !b1 || !w2 || !b2) return fail_status(CX_E_INVALID, "cx_set_policy: NULL weight array");
   if (ctx->classes.size() != 1) return fail_status(CX_E_INVALID, "cx_set_policy: single-class contexts only");
   const ClassRt &c = ctx->classes[0];
-  if (c.comp.bidirectional())
+  if (c.comp.extended())
     return fail_status(CX_E_INVALID, "cx_set_policy: charging-only stations only (no V2G, no battery)");
   const int N = c.comp.N, L1 = c.spec.s.n_levels + 1, in_dim = 6 * N + 4;
   if (hidden < 32 || hidden > 32 * kPolHP || hidden % 32 != 0)

@@ -65,6 +65,8 @@ bool copy_spec(const cx_station_spec &in, SpecCopy *out, std::string *err) {
 
 static bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 
+static uint32_t cdf_threshold(double F);
+
 bool compile_spec(const SpecCopy &sc, Compiled *c, std::string *err) {
   const cx_station_spec &s = sc.s;
   const int N = s.n_ports, H = s.n_nodes;
@@ -102,6 +104,11 @@ bool compile_spec(const SpecCopy &sc, Compiled *c, std::string *err) {
   }
   if (!std::isfinite(s.alpha_degrad_battery) || !std::isfinite(s.alpha_degrad_cars))
     return fail(err, "degradation weights must be finite");
+  if (!(s.charge_sensitive_share >= 0.0 && s.charge_sensitive_share <= 1.0))
+    return fail(err, "charge_sensitive_share must be in [0,1]");
+  if (!std::isfinite(s.alpha_sat1) || !std::isfinite(s.beta_sat1)) return fail(err, "alpha_sat1, beta_sat1 must be finite");
+  if (s.charge_sensitive_share > 0.0 && s.steps_per_episode > 30000)
+    return fail(err, "steps_per_episode must be <= 30000 with charge-sensitive users");
   // ---- tree
   if (sc.node_parent[0] != -1) return fail(err, "node 0 must be the root (parent -1)");
   for (int h = 1; h < H; ++h)
@@ -198,8 +205,11 @@ bool compile_spec(const SpecCopy &sc, Compiled *c, std::string *err) {
   c->inv_eta_uniform = (float)(1.0 / sc.port_eta[0]);
   c->v2g = s.v2g == 1;
   c->battery = s.battery_kwh > 0.0;
+  c->users = s.charge_sensitive_share > 0.0;
+  c->cs_thresh = c->users ? cdf_threshold(s.charge_sensitive_share) : 0u;
   c->n_act = N + (c->battery ? 1 : 0);
-  c->obs_dim = 6 * N + 4 + (c->battery ? 2 : 0);
+  c->user_obs = 6 * N + 4 + (c->battery ? 2 : 0);
+  c->obs_dim = c->user_obs + (c->users ? N : 0);
   return true;
 }
 

@@ -32,8 +32,11 @@ struct Compiled {
   bool uniform_eta = true;
   float inv_eta_uniform = 1.f;
   bool v2g = false, battery = false;       // ports discharge / a station battery
+  bool users = false;                      // some users are charge-sensitive (u = 1)
+  uint32_t cs_thresh = 0;                  // u = 1 iff the user word <= cs_thresh
   int n_act = 0, obs_dim = 0;              // action bytes and observation floats per env
-  bool bidirectional() const { return v2g || battery; }  // needs the V2G kernels
+  int user_obs = 0;                        // observation offset of the user flags
+  bool extended() const { return v2g || battery || users; }  // needs the extended kernels
 };
 
 struct Tables {

@@ -43,7 +43,8 @@ class StationSpecC(C.Structure):
                 ("arrival_rate", C.c_void_p), ("price_table", C.c_void_p), ("v2g", C.c_int32),
                 ("port_pdis_kw", C.c_void_p), ("battery_kwh", C.c_double), ("battery_kw", C.c_double),
                 ("battery_tau", C.c_double), ("battery_soc0", C.c_double),
-                ("alpha_degrad_battery", C.c_double), ("alpha_degrad_cars", C.c_double)]
+                ("alpha_degrad_battery", C.c_double), ("alpha_degrad_cars", C.c_double),
+                ("charge_sensitive_share", C.c_double), ("alpha_sat1", C.c_double), ("beta_sat1", C.c_double)]
 
 
 class TrajC(C.Structure):
@@ -186,7 +187,9 @@ class _SpecHolder:
                               float(getattr(spec, "battery_kwh", 0.0)), float(getattr(spec, "battery_kw", 0.0)),
                               float(getattr(spec, "battery_tau", 0.8)), float(getattr(spec, "battery_soc0", 0.5)),
                               float(getattr(spec, "alpha_degrad_battery", 0.0)),
-                              float(getattr(spec, "alpha_degrad_cars", 0.0)))
+                              float(getattr(spec, "alpha_degrad_cars", 0.0)),
+                              float(getattr(spec, "charge_sensitive_share", 0.0)),
+                              float(getattr(spec, "alpha_sat1", 0.0)), float(getattr(spec, "beta_sat1", 0.0)))
 
 
 def compile_layout(spec) -> Dict[str, np.ndarray]:
@@ -335,9 +338,9 @@ class Env:
         check(lib().cx_set_state(self.h, buf, len(blob)))
 
     def state_arrays(self) -> Dict[str, np.ndarray]:
-        """Decode get_state(): per-port dwell/soc/e_rem/cap/p_last (env-major port order),
-        returns, and per env the station battery's SoC and last power (battery
-        classes; other envs read as 0)."""
+        """Decode get_state(): per-port dwell/soc/e_rem/cap/p_last/user (env-major port
+        order), returns, and per env the station battery's SoC and last power
+        (battery classes; other envs read as 0)."""
         blob = self.get_state()
         i = self.info()
         head = np.frombuffer(blob, dtype=np.uint8, count=32)
@@ -345,9 +348,9 @@ class Env:
         g = int(head[24:28].view(np.uint32)[0])
         t_day = int(head[28:32].view(np.int32)[0])
         rec = np.frombuffer(blob, dtype=np.dtype([("dwell", "<i4"), ("q", "<f8"), ("u", "<f4"),
-                                                  ("cap", "<f4"), ("p_last", "<f4")]),
+                                                  ("cap", "<f4"), ("p_last", "<f4"), ("user", "u1")]),
                             count=n_ports, offset=32)
-        off = 32 + 24 * n_ports
+        off = 32 + 25 * n_ports
         ret = np.frombuffer(blob, dtype="<f8", count=i.n_envs, offset=off)
         off += 8 * i.n_envs
         bsoc = np.zeros(i.n_envs)
@@ -361,7 +364,8 @@ class Env:
             bp[ci.env_begin:ci.env_begin + ci.n_envs] = b["p"]
             off += 12 * ci.n_envs
         out = {k: np.array(rec[k]) for k in rec.dtype.names}
-        occ = out["dwell"] > 0
+        out["user"] = out["user"].astype(np.int32)
+        occ = (out["dwell"] > 0) | (out["user"] == 1)
         out["soc"] = np.where(occ, 1.0 - out["q"], 0.0)
         out["e_rem"] = np.where(occ, (out["q"] - out["u"].astype(np.float64)) * out["cap"], 0.0)
         out["ret"] = np.array(ret)

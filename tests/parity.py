@@ -2,10 +2,16 @@
 oracle on the same seeded inputs and compare them element by element.
 
 Tolerances (FP32 library vs FP64 oracle):
-  * integers (levels, done flags, occupancy, dwell, arrivals) -- exact;
+  * integers (levels, done flags, occupancy, dwell, arrivals, user types) -- exact;
   * FP values: |gpu - ref| <= 1e-5 * max(|ref|, floor), with floor
       1 for SoC and observations, C (battery capacity) for e_rem,
       p_sell * L_root * dt (the largest profit of one step) for rewards/returns.
+
+Charge-sensitive users leave when a float (the energy still wanted) reaches
+zero, so the two sides may take that decision differently when it lands within
+rounding of zero.  compare_rollout_flips accepts such an env from the step it
+parts on -- only if the oracle, replayed step by step, shows a near-tie there --
+and leaves it out from then on; the flips are counted.
 """
 from __future__ import annotations
 
@@ -36,6 +42,9 @@ def obs_masks(specs, env_class):
         scale[o + 3 * N:o + 4 * N] = s.steps_per_episode
         kind[o + 6 * N + 3] = 3
         scale[o + 6 * N + 3] = N
+        if getattr(s, "has_users", False):
+            uo = o + 6 * N + 4 + (2 if s.has_battery else 0)
+            kind[uo:uo + N] = 1
     return kind, scale
 
 
@@ -89,17 +98,22 @@ def compare_rollout(gpu, ref, specs, env_class, check_obs=True):
         compare_obs(gpu["obs"], ref["obs"], specs, env_class)
 
 
-def compare_state(st, bs, specs, env_class):
-    """st: Env.state_arrays(); bs: oracle BatchState."""
-    assert np.array_equal(st["dwell"], bs.dwell), "dwell differs"
+def compare_state(st, bs, specs, env_class, keep=None):
+    """st: Env.state_arrays(); bs: oracle BatchState.  keep: optional env mask
+    (envs left out after a float-decided departure went the other way)."""
+    env_class = np.asarray(env_class)
+    keep = np.ones(len(env_class), bool) if keep is None else np.asarray(keep, bool)
+    pk = np.repeat(keep, np.diff(bs.port_off))
+    assert np.array_equal(st["dwell"][pk], bs.dwell[pk]), "dwell differs"
+    assert np.array_equal(st["user"][pk], bs.user[pk]), "user types differ"
     assert st["g"] == bs.g and st["t_day"] == bs.t_day
-    check_close("soc", st["soc"], bs.soc, 1.0)
-    check_close("cap", st["cap"], bs.cap, 1.0)
-    check_close("e_rem", st["e_rem"], bs.e_rem, np.maximum(bs.cap, 1.0))
+    check_close("soc", st["soc"][pk], bs.soc[pk], 1.0)
+    check_close("cap", st["cap"][pk], bs.cap[pk], 1.0)
+    check_close("e_rem", st["e_rem"][pk], bs.e_rem[pk], np.maximum(bs.cap[pk], 1.0))
     pmax = np.concatenate([specs[c].port_pmax_kw for c in env_class])
-    check_close("p_last", st["p_last"], bs.p_last, pmax)
-    check_close("return", st["ret"], bs.ret, reward_floor(specs, env_class))
-    has_b = np.array([specs[c].has_battery for c in env_class])
+    check_close("p_last", st["p_last"][pk], bs.p_last[pk], pmax[pk])
+    check_close("return", st["ret"][keep], bs.ret[keep], reward_floor(specs, env_class)[keep])
+    has_b = np.array([specs[c].has_battery for c in env_class]) & keep
     if has_b.any():
         check_close("battery soc", st["batt_soc"][has_b], bs.batt[0::2][has_b], 1.0)
         bkw = np.array([specs[c].battery_kw for c in env_class])[has_b]
@@ -108,3 +122,86 @@ def compare_state(st, bs, specs, env_class):
 
 def to_np(out):
     return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+# ---- float-decided departures (charge-sensitive users) -----------------------
+
+TIE_KWH = 1e-4   # |energy still wanted| below this at a departure decision is a near-tie
+
+
+def env_mismatch_steps(gpu, ref, specs, env_class):
+    """First step at which each env's records differ beyond tolerance (T if never)."""
+    T, E = gpu["reward"].shape
+    ao, oo = env_layout(specs, env_class)
+    bad = np.zeros((T, E), bool)
+    if "actions" in gpu and gpu["actions"] is not None and ref.get("act") is not None:
+        d = gpu["actions"] != ref["act"]
+        for e in range(E):
+            bad[:, e] |= d[:, ao[e]:ao[e + 1]].any(axis=1)
+    bad |= gpu["done"] != ref["done"]
+    floor = reward_floor(specs, env_class)[None, :]
+    g, r = np.asarray(gpu["reward"], np.float64), np.asarray(ref["reward"], np.float64)
+    bad |= np.abs(g - r) > REL * np.maximum(np.abs(r), floor)
+    if "obs" in gpu and ref.get("obs") is not None:
+        kind, scale = obs_masks(specs, env_class)
+        go, ro = np.asarray(gpu["obs"], np.float64), np.asarray(ref["obs"], np.float64)
+        ints = kind > 0
+        dint = np.zeros_like(go, dtype=bool)
+        dint[:, ints] = np.rint(go[:, ints] * scale[ints]) != np.rint(ro[:, ints] * scale[ints])
+        dfp = np.zeros_like(go, dtype=bool)
+        dfp[:, ~ints] = np.abs(go[:, ~ints] - ro[:, ~ints]) > REL * np.maximum(np.abs(ro[:, ~ints]), 1.0)
+        d = dint | dfp
+        for e in range(E):
+            bad[:, e] |= d[:, oo[e]:oo[e + 1]].any(axis=1)
+    first = np.where(bad.any(axis=0), bad.argmax(axis=0), T)
+    return first
+
+
+def near_tie_steps(o, spec, seed, env_id, T, mode=1, act_in=None, g0=0):
+    """Replay one env in the oracle; steps whose charge-sensitive departure test
+    (energy still wanted after charging <= 0) was within TIE_KWH of zero."""
+    c = o.OracleClass(spec)
+    st = c.new_state()
+    ties = []
+    for t in range(T):
+        g = g0 + t
+        ext = None if act_in is None else act_in[t]
+        k = c.draw_actions(mode, seed, env_id, g, ext)
+        x = c.draw_exo(seed, env_id, g, st.t_day)
+        cs = ((st.dwell > 0) | (st.user == 1)) & (st.user == 1)
+        e_before = st.e_rem.copy()
+        _, _, P = c.transition(st, k, x)
+        after = e_before - spec.dt_hours * P
+        if np.any(np.abs(after[cs]) < TIE_KWH):
+            ties.append(t)
+    return ties
+
+
+def compare_rollout_flips(o, gpu, ref, specs, env_class, seed, mode=1, act_in=None, lag=2):
+    """compare_rollout, except that an env whose records part from the oracle's at
+    step t is accepted when the oracle replay shows a near-tie at a step in
+    [t - lag, t]; such envs are left out from t on.  Returns the accepted (env, t)."""
+    env_class = np.asarray(env_class)
+    first = env_mismatch_steps(gpu, ref, specs, env_class)
+    T = gpu["reward"].shape[0]
+    flips = []
+    ao, _ = env_layout(specs, env_class)
+    for e in np.flatnonzero(first < T):
+        t = int(first[e])
+        spec = specs[env_class[e]]
+        ain = None if act_in is None else act_in[:, ao[e]:ao[e + 1]]
+        ties = near_tie_steps(o, spec, seed, int(e), t + 1, mode, ain)
+        assert any(t - lag <= s <= t for s in ties), (
+            f"env {e} (class {env_class[e]}) parts from the oracle at step {t} without a near-tie "
+            f"(near-ties at {ties[-5:]})")
+        flips.append((int(e), t))
+    keep = first == T
+    if keep.any():
+        ks = np.flatnonzero(keep)
+        sub = {k: v[:, ks] for k, v in (("reward", gpu["reward"]), ("done", gpu["done"]))}
+        rsub = {"reward": ref["reward"][:, ks], "done": ref["done"][:, ks]}
+        acols = np.concatenate([np.arange(ao[e], ao[e + 1]) for e in ks])
+        if "actions" in gpu:
+            sub["actions"], rsub["act"] = gpu["actions"][:, acols], ref["act"][:, acols]
+        compare_rollout(sub, rsub, specs, env_class[ks], check_obs=False)
+    return flips, keep

@@ -43,7 +43,8 @@ def test_library_exports_every_declared_symbol(cxm):
 SPECS = [W.tiny_parity_station(), W.scale_station(), W.policy_station(), W.two_charger_types(),
          W.tiny_parity_station().replace(arrival_peak=0.0, dwell_max=1),
          W.fanout4_tree(32, 2).replace(steps_per_episode=96, dwell_max=300, dwell_mu=math.log(12.0)),
-         W.fanout4_tree(128, 3).replace(arrival_peak=8.0)] + W.mixture_classes() + W.v2g_mixture()
+         W.fanout4_tree(128, 3).replace(arrival_peak=8.0)] + W.mixture_classes() + W.v2g_mixture() + \
+        [W.user_station()]
 
 
 @pytest.mark.parametrize("spec", SPECS, ids=[s.name or str(i) for i, s in enumerate(SPECS)])
@@ -112,6 +113,9 @@ BAD = [
     ("battery_tau", dict(battery_kwh=50.0, battery_kw=10.0, battery_tau=1.0)),
     ("battery_soc0", dict(battery_kwh=50.0, battery_kw=10.0, battery_soc0=1.5)),
     ("battery_kwh", dict(battery_kwh=float("nan"))),
+    ("cs_share", dict(charge_sensitive_share=1.5)),
+    ("cs_alpha", dict(charge_sensitive_share=0.5, alpha_sat1=float("inf"))),
+    ("cs_long_episode", dict(charge_sensitive_share=0.5, steps_per_episode=40000)),
 ]
 
 

@@ -238,6 +238,16 @@ def v2g_mixture() -> List[StationSpec]:
     return [a, b, c, d, e]
 
 
+def user_station(**kw) -> StationSpec:
+    """The 16-port two-level station (4 splitters of 60 kW x 4 ports under
+    200 kW) with half of the arriving users charge-sensitive (u = 1), c_satisfaction,1
+    weighted 0.2 with beta 0.5: the synthetic stand-in for the paper's user
+    profiles, for which it gives no data."""
+    s = splitter_tree(4, 4, 60.0, 200.0).replace(charge_sensitive_share=0.5, alpha_sat1=0.2, beta_sat1=0.5,
+                                                 name="split4x4_cs50")
+    return s.replace(**kw) if kw else s
+
+
 # ---- the five workloads ------------------------------------------------------
 
 def tiny_parity_station() -> StationSpec:
