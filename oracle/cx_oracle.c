@@ -27,6 +27,8 @@ struct ox_class {
   int32_t v2g;               /* 1: ports take levels -L..L */
   double b_cap, b_rate, b_tau, b_soc0, a_db, a_dc;  /* battery (b_cap = 0: none), degradation weights */
   double cs_share, a_sat1, beta1;  /* charge-sensitive users: share of arrivals, weight, beta */
+  int32_t n_days;            /* exploring starts: price days (0: none) */
+  double *price_days;        /* [n_days][steps_per_episode] */
   uint32_t cs_thresh;        /* a car's user is charge-sensitive iff its word <= cs_thresh (share > 0) */
   double p[OXP_COUNT];
   int32_t ip[OXI_COUNT];
@@ -35,6 +37,8 @@ struct ox_class {
   double *price;             /* [steps_per_episode] base buying price per step of the day */
   uint32_t *tdwell;          /* [dwell_max], entry 0 unused */
 };
+
+static int32_t has_days(const ox_class *c) { return c->n_days > 0; }
 
 /* ------------------------------------------------------------------------- */
 /* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy
@@ -107,6 +111,27 @@ void ox_class_set_users(ox_class *c, double share, double alpha, double beta) {
   c->cs_thresh = threshold_u32(share);
 }
 
+void ox_class_set_price_days(ox_class *c, int32_t n_days, const double *price_days) {
+  const int32_t S = c->ip[OXI_STEPS_PER_EPISODE];
+  free(c->price_days);
+  c->n_days = n_days;
+  c->price_days = (double *)malloc(sizeof(double) * (size_t)n_days * S);
+  memcpy(c->price_days, price_days, sizeof(double) * (size_t)n_days * S);
+}
+
+int32_t ox_episode_day(const ox_class *c, uint64_t seed, uint32_t env, uint32_t g0) {
+  if (!has_days(c)) return -1;
+  uint32_t w[4];
+  philox_seeded(seed, env, g0, 0u, OX_DOM_DAY, w);
+  return (int32_t)(((uint64_t)w[0] * (uint64_t)c->n_days) >> 32);
+}
+
+/* Base buying price at step t_day of an episode on price day `day`. */
+static double base_price(const ox_class *c, int32_t t_day, int32_t day) {
+  if (has_days(c)) return c->price_days[(size_t)day * c->ip[OXI_STEPS_PER_EPISODE] + t_day];
+  return c->price[t_day];
+}
+
 /* Dwell time, App. A.1 "User Profiles": the lognormal stay length rounded to
  * the nearest step, lumped into 1 below 1.5 and capped at dwell_max.
  * F(x) = erfc(-(ln x - mu) / (sigma sqrt 2)) / 2 is the lognormal CDF. */
@@ -171,7 +196,7 @@ ox_class *ox_class_new(int32_t n_ports, int32_t n_nodes, const int32_t *node_par
 void ox_class_free(ox_class *c) {
   if (!c) return;
   free(c->node_parent); free(c->node_depth); free(c->node_cap); free(c->anc);
-  free(c->pmax); free(c->peta); free(c->pdis); free(c->tpois); free(c->tdwell); free(c->lam); free(c->price);
+  free(c->pmax); free(c->peta); free(c->pdis); free(c->price_days); free(c->tpois); free(c->tdwell); free(c->lam); free(c->price);
   free(c);
 }
 
@@ -195,7 +220,7 @@ static int32_t has_users(const ox_class *c) { return c->cs_share > 0.0; }
 int32_t ox_class_ports(const ox_class *c) { return c->n_ports; }
 int32_t ox_class_actions(const ox_class *c) { return c->n_ports + has_battery(c); }
 int32_t ox_obs_dim(const ox_class *c) {
-  return 6 * c->n_ports + 4 + 2 * has_battery(c) + (has_users(c) ? c->n_ports : 0);
+  return 6 * c->n_ports + 4 + 2 * has_battery(c) + 2 * has_days(c) + (has_users(c) ? c->n_ports : 0);
 }
 
 /* Levels of action index i run from -lo(i) to L: ports of a V2G class and the
@@ -307,7 +332,10 @@ void ox_draw_exo(const ox_class *c, uint64_t seed, uint32_t env, uint32_t g, int
   double u1 = ((double)(w[1] >> 8) + 1.0) * (1.0 / 16777216.0);
   double u2 = ox_u24(w[2]);
   x->z = sqrt(-2.0 * log(u1)) * cos(2.0 * M_PI * u2);
-  x->p_buy = c->price[t_day] + c->p[OXP_PRICE_SIGMA] * x->z;
+  /* the episode's price day (exploring starts): drawn at the step it began */
+  x->day = ox_episode_day(c, seed, env, g - (uint32_t)t_day);
+  x->day_next = t_day + 1 == c->ip[OXI_STEPS_PER_EPISODE] ? ox_episode_day(c, seed, env, g + 1u) : x->day;
+  x->p_buy = base_price(c, t_day, x->day) + c->p[OXP_PRICE_SIGMA] * x->z;
   /* car and user profiles of every arriving car j (App. A.2 "Arrival of new Cars") */
   const int32_t D = c->ip[OXI_DWELL_MAX];
   for (int32_t j = 0; j < M; ++j) {
@@ -357,7 +385,7 @@ void ox_draw_actions(const ox_class *c, int32_t mode, uint64_t seed, uint32_t en
 /* ------------------------------------------------------------------------- */
 void ox_observe(const ox_class *c, const int32_t *dwell, const int32_t *user, const double *soc,
                 const double *e_rem, const double *cap, const double *p_last, const double *batt,
-                int32_t t_day, double *obs) {
+                int32_t t_day, int32_t day, double *obs) {
   const int32_t N = c->n_ports, S = c->ip[OXI_STEPS_PER_EPISODE];
   const double tau = c->p[OXP_TAU];
   int32_t n_occ = 0;
@@ -374,14 +402,19 @@ void ox_observe(const ox_class *c, const int32_t *dwell, const int32_t *user, co
   double ang = 2.0 * M_PI * (double)t_day / (double)S;
   obs[6 * N + 0] = sin(ang);
   obs[6 * N + 1] = cos(ang);
-  obs[6 * N + 2] = c->price[t_day];
+  obs[6 * N + 2] = base_price(c, t_day, day);
   obs[6 * N + 3] = (double)n_occ / (double)N;
   if (has_battery(c)) {
     obs[6 * N + 4] = batt[0];
     obs[6 * N + 5] = batt[1] / c->b_rate;
   }
-  if (has_users(c)) {  /* the user preference u of every port (0 when empty) */
+  if (has_days(c)) {   /* the episode's day and whether it falls on a weekend */
     double *o = obs + 6 * N + 4 + 2 * has_battery(c);
+    o[0] = (double)day / (double)c->n_days;
+    o[1] = day % 7 >= 5 ? 1.0 : 0.0;
+  }
+  if (has_users(c)) {  /* the user preference u of every port (0 when empty) */
+    double *o = obs + 6 * N + 4 + 2 * has_battery(c) + 2 * has_days(c);
     for (int32_t i = 0; i < N; ++i) o[i] = user[i] == 1 ? 1.0 : 0.0;
   }
 }
@@ -504,7 +537,7 @@ void ox_transition(const ox_class *c, int32_t *dwell, int32_t *user, double *soc
     info->done = done; info->n_occ = n_occ; info->e_to_grid = e_to_grid; info->e_batt = e_batt;
     info->c_sat1 = c_sat1;
   }
-  if (obs) ox_observe(c, dwell, user, soc, e_rem, cap, p_last, batt, *t_day, obs);
+  if (obs) ox_observe(c, dwell, user, soc, e_rem, cap, p_last, batt, *t_day, x->day_next, obs);
 }
 
 /* ------------------------------------------------------------------------- */

@@ -43,6 +43,9 @@
  *   users (u = 1)        reaching the target, overstay and early-leave terms of
  *                        c_satisfaction,1, share of drawn users (binomial), the
  *                        all-time-sensitive special case equal to the base model
+ *   exploring starts  -- (tests/test_oracle_days.py) uniform day draws, prices
+ *                        following the drawn day's row, a new day at each
+ *                        episode, one price day = the per-step price table
  *   V2G / battery     -- (tests/test_oracle_v2g.py) mirror symmetry: a mirrored
  *                        state (SoC -> 1 - SoC) under negated levels draws exactly
  *                        the negated powers through clip and projection;
@@ -72,6 +75,7 @@ extern "C" {
 #define OX_DOM_CAR 2u       /* ctr = (env, g, j, 2): j-th arriving car of step g */
 #define OX_DOM_GUM 3u       /* ctr = (env, g, 3*port + q, 3): Gumbel noise       */
 #define OX_DOM_USER 4u      /* ctr = (env, g, j, 4): user type of car j, word 0  */
+#define OX_DOM_DAY 5u       /* ctr = (env, g0, 0, 5): price day of the episode starting at g0 */
 
 /* action modes */
 #define OX_ACT_EXTERNAL 0
@@ -100,6 +104,8 @@ typedef struct {
   double car_tgt[OX_K_POIS];      /* desired SoC of car j                       */
   int32_t car_dwell[OX_K_POIS];   /* dwell time of car j in steps, >= 1         */
   int32_t car_user[OX_K_POIS];    /* 1: charge-sensitive user (u = 1), else 0   */
+  int32_t day, day_next;          /* price day of this step's episode and of the next
+                                     step's (-1 without price days)                */
 } ox_exo;
 
 /* Everything one transition reports besides the new state.  e_grid is the net
@@ -134,9 +140,17 @@ void ox_class_set_v2g(ox_class *c, int32_t v2g, const double *pdis, const double
  * wanted reaches zero, and c_satisfaction,1 (weight alpha) charges the hours
  * stayed past the planned departure minus beta times the hours left early. */
 void ox_class_set_users(ox_class *c, double share, double alpha, double beta);
+/* Exploring starts (Supp. B.1): n_days rows of steps_per_episode base buying
+ * prices; every episode uses the row of a day drawn at its start, and the
+ * observation shows that day (day / n_days) and whether it is a weekend day
+ * (day mod 7 >= 5). */
+void ox_class_set_price_days(ox_class *c, int32_t n_days, const double *price_days);
+/* The price day of the episode that started at global step g0 (-1 without days). */
+int32_t ox_episode_day(const ox_class *c, uint64_t seed, uint32_t env, uint32_t g0);
 int32_t ox_class_ports(const ox_class *c);
 int32_t ox_class_actions(const ox_class *c);  /* ports + 1 with a battery */
-int32_t ox_obs_dim(const ox_class *c);        /* 6 N + 4, + 2 with a battery, + N with u = 1 users */
+int32_t ox_obs_dim(const ox_class *c);        /* 6 N + 4, + 2 with a battery, + 2 with price
+                                                 days, + N with u = 1 users */
 /* The action byte of level k at action index i (i = n_ports: the battery). */
 int32_t ox_action_code(const ox_class *c, int32_t i, int32_t k);
 /* copies of the class's integer sampling tables (steps_per_episode x 24, dwell_max) */
@@ -176,7 +190,7 @@ void ox_transition(const ox_class *c, int32_t *dwell, int32_t *user, double *soc
 /* Observation of the current state (used after reset and by the policy). */
 void ox_observe(const ox_class *c, const int32_t *dwell, const int32_t *user, const double *soc,
                 const double *e_rem, const double *cap, const double *p_last, const double *batt,
-                int32_t t_day, double *obs);
+                int32_t t_day, int32_t day, double *obs);
 
 /* ---- batched rollout over many envs (threads over env ranges) ----
  * env_class[n_envs] indexes classes[]; envs may be in any class order.  State

@@ -46,7 +46,7 @@ class Exo(C.Structure):
     _fields_ = [("M", C.c_int32), ("z", C.c_double), ("p_buy", C.c_double),
                 ("car_cap", C.c_double * K_POIS), ("car_soc", C.c_double * K_POIS),
                 ("car_tgt", C.c_double * K_POIS), ("car_dwell", C.c_int32 * K_POIS),
-                ("car_user", C.c_int32 * K_POIS)]
+                ("car_user", C.c_int32 * K_POIS), ("day", C.c_int32), ("day_next", C.c_int32)]
 
 
 _lib = None
@@ -71,7 +71,10 @@ def lib():
         L.ox_draw_exo.argtypes = [P, C.c_uint64, C.c_uint32, C.c_uint32, I, P]
         L.ox_draw_actions.argtypes = [P, I, C.c_uint64, C.c_uint32, C.c_uint32, P, P]
         L.ox_transition.argtypes = [P] * 15
-        L.ox_observe.argtypes = [P, P, P, P, P, P, P, P, I, P]
+        L.ox_observe.argtypes = [P, P, P, P, P, P, P, P, I, I, P]
+        L.ox_class_set_price_days.argtypes = [P, I, P]
+        L.ox_episode_day.restype = I
+        L.ox_episode_day.argtypes = [P, C.c_uint64, C.c_uint32, C.c_uint32]
         L.ox_rollout.restype = I
         L.ox_rollout.argtypes = [P, P, P, C.c_int64, C.c_uint64, P, P, I, I, P, P, P, P, P, P, P, P,
                                  P, P, P, P, P, P, I]
@@ -147,6 +150,13 @@ class OracleClass:
         if getattr(spec, "charge_sensitive_share", 0.0) > 0.0:
             lib().ox_class_set_users(self.h, float(spec.charge_sensitive_share), float(spec.alpha_sat1),
                                      float(spec.beta_sat1))
+        days = getattr(spec, "price_days", None)
+        if days is not None:
+            d = np.ascontiguousarray(days, dtype=np.float64)
+            if d.ndim != 2 or d.shape[1] != spec.steps_per_episode:
+                raise ValueError("price_days needs shape [n_days][steps_per_episode]")
+            self._keep.append(d)
+            lib().ox_class_set_price_days(self.h, d.shape[0], _ptr(d))
         self.n_act = lib().ox_class_actions(self.h)
         self.has_battery = self.n_act > self.n
 
@@ -168,9 +178,16 @@ class OracleClass:
     def battery_power(self, soc_b: float, kb: int) -> float:
         return lib().ox_battery_power(self.h, float(soc_b), int(kb))
 
-    def new_state(self) -> "EnvState":
-        """An empty station at t_day 0 (battery at its initial SoC)."""
-        return EnvState(self.n, self.spec.battery_soc0 if self.has_battery else 0.0)
+    def episode_day(self, seed: int, env: int, g0: int) -> int:
+        """Price day of the episode that starts at global step g0 (-1 without days)."""
+        return lib().ox_episode_day(self.h, seed, env, g0)
+
+    def new_state(self, seed: int = 0, env: int = 0, g: int = 0) -> "EnvState":
+        """An empty station at t_day 0 (battery at its initial SoC; its episode's
+        price day drawn for (seed, env, g))."""
+        st = EnvState(self.n, self.spec.battery_soc0 if self.has_battery else 0.0)
+        st.day = self.episode_day(seed, env, g)
+        return st
 
     def tables(self):
         tp = np.zeros((self.spec.steps_per_episode, K_POIS), dtype=np.uint32)
@@ -208,7 +225,7 @@ class OracleClass:
     def observe(self, st: "EnvState") -> np.ndarray:
         obs = np.zeros(self.obs_dim, dtype=np.float64)
         lib().ox_observe(self.h, _ptr(st.dwell), _ptr(st.user), _ptr(st.soc), _ptr(st.e_rem), _ptr(st.cap),
-                         _ptr(st.p_last), _ptr(st.batt), st.t_day, _ptr(obs))
+                         _ptr(st.p_last), _ptr(st.batt), st.t_day, getattr(st, "day", -1), _ptr(obs))
         return obs
 
     def transition(self, st: "EnvState", k, exo: Exo):
@@ -225,6 +242,7 @@ class OracleClass:
                             C.byref(info), _ptr(obs), _ptr(P))
         st.ret = ret.value
         st.t_day = t_day.value
+        st.day = exo.day_next
         return info, obs, P
 
     def policy(self, hidden: int, weights, obs, seed: int, env: int, g: int, with_margin: bool = False):
@@ -254,6 +272,7 @@ class EnvState:
         self.p_last = np.zeros(n_ports, dtype=np.float64)
         self.ret = 0.0
         self.t_day = 0
+        self.day = -1        # price day of the current episode (exploring starts)
 
     def put_car(self, port: int, soc: float, cap: float, dwell: int, e_rem: float, user: int = 0):
         self.dwell[port] = dwell
@@ -269,6 +288,7 @@ def exo(M: int = 0, p_buy: float = 0.25, cars=()) -> Exo:
     x.M = M
     x.z = 0.0
     x.p_buy = p_buy
+    x.day = x.day_next = -1
     for j, car in enumerate(cars):
         cap, soc0, tgt, dwell = car[:4]
         x.car_cap[j], x.car_soc[j], x.car_tgt[j], x.car_dwell[j] = cap, soc0, tgt, dwell

@@ -161,7 +161,7 @@ def near_tie_steps(o, spec, seed, env_id, T, mode=1, act_in=None, g0=0):
     """Replay one env in the oracle; steps whose charge-sensitive departure test
     (energy still wanted after charging <= 0) was within TIE_KWH of zero."""
     c = o.OracleClass(spec)
-    st = c.new_state()
+    st = c.new_state(seed, env_id, g0)
     ties = []
     for t in range(T):
         g = g0 + t

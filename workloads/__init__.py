@@ -86,6 +86,9 @@ class StationSpec:
     charge_sensitive_share: float = 0.0
     alpha_sat1: float = 0.0
     beta_sat1: float = 0.0
+    # exploring starts: [n_days][steps_per_episode] base buying prices; every
+    # episode draws one day (None = one price curve for every day)
+    price_days: Optional[np.ndarray] = None
 
     @property
     def n_nodes(self) -> int:
@@ -106,8 +109,12 @@ class StationSpec:
         return self.charge_sensitive_share > 0.0
 
     @property
+    def has_days(self) -> bool:
+        return self.price_days is not None
+
+    @property
     def obs_dim(self) -> int:
-        return (6 * self.n_ports + 4 + (2 if self.has_battery else 0) +
+        return (6 * self.n_ports + 4 + (2 if self.has_battery else 0) + (2 if self.has_days else 0) +
                 (self.n_ports if self.has_users else 0))
 
     def replace(self, **kw) -> "StationSpec":
@@ -194,6 +201,19 @@ def time_of_use_prices(steps: int = STEPS_PER_DAY, off_peak: float = 0.16, mid: 
     """Synthetic time-of-use tariff: off-peak 23-07 h, peak 17-21 h, mid otherwise."""
     h = 24.0 * np.arange(steps) / steps
     return np.where((h >= 23.0) | (h < 7.0), off_peak, np.where((h >= 17.0) & (h < 21.0), peak, mid))
+
+
+def price_day_table(n_days: int = 28, steps: int = STEPS_PER_DAY, seed: int = 77) -> np.ndarray:
+    """Synthetic price days for exploring starts: the time-of-use tariff scaled per
+    day (weekends 15 % cheaper, a slow monthly swing, +-8 % daily noise) plus
+    hourly noise; day d is a weekend day when d mod 7 >= 5 (the paper's price data
+    are not available)."""
+    rng = np.random.default_rng(seed)
+    base = time_of_use_prices(steps)
+    d = np.arange(n_days)
+    level = (1.0 - 0.15 * (d % 7 >= 5)) * (1.0 + 0.1 * np.sin(2 * np.pi * d / 30.0)) * rng.uniform(0.92, 1.08, n_days)
+    hourly = rng.normal(0.0, 0.01, (n_days, 24)).repeat(steps // 24, axis=1)
+    return base[None, :] * level[:, None] + hourly
 
 
 def profile_station() -> StationSpec:
