@@ -10,7 +10,8 @@ all stations over all 288 steps in one persistent, graph-replayed launch.
 Other workloads (--workload): tiny (64 stations of 16 ports, the parity case),
 scale (4,096 stations on a two-level tree, persistent vs one launch per step),
 v2g (65,536 stations with bidirectional ports and a station battery), users
-(65,536 stations where half the users are charge-sensitive),
+(65,536 stations where half the users are charge-sensitive), exo (65,536
+two-charger-type stations driven by an arrival table and 28 price days),
 policy (1,048,576 stations of 32 ports, levels from the BF16 perceptron on the
 matrix cores), serve (a Poisson stream of rollout requests through the
 continuous-batching server).
@@ -158,6 +159,7 @@ def run_rollout_workload(args, name, specs, ec, seed, desc, cpu_stride):
     import paper_2507_01522_amd as cx
     n_ports = np.array([s.n_ports for s in specs])[ec]
     batt = np.array([1 if getattr(s, "has_battery", False) else 0 for s in specs])[ec]
+    dayf = np.array([1 if getattr(s, "has_days", False) else 0 for s in specs])[ec]
     users = np.array([1 if getattr(s, "has_users", False) else 0 for s in specs])[ec]
     n_envs = len(ec)
     env = cx.Env(specs, env_class=ec, seed=seed) if len(specs) > 1 else cx.Env(specs[0], n_envs=n_envs, seed=seed)
@@ -168,8 +170,8 @@ def run_rollout_workload(args, name, specs, ec, seed, desc, cpu_stride):
     wall_ms, kernel_ms = timed_rollouts(env, cx, T_DAY, cx.ACT_RANDOM, cx.OUT_FULL, out, args)
     env_steps = n_envs * T_DAY
     value = env_steps / (wall_ms / 1e3)
-    # records (+ the user flags, 4 bytes per port) and the state in and out (+ a user byte per port)
-    alg_bytes = float(((record_bytes(n_ports, "full", batt) + 4 * n_ports * users) * T_DAY
+    # records (+ user flags, 4 bytes per port; + the two day features) and the state in and out (+ a user byte per port)
+    alg_bytes = float(((record_bytes(n_ports, "full", batt) + 4 * n_ports * users + 8 * dayf) * T_DAY
                        + 2 * (state_bytes(n_ports, batt) + n_ports * users)).sum())
     achieved = alg_bytes / (kernel_ms / 1e3) / 1e9
     del out
@@ -232,6 +234,14 @@ def run_users(args):
                                       "the users charge-sensitive (leave when charged), random levels, full "
                                       "records", [W.user_station()], np.zeros(65536, np.int32), 4,
                                 "stations with charge-sensitive users", 64)
+
+
+def run_exo(args):
+    import workloads as W
+    return run_rollout_workload(args, "exo: 65536 stations x 288 steps, 10 DC + 6 AC ports under per-type splitters, "
+                                      "commuter arrival table, exploring starts over 28 price days, random "
+                                      "levels, full records", [W.exo_station()], np.zeros(65536, np.int32), 5,
+                                "table-driven stations", 64)
 
 
 def run_policy(args):
@@ -400,7 +410,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="uneven", choices=["uneven", "tiny", "scale", "v2g", "users", "policy", "serve"])
+    ap.add_argument("--workload", default="uneven", choices=["uneven", "tiny", "scale", "v2g", "users", "exo", "policy", "serve"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain per-step comparison")
     ap.add_argument("--no-tune", action="store_true")
@@ -422,7 +432,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    run = {"uneven": run_uneven, "tiny": run_tiny, "scale": run_scale, "v2g": run_v2g, "users": run_users,
+    run = {"uneven": run_uneven, "tiny": run_tiny, "scale": run_scale, "v2g": run_v2g, "users": run_users, "exo": run_exo,
            "policy": run_policy,
            "serve": run_serve}[args.workload]
     print(json.dumps(run(args)))

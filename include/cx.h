@@ -138,6 +138,15 @@ typedef struct {
   double charge_sensitive_share;  /* in [0,1]; 0 = every user time-sensitive        */
   double alpha_sat1;              /* weight of c_satisfaction,1                      */
   double beta_sat1;               /* its weight of the hours left early              */
+  /* Exploring starts (Supp. B.1): n_price_days rows of steps_per_episode base
+   * buying prices (host memory, copied at create; NULL / 0 = none).  Each
+   * episode uses the row of the day d = (w * n_price_days) >> 32, w = word 0 of
+   * Philox (env, g0, 0, 5) where g0 is the global step the episode began on (the
+   * noise sigma z is still added); the observation appends [d / n_price_days,
+   * 1 if d mod 7 >= 5 (a weekend day) else 0].  Replaces price_table and the
+   * default price curve. */
+  int32_t n_price_days;
+  const double *price_days;
 } cx_station_spec;
 
 typedef struct cx_ctx cx_ctx;
@@ -149,7 +158,9 @@ typedef struct cx_ctx cx_ctx;
  *           (feature-major: feature f of port p at f*N + p), then
  *           [sin 2 pi t/S, cos 2 pi t/S, base price(t), occupied ports / N],
  *           then, with a battery, [battery SoC, battery power / battery_kw],
+ *           then, with price days, [episode day / n_price_days, weekend flag],
  *           then, with charge-sensitive users, [u] x N ports (1 = charge-sensitive).
+ *           The base price is the episode's day's price with price days.
  *           p_last is negative while a port discharges; dwell/S is negative while a
  *           charge-sensitive user overstays.
  *   actions uint8 [T][total_ports] FULL and ACT_REWARD: the action byte applied per

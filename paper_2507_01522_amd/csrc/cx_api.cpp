@@ -47,6 +47,7 @@ size_t class_block(const SpecCopy &sc, const Compiled &k, const Tables &t, unsig
   const size_t o_gl = take(sizeof(float) * t.glob.size());
   const size_t o_pdis = take(sizeof(float) * k.S);
   const size_t o_eta = take(sizeof(float) * k.S);
+  const size_t o_days = take(sizeof(float) * t.price_days.size());
   unsigned char *base = dev_base;
   ClassDev d{};
   d.n_ports = k.N; d.S = k.S; d.D = k.D; d.n_levels = s.n_levels;
@@ -101,6 +102,9 @@ size_t class_block(const SpecCopy &sc, const Compiled &k, const Tables &t, unsig
   d.user_obs = k.user_obs;
   d.alpha_sat1 = (float)s.alpha_sat1;
   d.beta_sat1 = (float)s.beta_sat1;
+  d.n_days = k.n_days;
+  d.day_obs = k.day_obs;
+  d.inv_n_days = k.n_days > 0 ? (float)(1.0 / k.n_days) : 0.f;
   d.pmax_u = k.slot_pmax[0];
   d.inv_pmax_u = k.slot_inv_pmax[0];
   d.slot_port = reinterpret_cast<const int32_t *>(base + o_port);
@@ -114,6 +118,7 @@ size_t class_block(const SpecCopy &sc, const Compiled &k, const Tables &t, unsig
   d.glob = reinterpret_cast<const float *>(base + o_gl);
   d.slot_pdis = reinterpret_cast<const float *>(base + o_pdis);
   d.slot_eta = reinterpret_cast<const float *>(base + o_eta);
+  d.price_days = reinterpret_cast<const float *>(base + o_days);
   if (view) *view = d;
   if (host) {
     host->assign(off, 0);
@@ -129,6 +134,8 @@ size_t class_block(const SpecCopy &sc, const Compiled &k, const Tables &t, unsig
     std::memcpy(host->data() + o_gl, t.glob.data(), sizeof(float) * t.glob.size());
     std::memcpy(host->data() + o_pdis, k.slot_pdis.data(), sizeof(float) * k.S);
     std::memcpy(host->data() + o_eta, k.slot_eta.data(), sizeof(float) * k.S);
+    if (!t.price_days.empty())
+      std::memcpy(host->data() + o_days, t.price_days.data(), sizeof(float) * t.price_days.size());
   }
   return off;
 }
@@ -471,7 +478,7 @@ cx_status cx_reset(cx_ctx *ctx, float *obs_dev) {
   ctx->t_day = 0;
   if (obs_dev) {
     for (auto &c : ctx->classes) {
-      e = launch_reset_obs_one(c.dev, c.n_envs, obs_dev + c.obs_off, ctx->stream);
+      e = launch_reset_obs_one(c.dev, c.n_envs, obs_dev + c.obs_off, ctx->seed, c.env_begin, ctx->g, ctx->stream);
       if (e != hipSuccess) return hip_fail(ctx, e, "cx_reset observation kernel");
     }
   }

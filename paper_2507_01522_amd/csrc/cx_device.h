@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "cx_internal.h"
+
 namespace cx {
 namespace {
 
@@ -36,6 +38,12 @@ __device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint
 }
 
 __device__ __forceinline__ float u24(uint32_t w) { return (float)(w >> 8) * 0x1p-24f; }
+
+// Exploring starts: the price day of the episode that began at global step g0,
+// (word 0 of Philox (env, g0, 0, DAY) * n_days) >> 32.
+__device__ __forceinline__ int episode_day(uint32_t env, uint32_t g0, uint32_t k0, uint32_t k1, int n_days) {
+  return (int)__umulhi(philox(env, g0, 0u, kDomDay, k0, k1).x, (uint32_t)n_days);
+}
 
 // Loads through the global address space (the tables live in device memory;
 // plain pointers from a struct would be generic and compile to flat loads).

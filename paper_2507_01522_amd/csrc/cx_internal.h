@@ -17,7 +17,7 @@ constexpr int kMaxWaves = 8;     // waves per block
 
 // Philox counter domains (word 3 of the counter); see the action / arrival
 // / noise derivations in the kernels.
-enum : uint32_t { kDomEnv = 0, kDomAct = 1, kDomCar = 2, kDomGum = 3, kDomUser = 4 };
+enum : uint32_t { kDomEnv = 0, kDomAct = 1, kDomCar = 2, kDomGum = 3, kDomUser = 4, kDomDay = 5 };
 
 // Packings: lanes per station L in {4,...,64} and slots per lane P in {1,2,4};
 // L * P = padded slots of the class.
@@ -78,7 +78,10 @@ struct ClassDev {
   uint32_t cs_thresh;          // a user is charge-sensitive iff its Philox word <= cs_thresh
   int32_t user_obs;            // observation offset of the per-port user flags
   float alpha_sat1, beta_sat1; // c_satisfaction,1 weight and its early-leave weight
-  float pad_u;
+  float inv_n_days;            // exploring starts: 1 / n_days
+  int32_t n_days, day_obs;     // price days (0: none) and the observation offset of the day features
+  int32_t pad_d;
+  const float *price_days;     // [n_days][steps_ep]
 };
 
 // One class's env range inside a launch.  Static fields are set when the
@@ -168,7 +171,8 @@ hipError_t launch_groups(const LaunchArgs &a, const LaunchGroup *groups, int n_g
 hipError_t graph_rollout(RolloutGraph &g, const LaunchArgs &a, const LaunchGroup *groups, int n_groups,
                          int waves_per_block, hipStream_t st);
 void graph_destroy(RolloutGraph &g);
-hipError_t launch_reset_obs_one(const ClassDev *cls_dev, int64_t n_envs, float *obs, hipStream_t st);
+hipError_t launch_reset_obs_one(const ClassDev *cls_dev, int64_t n_envs, float *obs, uint64_t seed, int64_t env0,
+                                uint32_t g, hipStream_t st);
 // Sets n doubles at p to v (battery SoC at the start of a day).
 hipError_t launch_fill_f64(double *p, int64_t n, double v, hipStream_t st);
 

@@ -177,6 +177,8 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
   const int n_neg = EXT ? C.n_neg : 0;      // discharge levels of a port
   const bool batt = EXT && C.has_batt != 0;
   const bool users = EXT && C.has_users != 0;  // some users are charge-sensitive
+  const int n_days = EXT ? C.n_days : 0;       // exploring starts: price days
+  const bool days = n_days > 0;
 
   // ---- per-slot constants
   int port[P];
@@ -250,6 +252,10 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
   const int n_levels = C.n_levels;
   int t_day = dy.t_day0;
   uint32_t g = dy.g0;
+  int dday = 0;  // EXT: price day of the current episode (drawn at its first step)
+  if constexpr (EXT) {
+    if (days) dday = episode_day(env_id, g - (uint32_t)t_day, k0, k1, n_days);
+  }
   int bM = 0, bdw = 1, bus = 0;
   float bpb = 0.f, bcp = 0.f, bs0 = 0.f, btg = 0.f;
   U4 aw[P];
@@ -287,7 +293,11 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
       const float u1 = (float)((w.y >> 8) + 1u) * 0x1p-24f;
       const float u2 = u24(w.z);
       const float z = __builtin_amdgcn_sqrtf(-2.0f * __logf(u1)) * __builtin_amdgcn_cosf(u2);
-      bpb = gld(C.glob, td * 4 + 2) + C.price_sigma * z;
+      float base = gld(C.glob, td * 4 + 2);
+      if constexpr (EXT) {
+        if (days) base = gld(C.price_days, episode_day(env_id, gl - (uint32_t)td, k0, k1, n_days) * steps_ep + td);
+      }
+      bpb = base + C.price_sigma * z;
       const U4 b = philox(env_id, gl, 0u, kDomCar, k0, k1);
       bcp = C.cap_lo + C.cap_span * u24(b.x);
       bs0 = C.soc_lo + C.soc_span * u24(b.y);
@@ -597,6 +607,9 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
         if constexpr (EXT) cs[j] = 0;
       }
       if constexpr (EXT) {
+        if (days) dday = episode_day(env_id, g + 1u, k0, k1, n_days);  // the next episode begins
+      }
+      if constexpr (EXT) {
         if (batt) {
           bsoc = C.b_soc0;
           bpw = 0.f;
@@ -626,12 +639,18 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
         }
         if (l < 4) {
           const int n_occ = done ? 0 : (N - n_free + acc);
-          const float gv = l == 3 ? (float)n_occ * (1.0f / (float)N) : gld(C.glob, t_day * 4 + l);
+          float gv = l == 3 ? (float)n_occ * (1.0f / (float)N) : gld(C.glob, t_day * 4 + l);
+          if constexpr (EXT) {
+            if (days && l == 2) gv = gld(C.price_days, dday * steps_ep + t_day);
+          }
           st_at(ob, obs_bo + 4u * (uint32_t)(6 * N + l), gv);
         }
         if constexpr (EXT) {
           if (batt && l < 2)
             st_at(ob, obs_bo + 4u * (uint32_t)(6 * N + 4 + l), l == 0 ? (float)bsoc : bpw * C.b_inv_rate);
+          if (days && l < 2)
+            st_at(ob, obs_bo + 4u * (uint32_t)(C.day_obs + l),
+                  l == 0 ? (float)dday * C.inv_n_days : (dday % 7 >= 5 ? 1.0f : 0.0f));
         }
       }
       if (w_act) {
@@ -725,17 +744,24 @@ __global__ __launch_bounds__(512) void k_rollout(LaunchArgs a) {
   run_group<L, P, SIMPLE, EXT>(sg, dy, group, tdw, tdw_lds);
 }
 
-// Observation of empty stations at t_day = 0 for every env of one segment.
-__global__ void k_reset_obs(const ClassDev *cls, int64_t n_envs, float *obs) {
+// Observation of empty stations at t_day = 0 for every env of one segment
+// (env0: Philox index of its first env; g: the step the new episodes begin on).
+__global__ void k_reset_obs(const ClassDev *cls, int64_t n_envs, float *obs, uint64_t seed, int64_t env0,
+                            uint32_t g) {
   const int64_t dim = cls->obs_dim;
-  const int N = cls->n_ports;
+  const int N = cls->n_ports, n_days = cls->n_days, day_obs = cls->day_obs;
   const int64_t total = n_envs * dim;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
        i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t f = i % dim;
     float v = 0.f;
     if (f >= 6 * N && f < 6 * N + 3) v = cls->glob[f - 6 * N];
-    if (f == 6 * N + 4) v = (float)cls->b_soc0;  // a battery starts the day at its initial SoC
+    if (cls->has_batt && f == 6 * N + 4) v = (float)cls->b_soc0;  // a battery starts the day at its initial SoC
+    if (n_days > 0 && (f == 6 * N + 2 || f == day_obs || f == day_obs + 1)) {
+      const int d = episode_day((uint32_t)(env0 + i / dim), g, (uint32_t)seed, (uint32_t)(seed >> 32), n_days);
+      v = f == 6 * N + 2 ? cls->price_days[(int64_t)d * cls->steps_ep]
+                         : f == day_obs ? (float)d * cls->inv_n_days : (d % 7 >= 5 ? 1.0f : 0.0f);
+    }
     obs[i] = v;
   }
 }
@@ -839,9 +865,10 @@ void graph_destroy(RolloutGraph &g) {
   g = RolloutGraph{};
 }
 
-hipError_t launch_reset_obs_one(const ClassDev *cls_dev, int64_t n_envs, float *obs, hipStream_t st) {
+hipError_t launch_reset_obs_one(const ClassDev *cls_dev, int64_t n_envs, float *obs, uint64_t seed, int64_t env0,
+                                uint32_t g, hipStream_t st) {
   if (n_envs <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_reset_obs, dim3(256), dim3(256), 0, st, cls_dev, n_envs, obs);
+  hipLaunchKernelGGL(k_reset_obs, dim3(256), dim3(256), 0, st, cls_dev, n_envs, obs, seed, env0, g);
   return hipGetLastError();
 }
 

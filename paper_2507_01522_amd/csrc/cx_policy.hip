@@ -309,7 +309,7 @@ __global__ __launch_bounds__(64 * kPolWaves) void k_policy(PolicyArgs a) {
 // Observation of the current state (the features the step kernel records).
 __global__ void k_observe(const ClassDev *cls, int64_t n_envs, const double *q, const float *u,
                           const float *p_last, const int16_t *dwell, const uint8_t *utype, const double *bsoc,
-                          const float *bp, int32_t t_day, float *obs) {
+                          const float *bp, int32_t t_day, uint64_t seed, int64_t env0, uint32_t g, float *obs) {
   const ClassDev C = *cls;
   const int S = C.S, N = C.n_ports, dim = C.obs_dim;
   const int64_t total = n_envs * S;
@@ -346,6 +346,13 @@ __global__ void k_observe(const ClassDev *cls, int64_t n_envs, const double *q, 
       o[4] = (float)bsoc[env];
       o[5] = bp[env] * C.b_inv_rate;
     }
+    if (C.n_days > 0) {  // the episode's price day, drawn at the step it began
+      const int d = episode_day((uint32_t)(env0 + env), g - (uint32_t)t_day, (uint32_t)seed, (uint32_t)(seed >> 32),
+                                C.n_days);
+      o[2] = C.price_days[(int64_t)d * C.steps_ep + t_day];
+      obs[env * dim + C.day_obs] = (float)d * C.inv_n_days;
+      obs[env * dim + C.day_obs + 1] = d % 7 >= 5 ? 1.0f : 0.0f;
+    }
   }
 }
 
@@ -365,7 +372,7 @@ hipError_t launch_observe(const cx_ctx *ctx, float *obs, hipStream_t st) {
     hipLaunchKernelGGL(k_observe, dim3(blocks), dim3(256), 0, st, c.dev, c.n_envs, ctx->q + c.slot_off,
                        ctx->u + c.slot_off, ctx->p_last + c.slot_off, ctx->dwell + c.slot_off,
                        ctx->utype + c.slot_off, ctx->bsoc + c.env_begin, ctx->bp + c.env_begin, ctx->t_day,
-                       obs + c.obs_off);
+                       ctx->seed, c.env_begin, ctx->g, obs + c.obs_off);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

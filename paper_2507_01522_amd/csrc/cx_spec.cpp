@@ -60,6 +60,16 @@ bool copy_spec(const cx_station_spec &in, SpecCopy *out, std::string *err) {
   if (in.port_pdis_kw) out->port_pdis.assign(in.port_pdis_kw, in.port_pdis_kw + in.n_ports);
   else out->port_pdis = out->port_pmax;
   out->s.port_pdis_kw = out->port_pdis.data();
+  out->price_days.clear();
+  if (in.n_price_days < 0 || in.n_price_days > 100000) return fail(err, "n_price_days must be in 0..100000");
+  if (in.n_price_days > 0) {
+    if (!in.price_days) return fail(err, "price_days must not be NULL when n_price_days > 0");
+    if (S < 1 || S > 100000) return fail(err, "steps_per_episode must be in 1..100000");
+    if ((int64_t)in.n_price_days * S > (int64_t)1 << 24) return fail(err, "price_days holds more than 2^24 prices");
+    out->price_days.assign(in.price_days, in.price_days + (size_t)in.n_price_days * S);
+  }
+  out->s.price_days = out->price_days.empty() ? nullptr : out->price_days.data();
+  if (out->price_days.empty()) out->s.n_price_days = 0;
   return true;
 }
 
@@ -91,6 +101,8 @@ bool compile_spec(const SpecCopy &sc, Compiled *c, std::string *err) {
     if (!(v >= 0.0 && v <= 8.0)) return fail(err, "arrival_rate entries must be in [0, 8]");
   for (double v : sc.price_table)
     if (!std::isfinite(v)) return fail(err, "price_table entries must be finite");
+  for (double v : sc.price_days)
+    if (!std::isfinite(v)) return fail(err, "price_days entries must be finite");
   if (s.v2g != 0 && s.v2g != 1) return fail(err, "v2g must be 0 or 1");
   if ((s.v2g || s.battery_kwh > 0.0) && s.n_levels > 127)
     return fail(err, "n_levels must be at most 127 with discharging (signed levels fit an action byte)");
@@ -208,7 +220,9 @@ bool compile_spec(const SpecCopy &sc, Compiled *c, std::string *err) {
   c->users = s.charge_sensitive_share > 0.0;
   c->cs_thresh = c->users ? cdf_threshold(s.charge_sensitive_share) : 0u;
   c->n_act = N + (c->battery ? 1 : 0);
-  c->user_obs = 6 * N + 4 + (c->battery ? 2 : 0);
+  c->n_days = s.n_price_days;
+  c->day_obs = 6 * N + 4 + (c->battery ? 2 : 0);
+  c->user_obs = c->day_obs + (c->n_days > 0 ? 2 : 0);
   c->obs_dim = c->user_obs + (c->users ? N : 0);
   return true;
 }
@@ -266,6 +280,7 @@ void build_tables(const SpecCopy &sc, Tables *t) {
     t->glob[(size_t)step * 4 + 2] =
         (float)(sc.price_table.empty() ? s.price_base + s.price_amp * std::sin(a) : sc.price_table[step]);
   }
+  t->price_days.assign(sc.price_days.begin(), sc.price_days.end());  // to FP32
 }
 
 bool tables_monotone(const Tables &t) {

@@ -15,6 +15,7 @@ struct SpecCopy {
   std::vector<double> node_limit, node_eta, port_pmax, port_eta;
   std::vector<double> arrival_rate, price_table;  // empty: the default curves
   std::vector<double> port_pdis;                  // discharge maxima (port maxima if not given)
+  std::vector<double> price_days;                 // [n_price_days][steps] (empty: none)
 };
 
 // The capacity tree in the kernels' layout.  Every node owns an aligned block of
@@ -33,10 +34,12 @@ struct Compiled {
   float inv_eta_uniform = 1.f;
   bool v2g = false, battery = false;       // ports discharge / a station battery
   bool users = false;                      // some users are charge-sensitive (u = 1)
+  int n_days = 0;                          // exploring starts: price days (0: none)
+  int day_obs = 0;                         // observation offset of [day / n_days, weekend]
   uint32_t cs_thresh = 0;                  // u = 1 iff the user word <= cs_thresh
   int n_act = 0, obs_dim = 0;              // action bytes and observation floats per env
   int user_obs = 0;                        // observation offset of the user flags
-  bool extended() const { return v2g || battery || users; }  // needs the extended kernels
+  bool extended() const { return v2g || battery || users || n_days > 0; }  // needs the extended kernels
 };
 
 struct Tables {
@@ -46,6 +49,7 @@ struct Tables {
   std::vector<uint32_t> tdwell_dev; // [2^dwell_log2]: entries 1.. of tdwell, then 0xFFFFFFFF
   int dwell_log2 = 1;
   std::vector<float> glob;          // [steps][4]
+  std::vector<float> price_days;    // [n_days][steps] (exploring starts)
 };
 
 bool copy_spec(const cx_station_spec &in, SpecCopy *out, std::string *err);

@@ -44,7 +44,8 @@ class StationSpecC(C.Structure):
                 ("port_pdis_kw", C.c_void_p), ("battery_kwh", C.c_double), ("battery_kw", C.c_double),
                 ("battery_tau", C.c_double), ("battery_soc0", C.c_double),
                 ("alpha_degrad_battery", C.c_double), ("alpha_degrad_cars", C.c_double),
-                ("charge_sensitive_share", C.c_double), ("alpha_sat1", C.c_double), ("beta_sat1", C.c_double)]
+                ("charge_sensitive_share", C.c_double), ("alpha_sat1", C.c_double), ("beta_sat1", C.c_double),
+                ("n_price_days", C.c_int32), ("price_days", C.c_void_p)]
 
 
 class TrajC(C.Structure):
@@ -169,6 +170,10 @@ class _SpecHolder:
         for arr in self.profiles:
             if arr is not None and arr.shape != (spec.steps_per_episode,):
                 raise ValueError("arrival_rate / price_table need steps_per_episode entries")
+        days = getattr(spec, "price_days", None)
+        self.days = None if days is None else np.ascontiguousarray(days, np.float64)
+        if self.days is not None and (self.days.ndim != 2 or self.days.shape[1] != spec.steps_per_episode):
+            raise ValueError("price_days needs shape [n_days][steps_per_episode]")
         pdis = getattr(spec, "port_pdis_kw", None)
         self.pdis = None if pdis is None else np.ascontiguousarray(pdis, np.float64)
         if self.pdis is not None and self.pdis.shape != (spec.n_ports,):
@@ -189,7 +194,9 @@ class _SpecHolder:
                               float(getattr(spec, "alpha_degrad_battery", 0.0)),
                               float(getattr(spec, "alpha_degrad_cars", 0.0)),
                               float(getattr(spec, "charge_sensitive_share", 0.0)),
-                              float(getattr(spec, "alpha_sat1", 0.0)), float(getattr(spec, "beta_sat1", 0.0)))
+                              float(getattr(spec, "alpha_sat1", 0.0)), float(getattr(spec, "beta_sat1", 0.0)),
+                              0 if self.days is None else self.days.shape[0],
+                              None if self.days is None else self.days.ctypes.data)
 
 
 def compile_layout(spec) -> Dict[str, np.ndarray]:

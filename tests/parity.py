@@ -42,9 +42,12 @@ def obs_masks(specs, env_class):
         scale[o + 3 * N:o + 4 * N] = s.steps_per_episode
         kind[o + 6 * N + 3] = 3
         scale[o + 6 * N + 3] = N
+        do = o + 6 * N + 4 + (2 if getattr(s, "has_battery", False) else 0)
+        if getattr(s, "has_days", False):
+            kind[do + 1] = 1                      # weekend flag
+            do += 2
         if getattr(s, "has_users", False):
-            uo = o + 6 * N + 4 + (2 if s.has_battery else 0)
-            kind[uo:uo + N] = 1
+            kind[do:do + N] = 1
     return kind, scale
 
 

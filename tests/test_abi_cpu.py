@@ -44,7 +44,7 @@ SPECS = [W.tiny_parity_station(), W.scale_station(), W.policy_station(), W.two_c
          W.tiny_parity_station().replace(arrival_peak=0.0, dwell_max=1),
          W.fanout4_tree(32, 2).replace(steps_per_episode=96, dwell_max=300, dwell_mu=math.log(12.0)),
          W.fanout4_tree(128, 3).replace(arrival_peak=8.0)] + W.mixture_classes() + W.v2g_mixture() + \
-        [W.user_station()]
+        [W.user_station(), W.exo_station()]
 
 
 @pytest.mark.parametrize("spec", SPECS, ids=[s.name or str(i) for i, s in enumerate(SPECS)])
@@ -116,6 +116,7 @@ BAD = [
     ("cs_share", dict(charge_sensitive_share=1.5)),
     ("cs_alpha", dict(charge_sensitive_share=0.5, alpha_sat1=float("inf"))),
     ("cs_long_episode", dict(charge_sensitive_share=0.5, steps_per_episode=40000)),
+    ("price_days_nan", dict(price_days=np.full((3, 288), np.nan))),
 ]
 
 

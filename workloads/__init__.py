@@ -216,6 +216,15 @@ def price_day_table(n_days: int = 28, steps: int = STEPS_PER_DAY, seed: int = 77
     return base[None, :] * level[:, None] + hourly
 
 
+def exo_station(**kw) -> StationSpec:
+    """The paper's default two-charger-type station (10 DC + 6 AC ports) driven
+    by tables: commuter arrivals per step and exploring starts over 28 synthetic
+    price days."""
+    s = two_charger_types().replace(name="types10dc6ac_commute_days", arrival_rate=commuter_arrivals(),
+                                    price_days=price_day_table(28))
+    return s.replace(**kw) if kw else s
+
+
 def profile_station() -> StationSpec:
     """The two-charger-type station with commuter arrivals and a time-of-use tariff."""
     return two_charger_types().replace(name="types10dc6ac_tou", arrival_rate=commuter_arrivals(),
