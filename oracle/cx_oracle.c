@@ -28,6 +28,10 @@ struct ox_class {
   double b_cap, b_rate, b_tau, b_soc0, a_db, a_dc;  /* battery (b_cap = 0: none), degradation weights */
   double cs_share, a_sat1, beta1;  /* charge-sensitive users: share of arrivals, weight, beta */
   int32_t n_days;            /* exploring starts: price days (0: none) */
+  int32_t n_models;          /* car models (0: none) */
+  uint32_t model_thresh[8];  /* cumulative thresholds: model = #{m : w > model_thresh[m]} */
+  double model_cap[8], model_rac[8], model_rdc[8];
+  int32_t *port_dc;          /* [n_ports] 1 = DC charger */
   double *price_days;        /* [n_days][steps_per_episode] */
   uint32_t cs_thresh;        /* a car's user is charge-sensitive iff its word <= cs_thresh (share > 0) */
   double p[OXP_COUNT];
@@ -119,6 +123,22 @@ void ox_class_set_price_days(ox_class *c, int32_t n_days, const double *price_da
   memcpy(c->price_days, price_days, sizeof(double) * (size_t)n_days * S);
 }
 
+void ox_class_set_car_models(ox_class *c, int32_t n_models, const double *models, const int32_t *port_dc) {
+  c->n_models = n_models;
+  double F = 0.0;
+  for (int32_t m = 0; m < n_models; ++m) {
+    F += models[4 * m + 0];
+    /* the last model takes all the remaining mass */
+    c->model_thresh[m] = m + 1 == n_models ? 0xFFFFFFFFu : threshold_u32(F);
+    c->model_cap[m] = models[4 * m + 1];
+    c->model_rac[m] = models[4 * m + 2];
+    c->model_rdc[m] = models[4 * m + 3];
+  }
+  free(c->port_dc);
+  c->port_dc = (int32_t *)calloc((size_t)c->n_ports, sizeof(int32_t));
+  if (port_dc) memcpy(c->port_dc, port_dc, sizeof(int32_t) * c->n_ports);
+}
+
 int32_t ox_episode_day(const ox_class *c, uint64_t seed, uint32_t env, uint32_t g0) {
   if (!has_days(c)) return -1;
   uint32_t w[4];
@@ -196,7 +216,7 @@ ox_class *ox_class_new(int32_t n_ports, int32_t n_nodes, const int32_t *node_par
 void ox_class_free(ox_class *c) {
   if (!c) return;
   free(c->node_parent); free(c->node_depth); free(c->node_cap); free(c->anc);
-  free(c->pmax); free(c->peta); free(c->pdis); free(c->price_days); free(c->tpois); free(c->tdwell); free(c->lam); free(c->price);
+  free(c->pmax); free(c->peta); free(c->pdis); free(c->price_days); free(c->port_dc); free(c->tpois); free(c->tdwell); free(c->lam); free(c->price);
   free(c);
 }
 
@@ -250,21 +270,22 @@ static double discharge_rate(double pmax, double tau, double soc) {
 }
 
 /* Power of one pole for signed level k (App. A.2 "Apply Actions"): charging
- * asks for k/L of the charge maximum, clipped by the charging curve and by the
- * room left in the battery; discharging asks for |k|/L of the discharge
- * maximum, clipped by the mirrored curve and by the energy stored. */
-static double pole_power(int32_t k, int32_t L, double pmax, double pdis, double tau, double soc,
+ * asks for k/L of the charge maximum, clipped by the car's charging curve (its
+ * maximum rate rbar) and by the room left in the battery; discharging asks for
+ * |k|/L of the discharge maximum, clipped by the mirrored curve and by the
+ * energy stored. */
+static double pole_power(int32_t k, int32_t L, double pmax, double pdis, double rbar, double tau, double soc,
                          double cap, double dt) {
   if (k >= 0) {
     double v = (double)k / (double)L * pmax;
-    double rhat = charge_rate(pmax, tau, soc);
+    double rhat = charge_rate(rbar, tau, soc);
     double room = (1.0 - soc) * cap / dt;
     if (rhat < v) v = rhat;
     if (room < v) v = room;
     return v;
   }
   double v = (double)(-k) / (double)L * pdis;
-  double rhat = discharge_rate(pmax, tau, soc);
+  double rhat = discharge_rate(rbar, tau, soc);
   double stored = soc * cap / dt;
   if (rhat < v) v = rhat;
   if (stored < v) v = stored;
@@ -273,7 +294,7 @@ static double pole_power(int32_t k, int32_t L, double pmax, double pdis, double 
 
 double ox_battery_power(const ox_class *c, double soc_b, int32_t kb) {
   if (!has_battery(c)) return 0.0;
-  return pole_power(kb, c->ip[OXI_N_LEVELS], c->b_rate, c->b_rate, c->b_tau, soc_b, c->b_cap,
+  return pole_power(kb, c->ip[OXI_N_LEVELS], c->b_rate, c->b_rate, c->b_rate, c->b_tau, soc_b, c->b_cap,
                     c->p[OXP_DT]);
 }
 
@@ -308,12 +329,13 @@ static int32_t occupied(const int32_t *dwell, const int32_t *user, int32_t i) {
 }
 
 void ox_apply_actions(const ox_class *c, const int32_t *dwell, const int32_t *user, const double *soc,
-                      const double *cap, const int32_t *k, double *P) {
+                      const double *cap, const double *rbar, const int32_t *k, double *P) {
   const double tau = c->p[OXP_TAU], dt = c->p[OXP_DT];
   const int32_t L = c->ip[OXI_N_LEVELS];
   for (int32_t i = 0; i < c->n_ports; ++i)
-    P[i] = occupied(dwell, user, i) ? pole_power(k[i], L, c->pmax[i], c->pdis[i], tau, soc[i], cap[i], dt)
-                                    : 0.0;
+    P[i] = occupied(dwell, user, i)
+               ? pole_power(k[i], L, c->pmax[i], c->pdis[i], rbar ? rbar[i] : c->pmax[i], tau, soc[i], cap[i], dt)
+               : 0.0;
   ox_project(c, P);
 }
 
@@ -342,6 +364,13 @@ void ox_draw_exo(const ox_class *c, uint64_t seed, uint32_t env, uint32_t g, int
     uint32_t b[4];
     philox_seeded(seed, env, g, (uint32_t)j, OX_DOM_CAR, b);
     x->car_cap[j] = c->p[OXP_CAP_LO] + (c->p[OXP_CAP_HI] - c->p[OXP_CAP_LO]) * ox_u24(b[0]);
+    x->car_model[j] = -1;
+    if (c->n_models > 0) {  /* the car's model (App. A.1 car distribution) fixes its capacity */
+      int32_t m = 0;
+      for (int32_t q = 0; q < c->n_models; ++q) m += b[0] > c->model_thresh[q];
+      x->car_model[j] = m;
+      x->car_cap[j] = c->model_cap[m];
+    }
     x->car_soc[j] = c->p[OXP_SOC0_LO] + (c->p[OXP_SOC0_HI] - c->p[OXP_SOC0_LO]) * ox_u24(b[1]);
     x->car_tgt[j] = c->p[OXP_TGT_LO] + (c->p[OXP_TGT_HI] - c->p[OXP_TGT_LO]) * ox_u24(b[2]);
     int32_t d = 1;
@@ -384,8 +413,8 @@ void ox_draw_actions(const ox_class *c, int32_t mode, uint64_t seed, uint32_t en
 
 /* ------------------------------------------------------------------------- */
 void ox_observe(const ox_class *c, const int32_t *dwell, const int32_t *user, const double *soc,
-                const double *e_rem, const double *cap, const double *p_last, const double *batt,
-                int32_t t_day, int32_t day, double *obs) {
+                const double *e_rem, const double *cap, const double *rbar, const double *p_last,
+                const double *batt, int32_t t_day, int32_t day, double *obs) {
   const int32_t N = c->n_ports, S = c->ip[OXI_STEPS_PER_EPISODE];
   const double tau = c->p[OXP_TAU];
   int32_t n_occ = 0;
@@ -396,7 +425,7 @@ void ox_observe(const ox_class *c, const int32_t *dwell, const int32_t *user, co
     obs[1 * N + i] = occ ? soc[i] : 0.0;
     obs[2 * N + i] = occ ? e_rem[i] / cap[i] : 0.0;
     obs[3 * N + i] = (double)dwell[i] / (double)S;
-    obs[4 * N + i] = occ ? charge_rate(c->pmax[i], tau, soc[i]) / c->pmax[i] : 0.0;
+    obs[4 * N + i] = occ ? charge_rate(rbar ? rbar[i] : c->pmax[i], tau, soc[i]) / c->pmax[i] : 0.0;
     obs[5 * N + i] = occ ? p_last[i] / c->pmax[i] : 0.0;
   }
   double ang = 2.0 * M_PI * (double)t_day / (double)S;
@@ -420,22 +449,24 @@ void ox_observe(const ox_class *c, const int32_t *dwell, const int32_t *user, co
 }
 
 static void clear_port(int32_t i, int32_t *dwell, int32_t *user, double *soc, double *e_rem, double *cap,
-                       double *p_last) {
+                       double *rbar, double *p_last) {
   dwell[i] = 0; user[i] = 0; soc[i] = 0.0; e_rem[i] = 0.0; cap[i] = 0.0; p_last[i] = 0.0;
+  if (rbar) rbar[i] = 0.0;
 }
 
 /* App. A.2: (i) apply actions, (ii) charge, (iii) departures, (iv) arrivals;
  * then the reward of App. A.3 and the day boundary of Supp. B.1. */
 void ox_transition(const ox_class *c, int32_t *dwell, int32_t *user, double *soc, double *e_rem,
-                   double *cap, double *p_last, double *batt, double *ret, int32_t *t_day,
+                   double *cap, double *rbar, double *p_last, double *batt, double *ret, int32_t *t_day,
                    const int32_t *k, const ox_exo *x, ox_step_info *info, double *obs, double *P_out) {
+  if (c->n_models == 0) rbar = NULL;  /* the base model: every car's rate is the port maximum */
   const int32_t N = c->n_ports;
   const double dt = c->p[OXP_DT];
   double P[OX_MAX_PORTS];
   unsigned char was_occ[OX_MAX_PORTS];
 
   /* (i) apply actions */
-  ox_apply_actions(c, dwell, user, soc, cap, k, P);
+  ox_apply_actions(c, dwell, user, soc, cap, rbar, k, P);
   if (P_out)
     for (int32_t i = 0; i < N; ++i) P_out[i] = P[i];
 
@@ -480,12 +511,12 @@ void ox_transition(const ox_class *c, int32_t *dwell, int32_t *user, double *soc
         double t_left = (double)dwell[i] * dt;
         c_sat1 += (t_left < 0.0 ? -t_left : 0.0) - c->beta1 * (t_left > 0.0 ? t_left : 0.0);
         ++n_dep;
-        clear_port(i, dwell, user, soc, e_rem, cap, p_last);
+        clear_port(i, dwell, user, soc, e_rem, cap, rbar, p_last);
       }
     } else if (dwell[i] == 0) {
       c_sat += e_rem[i] > 0.0 ? e_rem[i] : 0.0;
       ++n_dep;
-      clear_port(i, dwell, user, soc, e_rem, cap, p_last);
+      clear_port(i, dwell, user, soc, e_rem, cap, rbar, p_last);
     }
   }
 
@@ -499,6 +530,7 @@ void ox_transition(const ox_class *c, int32_t *dwell, int32_t *user, double *soc
     if (occupied(dwell, user, i)) continue;
     dwell[i] = x->car_dwell[j];
     user[i] = x->car_user[j];
+    if (rbar) rbar[i] = c->port_dc[i] ? c->model_rdc[x->car_model[j]] : c->model_rac[x->car_model[j]];
     soc[i] = x->car_soc[j];
     cap[i] = x->car_cap[j];
     e_rem[i] = (x->car_tgt[j] - x->car_soc[j]) * x->car_cap[j];
@@ -521,7 +553,7 @@ void ox_transition(const ox_class *c, int32_t *dwell, int32_t *user, double *soc
   *t_day += 1;
   int32_t done = *t_day == c->ip[OXI_STEPS_PER_EPISODE];
   if (done) {
-    for (int32_t i = 0; i < N; ++i) clear_port(i, dwell, user, soc, e_rem, cap, p_last);
+    for (int32_t i = 0; i < N; ++i) clear_port(i, dwell, user, soc, e_rem, cap, rbar, p_last);
     if (has_battery(c)) {
       batt[0] = c->b_soc0;
       batt[1] = 0.0;
@@ -537,7 +569,7 @@ void ox_transition(const ox_class *c, int32_t *dwell, int32_t *user, double *soc
     info->done = done; info->n_occ = n_occ; info->e_to_grid = e_to_grid; info->e_batt = e_batt;
     info->c_sat1 = c_sat1;
   }
-  if (obs) ox_observe(c, dwell, user, soc, e_rem, cap, p_last, batt, *t_day, x->day_next, obs);
+  if (obs) ox_observe(c, dwell, user, soc, e_rem, cap, rbar, p_last, batt, *t_day, x->day_next, obs);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -553,7 +585,7 @@ typedef struct {
   int32_t t0, T, mode;
   const uint8_t *act_in;
   int32_t *dwell, *user;
-  double *soc, *e_rem, *cap, *p_last, *batt, *ret, *obs, *reward;
+  double *soc, *e_rem, *cap, *rbar, *p_last, *batt, *ret, *obs, *reward;
   uint8_t *act, *done;
   ox_step_info *info;
 } rollout_job;
@@ -577,7 +609,7 @@ static void *rollout_worker(void *arg) {
       ox_step_info inf;
       double *o = J->obs ? J->obs + (size_t)t * J->total_obs + oo : NULL;
       ox_transition(c, J->dwell + po, J->user + po, J->soc + po, J->e_rem + po, J->cap + po,
-                    J->p_last + po, bt, J->ret + e, &t_day, k, &x, &inf, o, NULL);
+                    J->rbar ? J->rbar + po : NULL, J->p_last + po, bt, J->ret + e, &t_day, k, &x, &inf, o, NULL);
       if (J->act)
         for (int32_t i = 0; i < n_act; ++i)
           J->act[(size_t)t * J->total_act + ao + i] = (uint8_t)ox_action_code(c, i, k[i]);
@@ -592,7 +624,7 @@ static void *rollout_worker(void *arg) {
 int32_t ox_rollout(ox_class *const *classes, const int32_t *env_class, const int64_t *env_ids,
                    int64_t n_envs, uint64_t seed, uint32_t *g, int32_t *t_day, int32_t T, int32_t mode,
                    const uint8_t *act_in, int32_t *dwell, int32_t *user, double *soc, double *e_rem,
-                   double *cap, double *p_last, double *batt, double *ret, double *obs, uint8_t *act,
+                   double *cap, double *rbar, double *p_last, double *batt, double *ret, double *obs, uint8_t *act,
                    double *reward, uint8_t *done, ox_step_info *info, int32_t n_threads) {
   int64_t *port_off = (int64_t *)malloc(sizeof(int64_t) * (n_envs + 1));
   int64_t *act_off = (int64_t *)malloc(sizeof(int64_t) * (n_envs + 1));
@@ -615,7 +647,8 @@ int32_t ox_rollout(ox_class *const *classes, const int32_t *env_class, const int
     J->total_act = act_off[n_envs]; J->total_obs = obs_off[n_envs]; J->n_envs = n_envs;
     J->e_begin = n_envs * w / n_threads; J->e_end = n_envs * (w + 1) / n_threads;
     J->seed = seed; J->g0 = *g; J->t0 = *t_day; J->T = T; J->mode = mode; J->act_in = act_in;
-    J->dwell = dwell; J->user = user; J->soc = soc; J->e_rem = e_rem; J->cap = cap; J->p_last = p_last;
+    J->dwell = dwell; J->user = user; J->soc = soc; J->e_rem = e_rem; J->cap = cap; J->rbar = rbar;
+    J->p_last = p_last;
     J->batt = batt;
     J->ret = ret; J->obs = obs; J->act = act; J->reward = reward; J->done = done; J->info = info;
   }

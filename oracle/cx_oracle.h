@@ -43,6 +43,9 @@
  *   users (u = 1)        reaching the target, overstay and early-leave terms of
  *                        c_satisfaction,1, share of drawn users (binomial), the
  *                        all-time-sensitive special case equal to the base model
+ *   car models        -- (tests/test_oracle_cars.py) model frequencies (chi-square),
+ *   (AC / DC)            hand-worked AC and DC clips, the one-model special case
+ *                        equal to the base model, P <= the car's rate
  *   exploring starts  -- (tests/test_oracle_days.py) uniform day draws, prices
  *                        following the drawn day's row, a new day at each
  *                        episode, one price day = the per-step price table
@@ -106,6 +109,7 @@ typedef struct {
   int32_t car_user[OX_K_POIS];    /* 1: charge-sensitive user (u = 1), else 0   */
   int32_t day, day_next;          /* price day of this step's episode and of the next
                                      step's (-1 without price days)                */
+  int32_t car_model[OX_K_POIS];   /* car model of car j (-1 without car models)   */
 } ox_exo;
 
 /* Everything one transition reports besides the new state.  e_grid is the net
@@ -145,6 +149,13 @@ void ox_class_set_users(ox_class *c, double share, double alpha, double beta);
  * observation shows that day (day / n_days) and whether it is a weekend day
  * (day mod 7 >= 5). */
 void ox_class_set_price_days(ox_class *c, int32_t n_days, const double *price_days);
+/* Car models (App. A.1 "Car Profiles": each car has a capacity and a maximum
+ * rate per charger type, AC and DC; both curves share tau): n_models rows of
+ * {probability, capacity kWh, AC rate kW, DC rate kW}; port_dc[i] = 1 marks a
+ * DC port (NULL: all AC).  An arriving car's model replaces the uniform
+ * capacity draw (same Philox word), and its curve at port i uses the rate of
+ * the port's type instead of the port maximum. */
+void ox_class_set_car_models(ox_class *c, int32_t n_models, const double *models, const int32_t *port_dc);
 /* The price day of the episode that started at global step g0 (-1 without days). */
 int32_t ox_episode_day(const ox_class *c, uint64_t seed, uint32_t env, uint32_t g0);
 int32_t ox_class_ports(const ox_class *c);
@@ -163,9 +174,10 @@ double ox_u24(uint32_t w);  /* (w >> 8) * 2^-24 */
 /* Apply-actions step: clip by port maximum, charging curve and remaining capacity,
  * then project onto the architecture constraints.  P (n_ports) is written.
  * A port is occupied when dwell > 0 or it holds a charge-sensitive user
- * (user[i] = 1; user may be NULL: all time-sensitive). */
+ * (user[i] = 1; user may be NULL: all time-sensitive).  rbar[i] is the car's
+ * maximum rate at port i (NULL: the port maximum, the base model). */
 void ox_apply_actions(const ox_class *c, const int32_t *dwell, const int32_t *user, const double *soc,
-                      const double *cap, const int32_t *k, double *P);
+                      const double *cap, const double *rbar, const int32_t *k, double *P);
 /* The projection of Eq. (ArchConst) alone, in place on P. */
 void ox_project(const ox_class *c, double *P);
 
@@ -185,17 +197,18 @@ void ox_draw_actions(const ox_class *c, int32_t mode, uint64_t seed, uint32_t en
  * one).  obs (obs_dim) may be NULL; P_out (n_ports) receives the applied powers
  * and may be NULL. */
 void ox_transition(const ox_class *c, int32_t *dwell, int32_t *user, double *soc, double *e_rem,
-                   double *cap, double *p_last, double *batt, double *ret, int32_t *t_day,
+                   double *cap, double *rbar, double *p_last, double *batt, double *ret, int32_t *t_day,
                    const int32_t *k, const ox_exo *x, ox_step_info *info, double *obs, double *P_out);
 /* Observation of the current state (used after reset and by the policy). */
 void ox_observe(const ox_class *c, const int32_t *dwell, const int32_t *user, const double *soc,
-                const double *e_rem, const double *cap, const double *p_last, const double *batt,
-                int32_t t_day, int32_t day, double *obs);
+                const double *e_rem, const double *cap, const double *rbar, const double *p_last,
+                const double *batt, int32_t t_day, int32_t day, double *obs);
 
 /* ---- batched rollout over many envs (threads over env ranges) ----
  * env_class[n_envs] indexes classes[]; envs may be in any class order.  State
  * arrays are port-major per env, envs concatenated (port offset = prefix sum of
- * the envs' port counts); batt holds {SoC, last power} per env (2 n_envs
+ * the envs' port counts; rbar: the car's rate per port, kept for classes with car
+ * models); batt holds {SoC, last power} per env (2 n_envs
  * doubles, used by battery classes only; may be NULL if no class has one).
  * Outputs are time-major:
  *   obs    [T][sum_e obs_dim(e)]   (may be NULL)
@@ -210,7 +223,7 @@ int32_t ox_rollout(ox_class *const *classes, const int32_t *env_class, const int
                    int64_t n_envs,
                    uint64_t seed, uint32_t *g, int32_t *t_day, int32_t T, int32_t mode,
                    const uint8_t *act_in, int32_t *dwell, int32_t *user, double *soc, double *e_rem,
-                   double *cap, double *p_last, double *batt, double *ret, double *obs, uint8_t *act,
+                   double *cap, double *rbar, double *p_last, double *batt, double *ret, double *obs, uint8_t *act,
                    double *reward, uint8_t *done, ox_step_info *info, int32_t n_threads);
 
 /* ---- policy (observation -> MLP -> Gumbel-argmax levels) ----

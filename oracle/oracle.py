@@ -46,7 +46,8 @@ class Exo(C.Structure):
     _fields_ = [("M", C.c_int32), ("z", C.c_double), ("p_buy", C.c_double),
                 ("car_cap", C.c_double * K_POIS), ("car_soc", C.c_double * K_POIS),
                 ("car_tgt", C.c_double * K_POIS), ("car_dwell", C.c_int32 * K_POIS),
-                ("car_user", C.c_int32 * K_POIS), ("day", C.c_int32), ("day_next", C.c_int32)]
+                ("car_user", C.c_int32 * K_POIS), ("day", C.c_int32), ("day_next", C.c_int32),
+                ("car_model", C.c_int32 * K_POIS)]
 
 
 _lib = None
@@ -67,17 +68,18 @@ def lib():
         L.ox_u24.restype = C.c_double
         L.ox_u24.argtypes = [C.c_uint32]
         L.ox_project.argtypes = [P, P]
-        L.ox_apply_actions.argtypes = [P, P, P, P, P, P, P]
+        L.ox_apply_actions.argtypes = [P, P, P, P, P, P, P, P]
         L.ox_draw_exo.argtypes = [P, C.c_uint64, C.c_uint32, C.c_uint32, I, P]
         L.ox_draw_actions.argtypes = [P, I, C.c_uint64, C.c_uint32, C.c_uint32, P, P]
-        L.ox_transition.argtypes = [P] * 15
-        L.ox_observe.argtypes = [P, P, P, P, P, P, P, P, I, I, P]
+        L.ox_transition.argtypes = [P] * 16
+        L.ox_observe.argtypes = [P, P, P, P, P, P, P, P, P, I, I, P]
+        L.ox_class_set_car_models.argtypes = [P, I, P, P]
         L.ox_class_set_price_days.argtypes = [P, I, P]
         L.ox_episode_day.restype = I
         L.ox_episode_day.argtypes = [P, C.c_uint64, C.c_uint32, C.c_uint32]
         L.ox_rollout.restype = I
         L.ox_rollout.argtypes = [P, P, P, C.c_int64, C.c_uint64, P, P, I, I, P, P, P, P, P, P, P, P,
-                                 P, P, P, P, P, P, I]
+                                 P, P, P, P, P, P, P, I]
         L.ox_class_set_users.argtypes = [P, C.c_double, C.c_double, C.c_double]
         L.ox_class_set_v2g.argtypes = [P, I, P, P]
         L.ox_class_actions.restype = I
@@ -157,6 +159,16 @@ class OracleClass:
                 raise ValueError("price_days needs shape [n_days][steps_per_episode]")
             self._keep.append(d)
             lib().ox_class_set_price_days(self.h, d.shape[0], _ptr(d))
+        models = getattr(spec, "car_models", None)
+        self.has_models = models is not None
+        if models is not None:
+            m = np.ascontiguousarray(models, dtype=np.float64)
+            if m.ndim != 2 or m.shape[1] != 4 or not 1 <= m.shape[0] <= 8:
+                raise ValueError("car_models needs shape [1..8][4]")
+            dc = getattr(spec, "port_dc", None)
+            dca = None if dc is None else np.ascontiguousarray(dc, dtype=np.int32)
+            self._keep += [a for a in (m, dca) if a is not None]
+            lib().ox_class_set_car_models(self.h, m.shape[0], _ptr(m), _ptr(dca))
         self.n_act = lib().ox_class_actions(self.h)
         self.has_battery = self.n_act > self.n
 
@@ -200,14 +212,15 @@ class OracleClass:
         lib().ox_project(self.h, _ptr(P))
         return P
 
-    def apply_actions(self, dwell, soc, cap, k, user=None) -> np.ndarray:
+    def apply_actions(self, dwell, soc, cap, k, user=None, rbar=None) -> np.ndarray:
         d = np.ascontiguousarray(dwell, dtype=np.int32)
         u = None if user is None else np.ascontiguousarray(user, dtype=np.int32)
+        rb = None if rbar is None else np.ascontiguousarray(rbar, dtype=np.float64)
         s = np.ascontiguousarray(soc, dtype=np.float64)
         c = np.ascontiguousarray(cap, dtype=np.float64)
         kk = np.ascontiguousarray(k, dtype=np.int32)
         P = np.zeros(self.n, dtype=np.float64)
-        lib().ox_apply_actions(self.h, _ptr(d), _ptr(u), _ptr(s), _ptr(c), _ptr(kk), _ptr(P))
+        lib().ox_apply_actions(self.h, _ptr(d), _ptr(u), _ptr(s), _ptr(c), _ptr(rb), _ptr(kk), _ptr(P))
         return P
 
     def draw_exo(self, seed: int, env: int, g: int, t_day: int) -> Exo:
@@ -224,8 +237,9 @@ class OracleClass:
 
     def observe(self, st: "EnvState") -> np.ndarray:
         obs = np.zeros(self.obs_dim, dtype=np.float64)
+        rb = st.rbar if self.has_models else None
         lib().ox_observe(self.h, _ptr(st.dwell), _ptr(st.user), _ptr(st.soc), _ptr(st.e_rem), _ptr(st.cap),
-                         _ptr(st.p_last), _ptr(st.batt), st.t_day, getattr(st, "day", -1), _ptr(obs))
+                         _ptr(rb), _ptr(st.p_last), _ptr(st.batt), st.t_day, getattr(st, "day", -1), _ptr(obs))
         return obs
 
     def transition(self, st: "EnvState", k, exo: Exo):
@@ -237,7 +251,7 @@ class OracleClass:
         ret = C.c_double(st.ret)
         t_day = C.c_int32(st.t_day)
         lib().ox_transition(self.h, _ptr(st.dwell), _ptr(st.user), _ptr(st.soc), _ptr(st.e_rem),
-                            _ptr(st.cap), _ptr(st.p_last), _ptr(st.batt), C.byref(ret), C.byref(t_day),
+                            _ptr(st.cap), _ptr(st.rbar), _ptr(st.p_last), _ptr(st.batt), C.byref(ret), C.byref(t_day),
                             _ptr(kk), C.byref(exo),
                             C.byref(info), _ptr(obs), _ptr(P))
         st.ret = ret.value
@@ -266,6 +280,7 @@ class EnvState:
         self.batt = np.array([battery_soc, 0.0])   # station battery: SoC, last power
         self.dwell = np.zeros(n_ports, dtype=np.int32)
         self.user = np.zeros(n_ports, dtype=np.int32)   # 1: charge-sensitive user
+        self.rbar = np.zeros(n_ports)                   # the car's maximum rate (car models)
         self.soc = np.zeros(n_ports, dtype=np.float64)
         self.e_rem = np.zeros(n_ports, dtype=np.float64)
         self.cap = np.zeros(n_ports, dtype=np.float64)
@@ -274,16 +289,18 @@ class EnvState:
         self.t_day = 0
         self.day = -1        # price day of the current episode (exploring starts)
 
-    def put_car(self, port: int, soc: float, cap: float, dwell: int, e_rem: float, user: int = 0):
+    def put_car(self, port: int, soc: float, cap: float, dwell: int, e_rem: float, user: int = 0,
+                rbar: float = 0.0):
         self.dwell[port] = dwell
         self.user[port] = user
+        self.rbar[port] = rbar
         self.soc[port] = soc
         self.cap[port] = cap
         self.e_rem[port] = e_rem
 
 
 def exo(M: int = 0, p_buy: float = 0.25, cars=()) -> Exo:
-    """Hand-built exogenous input: cars = [(cap, soc0, tgt, dwell[, user]), ...]."""
+    """Hand-built exogenous input: cars = [(cap, soc0, tgt, dwell[, user[, model]]), ...]."""
     x = Exo()
     x.M = M
     x.z = 0.0
@@ -293,6 +310,7 @@ def exo(M: int = 0, p_buy: float = 0.25, cars=()) -> Exo:
         cap, soc0, tgt, dwell = car[:4]
         x.car_cap[j], x.car_soc[j], x.car_tgt[j], x.car_dwell[j] = cap, soc0, tgt, dwell
         x.car_user[j] = car[4] if len(car) > 4 else 0
+        x.car_model[j] = car[5] if len(car) > 5 else -1
     return x
 
 
@@ -319,6 +337,7 @@ class BatchState:
         self.batt[0::2] = soc0[self.env_class]
         self.dwell = np.zeros(P, dtype=np.int32)
         self.user = np.zeros(P, dtype=np.int32)
+        self.rbar = np.zeros(P)
         self.soc = np.zeros(P)
         self.e_rem = np.zeros(P)
         self.cap = np.zeros(P)
@@ -345,7 +364,7 @@ def rollout(bs: BatchState, seed: int, T: int, mode: int = ACT_RANDOM, act_in=No
     t_day = C.c_int32(bs.t_day)
     used = lib().ox_rollout(handles, _ptr(bs.env_class), _ptr(bs.env_ids), bs.n_envs, seed, C.byref(g), C.byref(t_day),
                             T, mode, _ptr(ain), _ptr(bs.dwell), _ptr(bs.user), _ptr(bs.soc), _ptr(bs.e_rem),
-                            _ptr(bs.cap), _ptr(bs.p_last), _ptr(bs.batt), _ptr(bs.ret), _ptr(obs), _ptr(act),
+                            _ptr(bs.cap), _ptr(bs.rbar), _ptr(bs.p_last), _ptr(bs.batt), _ptr(bs.ret), _ptr(obs), _ptr(act),
                             _ptr(rew), _ptr(done), None if info is None else C.cast(info, C.c_void_p),
                             n_threads)
     bs.g = g.value

@@ -89,6 +89,10 @@ class StationSpec:
     # exploring starts: [n_days][steps_per_episode] base buying prices; every
     # episode draws one day (None = one price curve for every day)
     price_days: Optional[np.ndarray] = None
+    # car models (App. A.1 car distribution): [n][4] rows of probability, capacity
+    # kWh, AC rate kW, DC rate kW; port_dc marks DC ports (None = all AC)
+    car_models: Optional[np.ndarray] = None
+    port_dc: Optional[List[int]] = None
 
     @property
     def n_nodes(self) -> int:
@@ -216,12 +220,25 @@ def price_day_table(n_days: int = 28, steps: int = STEPS_PER_DAY, seed: int = 77
     return base[None, :] * level[:, None] + hourly
 
 
+def car_mix(region: str = "europe") -> np.ndarray:
+    """Synthetic car distributions (probability, capacity kWh, AC kW, DC kW) in
+    place of the paper's Europe / US car data: small, compact, large and premium
+    cars; the US mix leans to larger batteries and faster DC charging."""
+    if region == "europe":
+        return np.array([[0.30, 40.0, 7.4, 50.0], [0.35, 58.0, 11.0, 100.0],
+                         [0.25, 77.0, 11.0, 150.0], [0.10, 95.0, 22.0, 250.0]])
+    return np.array([[0.10, 50.0, 7.4, 60.0], [0.30, 70.0, 11.5, 150.0],
+                     [0.40, 85.0, 11.5, 200.0], [0.20, 110.0, 19.2, 250.0]])
+
+
 def exo_station(**kw) -> StationSpec:
     """The paper's default two-charger-type station (10 DC + 6 AC ports) driven
-    by tables: commuter arrivals per step and exploring starts over 28 synthetic
-    price days."""
-    s = two_charger_types().replace(name="types10dc6ac_commute_days", arrival_rate=commuter_arrivals(),
-                                    price_days=price_day_table(28))
+    by tables: commuter arrivals per step, exploring starts over 28 synthetic
+    price days, and the European car mix (each car charges at its own AC or DC
+    rate)."""
+    s = two_charger_types().replace(name="types10dc6ac_commute_days_cars", arrival_rate=commuter_arrivals(),
+                                    price_days=price_day_table(28), car_models=car_mix("europe"),
+                                    port_dc=[1] * 10 + [0] * 6)
     return s.replace(**kw) if kw else s
 
 
