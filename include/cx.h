@@ -147,6 +147,17 @@ typedef struct {
    * default price curve. */
   int32_t n_price_days;
   const double *price_days;
+  /* Car models (App. A.1 "Car Profiles": a capacity and a maximum rate per
+   * charger type, AC and DC, from a car distribution; both curves share tau):
+   * n_car_models (0..8) rows of {probability, capacity kWh, AC rate kW, DC rate
+   * kW} (probabilities summing to 1), and port_dc [n_ports] (1 = DC charger;
+   * NULL = all AC).  An arriving car's model is the number of cumulative
+   * integer thresholds that the capacity word of its CAR draw exceeds; the
+   * model fixes its capacity, and its charging curve at port i uses the rate of
+   * the port's type (its request is still a share of the port maximum). */
+  int32_t n_car_models;
+  const double *car_models;
+  const int32_t *port_dc;
 } cx_station_spec;
 
 typedef struct cx_ctx cx_ctx;
@@ -275,12 +286,13 @@ cx_status cx_observe(cx_ctx *ctx, float *obs_dev);
  * packing-independent host format of cx_info.state_bytes bytes, bit-exact, so a
  * restored context continues exactly as the original.  Both calls synchronise
  * the context's stream.  Format (little endian):
- *   u64 magic 0x32305843 ('CX02'), i64 n_envs, i64 ports (sum of n_ports over
+ *   u64 magic 0x33305843 ('CX03'), i64 n_envs, i64 ports (sum of n_ports over
  *   the envs), u32 g, i32 t_day,
- *   then per port in env/port order (25 bytes): i32 dwell (steps left; <= 0 only
+ *   then per port in env/port order (29 bytes): i32 dwell (steps left; <= 0 only
  *   for a charge-sensitive user), f64 1 - SoC, f32 1 - target SoC, f32 battery
  *   capacity C, f32 last power, u8 user (1 = charge-sensitive; a port is empty
- *   when dwell <= 0 and user = 0);
+ *   when dwell <= 0 and user = 0), f32 the car's maximum rate at this port
+ *   (classes with car models; 0 otherwise);
  *   then per env: f64 return; then per env of a class with a station battery,
  *   in env order (12 bytes): f64 battery SoC, f32 battery last power.
  *   The energy still wanted is (target - SoC) * C.  An empty port is all zeros. */

@@ -48,6 +48,9 @@ size_t class_block(const SpecCopy &sc, const Compiled &k, const Tables &t, unsig
   const size_t o_pdis = take(sizeof(float) * k.S);
   const size_t o_eta = take(sizeof(float) * k.S);
   const size_t o_days = take(sizeof(float) * t.price_days.size());
+  const size_t o_mth = take(sizeof(uint32_t) * 8);
+  const size_t o_mdat = take(sizeof(float) * 24);
+  const size_t o_sdc = take(sizeof(int32_t) * k.S);
   unsigned char *base = dev_base;
   ClassDev d{};
   d.n_ports = k.N; d.S = k.S; d.D = k.D; d.n_levels = s.n_levels;
@@ -105,6 +108,7 @@ size_t class_block(const SpecCopy &sc, const Compiled &k, const Tables &t, unsig
   d.n_days = k.n_days;
   d.day_obs = k.day_obs;
   d.inv_n_days = k.n_days > 0 ? (float)(1.0 / k.n_days) : 0.f;
+  d.n_models = k.n_models;
   d.pmax_u = k.slot_pmax[0];
   d.inv_pmax_u = k.slot_inv_pmax[0];
   d.slot_port = reinterpret_cast<const int32_t *>(base + o_port);
@@ -119,6 +123,9 @@ size_t class_block(const SpecCopy &sc, const Compiled &k, const Tables &t, unsig
   d.slot_pdis = reinterpret_cast<const float *>(base + o_pdis);
   d.slot_eta = reinterpret_cast<const float *>(base + o_eta);
   d.price_days = reinterpret_cast<const float *>(base + o_days);
+  d.model_thresh = reinterpret_cast<const uint32_t *>(base + o_mth);
+  d.model_data = reinterpret_cast<const float *>(base + o_mdat);
+  d.slot_dc = reinterpret_cast<const int32_t *>(base + o_sdc);
   if (view) *view = d;
   if (host) {
     host->assign(off, 0);
@@ -136,6 +143,9 @@ size_t class_block(const SpecCopy &sc, const Compiled &k, const Tables &t, unsig
     std::memcpy(host->data() + o_eta, k.slot_eta.data(), sizeof(float) * k.S);
     if (!t.price_days.empty())
       std::memcpy(host->data() + o_days, t.price_days.data(), sizeof(float) * t.price_days.size());
+    std::memcpy(host->data() + o_mth, k.model_thresh.data(), sizeof(uint32_t) * 8);
+    std::memcpy(host->data() + o_mdat, k.model_data.data(), sizeof(float) * 24);
+    std::memcpy(host->data() + o_sdc, k.slot_dc.data(), sizeof(int32_t) * k.S);
   }
   return off;
 }
@@ -233,6 +243,7 @@ cx_status rebuild_segments(cx_ctx *ctx) {
       sg.bsoc = ctx->bsoc + c.env_begin + e0;
       sg.bp = ctx->bp + c.env_begin + e0;
       sg.utype = ctx->utype + so;
+      sg.rbar = ctx->rbar + so;
       sg.obs_off = c.obs_off + e0 * c.comp.obs_dim;
       sg.act_off = c.port_off + e0 * c.comp.n_act;
       sg.env_off = c.env_begin + e0;
@@ -359,7 +370,7 @@ static cx_status create_impl(const cx_station_spec *specs, int32_t n_specs, cons
   const size_t rbytes = align256(sizeof(double) * (size_t)n_envs);
   const size_t bbytes = align256(sizeof(float) * (size_t)n_envs);
   const size_t ubytes = align256((size_t)slot_off);
-  const size_t total = qbytes + 3 * fbytes + dbytes + 2 * rbytes + bbytes + ubytes;
+  const size_t total = qbytes + 4 * fbytes + dbytes + 2 * rbytes + bbytes + ubytes;
   if (hipMalloc(&ctx->state_mem, total) != hipSuccess) {
     free_ctx(ctx);
     return fail_status(CX_E_OOM, "hipMalloc of station state failed");
@@ -376,6 +387,7 @@ static cx_status create_impl(const cx_station_spec *specs, int32_t n_specs, cons
   ctx->bsoc = reinterpret_cast<double *>(b + qbytes + 3 * fbytes + dbytes + rbytes);
   ctx->bp = reinterpret_cast<float *>(b + qbytes + 3 * fbytes + dbytes + 2 * rbytes);
   ctx->utype = reinterpret_cast<uint8_t *>(b + qbytes + 3 * fbytes + dbytes + 2 * rbytes + bbytes);
+  ctx->rbar = reinterpret_cast<float *>(b + qbytes + 3 * fbytes + dbytes + 2 * rbytes + bbytes + ubytes);
   if (hipMemset(ctx->state_mem, 0, total) != hipSuccess) {
     free_ctx(ctx);
     return fail_status(CX_E_DEVICE, "hipMemset of station state failed");

@@ -45,6 +45,7 @@ struct cx_ctx {
   double *bsoc = nullptr;         // station battery SoC per env (battery classes)
   float *bp = nullptr;            // station battery last power per env
   uint8_t *utype = nullptr;       // user type per slot (1 = charge-sensitive)
+  float *rbar = nullptr;          // the car's maximum rate per slot (car models)
   // launch layout: segments grouped by slots per lane, one kernel per group
   cx::SegDev *segs_dev = nullptr;
   size_t segs_cap = 0;            // entries allocated at segs_dev

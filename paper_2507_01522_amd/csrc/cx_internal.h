@@ -80,8 +80,11 @@ struct ClassDev {
   float alpha_sat1, beta_sat1; // c_satisfaction,1 weight and its early-leave weight
   float inv_n_days;            // exploring starts: 1 / n_days
   int32_t n_days, day_obs;     // price days (0: none) and the observation offset of the day features
-  int32_t pad_d;
+  int32_t n_models;            // car models (0: none)
   const float *price_days;     // [n_days][steps_ep]
+  const uint32_t *model_thresh;// [8]: model = #{m < n_models : w > model_thresh[m]}
+  const float *model_data;     // [8][3]: capacity, AC rate, DC rate
+  const int32_t *slot_dc;      // [S]: 1 = DC charger
 };
 
 // One class's env range inside a launch.  Static fields are set when the
@@ -121,6 +124,8 @@ struct SegDev {
   float *bp;
   // user type per slot (classes with charge-sensitive users): 1 = charge-sensitive
   uint8_t *utype;
+  // the car's maximum rate per slot (classes with car models)
+  float *rbar;
 };
 
 // Launch-wide arguments (by value).

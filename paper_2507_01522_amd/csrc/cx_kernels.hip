@@ -179,6 +179,8 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
   const bool users = EXT && C.has_users != 0;  // some users are charge-sensitive
   const int n_days = EXT ? C.n_days : 0;       // exploring starts: price days
   const bool days = n_days > 0;
+  const int n_models = EXT ? C.n_models : 0;   // car models (AC / DC rates)
+  const bool models = n_models > 0;
 
   // ---- per-slot constants
   int port[P];
@@ -216,6 +218,8 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
   float u[P], cap[P], icap[P], plast[P];
   int dw[P];
   int cs[P];  // EXT: 1 = a charge-sensitive user holds the slot (its dw may be <= 0)
+  float rb[P];  // EXT: the car's maximum rate at this port (the port maximum without car models)
+  int dc[P];    // EXT with car models: 1 = DC charger
   const int64_t sofs = (int64_t)env * S;
 #pragma unroll
   for (int j = 0; j < P; ++j) {
@@ -227,6 +231,8 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
     plast[j] = active ? sg.p_last[i] : 0.f;
     dw[j] = active ? (int)sg.dwell[i] : 0;
     cs[j] = (users && active) ? (int)sg.utype[i] : 0;
+    rb[j] = models ? (active ? sg.rbar[i] : 0.f) : pmax[j];
+    dc[j] = models ? gld(C.slot_dc, j * L + l) : 0;
     icap[j] = cap[j] > 0.f ? frcp(cap[j]) : 0.f;
   }
   // a slot is occupied while its car's stay runs, or while a charge-sensitive
@@ -256,7 +262,7 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
   if constexpr (EXT) {
     if (days) dday = episode_day(env_id, g - (uint32_t)t_day, k0, k1, n_days);
   }
-  int bM = 0, bdw = 1, bus = 0;
+  int bM = 0, bdw = 1, bus = 0, bmod = 0;
   float bpb = 0.f, bcp = 0.f, bs0 = 0.f, btg = 0.f;
   U4 aw[P];
 #pragma unroll
@@ -300,6 +306,13 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
       bpb = base + C.price_sigma * z;
       const U4 b = philox(env_id, gl, 0u, kDomCar, k0, k1);
       bcp = C.cap_lo + C.cap_span * u24(b.x);
+      if constexpr (EXT) {
+        if (models) {  // the car's model fixes its capacity
+          bmod = 0;
+          for (int m = 0; m < n_models; ++m) bmod += b.x > gld(C.model_thresh, m) ? 1 : 0;
+          bcp = gld(C.model_data, 3 * bmod);
+        }
+      }
       bs0 = C.soc_lo + C.soc_span * u24(b.y);
       btg = C.tgt_lo + C.tgt_span * u24(b.z);
       bdw = stay_len(tdw, tdw_lds, C.dwell_log2, b.w);
@@ -365,9 +378,10 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
         const float soc = (float)(1.0 - q[j]);
         const float creq = (float)lev * C.inv_n_levels * pmax[j];
         const float dreq = (float)(-lev) * C.inv_n_levels * pdis[j];
-        const float drate = pmax[j] * fminf(1.0f, soc * C.inv_1mtau);
+        const float crate = rb[j] * fminf(1.0f, qf[j] * C.inv_1mtau);   // the car's curve
+        const float drate = rb[j] * fminf(1.0f, soc * C.inv_1mtau);
         const float stored = soc * cap[j] * C.inv_dt;
-        const float p = lev >= 0 ? fminf(fminf(creq, rhat), room) : -fminf(fminf(dreq, drate), stored);
+        const float p = lev >= 0 ? fminf(fminf(creq, crate), room) : -fminf(fminf(dreq, drate), stored);
         pw[j] = CX_OCCUPIED(j) ? p : 0.0f;
       } else {
         pw[j] = dw[j] > 0 ? fminf(fminf(req, rhat), room) : 0.0f;
@@ -518,6 +532,7 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
           cs[j] = dep ? 0 : cs[j];
           dw[j] = dep ? 0 : dw[j];   // a charged user may leave with steps of its stay left
         }
+        if (models) rb[j] = dep ? 0.f : rb[j];
       }
       const float miss = fmaxf(0.0f, (qf[j] - u[j]) * cap[j]);
       csat += dep0 ? miss : 0.0f;
@@ -552,6 +567,7 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
       const float f_cp = bcastf<L>(bcp, tb), f_s0 = bcastf<L>(bs0, tb), f_tg = bcastf<L>(btg, tb);
       const int f_dw = bcast<L>(bdw, tb);
       const int f_us = EXT ? bcast<L>(bus, tb) : 0;
+      const int f_mod = EXT ? bcast<L>(bmod, tb) : 0;
       int run = 0;
 #pragma unroll
       for (int j = 0; j < P; ++j) {
@@ -559,10 +575,17 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
         if (fr[j] && rank < acc) {
           float cp = f_cp, s0 = f_s0, tg = f_tg;
           int dd = f_dw;
-          int us = f_us;
+          int us = f_us, md = f_mod;
           if (rank > 0) {
             const U4 b = philox(env_id, g, (uint32_t)rank, kDomCar, k0, k1);
             cp = C.cap_lo + C.cap_span * u24(b.x);
+            if constexpr (EXT) {
+              if (models) {
+                md = 0;
+                for (int m = 0; m < n_models; ++m) md += b.x > gld(C.model_thresh, m) ? 1 : 0;
+                cp = gld(C.model_data, 3 * md);
+              }
+            }
             s0 = C.soc_lo + C.soc_span * u24(b.y);
             tg = C.tgt_lo + C.tgt_span * u24(b.z);
             dd = stay_len(tdw, tdw_lds, C.dwell_log2, b.w);
@@ -571,7 +594,10 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
             }
           }
           dw[j] = dd;
-          if constexpr (EXT) cs[j] = us;
+          if constexpr (EXT) {
+            cs[j] = us;
+            if (models) rb[j] = gld(C.model_data, 3 * md + (dc[j] ? 2 : 1));
+          }
           cap[j] = cp;
           icap[j] = frcp(cp);
           q[j] = 1.0 - (double)s0;
@@ -604,7 +630,10 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
 #pragma unroll
       for (int j = 0; j < P; ++j) {
         dw[j] = 0; q[j] = 0.0; qf[j] = 0.f; u[j] = 0.f; cap[j] = 0.f; icap[j] = 0.f; plast[j] = 0.f;
-        if constexpr (EXT) cs[j] = 0;
+        if constexpr (EXT) {
+          cs[j] = 0;
+          if (models) rb[j] = 0.f;
+        }
       }
       if constexpr (EXT) {
         if (days) dday = episode_day(env_id, g + 1u, k0, k1, n_days);  // the next episode begins
@@ -630,7 +659,11 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
             st_at(ob, o + 1u * 4u * N, occ ? 1.0f - qf[j] : 0.0f);
             st_at(ob, o + 2u * 4u * N, occ ? qf[j] - u[j] : 0.0f);
             st_at(ob, o + 3u * 4u * N, (float)dw[j] * C.inv_steps_ep);
-            st_at(ob, o + 4u * 4u * N, occ ? fminf(1.0f, qf[j] * C.inv_1mtau) : 0.0f);
+            float rh = fminf(1.0f, qf[j] * C.inv_1mtau);
+            if constexpr (EXT) {
+              if (models) rh *= rb[j] * inv_pmax[j];  // the car's curve, as a share of the port maximum
+            }
+            st_at(ob, o + 4u * 4u * N, occ ? rh : 0.0f);
             st_at(ob, o + 5u * 4u * N, plast[j] * inv_pmax[j]);
             if constexpr (EXT) {
               if (users) st_at(ob, obs_bo + 4u * (uint32_t)(C.user_obs + port[j]), cs[j] ? 1.0f : 0.0f);
@@ -691,6 +724,7 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
       sg.dwell[i] = (int16_t)dw[j];
       if constexpr (EXT) {
         if (users) sg.utype[i] = (uint8_t)cs[j];
+        if (models) sg.rbar[i] = rb[j];
       }
     }
     if (l == 0) sg.ret[env] = ret;

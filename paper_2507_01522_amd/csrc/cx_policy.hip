@@ -309,7 +309,8 @@ __global__ __launch_bounds__(64 * kPolWaves) void k_policy(PolicyArgs a) {
 // Observation of the current state (the features the step kernel records).
 __global__ void k_observe(const ClassDev *cls, int64_t n_envs, const double *q, const float *u,
                           const float *p_last, const int16_t *dwell, const uint8_t *utype, const double *bsoc,
-                          const float *bp, int32_t t_day, uint64_t seed, int64_t env0, uint32_t g, float *obs) {
+                          const float *bp, const float *rbar, int32_t t_day, uint64_t seed, int64_t env0, uint32_t g,
+                          float *obs) {
   const ClassDev C = *cls;
   const int S = C.S, N = C.n_ports, dim = C.obs_dim;
   const int64_t total = n_envs * S;
@@ -328,7 +329,9 @@ __global__ void k_observe(const ClassDev *cls, int64_t n_envs, const double *q, 
     o[1 * N] = occ ? 1.0f - qf : 0.0f;
     o[2 * N] = occ ? qf - u[i] : 0.0f;
     o[3 * N] = (float)dw * C.inv_steps_ep;
-    o[4 * N] = occ ? fminf(1.0f, qf * C.inv_1mtau) : 0.0f;
+    float rh = fminf(1.0f, qf * C.inv_1mtau);
+    if (C.n_models > 0) rh *= rbar[i] * C.slot_inv_pmax[s];  // the car's curve, as a share of the port maximum
+    o[4 * N] = occ ? rh : 0.0f;
     o[5 * N] = p_last[i] * C.slot_inv_pmax[s];
     if (C.has_users) obs[env * dim + C.user_obs + port] = cs ? 1.0f : 0.0f;
   }
@@ -371,8 +374,8 @@ hipError_t launch_observe(const cx_ctx *ctx, float *obs, hipStream_t st) {
     const int blocks = (int)std::min<int64_t>(4096, (work + 255) / 256);
     hipLaunchKernelGGL(k_observe, dim3(blocks), dim3(256), 0, st, c.dev, c.n_envs, ctx->q + c.slot_off,
                        ctx->u + c.slot_off, ctx->p_last + c.slot_off, ctx->dwell + c.slot_off,
-                       ctx->utype + c.slot_off, ctx->bsoc + c.env_begin, ctx->bp + c.env_begin, ctx->t_day,
-                       ctx->seed, c.env_begin, ctx->g, obs + c.obs_off);
+                       ctx->utype + c.slot_off, ctx->bsoc + c.env_begin, ctx->bp + c.env_begin,
+                       ctx->rbar + c.slot_off, ctx->t_day, ctx->seed, c.env_begin, ctx->g, obs + c.obs_off);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

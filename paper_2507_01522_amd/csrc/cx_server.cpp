@@ -52,7 +52,7 @@ struct Req {
   // device layout: [class block | state | server-owned outputs]
   size_t class_bytes = 0, state_bytes = 0, out_bytes = 0, total = 0;
   size_t off_q = 0, off_u = 0, off_cap = 0, off_pl = 0, off_dw = 0, off_ret = 0, off_bsoc = 0, off_bp = 0;
-  size_t off_ut = 0;
+  size_t off_ut = 0, off_rb = 0;
   size_t off_obs = 0, off_act = 0, off_rew = 0, off_done = 0;
   std::vector<unsigned char> class_host;  // kept until the request ends (async upload source)
   ClassDev view{};
@@ -176,6 +176,7 @@ void plan(Req &r) {
   r.off_bsoc = o; o = a256(o + (r.comp.battery ? 8 * (size_t)E : 0));
   r.off_bp = o; o = a256(o + (r.comp.battery ? 4 * (size_t)E : 0));
   r.off_ut = o; o = a256(o + (r.comp.users ? (size_t)(E * S) : 0));
+  r.off_rb = o; o = a256(o + (r.comp.n_models > 0 ? 4 * (size_t)(E * S) : 0));
   r.state_bytes = o - r.class_bytes;
   const size_t out0 = o;
   const bool want_obs = r.out_mode == CX_OUT_FULL;
@@ -324,6 +325,7 @@ bool launch(cx_server *s) {
       sg.bsoc = reinterpret_cast<double *>(b + r.off_bsoc);
       sg.bp = reinterpret_cast<float *>(b + r.off_bp);
       sg.utype = b + r.off_ut;
+      sg.rbar = reinterpret_cast<float *>(b + r.off_rb);
       sg.obs = r.traj.obs ? r.traj.obs + t * E * od : nullptr;
       sg.act = r.traj.actions ? r.traj.actions + t * E * A : nullptr;
       sg.reward = r.traj.reward + t * E;

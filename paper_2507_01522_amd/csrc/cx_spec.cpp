@@ -70,6 +70,13 @@ bool copy_spec(const cx_station_spec &in, SpecCopy *out, std::string *err) {
   }
   out->s.price_days = out->price_days.empty() ? nullptr : out->price_days.data();
   if (out->price_days.empty()) out->s.n_price_days = 0;
+  if (in.n_car_models < 0 || in.n_car_models > 8) return fail(err, "n_car_models must be in 0..8");
+  if (in.n_car_models > 0 && !in.car_models) return fail(err, "car_models must not be NULL when n_car_models > 0");
+  out->car_models.assign(in.car_models, in.car_models + 4 * (size_t)in.n_car_models);
+  out->s.car_models = out->car_models.empty() ? nullptr : out->car_models.data();
+  out->port_dc.assign(in.n_ports, 0);
+  if (in.port_dc) out->port_dc.assign(in.port_dc, in.port_dc + in.n_ports);
+  out->s.port_dc = out->port_dc.data();
   return true;
 }
 
@@ -103,6 +110,19 @@ bool compile_spec(const SpecCopy &sc, Compiled *c, std::string *err) {
     if (!std::isfinite(v)) return fail(err, "price_table entries must be finite");
   for (double v : sc.price_days)
     if (!std::isfinite(v)) return fail(err, "price_days entries must be finite");
+  {
+    double psum = 0.0;
+    for (int m = 0; m < s.n_car_models; ++m) {
+      const double *r = &sc.car_models[4 * (size_t)m];
+      if (!(r[0] >= 0.0 && r[0] <= 1.0)) return fail(err, "car model probabilities must be in [0,1]");
+      if (!finite_pos(r[1]) || !finite_pos(r[2]) || !finite_pos(r[3]))
+        return fail(err, "car model capacity and rates must be > 0");
+      psum += r[0];
+    }
+    if (s.n_car_models > 0 && std::fabs(psum - 1.0) > 1e-6) return fail(err, "car model probabilities must sum to 1");
+    for (int32_t v : sc.port_dc)
+      if (v != 0 && v != 1) return fail(err, "port_dc entries must be 0 or 1");
+  }
   if (s.v2g != 0 && s.v2g != 1) return fail(err, "v2g must be 0 or 1");
   if ((s.v2g || s.battery_kwh > 0.0) && s.n_levels > 127)
     return fail(err, "n_levels must be at most 127 with discharging (signed levels fit an action byte)");
@@ -221,6 +241,23 @@ bool compile_spec(const SpecCopy &sc, Compiled *c, std::string *err) {
   c->cs_thresh = c->users ? cdf_threshold(s.charge_sensitive_share) : 0u;
   c->n_act = N + (c->battery ? 1 : 0);
   c->n_days = s.n_price_days;
+  c->n_models = s.n_car_models;
+  c->model_thresh.assign(8, 0xFFFFFFFFu);
+  c->model_data.assign(24, 0.f);
+  {
+    double F = 0.0;
+    for (int m = 0; m < c->n_models; ++m) {
+      const double *r = &sc.car_models[4 * (size_t)m];
+      F += r[0];
+      // model = #{m : w > thresh[m]}; the last model takes the remaining mass
+      c->model_thresh[m] = m + 1 == c->n_models ? 0xFFFFFFFFu : cdf_threshold(F);
+      c->model_data[3 * m + 0] = (float)r[1];
+      c->model_data[3 * m + 1] = (float)r[2];
+      c->model_data[3 * m + 2] = (float)r[3];
+    }
+  }
+  c->slot_dc.assign(S, 0);
+  for (int i = 0; i < N; ++i) c->slot_dc[c->port_slot[i]] = sc.port_dc[i];
   c->day_obs = 6 * N + 4 + (c->battery ? 2 : 0);
   c->user_obs = c->day_obs + (c->n_days > 0 ? 2 : 0);
   c->obs_dim = c->user_obs + (c->users ? N : 0);

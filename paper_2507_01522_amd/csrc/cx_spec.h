@@ -16,6 +16,8 @@ struct SpecCopy {
   std::vector<double> arrival_rate, price_table;  // empty: the default curves
   std::vector<double> port_pdis;                  // discharge maxima (port maxima if not given)
   std::vector<double> price_days;                 // [n_price_days][steps] (empty: none)
+  std::vector<double> car_models;                 // [n_car_models][4] (empty: none)
+  std::vector<int32_t> port_dc;                   // [n_ports] (all 0 if not given)
 };
 
 // The capacity tree in the kernels' layout.  Every node owns an aligned block of
@@ -35,11 +37,15 @@ struct Compiled {
   bool v2g = false, battery = false;       // ports discharge / a station battery
   bool users = false;                      // some users are charge-sensitive (u = 1)
   int n_days = 0;                          // exploring starts: price days (0: none)
+  int n_models = 0;                        // car models (0: none)
+  std::vector<uint32_t> model_thresh;      // [8] cumulative thresholds (0xFFFFFFFF past the last)
+  std::vector<float> model_data;           // [8][3]: capacity, AC rate, DC rate
+  std::vector<int32_t> slot_dc;            // [S] 1 = DC charger
   int day_obs = 0;                         // observation offset of [day / n_days, weekend]
   uint32_t cs_thresh = 0;                  // u = 1 iff the user word <= cs_thresh
   int n_act = 0, obs_dim = 0;              // action bytes and observation floats per env
   int user_obs = 0;                        // observation offset of the user flags
-  bool extended() const { return v2g || battery || users || n_days > 0; }  // needs the extended kernels
+  bool extended() const { return v2g || battery || users || n_days > 0 || n_models > 0; }  // extended kernels
 };
 
 struct Tables {

@@ -8,9 +8,9 @@
 
 namespace cx {
 
-static const uint64_t kMagic = 0x32305843ull;  // "CX02"
+static const uint64_t kMagic = 0x33305843ull;  // "CX03"
 static const size_t kHeader = 8 + 8 + 8 + 4 + 4;
-static const size_t kPortRec = 4 + 8 + 4 + 4 + 4 + 1;
+static const size_t kPortRec = 4 + 8 + 4 + 4 + 4 + 1 + 4;
 static const size_t kBattRec = 8 + 4;
 
 static size_t battery_envs(const cx_ctx *ctx) {
@@ -41,6 +41,7 @@ cx_status cx_get_state(cx_ctx *ctx, void *host, size_t bytes) {
   std::vector<float> uv(ns), cap(ns), pl(ns);
   std::vector<int16_t> dw(ns);
   std::vector<uint8_t> ut(ns);
+  std::vector<float> rb(ns);
   std::vector<double> ret((size_t)ctx->n_envs), bsoc((size_t)ctx->n_envs);
   std::vector<float> bp((size_t)ctx->n_envs);
   if ((e = hipMemcpy(qv.data(), ctx->q, 8 * ns, hipMemcpyDeviceToHost)) != hipSuccess ||
@@ -51,6 +52,7 @@ cx_status cx_get_state(cx_ctx *ctx, void *host, size_t bytes) {
       (e = hipMemcpy(pl.data(), ctx->p_last, 4 * ns, hipMemcpyDeviceToHost)) != hipSuccess ||
       (e = hipMemcpy(dw.data(), ctx->dwell, 2 * ns, hipMemcpyDeviceToHost)) != hipSuccess ||
       (e = hipMemcpy(ut.data(), ctx->utype, ns, hipMemcpyDeviceToHost)) != hipSuccess ||
+      (e = hipMemcpy(rb.data(), ctx->rbar, 4 * ns, hipMemcpyDeviceToHost)) != hipSuccess ||
       (e = hipMemcpy(ret.data(), ctx->ret, 8 * ret.size(), hipMemcpyDeviceToHost)) != hipSuccess)
     return hip_fail(ctx, e, "cx_get_state copy");
   unsigned char *p = static_cast<unsigned char *>(host);
@@ -72,6 +74,7 @@ cx_status cx_get_state(cx_ctx *ctx, void *host, size_t bytes) {
         std::memcpy(q + 16, &cap[x], 4);
         std::memcpy(q + 20, &pl[x], 4);
         q[24] = ut[x];
+        std::memcpy(q + 25, &rb[x], 4);
         q += kPortRec;
       }
     }
@@ -111,6 +114,7 @@ cx_status cx_set_state(cx_ctx *ctx, const void *host, size_t bytes) {
   std::vector<float> uv(ns, 0.f), cap(ns, 0.f), pl(ns, 0.f);
   std::vector<int16_t> dw(ns, 0);
   std::vector<uint8_t> ut(ns, 0);
+  std::vector<float> rb(ns, 0.f);
   std::vector<double> ret((size_t)ctx->n_envs);
   const unsigned char *q = p + kHeader;
   for (const ClassRt &c : ctx->classes) {
@@ -125,6 +129,8 @@ cx_status cx_set_state(cx_ctx *ctx, const void *host, size_t bytes) {
         if (d > 32767 || d < (user ? -32767 : 0)) return fail_status(CX_E_INVALID, "snapshot dwell out of range");
         dw[x] = (int16_t)d;
         ut[x] = user;
+        std::memcpy(&rb[x], q + 25, 4);
+        if (!(rb[x] >= 0.f && rb[x] < 1e30f)) return fail_status(CX_E_INVALID, "snapshot car rate invalid");
         std::memcpy(&qv[x], q + 4, 8);
         std::memcpy(&uv[x], q + 12, 4);
         std::memcpy(&cap[x], q + 16, 4);
@@ -156,6 +162,7 @@ cx_status cx_set_state(cx_ctx *ctx, const void *host, size_t bytes) {
       (e = hipMemcpy(ctx->p_last, pl.data(), 4 * ns, hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(ctx->dwell, dw.data(), 2 * ns, hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(ctx->utype, ut.data(), ns, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(ctx->rbar, rb.data(), 4 * ns, hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(ctx->ret, ret.data(), 8 * ret.size(), hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(ctx->bsoc, bsoc.data(), 8 * bsoc.size(), hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(ctx->bp, bp.data(), 4 * bp.size(), hipMemcpyHostToDevice)) != hipSuccess)

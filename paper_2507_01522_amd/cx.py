@@ -45,7 +45,8 @@ class StationSpecC(C.Structure):
                 ("battery_tau", C.c_double), ("battery_soc0", C.c_double),
                 ("alpha_degrad_battery", C.c_double), ("alpha_degrad_cars", C.c_double),
                 ("charge_sensitive_share", C.c_double), ("alpha_sat1", C.c_double), ("beta_sat1", C.c_double),
-                ("n_price_days", C.c_int32), ("price_days", C.c_void_p)]
+                ("n_price_days", C.c_int32), ("price_days", C.c_void_p), ("n_car_models", C.c_int32),
+                ("car_models", C.c_void_p), ("port_dc", C.c_void_p)]
 
 
 class TrajC(C.Structure):
@@ -174,6 +175,12 @@ class _SpecHolder:
         self.days = None if days is None else np.ascontiguousarray(days, np.float64)
         if self.days is not None and (self.days.ndim != 2 or self.days.shape[1] != spec.steps_per_episode):
             raise ValueError("price_days needs shape [n_days][steps_per_episode]")
+        models = getattr(spec, "car_models", None)
+        self.models = None if models is None else np.ascontiguousarray(models, np.float64)
+        if self.models is not None and (self.models.ndim != 2 or self.models.shape[1] != 4):
+            raise ValueError("car_models needs shape [n][4]")
+        dc = getattr(spec, "port_dc", None)
+        self.port_dc = None if dc is None else np.ascontiguousarray(dc, np.int32)
         pdis = getattr(spec, "port_pdis_kw", None)
         self.pdis = None if pdis is None else np.ascontiguousarray(pdis, np.float64)
         if self.pdis is not None and self.pdis.shape != (spec.n_ports,):
@@ -196,7 +203,10 @@ class _SpecHolder:
                               float(getattr(spec, "charge_sensitive_share", 0.0)),
                               float(getattr(spec, "alpha_sat1", 0.0)), float(getattr(spec, "beta_sat1", 0.0)),
                               0 if self.days is None else self.days.shape[0],
-                              None if self.days is None else self.days.ctypes.data)
+                              None if self.days is None else self.days.ctypes.data,
+                              0 if self.models is None else self.models.shape[0],
+                              None if self.models is None else self.models.ctypes.data,
+                              None if self.port_dc is None else self.port_dc.ctypes.data)
 
 
 def compile_layout(spec) -> Dict[str, np.ndarray]:
@@ -355,9 +365,10 @@ class Env:
         g = int(head[24:28].view(np.uint32)[0])
         t_day = int(head[28:32].view(np.int32)[0])
         rec = np.frombuffer(blob, dtype=np.dtype([("dwell", "<i4"), ("q", "<f8"), ("u", "<f4"),
-                                                  ("cap", "<f4"), ("p_last", "<f4"), ("user", "u1")]),
+                                                  ("cap", "<f4"), ("p_last", "<f4"), ("user", "u1"),
+                                                  ("rbar", "<f4")]),
                             count=n_ports, offset=32)
-        off = 32 + 25 * n_ports
+        off = 32 + 29 * n_ports
         ret = np.frombuffer(blob, dtype="<f8", count=i.n_envs, offset=off)
         off += 8 * i.n_envs
         bsoc = np.zeros(i.n_envs)

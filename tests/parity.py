@@ -116,6 +116,10 @@ def compare_state(st, bs, specs, env_class, keep=None):
     pmax = np.concatenate([specs[c].port_pmax_kw for c in env_class])
     check_close("p_last", st["p_last"][pk], bs.p_last[pk], pmax[pk])
     check_close("return", st["ret"][keep], bs.ret[keep], reward_floor(specs, env_class)[keep])
+    has_m = np.repeat(np.array([getattr(specs[c], "car_models", None) is not None for c in env_class]) & keep,
+                      np.diff(bs.port_off))
+    if has_m.any():
+        check_close("car rate", st["rbar"][has_m], bs.rbar[has_m], 1.0)
     has_b = np.array([specs[c].has_battery for c in env_class]) & keep
     if has_b.any():
         check_close("battery soc", st["batt_soc"][has_b], bs.batt[0::2][has_b], 1.0)

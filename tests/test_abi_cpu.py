@@ -117,6 +117,9 @@ BAD = [
     ("cs_alpha", dict(charge_sensitive_share=0.5, alpha_sat1=float("inf"))),
     ("cs_long_episode", dict(charge_sensitive_share=0.5, steps_per_episode=40000)),
     ("price_days_nan", dict(price_days=np.full((3, 288), np.nan))),
+    ("car_model_sum", dict(car_models=np.array([[0.5, 40.0, 7.0, 50.0], [0.4, 60.0, 11.0, 100.0]]))),
+    ("car_model_rate", dict(car_models=np.array([[1.0, 40.0, 0.0, 50.0]]))),
+    ("port_dc", dict(car_models=np.array([[1.0, 40.0, 7.0, 50.0]]), port_dc=[2] * 16)),
 ]
 
 
