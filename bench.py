@@ -160,6 +160,8 @@ def run_rollout_workload(args, name, specs, ec, seed, desc, cpu_stride):
     n_ports = np.array([s.n_ports for s in specs])[ec]
     batt = np.array([1 if getattr(s, "has_battery", False) else 0 for s in specs])[ec]
     dayf = np.array([1 if getattr(s, "has_days", False) else 0 for s in specs])[ec]
+    cars = np.array([1 if getattr(s, "car_models", None) is not None else 0 for s in specs])[ec]
+    extra_state = n_ports * users + 4 * n_ports * cars   # user bytes and car rates per port
     users = np.array([1 if getattr(s, "has_users", False) else 0 for s in specs])[ec]
     n_envs = len(ec)
     env = cx.Env(specs, env_class=ec, seed=seed) if len(specs) > 1 else cx.Env(specs[0], n_envs=n_envs, seed=seed)
@@ -170,9 +172,9 @@ def run_rollout_workload(args, name, specs, ec, seed, desc, cpu_stride):
     wall_ms, kernel_ms = timed_rollouts(env, cx, T_DAY, cx.ACT_RANDOM, cx.OUT_FULL, out, args)
     env_steps = n_envs * T_DAY
     value = env_steps / (wall_ms / 1e3)
-    # records (+ user flags, 4 bytes per port; + the two day features) and the state in and out (+ a user byte per port)
+    # records (+ user flags, 4 bytes per port; + the two day features) and the state in and out
     alg_bytes = float(((record_bytes(n_ports, "full", batt) + 4 * n_ports * users + 8 * dayf) * T_DAY
-                       + 2 * (state_bytes(n_ports, batt) + n_ports * users)).sum())
+                       + 2 * (state_bytes(n_ports, batt) + extra_state)).sum())
     achieved = alg_bytes / (kernel_ms / 1e3) / 1e9
     del out
     # records of rewards and done flags only (the same rollout, 5 bytes per env-step)
@@ -192,7 +194,7 @@ def run_rollout_workload(args, name, specs, ec, seed, desc, cpu_stride):
                         "kernel": "k_rollout", "kernel_ms": kernel_ms, "algorithmic_bytes": alg_bytes}
     line["reward_only"] = {"env_steps_per_s": env_steps / (r_wall / 1e3), "kernel_ms": r_kernel,
                            "algorithmic_bytes": float((record_bytes(n_ports, "reward") * T_DAY
-                                                       + 2 * (state_bytes(n_ports, batt) + n_ports * users)).sum())}
+                                                       + 2 * (state_bytes(n_ports, batt) + extra_state)).sum())}
     line["plain"] = plain
     line["speedup_vs_plain"] = (value / plain["env_steps_per_s"]) if plain else None
     line["cpu_baseline"] = cpu
@@ -239,8 +241,8 @@ def run_users(args):
 def run_exo(args):
     import workloads as W
     return run_rollout_workload(args, "exo: 65536 stations x 288 steps, 10 DC + 6 AC ports under per-type splitters, "
-                                      "commuter arrival table, exploring starts over 28 price days, random "
-                                      "levels, full records", [W.exo_station()], np.zeros(65536, np.int32), 5,
+                                      "commuter arrival table, exploring starts over 28 price days, European car "
+                                      "mix (AC / DC rates), random levels, full records", [W.exo_station()], np.zeros(65536, np.int32), 5,
                                 "table-driven stations", 64)
 
 
