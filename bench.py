@@ -38,21 +38,33 @@ BF16_PEAK_TFLOPS = 2500.0
 T_DAY = 288
 
 
-def record_bytes(n_ports: np.ndarray, out_mode: str = "full", battery=0) -> np.ndarray:
-    """Bytes of one record per env-step: obs (6N+4, +2 with a station battery) f32,
-    one action byte per port (+1 for the battery), reward f32, done u8."""
-    b = np.asarray(battery, dtype=np.int64)
+def record_bytes(spec, out_mode: str = "full") -> int:
+    """Bytes of one record per env-step: obs (obs_dim f32: 6N+4, +2 with a
+    station battery, +2 with price days, +N with charge-sensitive users), one
+    action byte per port (+1 for the battery), reward f32, done u8."""
     if out_mode == "full":
-        return 4 * (6 * n_ports + 4 + 2 * b) + n_ports + b + 4 + 1
+        return 4 * spec.obs_dim + spec.n_actions + 4 + 1
     if out_mode == "act_reward":
-        return n_ports + b + 4 + 1
-    return np.full_like(n_ports, 4 + 1)
+        return spec.n_actions + 4 + 1
+    return 4 + 1
 
 
-def state_bytes(n_ports: np.ndarray, battery=0) -> np.ndarray:
+def state_bytes(spec) -> int:
     """Per env: 1 - SoC (f64), 1 - target, capacity, last power (f32) and dwell (i16)
-    per port, plus the f64 return (and the battery's f64 SoC and f32 power)."""
-    return 22 * n_ports + 8 + 12 * np.asarray(battery, dtype=np.int64)
+    per port and the f64 return; with a battery its f64 SoC and f32 power, with
+    charge-sensitive users a user byte per port, with car models the car's f32
+    rate per port."""
+    N = spec.n_ports
+    return (22 * N + 8 + (12 if getattr(spec, "has_battery", False) else 0)
+            + (N if getattr(spec, "has_users", False) else 0)
+            + (4 * N if getattr(spec, "car_models", None) is not None else 0))
+
+
+def rollout_bytes(specs, ec, T: int, out_mode: str = "full") -> float:
+    """Algorithmic bytes of one T-step rollout: every record once, the state read
+    once and written once."""
+    counts = np.bincount(np.asarray(ec), minlength=len(specs))
+    return float(sum(int(n) * (T * record_bytes(s, out_mode) + 2 * state_bytes(s)) for s, n in zip(specs, counts)))
 
 
 def measured_traffic():
@@ -158,11 +170,6 @@ def run_rollout_workload(args, name, specs, ec, seed, desc, cpu_stride):
     import torch  # noqa: F401
     import paper_2507_01522_amd as cx
     n_ports = np.array([s.n_ports for s in specs])[ec]
-    batt = np.array([1 if getattr(s, "has_battery", False) else 0 for s in specs])[ec]
-    dayf = np.array([1 if getattr(s, "has_days", False) else 0 for s in specs])[ec]
-    cars = np.array([1 if getattr(s, "car_models", None) is not None else 0 for s in specs])[ec]
-    extra_state = n_ports * users + 4 * n_ports * cars   # user bytes and car rates per port
-    users = np.array([1 if getattr(s, "has_users", False) else 0 for s in specs])[ec]
     n_envs = len(ec)
     env = cx.Env(specs, env_class=ec, seed=seed) if len(specs) > 1 else cx.Env(specs[0], n_envs=n_envs, seed=seed)
     if not args.no_tune:
@@ -172,9 +179,7 @@ def run_rollout_workload(args, name, specs, ec, seed, desc, cpu_stride):
     wall_ms, kernel_ms = timed_rollouts(env, cx, T_DAY, cx.ACT_RANDOM, cx.OUT_FULL, out, args)
     env_steps = n_envs * T_DAY
     value = env_steps / (wall_ms / 1e3)
-    # records (+ user flags, 4 bytes per port; + the two day features) and the state in and out
-    alg_bytes = float(((record_bytes(n_ports, "full", batt) + 4 * n_ports * users + 8 * dayf) * T_DAY
-                       + 2 * (state_bytes(n_ports, batt) + extra_state)).sum())
+    alg_bytes = rollout_bytes(specs, ec, T_DAY, "full")
     achieved = alg_bytes / (kernel_ms / 1e3) / 1e9
     del out
     # records of rewards and done flags only (the same rollout, 5 bytes per env-step)
@@ -193,8 +198,7 @@ def run_rollout_workload(args, name, specs, ec, seed, desc, cpu_stride):
                         "traffic": measured_traffic() if name.startswith("uneven") else None,
                         "kernel": "k_rollout", "kernel_ms": kernel_ms, "algorithmic_bytes": alg_bytes}
     line["reward_only"] = {"env_steps_per_s": env_steps / (r_wall / 1e3), "kernel_ms": r_kernel,
-                           "algorithmic_bytes": float((record_bytes(n_ports, "reward") * T_DAY
-                                                       + 2 * (state_bytes(n_ports, batt) + extra_state)).sum())}
+                           "algorithmic_bytes": rollout_bytes(specs, ec, T_DAY, "reward")}
     line["plain"] = plain
     line["speedup_vs_plain"] = (value / plain["env_steps_per_s"]) if plain else None
     line["cpu_baseline"] = cpu
@@ -271,7 +275,7 @@ def run_policy(args):
     step_ms = time_events(lambda: env.step(cx.ACT_EXTERNAL, act.view(-1), out=out1), 10, env.stream)
     flops = 2.0 * E * (dim * H + H * N * (spec.n_levels + 1))
     achieved = flops / (pol_ms / 1e3) / 1e12
-    step_bytes = float(E * (2 * state_bytes(np.array([N]))[0] + N + 4 * dim + 4 + 1))
+    step_bytes = rollout_bytes([spec], np.zeros(E, np.int64), 1, "full")
     cpu = None
     if not args.no_cpu:
         cpu = policy_oracle_baseline(spec, H, weights, seed)
@@ -386,8 +390,8 @@ def run_serve(args):
     wall, st, lat, wq = serve(stream, True)
     srv.close()
     env_steps = sum(r.n_envs * r.horizon for r in stream)
-    rec = {c: record_bytes(np.array([classes[c].n_ports]))[0] for c in range(len(classes))}
-    alg = float(sum(r.n_envs * (r.horizon * rec[r.class_index] + 2 * state_bytes(np.array([classes[r.class_index].n_ports]))[0])
+    rec = {c: record_bytes(classes[c]) for c in range(len(classes))}
+    alg = float(sum(r.n_envs * (r.horizon * rec[r.class_index] + 2 * state_bytes(classes[r.class_index]))
                     for r in stream))
     value = env_steps / wall
     line = base_line("env-steps/s (continuous-batching server, Poisson request stream)", value, "env-steps/s",

@@ -196,3 +196,25 @@ def test_invalid_arguments_raise(cxm):
         env.set_packing(0, 128, 4)                # more lanes than slots
     with pytest.raises(cxm.CxError):
         cxm.Env(W.tiny_parity_station().replace(tau=2.0), n_envs=4)
+
+
+@pytest.mark.parametrize("kind", ["charging", "extended"])
+def test_largest_station(cxm, oracle_lib, kind):
+    """256 ports (the most slots a station may have: 64 lanes x 4 slots), a
+    four-level tree, busy arrivals; charging-only and with V2G, a battery,
+    charge-sensitive users, price days and car models."""
+    o = oracle_lib
+    spec = W.fanout4_tree(256, 4, factor=0.6).replace(arrival_peak=6.0, alpha_sat=0.1)
+    if kind == "extended":
+        spec = spec.replace(v2g=1, battery_kwh=300.0, battery_kw=100.0, charge_sensitive_share=0.4,
+                            alpha_sat1=0.1, beta_sat1=0.3, price_days=W.price_day_table(5),
+                            car_models=W.car_mix("us"), port_dc=[1, 0] * 128)
+    ec = np.zeros(11, np.int32)
+    env = cxm.Env(spec, n_envs=len(ec), seed=81)
+    assert env.class_info(0).slots == 256 and env.class_info(0).lanes_per_station == 64
+    bs = o.BatchState([o.OracleClass(spec)], ec)
+    g = PY.to_np(env.rollout(300, cxm.ACT_RANDOM, cxm.OUT_FULL))
+    r = o.rollout(bs, 81, 300)
+    flips, keep = PY.compare_rollout_flips(o, g, r, [spec], ec, 81)
+    assert len(flips) <= 1
+    PY.compare_state(env.state_arrays(), bs, [spec], ec, keep=keep)
