@@ -109,6 +109,7 @@ size_t class_block(const SpecCopy &sc, const Compiled &k, const Tables &t, unsig
   d.day_obs = k.day_obs;
   d.inv_n_days = k.n_days > 0 ? (float)(1.0 / k.n_days) : 0.f;
   d.n_models = k.n_models;
+  d.dense_nodes = k.dense_nodes;
   d.pmax_u = k.slot_pmax[0];
   d.inv_pmax_u = k.slot_inv_pmax[0];
   d.slot_port = reinterpret_cast<const int32_t *>(base + o_port);

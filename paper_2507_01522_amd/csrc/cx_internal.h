@@ -56,7 +56,8 @@ struct ClassDev {
   const float *slot_pmax;      // [S]
   const float *slot_inv_pmax;  // [S]
   const float *slot_inv_eta;   // [S]
-  const uint32_t *slot_lb;     // [S]: log2 block size per level, 8 bits each, level 0 = deepest
+  const uint32_t *slot_lb;     // [S]: per level (8 bits, level 0 = deepest) the log2 block size, or
+                               // 0x80 | node for a dense level (0: no node of the level covers the slot)
   const float *slot_cap;       // [D][S]: eta_H * I_H of the level's node holding the slot (+inf if none)
   const uint32_t *tpois;       // [steps_ep][32]
   const uint32_t *tdwell;      // [1 << dwell_log2]: thresholds for stays of 2, 3, ... steps
@@ -81,6 +82,8 @@ struct ClassDev {
   float inv_n_days;            // exploring starts: 1 / n_days
   int32_t n_days, day_obs;     // price days (0: none) and the observation offset of the day features
   int32_t n_models;            // car models (0: none)
+  uint32_t dense_nodes;        // dense layout: per level below the root (8 bits) its node count; 0 = aligned
+  int32_t pad_dn;
   const float *price_days;     // [n_days][steps_ep]
   const uint32_t *model_thresh;// [8]: model = #{m < n_models : w > model_thresh[m]}
   const float *model_data;     // [8][3]: capacity, AC rate, DC rate

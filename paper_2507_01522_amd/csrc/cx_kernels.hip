@@ -395,7 +395,25 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
       if (d < D - 1) {
         float s[P];
         const int lbu = (int)((C.lvl_lb_uniform >> (8 * d)) & 0xFF);
-        if (SIMPLE || lbu != 0xFF) {  // every slot of the level sits in a block of 2^lbu slots
+        const int nd = SIMPLE ? 0 : (int)((C.dense_nodes >> (8 * d)) & 0xFF);
+        if (nd != 0) {
+          // dense layout: at most 4 nodes on this level, each summed over the
+          // whole station from the slots it covers
+#pragma unroll
+          for (int j = 0; j < P; ++j) s[j] = 0.f;
+#pragma unroll
+          for (int m = 0; m < 4; ++m) {
+            if (m < nd) {
+              const uint32_t code = 0x80u | (uint32_t)m;
+              float acc = 0.f;
+#pragma unroll
+              for (int j = 0; j < P; ++j) acc += ((lbp[j] >> (8 * d)) & 0xFFu) == code ? pw[j] : 0.f;
+              acc = station_sum<L>(acc);
+#pragma unroll
+              for (int j = 0; j < P; ++j) s[j] = ((lbp[j] >> (8 * d)) & 0xFFu) == code ? acc : s[j];
+            }
+          }
+        } else if (SIMPLE || lbu != 0xFF) {  // every slot of the level sits in a block of 2^lbu slots
 #pragma unroll
           for (int j = 0; j < P; ++j) s[j] = block_sum_lanes<L>(pw[j], lbu);
         } else {
@@ -403,15 +421,16 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
           for (int j = 0; j < P; ++j) s[j] = block_sum_lanes<L>(pw[j], (int)((lbp[j] >> (8 * d)) & 0xFF));
         }
         // blocks wider than a row of L slots span whole registers: add across them
+        // (aligned layout only: a dense level's sums are already station-wide)
         if constexpr (P >= 2) {
-          const int lb0 = (int)((lbp[0] >> (8 * d)) & 0xFF);
+          const int lb0 = nd != 0 ? 0 : (int)((lbp[0] >> (8 * d)) & 0xFF);
           if (lb0 > LOGL) {
             const float a = s[0] + s[1];
             s[0] = a;
             s[1] = a;
           }
           if constexpr (P == 4) {
-            const int lb2 = (int)((lbp[2] >> (8 * d)) & 0xFF);
+            const int lb2 = nd != 0 ? 0 : (int)((lbp[2] >> (8 * d)) & 0xFF);
             if (lb2 > LOGL) {
               const float a = s[2] + s[3];
               s[2] = a;

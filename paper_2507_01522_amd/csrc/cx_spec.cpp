@@ -189,35 +189,70 @@ bool compile_spec(const SpecCopy &sc, Compiled *c, std::string *err) {
     }
     size[h] = next_pow2(std::max(cur, 1));
   }
-  const int S = std::max(4, size[0]);
+  // dense layout when the aligned one pads and every level below the root has
+  // at most 4 nodes
+  const int S_aligned = std::max(4, size[0]);
+  const int S_dense = std::max(4, next_pow2(N));
+  std::vector<int> level_nodes(kMaxLevels, 0);
+  for (int h = 1; h < H; ++h) level_nodes[(D - 1) - depth[h]] += 1;
+  bool few = true;
+  for (int d = 0; d + 1 < D; ++d) few = few && level_nodes[d] <= 4;
+  const bool dense = few && S_dense < S_aligned;
+  const int S = dense ? S_dense : S_aligned;
   if (S > kMaxSlots) return fail(err, "aligned slot layout exceeds 256 slots");
   c->N = N; c->S = S; c->D = D;
   c->slot_port.assign(S, -1);
   c->slot_lb.assign(S, 0u);
   c->slot_cap.assign((size_t)D * S, std::numeric_limits<float>::infinity());
   c->port_slot.assign(N, -1);
-  std::function<void(int, int)> place = [&](int h, int base) {
-    const int d = (D - 1) - depth[h];            // level 0 = deepest
-    const int blk = h == 0 ? S : size[h];
-    const float capv = (float)(sc.node_eta[h] * sc.node_limit[h]);
-    for (int x = base; x < base + blk; ++x) {
-      c->slot_lb[x] = (c->slot_lb[x] & ~(0xFFu << (8 * d))) | ((uint32_t)ilog2(blk) << (8 * d));
-      c->slot_cap[(size_t)d * S + x] = capv;
+  c->dense_nodes = 0;
+  if (dense) {
+    for (int i = 0; i < N; ++i) {
+      c->slot_port[i] = i;
+      c->port_slot[i] = i;
     }
-    int cur = 0;
-    for (const Child &k : kids[h]) {
-      const int cs = k.is_port ? 1 : size[k.id];
-      cur = (cur + cs - 1) / cs * cs;
-      if (k.is_port) {
-        c->slot_port[base + cur] = k.id;
-        c->port_slot[k.id] = base + cur;
-      } else {
-        place(k.id, base + cur);
+    std::vector<int> rank(kMaxLevels, 0);
+    for (int h = 0; h < H; ++h) {
+      const int d = (D - 1) - depth[h];
+      const float capv = (float)(sc.node_eta[h] * sc.node_limit[h]);
+      if (h == 0) {  // the root covers the whole station
+        for (int x = 0; x < S; ++x) {
+          c->slot_lb[x] |= (uint32_t)ilog2(S) << (8 * d);
+          c->slot_cap[(size_t)d * S + x] = capv;
+        }
+        continue;
       }
-      cur += cs;
+      const uint32_t code = 0x80u | (uint32_t)rank[d]++;
+      for (int x = lo[h]; x <= hi[h]; ++x) {
+        c->slot_lb[x] |= code << (8 * d);
+        c->slot_cap[(size_t)d * S + x] = capv;
+      }
     }
-  };
-  place(0, 0);
+    for (int d = 0; d + 1 < D; ++d) c->dense_nodes |= (uint32_t)level_nodes[d] << (8 * d);
+  } else {
+    std::function<void(int, int)> place = [&](int h, int base) {
+      const int d = (D - 1) - depth[h];            // level 0 = deepest
+      const int blk = h == 0 ? S : size[h];
+      const float capv = (float)(sc.node_eta[h] * sc.node_limit[h]);
+      for (int x = base; x < base + blk; ++x) {
+        c->slot_lb[x] = (c->slot_lb[x] & ~(0xFFu << (8 * d))) | ((uint32_t)ilog2(blk) << (8 * d));
+        c->slot_cap[(size_t)d * S + x] = capv;
+      }
+      int cur = 0;
+      for (const Child &k : kids[h]) {
+        const int cs = k.is_port ? 1 : size[k.id];
+        cur = (cur + cs - 1) / cs * cs;
+        if (k.is_port) {
+          c->slot_port[base + cur] = k.id;
+          c->port_slot[k.id] = base + cur;
+        } else {
+          place(k.id, base + cur);
+        }
+        cur += cs;
+      }
+    };
+    place(0, 0);
+  }
   c->slot_pmax.assign(S, 0.f);
   c->slot_inv_pmax.assign(S, 0.f);
   c->slot_inv_eta.assign(S, 1.f);

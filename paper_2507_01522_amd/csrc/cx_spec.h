@@ -20,15 +20,21 @@ struct SpecCopy {
   std::vector<int32_t> port_dc;                   // [n_ports] (all 0 if not given)
 };
 
-// The capacity tree in the kernels' layout.  Every node owns an aligned block of
-// 2^b slots; children are placed in port order, each aligned to its own block
-// size, so the slot order of ports equals their port order.  Level 0 is the
-// deepest node level, level D-1 the root.
+// The capacity tree in the kernels' layout.  Aligned layout: every node owns an
+// aligned block of 2^b slots; children are placed in port order, each aligned to
+// its own block size, so the slot order of ports equals their port order and a
+// subtree sum is a butterfly over its block.  Dense layout (chosen when the
+// aligned one would pad and every level below the root has at most 4 nodes):
+// port i sits in slot i, and a slot's 8-bit level field holds 0x80 | m for the
+// level's node m that covers it (0 if none); each node's sum is then a station
+// sum of the slots it covers.  Level 0 is the deepest node level, level D-1 the
+// root.
 struct Compiled {
   int N = 0, S = 0, D = 0;
   std::vector<int32_t> slot_port;   // [S], -1 = padding
   std::vector<int32_t> port_slot;   // [N]
-  std::vector<uint32_t> slot_lb;    // [S], 8 bits per level
+  std::vector<uint32_t> slot_lb;    // [S], 8 bits per level: log2 block size (aligned) or 0x80 | node (dense)
+  uint32_t dense_nodes = 0;         // dense layout: nodes per level below the root (8 bits each), 0 = aligned
   std::vector<float> slot_cap;      // [D][S]
   std::vector<float> slot_pmax, slot_inv_pmax, slot_inv_eta;
   std::vector<float> slot_pdis, slot_eta;  // discharge maxima and efficiencies (V2G)

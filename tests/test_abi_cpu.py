@@ -85,17 +85,39 @@ def test_layout_is_aligned_and_order_preserving(cxm, spec):
         slots = [slot_of[i] for i in leaves_of(spec, h)]
         lb = (lay["slot_lb"][slots] >> (8 * lvl)) & 0xFF
         assert len(set(lb.tolist())) == 1
+        if h > 0 and lb[0] & 0x80:                                 # dense level: node code, exact cover
+            cover = np.flatnonzero(((lay["slot_lb"] >> (8 * lvl)) & 0xFF) == lb[0])
+            assert sorted(cover.tolist()) == sorted(slots)
+            assert np.allclose(lay["slot_cap"][lvl, slots], spec.node_limit_kw[h] * spec.node_eta[h])
+            continue
         B = 1 << int(lb[0])
         base = min(slots) // B * B
         assert max(slots) < base + B                               # one aligned block holds the subtree
         assert np.allclose(lay["slot_cap"][lvl, base:base + B], spec.node_limit_kw[h] * spec.node_eta[h])
 
 
-def test_uneven_tree_is_padded(cxm):
-    lay = cxm.compile_layout(W.two_charger_types())                 # 10 DC + 6 AC ports
-    assert lay["slots"] == 32 and lay["levels"] == 2
-    assert list(lay["slot_port"][:16]) == list(range(10)) + [-1] * 6
-    assert list(lay["slot_port"][16:24]) == list(range(10, 16)) + [-1] * 2
+def test_uneven_tree_layouts(cxm):
+    """A tree whose aligned layout would pad takes the dense layout when each
+    level below the root has at most 4 nodes; otherwise it is padded."""
+    lay = cxm.compile_layout(W.two_charger_types())                 # 10 DC + 6 AC ports: dense, 16 slots
+    assert lay["slots"] == 16 and lay["levels"] == 2
+    assert list(lay["slot_port"]) == list(range(16))
+    lvl0 = lay["slot_lb"] & 0xFF
+    assert list(lvl0) == [0x80] * 10 + [0x81] * 6
+    assert list(lay["slot_cap"][0]) == [800.0] * 10 + [50.0] * 6
+    # five splitters of 3 ports: more than 4 nodes on a level, so the aligned layout pads (4 per block)
+    five = W.splitter_tree(5, 3, 30.0, 100.0)
+    lay = cxm.compile_layout(five)
+    assert lay["slots"] == 32 and not (lay["slot_lb"] & 0x80).any()
+    assert list(lay["slot_port"][:8]) == [0, 1, 2, -1, 3, 4, 5, -1]
+    # 4 + 3 ports: the aligned layout does not pad (8 slots), so it stays aligned
+    lay = cxm.compile_layout(W.StationSpec(7, [-1, 0, 0], [50.0, 30.0, 30.0], [1.0] * 3, [1] * 4 + [2] * 3,
+                                           [22.0] * 7, [1.0] * 7))
+    assert lay["slots"] == 8 and not (lay["slot_lb"] & 0x80).any()
+    # 5 + 2 ports: aligned would take 16 slots; dense takes 8, the padding slot covered by no node
+    lay = cxm.compile_layout(W.StationSpec(7, [-1, 0, 0], [50.0, 30.0, 30.0], [1.0] * 3, [1] * 5 + [2] * 2,
+                                           [22.0] * 7, [1.0] * 7))
+    assert lay["slots"] == 8 and list(lay["slot_lb"] & 0xFF) == [0x80] * 5 + [0x81] * 2 + [0]
 
 
 BAD = [

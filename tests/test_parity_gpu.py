@@ -218,3 +218,33 @@ def test_largest_station(cxm, oracle_lib, kind):
     flips, keep = PY.compare_rollout_flips(o, g, r, [spec], ec, 81)
     assert len(flips) <= 1
     PY.compare_state(env.state_arrays(), bs, [spec], ec, keep=keep)
+
+
+def dense_specs():
+    """Trees that take the dense layout: the paper's default 10 DC + 6 AC station,
+    5 + 2 ports, and a three-level tree (root -> [A -> (4, 3) ports, B -> 9 ports])."""
+    three = W.StationSpec(16, [-1, 0, 0, 1, 1, 2], [120.0, 60.0, 90.0, 40.0, 30.0, 80.0], [1.0, 0.98, 1.0, 1.0, 0.95, 1.0],
+                          [3] * 4 + [4] * 3 + [5] * 9, [22.0] * 16, [1.0] * 16, arrival_peak=1.5, name="dense3")
+    return [W.two_charger_types().replace(arrival_peak=1.5, alpha_sat=0.1),
+            W.StationSpec(7, [-1, 0, 0], [50.0, 30.0, 30.0], [1.0] * 3, [1] * 5 + [2] * 2, [22.0] * 7, [1.0] * 7,
+                          arrival_peak=0.8, name="dense5p2"),
+            three]
+
+
+@pytest.mark.parametrize("lanes", [4, 8, 16])
+def test_dense_layouts(cxm, oracle_lib, lanes):
+    specs = dense_specs()
+    for s in specs:
+        lay = cxm.compile_layout(s)
+        assert (lay["slot_lb"] & 0x80).any() and lay["slots"] == (8 if s.n_ports == 7 else 16)
+    ec = np.repeat(np.arange(3, dtype=np.int32), [19, 13, 17])
+    L = [min(lanes, cxm.compile_layout(s)["slots"]) for s in specs]
+    for wpb in (1, 4):
+        env, bs, g, r = run_both(cxm, oracle_lib, specs, ec, 91, 300, cxm.ACT_RANDOM, lanes=L, wpb=wpb)
+        PY.compare_rollout(g, r, specs, ec)
+        PY.compare_state(env.state_arrays(), bs, specs, ec)
+    # the same trees as V2G classes (the extended kernels take the dense path too)
+    vspecs = [s.replace(v2g=1, name=s.name + "_v2g") for s in specs]
+    env, bs, g, r = run_both(cxm, oracle_lib, vspecs, ec, 92, 300, cxm.ACT_RANDOM, lanes=L)
+    PY.compare_rollout(g, r, vspecs, ec)
+    PY.compare_state(env.state_arrays(), bs, vspecs, ec)
