@@ -248,3 +248,29 @@ def test_dense_layouts(cxm, oracle_lib, lanes):
     env, bs, g, r = run_both(cxm, oracle_lib, vspecs, ec, 92, 300, cxm.ACT_RANDOM, lanes=L)
     PY.compare_rollout(g, r, vspecs, ec)
     PY.compare_state(env.state_arrays(), bs, vspecs, ec)
+
+
+def test_class_split_into_segments(cxm, oracle_lib):
+    """1,100,000 stations of 256 ports: one step's observation block (6.8 GB) is
+    beyond the kernels' 32-bit per-lane offsets, so the class runs as two
+    segments; stations on both sides of the cut and at the ends match the
+    oracle."""
+    o = oracle_lib
+    spec = W.fanout4_tree(256, 3).replace(arrival_peak=6.0)
+    n, T, seed = 1_100_000, 2, 83
+    chunk = ((1 << 32) - 1) // (4 * spec.obs_dim)
+    chunk -= chunk % 64
+    assert chunk < n
+    env = cxm.Env(spec, n_envs=n, seed=seed)
+    out = env.rollout(T, cxm.ACT_RANDOM)
+    ids = np.array([0, 1, chunk - 2, chunk - 1, chunk, chunk + 1, n - 2, n - 1], np.int64)
+    acols = (ids[:, None] * spec.n_actions + np.arange(spec.n_actions)).ravel()
+    ocols = (ids[:, None] * spec.obs_dim + np.arange(spec.obs_dim)).ravel()
+    g = {"actions": out["actions"][:, torch.from_numpy(acols).cuda()].cpu().numpy(),
+         "reward": out["reward"][:, torch.from_numpy(ids).cuda()].cpu().numpy(),
+         "done": out["done"][:, torch.from_numpy(ids).cuda()].cpu().numpy(),
+         "obs": out["obs"][:, torch.from_numpy(ocols).cuda()].cpu().numpy()}
+    del out
+    ec = np.zeros(len(ids), np.int32)
+    bs = o.BatchState([o.OracleClass(spec)], ec, env_ids=ids)
+    PY.compare_rollout(g, o.rollout(bs, seed, T), [spec], ec)

@@ -82,6 +82,10 @@ def test_never_fits_and_invalid(cxm):
         assert e.value.status == -1
     with pytest.raises(cxm.CxError):
         s.submit(spec, 4, 4, 1, cxm.OUT_FULL, act_mode=cxm.ACT_POLICY)
+    big = W.fanout4_tree(256, 3)                       # 700,000 x 1540 obs floats: past 2^32 bytes per step
+    with pytest.raises(cxm.CxError) as e:
+        s.submit(big, 700_000, 4, 1, cxm.OUT_FULL)
+    assert e.value.status == -1
     bad_spec = W.single_transformer(8)
     bad_spec.node_limit_kw = np.array([-1.0])
     with pytest.raises(cxm.CxError):
