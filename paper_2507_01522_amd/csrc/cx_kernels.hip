@@ -12,13 +12,15 @@
 //   apply actions    (clip by port max, charge curve, battery room)
 //   projection       (Eq. ArchConst, deepest level first, butterfly sums over
 //                     aligned power-of-two slot blocks: DPP inside a row,
-//                     ds_swizzle / bpermute across rows, adds across registers)
+//                     permlane swaps across rows, adds across registers; in the
+//                     dense layout, one station-wide sum per node of a level)
 //   charge, departures, arrivals (ballot + popcount ranks), reward, day end,
 //   records.
-// Bidirectional classes (V2G ports, a station battery) run their own kernels:
-// signed levels, the mirrored discharge curve, two-sided limits, the split of
-// the grid energy, and the battery as one FP64 scalar per station that every
-// lane of the station updates alike.
+// Extended classes run their own kernels: V2G ports (signed levels, the
+// mirrored discharge curve, two-sided limits, the split of the grid energy),
+// a station battery (one FP64 scalar per station that every lane of the station
+// updates alike), charge-sensitive users, per-episode price days and car
+// models with AC / DC rates.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -156,22 +158,23 @@ __device__ __forceinline__ T ld_at(const T *base, uint32_t byte_off) {
 // port maximum and efficiency, and per tree level one block size and one limit.
 // Port indices and record offsets are then compile-time constants and every
 // per-slot constant is wave-uniform (scalar registers).
-// EXT: V2G ports and / or a station battery (never SIMPLE).
+// EXT: V2G ports, a station battery, charge-sensitive users, price days and / or
+// car models (never SIMPLE); each switched on per class by a uniform flag.
 template <int L, int P, bool SIMPLE, bool EXT>
 __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int group, const uint32_t *tdw,
                                           bool tdw_lds) {
   constexpr int SPW = 64 / L;
   constexpr int LOGL = (L == 4) ? 2 : (L == 8) ? 3 : (L == 16) ? 4 : (L == 32) ? 5 : 6;
-  constexpr bool DENSE = SIMPLE;
+  constexpr bool NOPAD = SIMPLE;  // every slot holds a port: slot s = port s
   const ClassDev C = *sg.cls;  // by value: scalar loads once, kept in SGPRs
   const int lane = __lane_id();
   const int l = lane & (L - 1);
   const int sbase = lane & ~(L - 1);
   const int env = group * SPW + (lane >> LOGL);     // env index inside the segment
   const bool active = env < sg.n_envs;
-  const int S = DENSE ? L * P : C.S;
+  const int S = NOPAD ? L * P : C.S;
   const int D = C.D;
-  const int N = DENSE ? L * P : C.n_ports;
+  const int N = NOPAD ? L * P : C.n_ports;
   const int obs_dim = EXT ? C.obs_dim : 6 * N + 4;
   const int n_act = EXT ? C.n_act : N;      // action bytes per env
   const int n_neg = EXT ? C.n_neg : 0;      // discharge levels of a port
@@ -190,7 +193,7 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
 #pragma unroll
   for (int j = 0; j < P; ++j) {
     const int s = j * L + l;
-    port[j] = DENSE ? s : gld(C.slot_port, s);
+    port[j] = NOPAD ? s : gld(C.slot_port, s);
     if constexpr (SIMPLE) {
       pmax[j] = C.pmax_u;
       inv_pmax[j] = C.inv_pmax_u;
@@ -573,7 +576,7 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
     int n_free = 0;
 #pragma unroll
     for (int j = 0; j < P; ++j) {
-      fr[j] = (EXT ? !CX_OCCUPIED(j) : dw[j] == 0) && (DENSE || port[j] >= 0);
+      fr[j] = (EXT ? !CX_OCCUPIED(j) : dw[j] == 0) && (NOPAD || port[j] >= 0);
       const uint64_t m = __ballot(fr[j]) & smask;
       cnt[j] = __popcll(m);
       below[j] = __popcll(m & below_mask);
@@ -671,7 +674,7 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
         float *ob = ob_t;
 #pragma unroll
         for (int j = 0; j < P; ++j) {
-          if (DENSE || port[j] >= 0) {
+          if (NOPAD || port[j] >= 0) {
             const bool occ = CX_OCCUPIED(j);
             const uint32_t o = obs_bo + 4u * (uint32_t)port[j];
             st_at(ob, o + 0u * 4u * N, occ ? 1.0f : 0.0f);
@@ -709,7 +712,7 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
         uint8_t *ab = ab_t;
 #pragma unroll
         for (int j = 0; j < P; ++j)
-          if (DENSE || port[j] >= 0) st_at(ab, act_bo + (uint32_t)port[j], (uint8_t)k[j]);
+          if (NOPAD || port[j] >= 0) st_at(ab, act_bo + (uint32_t)port[j], (uint8_t)k[j]);
         if constexpr (EXT) {
           if (batt && l == 0) st_at(ab, act_bo + (uint32_t)N, (uint8_t)kb);
         }
