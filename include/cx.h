@@ -306,12 +306,22 @@ cx_status cx_get_tables(const cx_ctx *ctx, int32_t cls, uint32_t *tpois_host, ui
 
 /* Packing of class cls: lanes per station (a power of two, 4..64, dividing or
  * equal to the padded slot count / 1, 2 or 4 slots per lane) and waves per
- * block (1..16).  Results do not depend on it beyond FP32 rounding order. */
+ * block (1..8).  Results do not depend on it beyond FP32 rounding order. */
 cx_status cx_set_packing(cx_ctx *ctx, int32_t cls, int32_t lanes_per_station, int32_t waves_per_block);
 
+/* on = 1: classes without padding slots, with one port maximum and efficiency
+ * and one block size per tree level, packed at up to 32 lanes per station,
+ * write their observation records through an LDS stage of each block, as
+ * 16-byte stores of whole record runs; on = 0 (the default): every lane stores
+ * its own values.  The records are bit for bit the same either way; which is
+ * faster depends on the launch (cx_autotune chooses).  CX_E_INVALID unless on
+ * is 0 or 1. */
+cx_status cx_set_obs_stage(cx_ctx *ctx, int32_t on);
+
 /* Time every legal packing of every class on a T_probe-step rollout (state is
- * saved and restored) and keep the fastest.  cache_path (nullable) is a JSON
- * file of earlier results keyed by class shape, read first and updated. */
+ * saved and restored) and keep the fastest, then the waves per block and the
+ * observation stage (cx_set_obs_stage) likewise.  cache_path (nullable) is a
+ * JSON file of earlier results keyed by class shape, read first and updated. */
 cx_status cx_autotune(cx_ctx *ctx, int32_t T_probe, const char *cache_path);
 
 cx_status cx_synchronize(cx_ctx *ctx);

@@ -196,14 +196,23 @@ void build_groups(const std::vector<SegDev> &in, const std::vector<int> &log2_dw
     g.pack = kd / kNumKinds;
     g.kind = kd % kNumKinds;
     g.seg_begin = (int)out->size();
+    for (size_t i = 0; i < in.size(); ++i) {
+      if (kNumKinds * in[i].pack + kind[i] != kd) continue;
+      g.max_dwell_log2 = std::max(g.max_dwell_log2, log2_dwell[i]);
+      g.max_T = std::max(g.max_T, in[i].T);
+      g.max_obs_dim = std::max(g.max_obs_dim, in[i].obs_dim);
+    }
+    // fewer waves per block where the observation stages would not fit
+    g.wpb = wpb;
+    while (group_stages(g.kind, g.pack) && g.wpb > 1 &&
+           group_lds_bytes(g.wpb, g.pack, g.max_obs_dim, g.max_dwell_log2, nullptr, nullptr) > kMaxBlockLds)
+      g.wpb >>= 1;
     int blocks = 0;
     for (size_t i = 0; i < in.size(); ++i) {
       if (kNumKinds * in[i].pack + kind[i] != kd) continue;
       SegDev sg = in[i];
       sg.block_begin = blocks;
-      blocks += (sg.n_groups + wpb - 1) / wpb;
-      g.max_dwell_log2 = std::max(g.max_dwell_log2, log2_dwell[i]);
-      g.max_T = std::max(g.max_T, sg.T);
+      blocks += (sg.n_groups + g.wpb - 1) / g.wpb;
       out->push_back(sg);
     }
     g.n_segs = (int)out->size() - g.seg_begin;
@@ -233,6 +242,7 @@ cx_status rebuild_segments(cx_ctx *ctx) {
       sg.n_envs = n;
       sg.n_groups = (int32_t)((n + spw - 1) / spw);
       sg.pack = pack_id(L, P);
+      sg.obs_dim = c.comp.obs_dim;
       sg.seed = ctx->seed;
       const int64_t so = c.slot_off + e0 * c.comp.S;
       sg.q = ctx->q + so;
@@ -250,7 +260,7 @@ cx_status rebuild_segments(cx_ctx *ctx) {
       sg.env_off = c.env_begin + e0;
       segs.push_back(sg);
       dl.push_back(c.tab.dwell_log2);
-      kind.push_back(c.host_view.kind);
+      kind.push_back(c.host_view.kind == kKindSimple && ctx->stage_obs ? kKindSimpleStaged : c.host_view.kind);
     }
   }
   build_groups(segs, dl, kind, ctx->wpb, &ctx->segs_host, &ctx->groups);
@@ -511,7 +521,7 @@ cx_status cx_step_ex(cx_ctx *ctx, cx_action_mode mode, const uint8_t *actions_in
   if (out) {
     a.obs = out->obs; a.act = out->actions; a.reward = out->reward; a.done = out->done;
   }
-  hipError_t e = launch_groups(a, ctx->groups.data(), (int)ctx->groups.size(), ctx->wpb, ctx->stream);
+  hipError_t e = launch_groups(a, ctx->groups.data(), (int)ctx->groups.size(), ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "cx_step launch");
   advance_clock(ctx, 1);
   return CX_OK;
@@ -543,8 +553,7 @@ cx_status cx_rollout(cx_ctx *ctx, int32_t T, cx_action_mode mode, cx_out_mode ou
     a.reward = out->reward;
     a.done = out->done;
   }
-  hipError_t e = graph_rollout(ctx->graph, a, ctx->groups.data(), (int)ctx->groups.size(), ctx->wpb,
-                               ctx->stream);
+  hipError_t e = graph_rollout(ctx->graph, a, ctx->groups.data(), (int)ctx->groups.size(), ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "cx_rollout graph launch");
   advance_clock(ctx, T);
   return CX_OK;
@@ -567,6 +576,13 @@ cx_status cx_set_packing(cx_ctx *ctx, int32_t cls, int32_t lanes_per_station, in
   if (waves_per_block < 1 || waves_per_block > kMaxWaves) return fail_status(CX_E_INVALID, "waves_per_block must be in 1..8");
   ctx->classes[cls].lanes = lanes_per_station;
   ctx->wpb = waves_per_block;
+  return rebuild_segments(ctx);
+}
+
+cx_status cx_set_obs_stage(cx_ctx *ctx, int32_t on) {
+  CTX_CHECK(ctx);
+  if (on != 0 && on != 1) return fail_status(CX_E_INVALID, "on must be 0 or 1");
+  ctx->stage_obs = on != 0;
   return rebuild_segments(ctx);
 }
 

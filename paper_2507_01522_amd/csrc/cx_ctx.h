@@ -52,6 +52,9 @@ struct cx_ctx {
   std::vector<cx::SegDev> segs_host;
   std::vector<cx::LaunchGroup> groups;
   int wpb = 4;
+  // SIMPLE classes of up to 32 lanes per station write their observations
+  // through an LDS stage (cx_set_obs_stage / cx_autotune)
+  bool stage_obs = false;
   bool failed = false;
   int64_t device_bytes = 0;
   cx::RolloutGraph graph;

@@ -25,7 +25,9 @@ constexpr int kNumPackings = 15;
 // Kernel kinds per packing: general classes, SIMPLE classes (every per-slot
 // constant uniform), and extended classes (V2G ports, a station battery or
 // charge-sensitive users).
-enum : int { kKindGeneral = 0, kKindSimple = 1, kKindExt = 2, kNumKinds = 3 };
+// kKindSimpleStaged: a SIMPLE class whose observations go through the block's
+// LDS stage (stations of at most 32 lanes; a context option, see stage_obs).
+enum : int { kKindGeneral = 0, kKindSimple = 1, kKindExt = 2, kKindSimpleStaged = 3, kNumKinds = 4 };
 __host__ __device__ constexpr int pack_lanes(int id) { return 4 << (id % 5); }
 __host__ __device__ constexpr int pack_per_lane(int id) { return 1 << (id / 5); }
 inline int pack_id(int lanes, int per_lane) {
@@ -100,7 +102,7 @@ struct SegDev {
   int32_t n_groups;     // waves needed: ceil(n_envs / stations per wave)
   int32_t block_begin;  // first block of this segment in the launch
   int32_t pack;
-  int32_t pad_;
+  int32_t obs_dim;      // floats per env observation (sizes the LDS record stage of its launch)
   uint64_t seed;
   // state, env-major slot layout, at the segment's first env.  A car is kept
   // as q = 1 - SoC (FP64: the per-step increments are accumulated here),
@@ -140,6 +142,10 @@ struct LaunchArgs {
   uint32_t g0;
   int32_t mode, out_mode;
   int32_t lds_tdwell;   // 1: stage the stay thresholds in LDS (set per launch group)
+  // observation records staged in LDS (set per launch group): byte offset of
+  // the two stage buffers in the dynamic LDS and floats per buffer (0: each
+  // lane stores its observation values to HBM itself)
+  int32_t stage_off, stage_floats;
   float *obs;
   uint8_t *act;
   float *reward;
@@ -158,7 +164,38 @@ struct LaunchGroup {
   int n_blocks = 0;
   int max_dwell_log2 = 1;  // largest stay table among its classes (LDS bytes = 4 << this)
   int max_T = 0;           // per-segment launches: the longest horizon among its segments
+  int max_obs_dim = 0;     // largest observation among its classes (floats)
+  int wpb = 1;             // waves per block: the context's choice, halved until the LDS fits
 };
+
+// Packings whose staged kernels write observations through an LDS stage:
+// stations of at most 32 lanes.  A 64-lane station writes 256 contiguous bytes
+// per store already, and its kernels are bound by arithmetic, which the stage
+// adds to.
+__host__ __device__ constexpr bool stage_obs(int lanes) { return lanes <= 32; }
+// Does a launch group stage its observations?
+__host__ __device__ constexpr bool group_stages(int kind, int pack) {
+  return kind == kKindSimpleStaged && stage_obs(pack_lanes(pack));
+}
+
+// LDS a block may take for the stay table and the two observation stages.
+constexpr size_t kMaxBlockLds = 64 << 10;
+
+// LDS layout of a launch group's blocks: the stay table (4 << dwell_log2
+// bytes), then two observation stages of waves x stations per wave x the
+// largest observation floats, plus 3 floats to align them with HBM (rounded to
+// 16 bytes).  Returns the bytes with the stages; *stage_off / *stage_floats:
+// where the stages begin and floats per stage.
+inline size_t group_lds_bytes(int wpb, int pack, int max_obs_dim, int dwell_log2, int32_t *stage_off,
+                              int32_t *stage_floats) {
+  const size_t table = (size_t)4 << dwell_log2;
+  const size_t off = (table + 15) & ~(size_t)15;
+  const size_t floats =
+      ((size_t)wpb * (size_t)(64 / pack_lanes(pack)) * (size_t)max_obs_dim + 3 + 3) & ~(size_t)3;
+  if (stage_off) *stage_off = (int32_t)off;
+  if (stage_floats) *stage_floats = (int32_t)floats;
+  return off + 8 * floats;
+}
 
 // The persistent rollout as a HIP graph with one kernel node per launch group
 // (no dependencies between them), instantiated once per launch shape and
@@ -168,16 +205,14 @@ struct RolloutGraph {
   hipGraphExec_t exec = nullptr;
   hipGraphNode_t node[kNumKinds * kNumPackings] = {};
   int n_nodes = 0;
-  int shape[kNumKinds * kNumPackings][3] = {};
-  int waves = -1;
+  int shape[kNumKinds * kNumPackings][4] = {};  // kernel, blocks, waves per block, LDS bytes
 };
 
 // Host-side launchers (defined in cx_kernels.hip).  `a.segs` is the base of
 // the device segment table; each group launches with its own slice.
-hipError_t launch_groups(const LaunchArgs &a, const LaunchGroup *groups, int n_groups, int waves_per_block,
-                         hipStream_t st);
+hipError_t launch_groups(const LaunchArgs &a, const LaunchGroup *groups, int n_groups, hipStream_t st);
 hipError_t graph_rollout(RolloutGraph &g, const LaunchArgs &a, const LaunchGroup *groups, int n_groups,
-                         int waves_per_block, hipStream_t st);
+                         hipStream_t st);
 void graph_destroy(RolloutGraph &g);
 hipError_t launch_reset_obs_one(const ClassDev *cls_dev, int64_t n_envs, float *obs, uint64_t seed, int64_t env0,
                                 uint32_t g, hipStream_t st);

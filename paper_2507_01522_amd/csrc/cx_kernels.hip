@@ -154,15 +154,50 @@ __device__ __forceinline__ T ld_at(const T *base, uint32_t byte_off) {
   return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + byte_off);
 }
 
+// Observation records staged in LDS (stations of up to 32 lanes).  Per step
+// every lane puts its values in the block's stage (the adjacent envs of the
+// block's waves, in record order); after the step barrier the block's running
+// waves write the stage out as one contiguous run of 16-byte non-temporal
+// stores.  HBM takes such whole-line streams much faster than the 4-byte
+// stores of every lane, which leave lines partly written (for stations of 8
+// lanes, 32 bytes per station and store).
+typedef __attribute__((address_space(3))) float lds_float;
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) f32x4 lds_f32x4;
+
+// Write n staged floats to dst (4-byte aligned).  The stage holds them from
+// float pad = (dst / 4) mod 4 on, so that LDS and HBM agree on 16-byte chunks:
+// the whole chunks go out as one 16-byte buffer store each (a resource over the
+// 16-byte-aligned address dst - pad, offset 16 c for chunk c, non-temporal),
+// the at most 3 floats before the first and after the last whole chunk one by
+// one.  tid / nthreads: this lane among the block's running lanes.
+__device__ __forceinline__ void flush_stage(const lds_float *sb, float *dst, int pad, int n, int tid,
+                                            int nthreads) {
+  const int c_end = (pad + n) >> 2;  // whole chunks: [pad ? 1 : 0, c_end)
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<char *>(dst) - 4 * pad, (short)0, 0x7fffffff, 0x00020000);
+  for (int c = (pad ? 1 : 0) + tid; c < c_end; c += nthreads) {
+    const f32x4 v = *reinterpret_cast<const lds_f32x4 *>(sb + 4 * c);
+    __builtin_amdgcn_raw_buffer_store_b128(v, rs, 16 * c, 0, 2 /* nt */);
+  }
+  if (pad != 0 || ((pad + n) & 3) != 0) {  // the same in every lane
+    const int head = (4 - pad) & 3;         // floats before the first whole chunk
+    if (tid < head && tid < n) dst[tid] = sb[pad + tid];
+    const int i = 4 * c_end - pad + (tid - 4);  // lanes 4..7: the floats after the last whole chunk
+    if (tid >= 4 && tid < 8 && i >= head && i < n) dst[i] = sb[pad + i];
+  }
+}
+
 // SIMPLE: the class has no padding slots (slot s holds port s, N = L * P), one
 // port maximum and efficiency, and per tree level one block size and one limit.
 // Port indices and record offsets are then compile-time constants and every
 // per-slot constant is wave-uniform (scalar registers).
 // EXT: V2G ports, a station battery, charge-sensitive users, price days and / or
 // car models (never SIMPLE); each switched on per class by a uniform flag.
-template <int L, int P, bool SIMPLE, bool EXT>
+template <int L, int P, bool SIMPLE, bool EXT, bool STAGE>
 __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int group, const uint32_t *tdw,
-                                          bool tdw_lds) {
+                                          bool tdw_lds, lds_float *stage, int stage_floats, int g_blk0,
+                                          int n_run) {
   constexpr int SPW = 64 / L;
   constexpr int LOGL = (L == 4) ? 2 : (L == 8) ? 3 : (L == 16) ? 4 : (L == 32) ? 5 : 6;
   constexpr bool NOPAD = SIMPLE;  // every slot holds a port: slot s = port s
@@ -274,7 +309,7 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
   const uint64_t below_mask = (1ull << lane) - 1ull;
 
   // per-lane byte offsets of this env's records inside a step's segment block
-  const uint32_t obs_bo = (uint32_t)env * (uint32_t)obs_dim * 4u;
+  const uint32_t obs_bo = STAGE ? 0u : (uint32_t)env * (uint32_t)obs_dim * 4u;
   const uint32_t act_bo = (uint32_t)env * (uint32_t)n_act;
   const uint32_t env_bo = (uint32_t)env;
   // wave-uniform record pointers of the current step, advanced every step
@@ -289,6 +324,13 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
   const int64_t obs_step = w_obs ? dy.obs_stride : 0;
   const int64_t act_step = (w_act || ai_t) ? dy.act_stride : 0;
   const int64_t env_step = (rw_t || dn_t) ? dy.env_stride : 0;
+  // the block's LDS observation stage (staging packings, whenever observations
+  // are written): the block's first env, the floats the block writes per step
+  // and this lane's env in the stage
+  const int env_blk0 = g_blk0 * SPW;
+  const int64_t blk_envs = sg.n_envs - env_blk0 < (int64_t)n_run * SPW ? sg.n_envs - env_blk0 : (int64_t)n_run * SPW;
+  const int n_blk = (int)blk_envs * obs_dim;
+  const uint32_t stage_bo = (uint32_t)(env - env_blk0) * (uint32_t)obs_dim * 4u;
 
   for (int t = 0; t < dy.T; ++t, ++g) {
     // ---- exogenous draws for the next L steps, lane l -> step t + l: the
@@ -668,44 +710,56 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
       }
     }
 
-    // ---- records
+    // ---- records: an env's observation (byte offsets o inside its record)
+    // goes to the block's LDS stage, or (wide stations) straight to HBM
+    float *const ob_now = ob_t;  // this step's observation block of the segment
+    const int pad =
+        STAGE && w_obs ? (int)((reinterpret_cast<uintptr_t>(ob_now + (int64_t)env_blk0 * obs_dim) >> 2) & 3u) : 0;
     if (active) {
       if (w_obs) {
-        float *ob = ob_t;
+        auto obs_record = [&](auto put) {
 #pragma unroll
-        for (int j = 0; j < P; ++j) {
-          if (NOPAD || port[j] >= 0) {
-            const bool occ = CX_OCCUPIED(j);
-            const uint32_t o = obs_bo + 4u * (uint32_t)port[j];
-            st_at(ob, o + 0u * 4u * N, occ ? 1.0f : 0.0f);
-            st_at(ob, o + 1u * 4u * N, occ ? 1.0f - qf[j] : 0.0f);
-            st_at(ob, o + 2u * 4u * N, occ ? qf[j] - u[j] : 0.0f);
-            st_at(ob, o + 3u * 4u * N, (float)dw[j] * C.inv_steps_ep);
-            float rh = fminf(1.0f, qf[j] * C.inv_1mtau);
-            if constexpr (EXT) {
-              if (models) rh *= rb[j] * inv_pmax[j];  // the car's curve, as a share of the port maximum
-            }
-            st_at(ob, o + 4u * 4u * N, occ ? rh : 0.0f);
-            st_at(ob, o + 5u * 4u * N, plast[j] * inv_pmax[j]);
-            if constexpr (EXT) {
-              if (users) st_at(ob, obs_bo + 4u * (uint32_t)(C.user_obs + port[j]), cs[j] ? 1.0f : 0.0f);
+          for (int j = 0; j < P; ++j) {
+            if (NOPAD || port[j] >= 0) {
+              const bool occ = CX_OCCUPIED(j);
+              const uint32_t o = 4u * (uint32_t)port[j];
+              put(o + 0u * 4u * N, occ ? 1.0f : 0.0f);
+              put(o + 1u * 4u * N, occ ? 1.0f - qf[j] : 0.0f);
+              put(o + 2u * 4u * N, occ ? qf[j] - u[j] : 0.0f);
+              put(o + 3u * 4u * N, (float)dw[j] * C.inv_steps_ep);
+              float rh = fminf(1.0f, qf[j] * C.inv_1mtau);
+              if constexpr (EXT) {
+                if (models) rh *= rb[j] * inv_pmax[j];  // the car's curve, as a share of the port maximum
+              }
+              put(o + 4u * 4u * N, occ ? rh : 0.0f);
+              put(o + 5u * 4u * N, plast[j] * inv_pmax[j]);
+              if constexpr (EXT) {
+                if (users) put(4u * (uint32_t)(C.user_obs + port[j]), cs[j] ? 1.0f : 0.0f);
+              }
             }
           }
-        }
-        if (l < 4) {
-          const int n_occ = done ? 0 : (N - n_free + acc);
-          float gv = l == 3 ? (float)n_occ * (1.0f / (float)N) : gld(C.glob, t_day * 4 + l);
+          if (l < 4) {
+            const int n_occ = done ? 0 : (N - n_free + acc);
+            float gv = l == 3 ? (float)n_occ * (1.0f / (float)N) : gld(C.glob, t_day * 4 + l);
+            if constexpr (EXT) {
+              if (days && l == 2) gv = gld(C.price_days, dday * steps_ep + t_day);
+            }
+            put(4u * (uint32_t)(6 * N + l), gv);
+          }
           if constexpr (EXT) {
-            if (days && l == 2) gv = gld(C.price_days, dday * steps_ep + t_day);
+            if (batt && l < 2) put(4u * (uint32_t)(6 * N + 4 + l), l == 0 ? (float)bsoc : bpw * C.b_inv_rate);
+            if (days && l < 2)
+              put(4u * (uint32_t)(C.day_obs + l), l == 0 ? (float)dday * C.inv_n_days : (dday % 7 >= 5 ? 1.0f : 0.0f));
           }
-          st_at(ob, obs_bo + 4u * (uint32_t)(6 * N + l), gv);
-        }
-        if constexpr (EXT) {
-          if (batt && l < 2)
-            st_at(ob, obs_bo + 4u * (uint32_t)(6 * N + 4 + l), l == 0 ? (float)bsoc : bpw * C.b_inv_rate);
-          if (days && l < 2)
-            st_at(ob, obs_bo + 4u * (uint32_t)(C.day_obs + l),
-                  l == 0 ? (float)dday * C.inv_n_days : (dday % 7 >= 5 ? 1.0f : 0.0f));
+        };
+        if constexpr (STAGE) {
+          lds_float *sb = stage + (t & 1) * stage_floats + pad;
+          obs_record([&](uint32_t o, float v) {
+            *reinterpret_cast<lds_float *>(reinterpret_cast<__attribute__((address_space(3))) char *>(sb) + stage_bo +
+                                           o) = v;
+          });
+        } else {
+          obs_record([&](uint32_t o, float v) { st_at(ob_now, obs_bo + o, v); });
         }
       }
       if (w_act) {
@@ -732,6 +786,11 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
     // noticeably faster (better row locality) than the same bytes spread over
     // many steps.  Waves that left early (past the last env) do not count.
     __syncthreads();
+    // the stage of this step is complete: out to HBM (the next step fills the
+    // other buffer; the barrier of that step keeps this one until it is read)
+    if (STAGE && w_obs)
+      flush_stage(stage + (t & 1) * stage_floats, ob_now + (int64_t)env_blk0 * obs_dim, pad, n_blk,
+                  (group - g_blk0) * 64 + lane, n_run * 64);
   }
 
   // ---- state back to HBM
@@ -763,7 +822,7 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
 
 // One kernel per packing (lanes per station L, slots per lane P) and class
 // kind (general, SIMPLE, bidirectional), so that each keeps its own register budget.
-template <int L, int P, bool SIMPLE, bool EXT>
+template <int L, int P, bool SIMPLE, bool EXT, bool STAGE>
 __global__ __launch_bounds__(512) void k_rollout(LaunchArgs a) {
   extern __shared__ uint32_t lds_tdwell[];
   const int b = blockIdx.x;
@@ -795,9 +854,13 @@ __global__ __launch_bounds__(512) void k_rollout(LaunchArgs a) {
     tdw = lds_tdwell;
   }
   const int W = blockDim.x >> 6;
-  const int group = __builtin_amdgcn_readfirstlane((b - sg.block_begin) * W + (int)(threadIdx.x >> 6));
+  const int g_blk0 = (b - sg.block_begin) * W;  // the block's first group
+  const int group = __builtin_amdgcn_readfirstlane(g_blk0 + (int)(threadIdx.x >> 6));
   if (group >= sg.n_groups) return;
-  run_group<L, P, SIMPLE, EXT>(sg, dy, group, tdw, tdw_lds);
+  const int n_run = min(W, sg.n_groups - g_blk0);  // waves of the block that run
+  lds_float *stage =
+      a.stage_floats > 0 ? (lds_float *)((__attribute__((address_space(3))) char *)lds_tdwell + a.stage_off) : nullptr;
+  run_group<L, P, SIMPLE, EXT, STAGE>(sg, dy, group, tdw, tdw_lds, stage, a.stage_floats, g_blk0, n_run);
 }
 
 // Observation of empty stations at t_day = 0 for every env of one segment
@@ -829,8 +892,11 @@ __global__ void k_fill_f64(double *p, int64_t n, double v) {
 
 using KernelFn = void (*)(LaunchArgs);
 
-// The three kernels of one packing: general, SIMPLE, bidirectional.
-#define CX_KINDS(L, P) &k_rollout<L, P, false, false>, &k_rollout<L, P, true, false>, &k_rollout<L, P, false, true>
+// The kernels of one packing: general, SIMPLE, extended, SIMPLE with staged
+// observations (the SIMPLE kernel itself for 64-lane stations).
+#define CX_KINDS(L, P)                                                                              \
+  &k_rollout<L, P, false, false, false>, &k_rollout<L, P, true, false, false>,                        \
+      &k_rollout<L, P, false, true, false>, &k_rollout<L, P, true, false, stage_obs(L)>
 
 // Kernel of each launch kind: packing id (P index * 5 + L index, as pack_id())
 // times kNumKinds, plus the kernel kind (kKind*).
@@ -840,21 +906,31 @@ const KernelFn kKernels[kNumKinds * kNumPackings] = {
     CX_KINDS(4, 4), CX_KINDS(8, 4), CX_KINDS(16, 4), CX_KINDS(32, 4), CX_KINDS(64, 4)};
 #undef CX_KINDS
 
-// Arguments of one group's launch: its slice of the segment table and its LDS.
+// Arguments of one group's launch: its slice of the segment table and its LDS
+// (the stay table; for staging packings the observation stages when
+// observations are written).
 LaunchArgs group_args(const LaunchArgs &a, const LaunchGroup &g, size_t *lds) {
   LaunchArgs b = a;
   b.segs = a.segs + g.seg_begin;
   b.n_segs = g.n_segs;
   b.lds_tdwell = 1;  // staging the table costs one load per thread and beats device-memory
                      // bisection even for one-step launches
-  *lds = b.lds_tdwell ? ((size_t)4 << g.max_dwell_log2) : 0;
+  const bool records =
+      group_stages(g.kind, g.pack) && (a.per_segment || (a.out_mode == CX_OUT_FULL && a.obs != nullptr));
+  const size_t with_stages = group_lds_bytes(g.wpb, g.pack, g.max_obs_dim, g.max_dwell_log2, &b.stage_off,
+                                             &b.stage_floats);
+  if (records) {
+    *lds = with_stages;
+  } else {
+    b.stage_floats = 0;
+    *lds = (size_t)4 << g.max_dwell_log2;
+  }
   return b;
 }
 
 }  // namespace
 
-hipError_t launch_groups(const LaunchArgs &a, const LaunchGroup *groups, int n_groups, int waves_per_block,
-                         hipStream_t st) {
+hipError_t launch_groups(const LaunchArgs &a, const LaunchGroup *groups, int n_groups, hipStream_t st) {
   for (int i = 0; i < n_groups; ++i) {
     const LaunchGroup &g = groups[i];
     if (g.n_blocks <= 0) continue;
@@ -862,18 +938,18 @@ hipError_t launch_groups(const LaunchArgs &a, const LaunchGroup *groups, int n_g
     LaunchArgs b = group_args(a, g, &lds);
     void *params[1] = {&b};
     hipError_t e = hipLaunchKernel(reinterpret_cast<const void *>(kKernels[kNumKinds * g.pack + g.kind]), dim3(g.n_blocks),
-                                   dim3(64 * waves_per_block), params, lds, st);
+                                   dim3(64 * g.wpb), params, lds, st);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
 }
 
 hipError_t graph_rollout(RolloutGraph &G, const LaunchArgs &a, const LaunchGroup *groups, int n_groups,
-                         int waves_per_block, hipStream_t st) {
+                         hipStream_t st) {
   LaunchArgs args[kNumKinds * kNumPackings];
   void *params[kNumKinds * kNumPackings][1];
   hipKernelNodeParams p[kNumKinds * kNumPackings];
-  int shape[kNumKinds * kNumPackings][3] = {};
+  int shape[kNumKinds * kNumPackings][4] = {};
   int n = 0;
   for (int i = 0; i < n_groups && n < kNumKinds * kNumPackings; ++i) {
     const LaunchGroup &g = groups[i];
@@ -884,19 +960,20 @@ hipError_t graph_rollout(RolloutGraph &G, const LaunchArgs &a, const LaunchGroup
     p[n] = hipKernelNodeParams{};
     p[n].func = reinterpret_cast<void *>(kKernels[kNumKinds * g.pack + g.kind]);
     p[n].gridDim = dim3(g.n_blocks);
-    p[n].blockDim = dim3(64 * waves_per_block);
+    p[n].blockDim = dim3(64 * g.wpb);
     p[n].sharedMemBytes = (unsigned)lds;
     p[n].kernelParams = params[n];
     p[n].extra = nullptr;
     shape[n][0] = kNumKinds * g.pack + g.kind;
     shape[n][1] = g.n_blocks;
-    shape[n][2] = (int)lds;
+    shape[n][2] = g.wpb;
+    shape[n][3] = (int)lds;
     ++n;
   }
   if (n == 0) return hipSuccess;
-  bool same = G.exec && G.n_nodes == n && G.waves == waves_per_block;
+  bool same = G.exec && G.n_nodes == n;
   for (int i = 0; same && i < n; ++i)
-    for (int j = 0; j < 3; ++j) same = same && G.shape[i][j] == shape[i][j];
+    for (int j = 0; j < 4; ++j) same = same && G.shape[i][j] == shape[i][j];
   hipError_t e;
   if (!same) {
     graph_destroy(G);
@@ -905,9 +982,8 @@ hipError_t graph_rollout(RolloutGraph &G, const LaunchArgs &a, const LaunchGroup
       if ((e = hipGraphAddKernelNode(&G.node[i], G.graph, nullptr, 0, &p[i])) != hipSuccess) return e;
     if ((e = hipGraphInstantiate(&G.exec, G.graph, nullptr, nullptr, 0)) != hipSuccess) return e;
     G.n_nodes = n;
-    G.waves = waves_per_block;
     for (int i = 0; i < n; ++i)
-      for (int j = 0; j < 3; ++j) G.shape[i][j] = shape[i][j];
+      for (int j = 0; j < 4; ++j) G.shape[i][j] = shape[i][j];
   } else {
     for (int i = 0; i < n; ++i)
       if ((e = hipGraphExecKernelNodeSetParams(G.exec, G.node[i], &p[i])) != hipSuccess) return e;

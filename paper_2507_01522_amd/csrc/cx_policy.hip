@@ -459,7 +459,7 @@ cx_status policy_step(cx_ctx *ctx, int32_t T, cx_out_mode out_mode, const cx_tra
     a.act = nullptr;
     a.reward = out && out->reward ? out->reward + (int64_t)t * ctx->n_envs : nullptr;
     a.done = out && out->done ? out->done + (int64_t)t * ctx->n_envs : nullptr;
-    if ((e = launch_groups(a, ctx->groups.data(), (int)ctx->groups.size(), ctx->wpb, ctx->stream)) !=
+    if ((e = launch_groups(a, ctx->groups.data(), (int)ctx->groups.size(), ctx->stream)) !=
         hipSuccess)
       return hip_fail(ctx, e, "policy rollout: step kernel");
     obs_prev = obs_t;

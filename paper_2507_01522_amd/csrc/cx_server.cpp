@@ -314,6 +314,7 @@ bool launch(cx_server *s) {
     sg.n_envs = E;
     sg.n_groups = (int32_t)((E + spw - 1) / spw);
     sg.pack = pack_id(L, P);
+    sg.obs_dim = (int32_t)od;
     sg.seed = r.seed;
     if (b) {
       sg.q = reinterpret_cast<double *>(b + r.off_q);
@@ -377,14 +378,14 @@ bool launch(cx_server *s) {
   a.per_segment = 1;
   if (e == hipSuccess) {
     if (groups.size() <= 1) {
-      e = launch_groups(a, groups.data(), (int)groups.size(), s->opts.waves_per_block, s->stream);
+      e = launch_groups(a, groups.data(), (int)groups.size(), s->stream);
     } else {
       // fork: each packing's kernel on its own stream, then join
       const int n_aux = std::min<int>((int)groups.size(), cx_server::kAux);
       e = hipEventRecord(s->ev_fork, s->stream);
       for (int k = 0; k < n_aux && e == hipSuccess; ++k) e = hipStreamWaitEvent(s->aux[k], s->ev_fork, 0);
       for (size_t gi = 0; gi < groups.size() && e == hipSuccess; ++gi)
-        e = launch_groups(a, groups.data() + gi, 1, s->opts.waves_per_block, s->aux[gi % n_aux]);
+        e = launch_groups(a, groups.data() + gi, 1, s->aux[gi % n_aux]);
       for (int k = 0; k < n_aux && e == hipSuccess; ++k) {
         e = hipEventRecord(s->ev_join[k], s->aux[k]);
         if (e == hipSuccess) e = hipStreamWaitEvent(s->stream, s->ev_join[k], 0);

@@ -131,15 +131,14 @@ extern "C" cx_status cx_autotune(cx_ctx *ctx, int32_t T_probe, const char *cache
   // its kernels concurrent); min over 3 after a warm-up
   RolloutGraph probe;
   probe_ptr = &probe;
-  auto time_launch = [&](const SegDev *segs, const std::vector<LaunchGroup> &groups, int wpb,
-                         float *best_ms) -> hipError_t {
+  auto time_launch = [&](const SegDev *segs, const std::vector<LaunchGroup> &groups, float *best_ms) -> hipError_t {
     LaunchArgs b = a;
     b.segs = segs;
     float best = 1e30f;
     for (int rep = 0; rep < 4; ++rep) {
       hipError_t r;
       if ((r = hipEventRecord(ev0, ctx->stream)) != hipSuccess) return r;
-      if ((r = graph_rollout(probe, b, groups.data(), (int)groups.size(), wpb, ctx->stream)) != hipSuccess)
+      if ((r = graph_rollout(probe, b, groups.data(), (int)groups.size(), ctx->stream)) != hipSuccess)
         return r;
       if ((r = hipEventRecord(ev1, ctx->stream)) != hipSuccess) return r;
       if ((r = hipEventSynchronize(ev1)) != hipSuccess) return r;
@@ -174,7 +173,7 @@ extern "C" cx_status cx_autotune(cx_ctx *ctx, int32_t T_probe, const char *cache
         break;
       }
       float ms = 0.f;
-      if ((e = time_launch(seg1, one_groups, ctx->wpb, &ms)) != hipSuccess) {
+      if ((e = time_launch(seg1, one_groups, &ms)) != hipSuccess) {
         st = hip_fail(ctx, e, "cx_autotune timing");
         break;
       }
@@ -198,7 +197,7 @@ extern "C" cx_status cx_autotune(cx_ctx *ctx, int32_t T_probe, const char *cache
         ctx->wpb = w;
         if ((st = rebuild_segments(ctx)) != CX_OK) break;
         float ms = 0.f;
-        if ((e = time_launch(ctx->segs_dev, ctx->groups, w, &ms)) != hipSuccess) {
+        if ((e = time_launch(ctx->segs_dev, ctx->groups, &ms)) != hipSuccess) {
           st = hip_fail(ctx, e, "cx_autotune timing");
           break;
         }
@@ -209,6 +208,39 @@ extern "C" cx_status cx_autotune(cx_ctx *ctx, int32_t T_probe, const char *cache
       }
       ctx->wpb = best_w;
       cache[wkey] = best_w;
+    }
+  }
+  if (st == CX_OK) {
+    // observations through the LDS stage or lane by lane: whichever runs this
+    // launch faster (the stage pays where the record stream, not the
+    // arithmetic, sets the pace)
+    bool any = false;
+    for (const ClassRt &c : ctx->classes)
+      any = any || (c.n_envs > 0 && c.host_view.kind == kKindSimple && stage_obs(c.lanes));
+    const std::string skey = "stage" + ctx_key(ctx).substr(3);
+    auto it = cache.find(skey);
+    if (!any) {
+      ctx->stage_obs = false;
+    } else if (it != cache.end() && (it->second == 0 || it->second == 1)) {
+      ctx->stage_obs = it->second != 0;
+    } else {
+      int best_s = 0;
+      float best_ms = 1e30f;
+      for (int s : {0, 1}) {
+        ctx->stage_obs = s != 0;
+        if ((st = rebuild_segments(ctx)) != CX_OK) break;
+        float ms = 0.f;
+        if ((e = time_launch(ctx->segs_dev, ctx->groups, &ms)) != hipSuccess) {
+          st = hip_fail(ctx, e, "cx_autotune timing");
+          break;
+        }
+        if (ms < best_ms) {
+          best_ms = ms;
+          best_s = s;
+        }
+      }
+      ctx->stage_obs = best_s != 0;
+      cache[skey] = best_s;
     }
   }
   if (st == CX_OK) st = rebuild_segments(ctx);

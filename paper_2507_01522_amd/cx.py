@@ -86,7 +86,7 @@ class ResultC(C.Structure):
 EXPORTS = ["cx_create", "cx_create_multi", "cx_set_stream", "cx_get_info", "cx_get_class_info", "cx_reset",
            "cx_step", "cx_step_ex", "cx_rollout", "cx_set_policy", "cx_policy_logits", "cx_policy_sample", "cx_observe",
            "cx_get_state",
-           "cx_set_state", "cx_get_tables", "cx_set_packing", "cx_autotune", "cx_synchronize",
+           "cx_set_state", "cx_get_tables", "cx_set_packing", "cx_set_obs_stage", "cx_autotune", "cx_synchronize",
            "cx_last_error", "cx_destroy", "cx_server_create", "cx_submit", "cx_poll", "cx_wait",
            "cx_cancel", "cx_release", "cx_server_stats", "cx_server_destroy", "cx_compile_layout",
            "cx_build_tables"]
@@ -112,7 +112,7 @@ def lib() -> C.CDLL:
         "cx_policy_logits": [P, P, I64, P], "cx_policy_sample": [P, P, I64, C.c_uint32, P],
         "cx_observe": [P, P], "cx_get_state": [P, P, C.c_size_t],
         "cx_set_state": [P, P, C.c_size_t], "cx_get_tables": [P, I32, P, P],
-        "cx_set_packing": [P, I32, I32, I32], "cx_autotune": [P, I32, C.c_char_p],
+        "cx_set_packing": [P, I32, I32, I32], "cx_set_obs_stage": [P, I32], "cx_autotune": [P, I32, C.c_char_p],
         "cx_synchronize": [P], "cx_last_error": [], "cx_destroy": [P],
         "cx_server_create": [C.c_size_t, P, P], "cx_submit": [P, P, P], "cx_poll": [P, U64, P],
         "cx_wait": [P, U64, P], "cx_cancel": [P, U64], "cx_release": [P, U64],
@@ -297,6 +297,11 @@ class Env:
 
     def set_packing(self, cls: int, lanes: int, waves_per_block: int = 4):
         check(lib().cx_set_packing(self.h, cls, lanes, waves_per_block))
+
+    def set_obs_stage(self, on: bool):
+        """Observations through each block's LDS stage (SIMPLE classes of up
+        to 32 lanes per station) or stored lane by lane; same records."""
+        check(lib().cx_set_obs_stage(self.h, 1 if on else 0))
 
     def autotune(self, T_probe: int = 32, cache_path: Optional[str] = None):
         check(lib().cx_autotune(self.h, T_probe, None if cache_path is None else cache_path.encode()))

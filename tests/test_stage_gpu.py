@@ -1,0 +1,138 @@
+"""The LDS observation stage (cx_set_obs_stage): with it, SIMPLE classes of up
+to 32 lanes per station write their observations through each block's stage as
+16-byte runs.  The records must be bit for bit those of lane-by-lane stores:
+in every packing and block size, for ragged env counts (partial blocks, runs
+that start at any 4-byte offset), across the day boundary, in one-step
+launches, in the policy loop and after autotuning; and they must match the
+oracle."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from tests import parity as PY
+
+pytestmark = pytest.mark.gpu
+
+# the uneven-batching classes (8..128 ports, trees 1-3 deep: SIMPLE kernels,
+# staged up to 32 lanes) plus a general class, a bidirectional one and the
+# dense-layout station, which keep their own kernels
+MIX = W.mixture_classes() + [W.two_charger_types(), W.v2g_station(), W.exo_station()]
+COUNTS = [5, 3, 7, 9, 1, 6, 4, 11, 2, 3, 5, 1, 2, 1, 3, 6, 5, 4]
+
+
+@pytest.fixture(scope="module")
+def cxm():
+    from paper_2507_01522_amd import cx
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+    return cx
+
+
+def ec_of(counts):
+    return np.concatenate([np.full(c, i, np.int32) for i, c in enumerate(counts)])
+
+
+def make(cxm, specs, ec, seed, stage, lanes=None, wpb=4):
+    env = cxm.Env(specs, env_class=ec, seed=seed) if len(specs) > 1 else cxm.Env(specs[0], n_envs=len(ec), seed=seed)
+    for c, s in enumerate(specs):
+        env.set_packing(c, lanes[c] if lanes is not None else min(s.n_ports if s.n_ports >= 4 else 4, 64), wpb)
+    env.set_obs_stage(stage)
+    return env
+
+
+def same(a, b):
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+
+
+def default_lanes(specs, env):
+    return [env.class_info(c).lanes_per_station for c in range(len(specs))]
+
+
+@pytest.mark.parametrize("wpb", [1, 2, 4, 8])
+def test_staged_equals_lane_stores(cxm, wpb):
+    """18 classes, ragged counts, 300 steps: every record and the final state."""
+    ec = ec_of(COUNTS)
+    ref = cxm.Env(MIX, env_class=ec, seed=41)
+    lanes = default_lanes(MIX, ref)
+    a = make(cxm, MIX, ec, 41, False, lanes, wpb)
+    b = make(cxm, MIX, ec, 41, True, lanes, wpb)
+    ra = PY.to_np(a.rollout(300, cxm.ACT_RANDOM))
+    rb = PY.to_np(b.rollout(300, cxm.ACT_RANDOM))
+    same(ra, rb)
+    assert a.get_state() == b.get_state()
+
+
+@pytest.mark.parametrize("ports,lanes", [(8, 4), (8, 8), (16, 4), (16, 8), (16, 16), (32, 8), (32, 16), (32, 32)])
+def test_staged_every_packing(cxm, ports, lanes):
+    """Stations of 8-32 ports at 1, 2 or 4 slots per lane, 37 envs (a partial
+    last block), depth-2 trees."""
+    spec = W.fanout4_tree(ports, 2)
+    ec = np.zeros(37, np.int32)
+    outs = []
+    for stage in (False, True):
+        env = make(cxm, [spec], ec, 42, stage, [lanes], 4)
+        outs.append(PY.to_np(env.rollout(120, cxm.ACT_RANDOM)))
+    same(*outs)
+
+
+def test_staged_one_step_launches(cxm):
+    """40 one-step launches with the stage equal a 40-step rollout without it."""
+    specs = W.mixture_classes()[:9]
+    ec = ec_of([3, 5, 2, 7, 1, 4, 6, 2, 3])
+    a = make(cxm, specs, ec, 43, False)
+    b = make(cxm, specs, ec, 43, True)
+    roll = PY.to_np(a.rollout(40, cxm.ACT_RANDOM))
+    steps = [PY.to_np(b.step(cxm.ACT_RANDOM)) for _ in range(40)]
+    same(roll, {k: np.concatenate([s[k] for s in steps]) for k in roll})
+    assert a.get_state() == b.get_state()
+
+
+def test_staged_matches_oracle(cxm, oracle_lib):
+    """The staged records against the FP64 oracle (integers exact, FP within
+    the parity tolerances), 300 steps."""
+    o = oracle_lib
+    specs = W.mixture_classes()[:12]
+    ec = ec_of([4, 3, 5, 2, 6, 1, 3, 2, 4, 1, 2, 3])
+    env = make(cxm, specs, ec, 44, True)
+    g = PY.to_np(env.rollout(300, cxm.ACT_RANDOM))
+    bs = o.BatchState([o.OracleClass(s) for s in specs], ec)
+    PY.compare_rollout(g, o.rollout(bs, 44, 300), specs, ec)
+    PY.compare_state(env.state_arrays(), bs, specs, ec)
+
+
+def test_staged_policy_loop(cxm):
+    """Levels from the MLP, one-step launches with the stage: the same records."""
+    spec = W.policy_station()
+    weights = W.policy_weights(spec.n_ports, hidden=256, std=0.2, seed=11)
+    outs = []
+    for stage in (False, True):
+        env = cxm.Env(spec, n_envs=45, seed=45)
+        env.set_obs_stage(stage)
+        env.set_policy(256, weights)
+        outs.append(PY.to_np(env.rollout(30, cxm.ACT_POLICY, cxm.OUT_FULL)))
+    same(*outs)
+
+
+def test_autotune_keeps_records(cxm, tmp_path):
+    """Whatever the autotuner picks (packings, block size, stage), the records
+    are those of the untuned launch."""
+    specs = W.mixture_classes()
+    ec = ec_of([40, 30, 20, 30, 25, 20, 15, 12, 10, 9, 8, 7, 3, 2, 2])
+    a = cxm.Env(specs, env_class=ec, seed=46)
+    b = cxm.Env(specs, env_class=ec, seed=46)
+    b.autotune(16, str(tmp_path / "tune.json"))
+    ra = PY.to_np(a.rollout(100, cxm.ACT_RANDOM))
+    rb = PY.to_np(b.rollout(100, cxm.ACT_RANDOM))
+    for k in ("actions", "done"):
+        assert np.array_equal(ra[k], rb[k]), k
+    # other packings may sum a station's powers in another order: FP32 rounding only
+    for k in ("reward", "obs"):
+        assert np.allclose(ra[k], rb[k], rtol=1e-5, atol=1e-5), k
+
+
+def test_obs_stage_argument_checked(cxm):
+    env = cxm.Env(W.tiny_parity_station(), n_envs=4, seed=1)
+    with pytest.raises(cxm.CxError):
+        cxm.check(cxm.lib().cx_set_obs_stage(env.h, 2))
