@@ -174,6 +174,8 @@ typedef __attribute__((address_space(3))) f32x4 lds_f32x4;
 __device__ __forceinline__ void flush_stage(const lds_float *sb, float *dst, int pad, int n, int tid,
                                             int nthreads) {
   const int c_end = (pad + n) >> 2;  // whole chunks: [pad ? 1 : 0, c_end)
+  // raw buffer: stride 0, range 2^31 - 1 bytes (offsets stay below 16 n + 64),
+  // format word of a plain 32-bit buffer on gfx9-family GPUs
   const __amdgpu_buffer_rsrc_t rs =
       __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<char *>(dst) - 4 * pad, (short)0, 0x7fffffff, 0x00020000);
   for (int c = (pad ? 1 : 0) + tid; c < c_end; c += nthreads) {
