@@ -192,7 +192,8 @@ def run_rollout_workload(args, name, specs, ec, seed, desc, cpu_stride):
     line = base_line(f"env-steps/s (batched persistent rollout, {desc})", value, "env-steps/s", args, wall_ms,
                      {"workload": name, "n_envs": n_envs, "T": T_DAY, "mean_ports": float(n_ports.mean()),
                       "packing": {f"N{c.n_ports}d{c.levels}": c.lanes_per_station for c in ci},
-                      "waves_per_block": ci[0].waves_per_block})
+                      "waves_per_block": ci[0].waves_per_block,
+                      "obs_stage": bool(env.info().obs_stage)})
     line["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": achieved / HBM_PEAK_GBS,
                         "traffic": measured_traffic() if name.startswith("uneven") else None,

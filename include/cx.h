@@ -198,6 +198,7 @@ typedef struct {
   uint64_t seed;
   size_t state_bytes;     /* size of a cx_get_state snapshot */
   int64_t device_bytes;   /* device memory the context holds */
+  int32_t obs_stage;      /* 1: observations go through the LDS stage (cx_set_obs_stage) */
 } cx_info;
 
 typedef struct {

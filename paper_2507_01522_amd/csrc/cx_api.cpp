@@ -468,6 +468,7 @@ cx_status cx_get_info(const cx_ctx *ctx, cx_info *info) {
   info->seed = ctx->seed;
   info->state_bytes = state_blob_bytes(ctx);
   info->device_bytes = ctx->device_bytes;
+  info->obs_stage = ctx->stage_obs ? 1 : 0;
   return CX_OK;
 }
 

@@ -57,7 +57,7 @@ class InfoC(C.Structure):
     _fields_ = [("n_envs", C.c_int64), ("total_ports", C.c_int64), ("obs_elems", C.c_int64),
                 ("n_classes", C.c_int32), ("steps_per_episode", C.c_int32), ("g", C.c_uint32),
                 ("t_day", C.c_int32), ("seed", C.c_uint64), ("state_bytes", C.c_size_t),
-                ("device_bytes", C.c_int64)]
+                ("device_bytes", C.c_int64), ("obs_stage", C.c_int32)]
 
 
 class ClassInfoC(C.Structure):

@@ -134,5 +134,10 @@ def test_autotune_keeps_records(cxm, tmp_path):
 
 def test_obs_stage_argument_checked(cxm):
     env = cxm.Env(W.tiny_parity_station(), n_envs=4, seed=1)
+    assert env.info().obs_stage == 0          # off unless set or chosen by cx_autotune
+    env.set_obs_stage(True)
+    assert env.info().obs_stage == 1
+    env.set_obs_stage(False)
+    assert env.info().obs_stage == 0
     with pytest.raises(cxm.CxError):
         cxm.check(cxm.lib().cx_set_obs_stage(env.h, 2))
