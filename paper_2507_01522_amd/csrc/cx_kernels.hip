@@ -15,7 +15,8 @@
 //                     permlane swaps across rows, adds across registers; in the
 //                     dense layout, one station-wide sum per node of a level)
 //   charge, departures, arrivals (ballot + popcount ranks), reward, day end,
-//   records.
+//   records (observations lane by lane, or, in the staged SIMPLE kernels,
+//   through the block's LDS stage as 16-byte runs).
 // Extended classes run their own kernels: V2G ports (signed levels, the
 // mirrored discharge curve, two-sided limits, the split of the grid energy),
 // a station battery (one FP64 scalar per station that every lane of the station
@@ -196,6 +197,10 @@ __device__ __forceinline__ void flush_stage(const lds_float *sb, float *dst, int
 // per-slot constant is wave-uniform (scalar registers).
 // EXT: V2G ports, a station battery, charge-sensitive users, price days and / or
 // car models (never SIMPLE); each switched on per class by a uniform flag.
+// STAGE: observations through the block's LDS stage (SIMPLE classes of up to
+// 32 lanes, when the context asks for it): stage / stage_floats are the two
+// stage buffers and floats per buffer, g_blk0 the block's first group and
+// n_run the number of its waves that run.
 template <int L, int P, bool SIMPLE, bool EXT, bool STAGE>
 __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int group, const uint32_t *tdw,
                                           bool tdw_lds, lds_float *stage, int stage_floats, int g_blk0,
