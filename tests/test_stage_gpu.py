@@ -141,3 +141,31 @@ def test_obs_stage_argument_checked(cxm):
     assert env.info().obs_stage == 0
     with pytest.raises(cxm.CxError):
         cxm.check(cxm.lib().cx_set_obs_stage(env.h, 2))
+
+
+def test_staged_class_split_into_segments(cxm, oracle_lib):
+    """5,600,000 stations of 32 ports through the stage: one step's observations
+    (4.4 GB) run as two segments; stations whose block's records start past
+    2 GiB, on both sides of the cut and at the ends match the oracle."""
+    o = oracle_lib
+    spec = W.fanout4_tree(32, 2).replace(arrival_peak=2.0)
+    n, T, seed = 5_600_000, 2, 84
+    chunk = ((1 << 32) - 1) // (4 * spec.obs_dim)
+    chunk -= chunk % 64
+    assert chunk < n
+    half = (1 << 31) // (4 * spec.obs_dim) + 8      # a block whose records start past 2 GiB
+    env = cxm.Env(spec, n_envs=n, seed=seed)
+    env.set_obs_stage(True)
+    assert env.info().obs_stage == 1
+    out = env.rollout(T, cxm.ACT_RANDOM)
+    ids = np.array([0, 1, half - 1, half, half + 1, chunk - 2, chunk - 1, chunk, chunk + 1, n - 2, n - 1], np.int64)
+    acols = (ids[:, None] * spec.n_actions + np.arange(spec.n_actions)).ravel()
+    ocols = (ids[:, None] * spec.obs_dim + np.arange(spec.obs_dim)).ravel()
+    g = {"actions": out["actions"][:, torch.from_numpy(acols).cuda()].cpu().numpy(),
+         "reward": out["reward"][:, torch.from_numpy(ids).cuda()].cpu().numpy(),
+         "done": out["done"][:, torch.from_numpy(ids).cuda()].cpu().numpy(),
+         "obs": out["obs"][:, torch.from_numpy(ocols).cuda()].cpu().numpy()}
+    del out
+    ec = np.zeros(len(ids), np.int32)
+    bs = o.BatchState([o.OracleClass(spec)], ec, env_ids=ids)
+    PY.compare_rollout(g, o.rollout(bs, seed, T), [spec], ec)
