@@ -309,6 +309,11 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
   }
   int bM = 0, bdw = 1, bus = 0, bmod = 0;
   float bpb = 0.f, bcp = 0.f, bs0 = 0.f, btg = 0.f;
+  // 64-lane SIMPLE stations, which often take two cars in a step: the
+  // second car (rank 1) drawn ahead as well
+  constexpr bool AHEAD2 = SIMPLE && L == 64;
+  int bdw1 = 1;
+  float bcp1 = 0.f, bs01 = 0.f, btg1 = 0.f;
   U4 aw[P];
 #pragma unroll
   for (int j = 0; j < P; ++j) aw[j] = U4{0, 0, 0, 0};
@@ -370,6 +375,15 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
       bdw = stay_len(tdw, tdw_lds, C.dwell_log2, b.w);
       if constexpr (EXT) {
         if (users) bus = philox(env_id, gl, 0u, kDomUser, k0, k1).x <= C.cs_thresh ? 1 : 0;
+      }
+      if constexpr (AHEAD2) {
+        if (__ballot(bM >= 2)) {  // some step ahead brings a second car
+          const U4 b1 = philox(env_id, gl, 1u, kDomCar, k0, k1);
+          bcp1 = C.cap_lo + C.cap_span * u24(b1.x);
+          bs01 = C.soc_lo + C.soc_span * u24(b1.y);
+          btg1 = C.tgt_lo + C.tgt_span * u24(b1.z);
+          bdw1 = stay_len(tdw, tdw_lds, C.dwell_log2, b1.w);
+        }
       }
     }
     const int tb = t & (L - 1);
@@ -639,6 +653,17 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
       const int f_dw = bcast<L>(bdw, tb);
       const int f_us = EXT ? bcast<L>(bus, tb) : 0;
       const int f_mod = EXT ? bcast<L>(bmod, tb) : 0;
+      // (AHEAD2) the second car's, when the station takes two
+      float f_cp1 = 0.f, f_s01 = 0.f, f_tg1 = 0.f;
+      int f_dw1 = 1;
+      if constexpr (AHEAD2) {
+        if (__ballot(acc > 1)) {
+          f_cp1 = bcastf<L>(bcp1, tb);
+          f_s01 = bcastf<L>(bs01, tb);
+          f_tg1 = bcastf<L>(btg1, tb);
+          f_dw1 = bcast<L>(bdw1, tb);
+        }
+      }
       int run = 0;
 #pragma unroll
       for (int j = 0; j < P; ++j) {
@@ -647,7 +672,12 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
           float cp = f_cp, s0 = f_s0, tg = f_tg;
           int dd = f_dw;
           int us = f_us, md = f_mod;
-          if (rank > 0) {
+          if (AHEAD2 && rank == 1) {
+            cp = f_cp1;
+            s0 = f_s01;
+            tg = f_tg1;
+            dd = f_dw1;
+          } else if (rank > 0) {
             const U4 b = philox(env_id, g, (uint32_t)rank, kDomCar, k0, k1);
             cp = C.cap_lo + C.cap_span * u24(b.x);
             if constexpr (EXT) {
