@@ -320,8 +320,8 @@ cx_status cx_set_packing(cx_ctx *ctx, int32_t cls, int32_t lanes_per_station, in
 cx_status cx_set_obs_stage(cx_ctx *ctx, int32_t on);
 
 /* Time every legal packing of every class on a T_probe-step rollout (state is
- * saved and restored) and keep the fastest, then the waves per block and the
- * observation stage (cx_set_obs_stage) likewise.  cache_path (nullable) is a
+ * saved and restored) and keep the fastest, then every pair of waves per block
+ * and observation stage (cx_set_obs_stage) likewise.  cache_path (nullable) is a
  * JSON file of earlier results keyed by class shape, read first and updated. */
 cx_status cx_autotune(cx_ctx *ctx, int32_t T_probe, const char *cache_path);
 

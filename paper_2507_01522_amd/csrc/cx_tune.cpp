@@ -186,61 +186,46 @@ extern "C" cx_status cx_autotune(cx_ctx *ctx, int32_t T_probe, const char *cache
     cache[key] = best_l;
   }
   if (st == CX_OK) {
-    const std::string wkey = ctx_key(ctx);
-    auto it = cache.find(wkey);
-    if (it != cache.end() && it->second >= 1 && it->second <= kMaxWaves) {
-      ctx->wpb = it->second;
-    } else {
-      int best_w = ctx->wpb;
-      float best_ms = 1e30f;
-      for (int w : {1, 2, 4, 8}) {
-        ctx->wpb = w;
-        if ((st = rebuild_segments(ctx)) != CX_OK) break;
-        float ms = 0.f;
-        if ((e = time_launch(ctx->segs_dev, ctx->groups, &ms)) != hipSuccess) {
-          st = hip_fail(ctx, e, "cx_autotune timing");
-          break;
-        }
-        if (ms < best_ms) {
-          best_ms = ms;
-          best_w = w;
-        }
-      }
-      ctx->wpb = best_w;
-      cache[wkey] = best_w;
-    }
-  }
-  if (st == CX_OK) {
-    // observations through the LDS stage or lane by lane: whichever runs this
-    // launch faster (the stage pays where the record stream, not the
-    // arithmetic, sets the pace)
+    // waves per block and the observation stage, chosen together (the stage
+    // pays where the record stream, not the arithmetic, sets the pace, and
+    // what it costs depends on the block size): every pair is timed
     bool any = false;
     for (const ClassRt &c : ctx->classes)
       any = any || (c.n_envs > 0 && c.host_view.kind == kKindSimple && stage_obs(c.lanes));
-    const std::string skey = "stage" + ctx_key(ctx).substr(3);
-    auto it = cache.find(skey);
-    if (!any) {
-      ctx->stage_obs = false;
-    } else if (it != cache.end() && (it->second == 0 || it->second == 1)) {
-      ctx->stage_obs = it->second != 0;
+    const std::string wkey = ctx_key(ctx);
+    const std::string skey = "stage" + wkey.substr(3);
+    auto wit = cache.find(wkey);
+    auto sit = cache.find(skey);
+    const bool w_cached = wit != cache.end() && wit->second >= 1 && wit->second <= kMaxWaves;
+    const bool s_cached = !any || (sit != cache.end() && (sit->second == 0 || sit->second == 1));
+    if (w_cached && s_cached) {
+      ctx->wpb = wit->second;
+      ctx->stage_obs = any && sit->second != 0;
     } else {
-      int best_s = 0;
+      int best_w = ctx->wpb, best_s = 0;
       float best_ms = 1e30f;
-      for (int s : {0, 1}) {
-        ctx->stage_obs = s != 0;
-        if ((st = rebuild_segments(ctx)) != CX_OK) break;
-        float ms = 0.f;
-        if ((e = time_launch(ctx->segs_dev, ctx->groups, &ms)) != hipSuccess) {
-          st = hip_fail(ctx, e, "cx_autotune timing");
-          break;
+      for (int w : {1, 2, 4, 8}) {
+        for (int s = 0; s <= (any ? 1 : 0) && st == CX_OK; ++s) {
+          ctx->wpb = w;
+          ctx->stage_obs = s != 0;
+          if ((st = rebuild_segments(ctx)) != CX_OK) break;
+          float ms = 0.f;
+          if ((e = time_launch(ctx->segs_dev, ctx->groups, &ms)) != hipSuccess) {
+            st = hip_fail(ctx, e, "cx_autotune timing");
+            break;
+          }
+          if (ms < best_ms) {
+            best_ms = ms;
+            best_w = w;
+            best_s = s;
+          }
         }
-        if (ms < best_ms) {
-          best_ms = ms;
-          best_s = s;
-        }
+        if (st != CX_OK) break;
       }
+      ctx->wpb = best_w;
       ctx->stage_obs = best_s != 0;
-      cache[skey] = best_s;
+      cache[wkey] = best_w;
+      if (any) cache[skey] = best_s;
     }
   }
   if (st == CX_OK) st = rebuild_segments(ctx);
