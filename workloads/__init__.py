@@ -316,6 +316,68 @@ MIX_PROBS = (0.3, 0.3, 0.2, 0.15, 0.05)
 MIX_DEPTHS = (1, 2, 3)
 
 
+def random_station(seed: int, max_ports: int = 64) -> StationSpec:
+    """A random capacity tree for parity sweeps: 1-4 levels (root included), 1-4
+    child nodes per node, 1-6 ports directly under each leaf node and 0-2 under
+    inner nodes, ports listed depth-first (every node's ports contiguous; nodes
+    left without a port below them are dropped); node limits 0.3-1.2x the sum
+    of their children's maxima, efficiencies 0.85-1, port maxima from common
+    charger ratings; a random arrival rate and level count."""
+    rng = np.random.default_rng(seed)
+    depth = int(rng.integers(1, 5))
+    parent: List[int] = []
+    children: List[List[int]] = []
+
+    def add(p: int, d: int) -> None:
+        h = len(parent)
+        parent.append(p)
+        children.append([])
+        if p >= 0:
+            children[p].append(h)
+        if d + 1 < depth:
+            for _ in range(int(rng.integers(1, 5))):
+                add(h, d + 1)
+
+    add(-1, 0)
+    ratings = np.array([7.4, 11.0, 22.0, 50.0, 150.0])
+    port_parent: List[int] = []
+    pmax: List[float] = []
+
+    def place(h: int) -> None:          # preorder: a node's own ports, then its children's
+        k = int(rng.integers(1, 7)) if not children[h] else int(rng.integers(0, 3))
+        for _ in range(k):
+            if len(port_parent) < max_ports:
+                port_parent.append(h)
+                pmax.append(float(rng.choice(ratings)))
+        for c in children[h]:
+            place(c)
+
+    place(0)
+    below = [0] * len(parent)
+    for h in port_parent:
+        while h >= 0:
+            below[h] += 1
+            h = parent[h]
+    keep = [h for h in range(len(parent)) if below[h] > 0]     # the root always has the first port
+    remap = {h: i for i, h in enumerate(keep)}
+    parent = [remap[parent[h]] if parent[h] >= 0 else -1 for h in keep]
+    port_parent = [remap[h] for h in port_parent]
+    n, H = len(port_parent), len(parent)
+    # limits bottom-up: factor x the sum of the children's maxima (node limit or port maximum)
+    child_max = [0.0] * H
+    for i in range(n):
+        child_max[port_parent[i]] += pmax[i]
+    limit = [0.0] * H
+    for h in reversed(range(H)):
+        limit[h] = float(rng.uniform(0.3, 1.2)) * child_max[h]
+        if parent[h] >= 0:
+            child_max[parent[h]] += limit[h]
+    return StationSpec(n, parent, limit, list(rng.uniform(0.9, 1.0, H)), port_parent, pmax,
+                       list(rng.uniform(0.85, 1.0, n)), arrival_peak=float(rng.uniform(0.05, 0.3)) * n / 4.0,
+                       n_levels=int(rng.choice([4, 10, 16])), alpha_sat=0.1, alpha_declined=0.2,
+                       name=f"random{seed}")
+
+
 def mixture_classes() -> List[StationSpec]:
     """The 15 station classes (ports x depth) of the uneven-batching workload."""
     return [fanout4_tree(n, d) for n in MIX_PORTS for d in MIX_DEPTHS]
