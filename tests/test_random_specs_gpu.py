@@ -47,3 +47,25 @@ def test_random_trees_match_oracle(cxm, oracle_lib, mode, first):
     bs = o.BatchState([o.OracleClass(s) for s in specs], ec)
     PY.compare_rollout(g, o.rollout(bs, 91 + first, 300, mode=m), specs, ec)
     PY.compare_state(env.state_arrays(), bs, specs, ec)
+
+
+@pytest.mark.parametrize("first", [0, 300])
+def test_random_bidirectional_trees_match_oracle(cxm, oracle_lib, first):
+    """The same random trees with V2G ports (every other one with a station
+    battery and both degradation penalties): the extended kernels, signed
+    levels, two-sided limits."""
+    o = oracle_lib
+    specs = []
+    for i, s in enumerate(random_classes(cxm, first)):
+        kw = dict(v2g=1, alpha_degrad_cars=0.02)
+        if i % 2:
+            kw.update(battery_kwh=float(40 + 20 * i), battery_kw=float(10 + 5 * i), battery_soc0=0.3 + 0.04 * i,
+                      alpha_degrad_battery=0.01)
+        specs.append(s.replace(**kw))
+    counts = [4, 2, 6, 3, 5, 1, 7, 3, 2, 4, 6, 2]
+    ec = np.concatenate([np.full(c, i, np.int32) for i, c in enumerate(counts)])
+    env = cxm.Env(specs, env_class=ec, seed=93 + first)
+    g = PY.to_np(env.rollout(300, cxm.ACT_RANDOM, cxm.OUT_FULL))
+    bs = o.BatchState([o.OracleClass(s) for s in specs], ec)
+    PY.compare_rollout(g, o.rollout(bs, 93 + first, 300), specs, ec)
+    PY.compare_state(env.state_arrays(), bs, specs, ec)
