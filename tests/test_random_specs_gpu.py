@@ -69,3 +69,30 @@ def test_random_bidirectional_trees_match_oracle(cxm, oracle_lib, first):
     bs = o.BatchState([o.OracleClass(s) for s in specs], ec)
     PY.compare_rollout(g, o.rollout(bs, 93 + first, 300), specs, ec)
     PY.compare_state(env.state_arrays(), bs, specs, ec)
+
+
+def test_random_trees_with_users_days_and_cars(cxm, oracle_lib):
+    """Random trees with charge-sensitive users, exploring starts over price
+    days and AC / DC car models (random DC ports): the extended kernels; a
+    charge-sensitive departure decided within rounding of zero may part the two
+    sides (counted near-ties, at most 1 env in 50)."""
+    o = oracle_lib
+    rng = np.random.default_rng(17)
+    specs = []
+    for i, s in enumerate(random_classes(cxm, 400)):
+        kw = dict(charge_sensitive_share=0.4, alpha_sat1=0.2, beta_sat1=0.3)
+        if i % 3 != 2:
+            kw.update(price_days=W.price_day_table(7, s.steps_per_episode, seed=i))
+        if i % 2 == 0:
+            kw.update(car_models=W.car_mix("europe" if i % 4 == 0 else "us"),
+                      port_dc=[int(v) for v in rng.integers(0, 2, s.n_ports)])
+        specs.append(s.replace(**kw))
+    counts = [5, 3, 4, 2, 6, 3, 5, 2, 4, 3, 6, 2]
+    ec = np.concatenate([np.full(c, i, np.int32) for i, c in enumerate(counts)])
+    env = cxm.Env(specs, env_class=ec, seed=94)
+    g = PY.to_np(env.rollout(300, cxm.ACT_RANDOM, cxm.OUT_FULL))
+    bs = o.BatchState([o.OracleClass(s) for s in specs], ec)
+    r = o.rollout(bs, 94, 300)
+    flips, keep = PY.compare_rollout_flips(o, g, r, specs, ec, 94)
+    assert len(flips) <= max(1, len(ec) // 50), flips
+    PY.compare_state(env.state_arrays(), bs, specs, ec, keep=keep)
