@@ -96,3 +96,23 @@ def test_random_trees_with_users_days_and_cars(cxm, oracle_lib):
     flips, keep = PY.compare_rollout_flips(o, g, r, specs, ec, 94)
     assert len(flips) <= max(1, len(ec) // 50), flips
     PY.compare_state(env.state_arrays(), bs, specs, ec, keep=keep)
+
+
+@pytest.mark.parametrize("wpb", [1, 8])
+def test_random_trees_in_the_widest_packing(cxm, oracle_lib, wpb):
+    """The random trees with the most slots per lane their layout allows (2 or 4
+    slots per lane where possible, fewer lanes per station), 1 and 8 waves per
+    block."""
+    o = oracle_lib
+    specs = random_classes(cxm, 500)
+    counts = [6, 2, 5, 3, 4, 7, 1, 3, 5, 2, 4, 6]
+    ec = np.concatenate([np.full(c, i, np.int32) for i, c in enumerate(counts)])
+    env = cxm.Env(specs, env_class=ec, seed=95)
+    for c, s in enumerate(specs):
+        S = cxm.compile_layout(s)["slots"]
+        legal = [L for L in (4, 8, 16, 32, 64) if (S == L or (S % L == 0 and S // L in (1, 2, 4)))]
+        env.set_packing(c, min(legal), wpb)
+    g = PY.to_np(env.rollout(300, cxm.ACT_RANDOM, cxm.OUT_FULL))
+    bs = o.BatchState([o.OracleClass(s) for s in specs], ec)
+    PY.compare_rollout(g, o.rollout(bs, 95, 300), specs, ec)
+    PY.compare_state(env.state_arrays(), bs, specs, ec)
