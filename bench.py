@@ -88,13 +88,15 @@ def uneven_workload():
     return W.compact_classes(classes, ec_full)
 
 
-def oracle_baseline(specs, ec, seed, T, stride, chunk=16, mode=1, min_s=10.0):
+def oracle_baseline(specs, ec, seed, T, stride, chunk=16, mode=1, min_s=10.0, threads=None):
     """The FP64 oracle on an evenly spaced sample of the same stations, whole days
-    repeated until about min_s seconds of host time have passed."""
+    repeated until about min_s seconds of host time have passed; threads: host
+    threads (default: the cores, at most 16)."""
     from oracle import oracle as o
     ids = np.arange(0, len(ec), stride, dtype=np.int64)
     classes = [o.OracleClass(s) for s in specs]
-    threads = max(1, min(16, os.cpu_count() or 1))
+    if threads is None:
+        threads = max(1, min(16, os.cpu_count() or 1))
     used, steps, days = 1, 0, 0
     t0 = time.perf_counter()
     while True:
