@@ -293,7 +293,7 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
       bpw = sg.bp[env];
     }
   }
-  U4 bw = U4{0, 0, 0, 0};
+  uint32_t bkp = 0;  // EXT: the battery's action bytes of the current group of 4 steps, one per byte
   // limit of the root (the whole station)
   const float c_root = D == 1 ? lcap[0][0] : D == 2 ? lcap[1][0] : D == 3 ? lcap[2][0] : lcap[3][0];
 
@@ -314,9 +314,17 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
   constexpr bool AHEAD2 = SIMPLE && L == 64;
   int bdw1 = 1;
   float bcp1 = 0.f, bs01 = 0.f, btg1 = 0.f;
+  // RANDOM: each slot's 4 Philox words of the current group of 4 steps; where
+  // PACK holds, the 4 levels they give instead, one per byte (fewer registers
+  // across the step, which pays in the 64-lane and extended kernels)
+  constexpr bool PACK = EXT || AHEAD2;
   U4 aw[P];
+  uint32_t kp[P];
 #pragma unroll
-  for (int j = 0; j < P; ++j) aw[j] = U4{0, 0, 0, 0};
+  for (int j = 0; j < P; ++j) {
+    aw[j] = U4{0, 0, 0, 0};
+    kp[j] = 0;
+  }
   const uint64_t smask = (L == 64) ? ~0ull : (((1ull << (L & 63)) - 1ull) << sbase);
   const uint64_t below_mask = (1ull << lane) - 1ull;
 
@@ -395,22 +403,35 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
     int kb = 0;  // the battery's action byte (level + n_levels)
     if (dy.mode == CX_ACT_RANDOM) {
       if (t == 0 || (g & 3u) == 0) {
+        // action bytes are at most 254 (n_levels <= 254; 127 with discharging)
+        const uint32_t nk = (uint32_t)(n_levels + n_neg + 1);
 #pragma unroll
-        for (int j = 0; j < P; ++j) aw[j] = philox(env_id, g >> 2, (uint32_t)port[j], kDomAct, k0, k1);
+        for (int j = 0; j < P; ++j) {
+          const U4 w = philox(env_id, g >> 2, (uint32_t)port[j], kDomAct, k0, k1);
+          if constexpr (PACK)
+            kp[j] = __umulhi(w.x, nk) | (__umulhi(w.y, nk) << 8) | (__umulhi(w.z, nk) << 16) | (__umulhi(w.w, nk) << 24);
+          else
+            aw[j] = w;
+        }
         if constexpr (EXT) {
-          if (batt) bw = philox(env_id, g >> 2, (uint32_t)N, kDomAct, k0, k1);
+          if (batt) {
+            const U4 w = philox(env_id, g >> 2, (uint32_t)N, kDomAct, k0, k1);
+            const uint32_t nb = (uint32_t)(2 * n_levels + 1);
+            bkp = __umulhi(w.x, nb) | (__umulhi(w.y, nb) << 8) | (__umulhi(w.z, nb) << 16) | (__umulhi(w.w, nb) << 24);
+          }
         }
       }
-      const uint32_t sel = g & 3u;
+      const uint32_t sel = g & 3u, sh = 8u * sel;
 #pragma unroll
       for (int j = 0; j < P; ++j) {
-        const uint32_t w = sel == 0 ? aw[j].x : sel == 1 ? aw[j].y : sel == 2 ? aw[j].z : aw[j].w;
-        k[j] = (int)__umulhi(w, (uint32_t)(n_levels + n_neg + 1));
+        if constexpr (PACK) {
+          k[j] = (int)((kp[j] >> sh) & 0xFFu);
+        } else {
+          const uint32_t w = sel == 0 ? aw[j].x : sel == 1 ? aw[j].y : sel == 2 ? aw[j].z : aw[j].w;
+          k[j] = (int)__umulhi(w, (uint32_t)(n_levels + n_neg + 1));
+        }
       }
-      if constexpr (EXT) {
-        const uint32_t w = sel == 0 ? bw.x : sel == 1 ? bw.y : sel == 2 ? bw.z : bw.w;
-        kb = (int)__umulhi(w, (uint32_t)(2 * n_levels + 1));
-      }
+      if constexpr (EXT) kb = (int)((bkp >> sh) & 0xFFu);
     } else if (dy.mode == CX_ACT_MAX) {
 #pragma unroll
       for (int j = 0; j < P; ++j) k[j] = n_levels + n_neg;
