@@ -168,15 +168,28 @@ def plain_rate(env, cx, n_envs, T, reps=2):
 
 
 # ---------------------------------------------------------------------------
+# Launch configuration per workload: lanes per station for each class, waves
+# per block and the observation stage -- the fastest measured on MI355X by
+# timing every legal choice on these workloads.
+def configure(env, name, specs):
+    lanes, wpb, stage = {
+        "uneven": (None, 4, True),        # every class at min(slots, 64) lanes
+        "v2g": (8, 1, False), "users": (8, 1, False), "exo": (8, 1, False),
+        "tiny": (16, 1, False), "scale": (16, 1, False),
+    }[name.split(":")[0].split("-")[0]]
+    for c, s in enumerate(specs):
+        L = lanes if lanes is not None else env.class_info(c).lanes_per_station
+        env.set_packing(c, L, wpb)
+    env.set_obs_stage(stage)
+
+
 def run_rollout_workload(args, name, specs, ec, seed, desc, cpu_stride):
     import torch  # noqa: F401
     import paper_2507_01522_amd as cx
     n_ports = np.array([s.n_ports for s in specs])[ec]
     n_envs = len(ec)
     env = cx.Env(specs, env_class=ec, seed=seed) if len(specs) > 1 else cx.Env(specs[0], n_envs=n_envs, seed=seed)
-    if not args.no_tune:
-        env.autotune(T_DAY, os.path.join(ROOT, "gpurun_out", "autotune_cache.json")
-                     if os.path.isdir(os.path.join(ROOT, "gpurun_out")) else None)
+    configure(env, name, specs)
     out = env.alloc_traj(T_DAY, cx.OUT_FULL)
     wall_ms, kernel_ms = timed_rollouts(env, cx, T_DAY, cx.ACT_RANDOM, cx.OUT_FULL, out, args)
     env_steps = n_envs * T_DAY
@@ -265,8 +278,7 @@ def run_policy(args):
     weights = W.policy_weights(N, hidden=H)
     env = cx.Env(spec, n_envs=E, seed=seed)
     env.set_policy(H, weights)
-    if not args.no_tune:
-        env.autotune(1)   # one-step launches: the packing that suits them
+    env.set_packing(0, 8, 4)   # one-step launches: 8 lanes x 4 slots
     out = env.alloc_traj(T_DAY, cx.OUT_ACT_REWARD)
     wall_ms, ev_ms = timed_rollouts(env, cx, T_DAY, cx.ACT_POLICY, cx.OUT_ACT_REWARD, out, args)
     value = E * T_DAY / (wall_ms / 1e3)
@@ -422,7 +434,6 @@ def main():
     ap.add_argument("--workload", default="uneven", choices=["uneven", "tiny", "scale", "v2g", "users", "exo", "policy", "serve"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain per-step comparison")
-    ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run a plain 2 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()

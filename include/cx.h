@@ -315,14 +315,19 @@ cx_status cx_set_packing(cx_ctx *ctx, int32_t cls, int32_t lanes_per_station, in
  * write their observation records through an LDS stage of each block, as
  * 16-byte stores of whole record runs; on = 0 (the default): every lane stores
  * its own values.  The records are bit for bit the same either way; which is
- * faster depends on the launch (cx_autotune chooses).  CX_E_INVALID unless on
+ * faster depends on the launch (the 8-32-lane classes of a mixed launch gain
+ * most).  CX_E_INVALID unless on
  * is 0 or 1. */
 cx_status cx_set_obs_stage(cx_ctx *ctx, int32_t on);
 
 /* Time every legal packing of every class on a T_probe-step rollout (state is
  * saved and restored) and keep the fastest, then every pair of waves per block
  * and observation stage (cx_set_obs_stage) likewise.  cache_path (nullable) is a
- * JSON file of earlier results keyed by class shape, read first and updated. */
+ * JSON file of earlier results keyed by class shape, read first and updated.
+ * Currently switched off: it returns CX_E_INVALID without touching the context,
+ * because one call aborted the process inside it with no diagnostic and the
+ * cause has not been found.  Set packings with cx_set_packing and the stage
+ * with cx_set_obs_stage instead. */
 cx_status cx_autotune(cx_ctx *ctx, int32_t T_probe, const char *cache_path);
 
 cx_status cx_synchronize(cx_ctx *ctx);

@@ -15,6 +15,8 @@
 namespace cx {
 namespace {
 
+constexpr bool kAutotuneEnabled = false;
+
 std::map<std::string, int> read_cache(const char *path) {
   std::map<std::string, int> m;
   if (!path) return m;
@@ -78,6 +80,14 @@ extern "C" cx_status cx_autotune(cx_ctx *ctx, int32_t T_probe, const char *cache
   if (!ctx) return fail_status(CX_E_INVALID, "context is NULL");
   if (ctx->failed) return fail_status(CX_E_DEVICE, "context has a sticky device error");
   if (T_probe < 1 || T_probe > 4096) return fail_status(CX_E_INVALID, "T_probe must be in 1..4096");
+  // Switched off: one call aborted the process inside the tuner without any
+  // diagnostic and the cause is not known yet.  The search below stays for
+  // when it is found; until then packings, block size and the stage are set
+  // with cx_set_packing and cx_set_obs_stage.
+  if (!kAutotuneEnabled)
+    return fail_status(CX_E_INVALID,
+                       "cx_autotune is switched off (an unexplained abort inside it is under investigation); "
+                       "set the packing with cx_set_packing and cx_set_obs_stage");
   std::map<std::string, int> cache = read_cache(cache_path);
   hipError_t e;
   void *saved = nullptr, *scratch = nullptr;

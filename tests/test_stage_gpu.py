@@ -115,6 +115,8 @@ def test_staged_policy_loop(cxm):
     same(*outs)
 
 
+@pytest.mark.skip(reason="cx_autotune is switched off: one run of this test aborted the process inside "
+                         "cx_autotune with no diagnostic (no device fault reported) and the cause is not found")
 def test_autotune_keeps_records(cxm, tmp_path):
     """Whatever the autotuner picks (packings, block size, stage), the records
     are those of the untuned launch."""
@@ -130,6 +132,16 @@ def test_autotune_keeps_records(cxm, tmp_path):
     # other packings may sum a station's powers in another order: FP32 rounding only
     for k in ("reward", "obs"):
         assert np.allclose(ra[k], rb[k], rtol=1e-5, atol=1e-5), k
+
+
+def test_autotune_switched_off(cxm):
+    """cx_autotune refuses before any device work and leaves the context as it was."""
+    env = cxm.Env(W.tiny_parity_station(), n_envs=4, seed=1)
+    before = env.info()
+    with pytest.raises(cxm.CxError, match="switched off"):
+        env.autotune(4)
+    after = env.info()
+    assert (after.obs_stage, env.class_info(0).lanes_per_station) == (before.obs_stage, 16)
 
 
 def test_obs_stage_argument_checked(cxm):
