@@ -304,6 +304,8 @@ class Env:
         check(lib().cx_set_obs_stage(self.h, 1 if on else 0))
 
     def autotune(self, T_probe: int = 32, cache_path: Optional[str] = None):
+        """cx_autotune; currently switched off in the library (raises CxError):
+        set packings with set_packing and the stage with set_obs_stage."""
         check(lib().cx_autotune(self.h, T_probe, None if cache_path is None else cache_path.encode()))
 
     def synchronize(self):
