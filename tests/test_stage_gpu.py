@@ -3,7 +3,8 @@ to 32 lanes per station write their observations through each block's stage as
 16-byte runs.  The records must be bit for bit those of lane-by-lane stores:
 in every packing and block size, for ragged env counts (partial blocks, runs
 that start at any 4-byte offset), across the day boundary, in one-step
-launches, in the policy loop and after autotuning; and they must match the
+launches, in the policy loop and after autotuning (skipped while cx_autotune is
+switched off); and they must match the
 oracle."""
 import numpy as np
 import pytest
