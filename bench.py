@@ -173,10 +173,10 @@ def plain_rate(env, cx, n_envs, T, reps=2):
 # timing every legal choice on these workloads.
 def configure(env, name, specs):
     lanes, wpb, stage = {
-        "uneven": (None, 4, True),        # every class at min(slots, 64) lanes
+        "uneven-batching": (None, 4, True),   # every class at min(slots, 64) lanes
         "v2g": (8, 1, False), "users": (8, 1, False), "exo": (8, 1, False),
         "tiny": (16, 1, False), "scale": (16, 1, False),
-    }[name.split(":")[0].split("-")[0]]
+    }[name.split(":")[0]]   # the workload's name opens its description
     for c, s in enumerate(specs):
         L = lanes if lanes is not None else env.class_info(c).lanes_per_station
         env.set_packing(c, L, wpb)
