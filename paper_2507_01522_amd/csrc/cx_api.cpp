@@ -112,21 +112,23 @@ size_t class_block(const SpecCopy &sc, const Compiled &k, const Tables &t, unsig
   d.dense_nodes = k.dense_nodes;
   d.pmax_u = k.slot_pmax[0];
   d.inv_pmax_u = k.slot_inv_pmax[0];
-  d.slot_port = reinterpret_cast<const int32_t *>(base + o_port);
-  d.slot_pmax = reinterpret_cast<const float *>(base + o_pmax);
-  d.slot_inv_pmax = reinterpret_cast<const float *>(base + o_ipmax);
-  d.slot_inv_eta = reinterpret_cast<const float *>(base + o_ieta);
-  d.slot_lb = reinterpret_cast<const uint32_t *>(base + o_lb);
-  d.slot_cap = reinterpret_cast<const float *>(base + o_cap);
-  d.tpois = reinterpret_cast<const uint32_t *>(base + o_tp);
-  d.tdwell = reinterpret_cast<const uint32_t *>(base + o_td);
-  d.glob = reinterpret_cast<const float *>(base + o_gl);
-  d.slot_pdis = reinterpret_cast<const float *>(base + o_pdis);
-  d.slot_eta = reinterpret_cast<const float *>(base + o_eta);
-  d.price_days = reinterpret_cast<const float *>(base + o_days);
-  d.model_thresh = reinterpret_cast<const uint32_t *>(base + o_mth);
-  d.model_data = reinterpret_cast<const float *>(base + o_mdat);
-  d.slot_dc = reinterpret_cast<const int32_t *>(base + o_sdc);
+  // device addresses of the arrays (none in the size-only pass)
+  auto at = [base](size_t o) { return base ? base + o : nullptr; };
+  d.slot_port = reinterpret_cast<const int32_t *>(at(o_port));
+  d.slot_pmax = reinterpret_cast<const float *>(at(o_pmax));
+  d.slot_inv_pmax = reinterpret_cast<const float *>(at(o_ipmax));
+  d.slot_inv_eta = reinterpret_cast<const float *>(at(o_ieta));
+  d.slot_lb = reinterpret_cast<const uint32_t *>(at(o_lb));
+  d.slot_cap = reinterpret_cast<const float *>(at(o_cap));
+  d.tpois = reinterpret_cast<const uint32_t *>(at(o_tp));
+  d.tdwell = reinterpret_cast<const uint32_t *>(at(o_td));
+  d.glob = reinterpret_cast<const float *>(at(o_gl));
+  d.slot_pdis = reinterpret_cast<const float *>(at(o_pdis));
+  d.slot_eta = reinterpret_cast<const float *>(at(o_eta));
+  d.price_days = reinterpret_cast<const float *>(at(o_days));
+  d.model_thresh = reinterpret_cast<const uint32_t *>(at(o_mth));
+  d.model_data = reinterpret_cast<const float *>(at(o_mdat));
+  d.slot_dc = reinterpret_cast<const int32_t *>(at(o_sdc));
   if (view) *view = d;
   if (host) {
     host->assign(off, 0);

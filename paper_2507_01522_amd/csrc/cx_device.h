@@ -13,7 +13,6 @@ namespace {
 struct U4 {
   uint32_t x, y, z, w;
 };
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 // Philox4x32-10 (Salmon et al., SC'11).  The key is wave-uniform, so its
 // schedule stays in scalar registers.

@@ -208,6 +208,25 @@ struct RolloutGraph {
   int shape[kNumKinds * kNumPackings][4] = {};  // kernel, blocks, waves per block, LDS bytes
 };
 
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// Arguments of the policy kernel (cx_policy.hip): the perceptron's weights in
+// fragment order and one step's observations in, levels and / or logits out.
+struct PolicyArgs {
+  const float *obs;  // [n][in_dim]
+  int64_t n;
+  int32_t in_dim, K1, HP, R, G, N, L1;
+  uint32_t g;        // global step of the draws
+  const u32x4 *w1f;  // [2 HP][K1][64] fragments of W1^T
+  const float *b1;   // [32 HP]
+  const u32x4 *w2f;  // [G][R][HP][64] fragments of W2^T
+  const float *b2f;  // [G][R][16]
+  uint8_t *act;      // [n][N] or NULL
+  float *logits;     // [n][N * L1] or NULL
+  uint64_t seed;
+  int64_t env0;      // Philox index of env 0
+};
+
 // Host-side launchers (defined in cx_kernels.hip).  `a.segs` is the base of
 // the device segment table; each group launches with its own slice.
 hipError_t launch_groups(const LaunchArgs &a, const LaunchGroup *groups, int n_groups, hipStream_t st);

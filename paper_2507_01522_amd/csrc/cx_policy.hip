@@ -55,21 +55,6 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-struct PolicyArgs {
-  const float *obs;  // [n][in_dim]
-  int64_t n;
-  int32_t in_dim, K1, HP, R, G, N, L1;
-  uint32_t g;        // global step of the draws
-  const u32x4 *w1f;
-  const float *b1;
-  const u32x4 *w2f;
-  const float *b2f;
-  uint8_t *act;      // [n][N] or NULL
-  float *logits;     // [n][N * L1] or NULL
-  uint64_t seed;
-  int64_t env0;      // Philox index of env 0
-};
-
 // FP32 -> BF16, round to nearest even (finite inputs).
 __device__ __forceinline__ uint32_t bf16_rne(float f) {
   const uint32_t u = __float_as_uint(f);

@@ -15,7 +15,10 @@
 namespace cx {
 namespace {
 
-constexpr bool kAutotuneEnabled = false;
+#ifndef CX_AUTOTUNE_ON
+#define CX_AUTOTUNE_ON 0
+#endif
+constexpr bool kAutotuneEnabled = CX_AUTOTUNE_ON != 0;
 
 std::map<std::string, int> read_cache(const char *path) {
   std::map<std::string, int> m;
