@@ -259,6 +259,27 @@ cx_status cx_step_ex(cx_ctx *ctx, cx_action_mode mode, const uint8_t *actions_in
 cx_status cx_rollout(cx_ctx *ctx, int32_t T, cx_action_mode mode, cx_out_mode out_mode,
                      const uint8_t *actions_in_dev, const cx_traj *out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): cx_rollout
+ * in CX_ACT_POLICY mode whose per-step scratch -- one step of observations
+ * (obs_elems floats, rounded up to 256 bytes) and one step of levels
+ * (total_ports bytes) -- lives in a fixed array of the library's device image,
+ * CX_NOALLOC_SCRATCH_BYTES per GPU, held until the process ends, instead of a
+ * buffer the context allocates.  The call allocates nothing (no hipMalloc, no
+ * hipFree, no allocating library routine) and launches the same kernels as
+ * cx_rollout, so its records are bit for bit those of cx_rollout with
+ * CX_ACT_POLICY on an equal context.  The caller passes the outputs (out, as
+ * for cx_rollout) and must have created the context and set its policy
+ * beforehand.  CX_E_INVALID (nothing launched) if the context needs more
+ * scratch than the fixed size (about 41,000 envs of 32 ports) or has no policy.
+ * Every call on one GPU shares that GPU's array, which keeps the last call's
+ * contents; nothing in it needs clearing (each element is written before it is
+ * read), but calls that overlap on one GPU (several contexts or streams at
+ * once) race on it and must be serialised by the caller.  The array's address
+ * is looked up on the first call on each device. */
+#define CX_NOALLOC_SCRATCH_BYTES 33554432
+cx_status cx_rollout_policy_noalloc(cx_ctx *ctx, int32_t T, cx_out_mode out_mode, const cx_traj *out);
+
 /* Policy for CX_ACT_POLICY: a two-layer perceptron obs -> hidden (tanh) ->
  * n_ports*(n_levels+1) logits, BF16 weights (uint16 bit patterns, host memory):
  * w1 [obs_dim][hidden], b1 [hidden], w2 [hidden][n_ports*(n_levels+1)], b2.

@@ -24,6 +24,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "cx_ctx.h"
@@ -413,22 +414,24 @@ void free_policy(cx_ctx *ctx) {
   ctx->policy = nullptr;
 }
 
-cx_status policy_step(cx_ctx *ctx, int32_t T, cx_out_mode out_mode, const cx_traj *out, bool graph) {
-  (void)graph;
-  if (!ctx->policy) return fail_status(CX_E_INVALID, "no policy set (cx_set_policy)");
-  cx_status st = ensure_scratch(ctx);
-  if (st != CX_OK) return st;
+namespace {
+
+// One policy rollout with the given scratch: obs_scr one step of observations
+// (obs_elems floats), act_scr one step of levels (total_ports bytes).  Every
+// element of both is written before it is read, so their contents on entry do
+// not matter.
+cx_status policy_step_with(cx_ctx *ctx, int32_t T, cx_out_mode out_mode, const cx_traj *out, float *obs_scr,
+                           uint8_t *act_scr) {
   const bool ret_obs = out && out_mode == CX_OUT_FULL && out->obs;
   const bool ret_act = out && out_mode != CX_OUT_REWARD && out->actions;
   if (ret_obs && (reinterpret_cast<uintptr_t>(out->obs) & 15u) != 0)
     return fail_status(CX_E_INVALID, "policy rollout: obs buffer must be 16-byte aligned");
-  PolicyRt &p = *ctx->policy;
-  hipError_t e = launch_observe(ctx, p.obs, ctx->stream);
+  hipError_t e = launch_observe(ctx, obs_scr, ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "policy rollout: observation kernel");
-  const float *obs_prev = p.obs;
+  const float *obs_prev = obs_scr;
   for (int32_t t = 0; t < T; ++t) {
-    float *obs_t = ret_obs ? out->obs + (int64_t)t * ctx->obs_elems : p.obs;
-    uint8_t *act_t = ret_act ? out->actions + (int64_t)t * ctx->total_ports : p.act;
+    float *obs_t = ret_obs ? out->obs + (int64_t)t * ctx->obs_elems : obs_scr;
+    uint8_t *act_t = ret_act ? out->actions + (int64_t)t * ctx->total_ports : act_scr;
     PolicyArgs pa = policy_args(ctx, obs_prev, ctx->n_envs);
     pa.g = ctx->g + (uint32_t)t;
     pa.act = act_t;
@@ -453,6 +456,54 @@ cx_status policy_step(cx_ctx *ctx, int32_t T, cx_out_mode out_mode, const cx_tra
   // read obs_prev), so the clock is the only state carried here
   advance_clock(ctx, T);
   return CX_OK;
+}
+
+}  // namespace
+
+// Scratch of the rollout that allocates nothing (cx_rollout_policy_noalloc):
+// a fixed array of the device image, one per GPU the library runs on, held
+// until the process ends.  In host code its name is only a stand-in for the
+// device array: the address kernels take is looked up per device.
+constexpr size_t kNoAllocScratchBytes = (size_t)CX_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on `device`, looked up on the first call for
+// that device with the device current (each GPU has its own copy).
+cx_status noalloc_scratch(int device, unsigned char **ptr) {
+  if (device < 0 || device >= kMaxDevices) return fail_status(CX_E_INVALID, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return fail_status(CX_E_DEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    if (cur != device && (e = hipSetDevice(device)) != hipSuccess)
+      return fail_status(CX_E_DEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e));
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != device) (void)hipSetDevice(cur);
+    if (e != hipSuccess || !p)
+      return fail_status(CX_E_DEVICE, std::string("hipGetSymbolAddress of the no-allocation scratch: ") +
+                                          hipGetErrorString(e));
+    g_scratch_ptr[device] = p;
+  }
+  *ptr = static_cast<unsigned char *>(g_scratch_ptr[device]);
+  return CX_OK;
+}
+
+}  // namespace
+
+cx_status policy_step(cx_ctx *ctx, int32_t T, cx_out_mode out_mode, const cx_traj *out, bool graph) {
+  (void)graph;
+  if (!ctx->policy) return fail_status(CX_E_INVALID, "no policy set (cx_set_policy)");
+  cx_status st = ensure_scratch(ctx);
+  if (st != CX_OK) return st;
+  return policy_step_with(ctx, T, out_mode, out, ctx->policy->obs, ctx->policy->act);
 }
 
 }  // namespace cx
@@ -584,6 +635,26 @@ cx_status cx_policy_sample(cx_ctx *ctx, const float *obs_dev, int64_t n, uint32_
   hipError_t e = launch_policy(a, ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "cx_policy_sample launch");
   return CX_OK;
+}
+
+cx_status cx_rollout_policy_noalloc(cx_ctx *ctx, int32_t T, cx_out_mode out_mode, const cx_traj *out) {
+  if (!ctx) return fail_status(CX_E_INVALID, "context is NULL");
+  if (ctx->failed) return fail_status(CX_E_DEVICE, "context has a sticky device error");
+  if (T < 0 || T > (1 << 24)) return fail_status(CX_E_INVALID, "T must be in 0..2^24");
+  if (out_mode < CX_OUT_FULL || out_mode > CX_OUT_ACT_REWARD) return fail_status(CX_E_INVALID, "bad out mode");
+  if (!ctx->policy) return fail_status(CX_E_INVALID, "no policy set (cx_set_policy)");
+  // one step of observations (16-byte aligned for the policy kernel), then one of levels
+  const size_t obs_bytes = ((size_t)ctx->obs_elems * sizeof(float) + 255) & ~(size_t)255;
+  const size_t need = obs_bytes + (size_t)ctx->total_ports;
+  if (need > kNoAllocScratchBytes)
+    return fail_status(CX_E_INVALID, "cx_rollout_policy_noalloc: the context needs " + std::to_string(need) +
+                                         " bytes of scratch per step, more than the fixed " +
+                                         std::to_string(kNoAllocScratchBytes) + " bytes");
+  if (T == 0) return CX_OK;
+  unsigned char *base = nullptr;
+  cx_status st = noalloc_scratch(ctx->device, &base);
+  if (st != CX_OK) return st;
+  return policy_step_with(ctx, T, out_mode, out, reinterpret_cast<float *>(base), base + obs_bytes);
 }
 
 cx_status cx_observe(cx_ctx *ctx, float *obs_dev) {

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libcx.so")
 CX_OK = 0
 ACT_EXTERNAL, ACT_RANDOM, ACT_MAX, ACT_POLICY = 0, 1, 2, 3
 OUT_FULL, OUT_REWARD, OUT_ACT_REWARD = 0, 1, 2
+NOALLOC_SCRATCH_BYTES = 33554432   # CX_NOALLOC_SCRATCH_BYTES of include/cx.h
 STATUS_NAMES = {0: "CX_OK", -1: "CX_E_INVALID", -2: "CX_E_OOM", -3: "CX_E_DEVICE", -4: "CX_E_BUSY",
                 -5: "CX_E_BUDGET", -6: "CX_E_CANCELLED", -7: "CX_E_NOTFOUND"}
 
@@ -89,7 +90,7 @@ EXPORTS = ["cx_create", "cx_create_multi", "cx_set_stream", "cx_get_info", "cx_g
            "cx_set_state", "cx_get_tables", "cx_set_packing", "cx_set_obs_stage", "cx_autotune", "cx_synchronize",
            "cx_last_error", "cx_destroy", "cx_server_create", "cx_submit", "cx_poll", "cx_wait",
            "cx_cancel", "cx_release", "cx_server_stats", "cx_server_destroy", "cx_compile_layout",
-           "cx_build_tables"]
+           "cx_build_tables", "cx_rollout_policy_noalloc"]
 
 _lib = None
 
@@ -118,6 +119,7 @@ def lib() -> C.CDLL:
         "cx_wait": [P, U64, P], "cx_cancel": [P, U64], "cx_release": [P, U64],
         "cx_server_stats": [P, P, P, P, P], "cx_server_destroy": [P],
         "cx_compile_layout": [P, P, P, P, P, P], "cx_build_tables": [P, P, P],
+        "cx_rollout_policy_noalloc": [P, I32, I32, P],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -348,6 +350,17 @@ class Env:
             out = self.alloc_traj(T, out_mode)
         t = self._traj(out)
         check(lib().cx_rollout(self.h, T, mode, out_mode, _p(actions), C.byref(t)))
+        return out
+
+    def rollout_policy_noalloc(self, T: int, out_mode: int = OUT_FULL,
+                               out: Optional[Dict[str, torch.Tensor]] = None) -> Dict[str, torch.Tensor]:
+        """cx_rollout_policy_noalloc: a policy rollout whose per-step scratch is the
+        library's fixed device array (the library allocates nothing; the output
+        buffers are allocated here unless given)."""
+        if out is None:
+            out = self.alloc_traj(T, out_mode)
+        t = self._traj(out)
+        check(lib().cx_rollout_policy_noalloc(self.h, T, out_mode, C.byref(t)))
         return out
 
     # ---- state

@@ -277,6 +277,9 @@ void run_policy(Scenario &sc) {
   CK(cx_policy_sample(ctx, tr.t.obs, E, 3, tr.t.actions));
   CK(cx_set_policy(ctx, H, w1.data(), b1.data(), w2.data(), b2.data()));  // replaced in place
   CK(cx_rollout(ctx, T, CX_ACT_POLICY, CX_OUT_REWARD, nullptr, &tr.t));
+  // the rollout that allocates nothing: scratch in the library's fixed array
+  CK(cx_rollout_policy_noalloc(ctx, T, CX_OUT_ACT_REWARD, &tr.t));
+  CK(cx_rollout_policy_noalloc(ctx, T, CX_OUT_FULL, &tr.t));
   CK(cx_synchronize(ctx));
   cx_destroy(ctx);
 }

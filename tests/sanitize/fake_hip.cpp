@@ -50,10 +50,21 @@ namespace fake {
 struct Alloc {
   size_t size;
   bool pinned;  // host memory from hipHostMalloc
+  bool symbol = false;  // a __device__ variable of the image (lives until the process ends)
 };
 
-std::mutex amu;                            // guards allocs
+std::mutex amu;                            // guards allocs and symbols
 std::map<uintptr_t, Alloc> allocs;         // live allocations by base address (used after main starts)
+// device copies of __device__ variables by host shadow address (filled by the
+// module constructors, before main: a function-local static)
+struct Symbol {
+  size_t size;
+  void *dev;
+};
+std::map<const void *, Symbol> &symbols() {
+  static std::map<const void *, Symbol> m;
+  return m;
+}
 std::atomic<long> n_graph_destroy_in_flight{0};
 
 // Does [p, p + n) lie inside one live allocation?  (n = 0: p inside or at its end.)
@@ -455,6 +466,12 @@ void **__hipRegisterFatBinary(const void *) {
   return &handle;
 }
 void __hipUnregisterFatBinary(void **) {}
+// A __device__ variable: its device copy is host memory of the variable's size,
+// made (and entered as a live allocation for the range checks) when its
+// address is first asked for; module constructors only record the size.
+void __hipRegisterVar(void **, void *var, char *, char *, int, size_t size, int, int) {
+  symbols()[var] = Symbol{size, nullptr};
+}
 void __hipRegisterFunction(void **, const void *hostFunction, char *deviceFunction, const char *, unsigned int,
                            uint3 *, uint3 *, dim3 *, dim3 *, int *) {
   KernelInfo k = describe(deviceFunction);
@@ -483,6 +500,19 @@ hipError_t hipLaunchKernel(const void *f, dim3 g, dim3 b, void **args, size_t ld
   if (lds > (160u << 10)) return ret(hipErrorInvalidValue);
   Launch l = make_launch(f, g, b, args, lds);
   dev().push([l] { run_kernel(l); });
+  return hipSuccess;
+}
+
+hipError_t hipGetSymbolAddress(void **p, const void *symbol) {
+  std::lock_guard<std::mutex> lk(amu);
+  auto it = symbols().find(symbol);
+  if (!p || it == symbols().end()) return ret(hipErrorInvalidSymbol);
+  Symbol &v = it->second;
+  if (!v.dev) {
+    v.dev = std::aligned_alloc(256, std::max<size_t>(256, (v.size + 255) & ~(size_t)255));
+    allocs[reinterpret_cast<uintptr_t>(v.dev)] = Alloc{v.size, false, true};
+  }
+  *p = v.dev;
   return hipSuccess;
 }
 
@@ -715,5 +745,7 @@ hipError_t hipGraphExecDestroy(hipGraphExec_t ex) {
 extern "C" long fake_hip_graph_destroys_in_flight() { return n_graph_destroy_in_flight.load(); }
 extern "C" long fake_hip_live_allocations() {
   std::lock_guard<std::mutex> lk(amu);
-  return (long)allocs.size();
+  long n = 0;
+  for (const auto &a : allocs) n += a.second.symbol ? 0 : 1;
+  return n;
 }

@@ -156,3 +156,13 @@ def test_invalid_specs_rejected(cxm, what, kw):
     with pytest.raises(cxm.CxError) as ei:
         cxm.compile_layout(spec)
     assert ei.value.status == -1 and str(ei.value)
+
+
+def test_noalloc_scratch_size_matches_header(cxm):
+    txt = open(os.path.join(ROOT, "include", "cx.h")).read()
+    m = re.search(r"#define CX_NOALLOC_SCRATCH_BYTES (\d+)", txt)
+    assert m and int(m.group(1)) == cxm.NOALLOC_SCRATCH_BYTES
+
+
+def test_noalloc_refuses_without_context(cxm):
+    assert cxm.lib().cx_rollout_policy_noalloc(None, 4, cxm.OUT_FULL, None) == -1
