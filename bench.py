@@ -167,29 +167,14 @@ def plain_rate(env, cx, n_envs, T, reps=2):
     return {"ms_per_rollout": p_ms, "env_steps_per_s": n_envs * T / (p_ms / 1e3), "launches_per_rollout": T}
 
 
-# ---------------------------------------------------------------------------
-# Launch configuration per workload: lanes per station for each class, waves
-# per block and the observation stage -- the fastest measured on MI355X by
-# timing every legal choice on these workloads.
-def configure(env, name, specs):
-    lanes, wpb, stage = {
-        "uneven-batching": (None, 4, True),   # every class at min(slots, 64) lanes
-        "v2g": (8, 1, False), "users": (8, 1, False), "exo": (8, 1, False),
-        "tiny": (16, 1, False), "scale": (16, 1, False),
-    }[name.split(":")[0]]   # the workload's name opens its description
-    for c, s in enumerate(specs):
-        L = lanes if lanes is not None else env.class_info(c).lanes_per_station
-        env.set_packing(c, L, wpb)
-    env.set_obs_stage(stage)
-
-
 def run_rollout_workload(args, name, specs, ec, seed, desc, cpu_stride):
     import torch  # noqa: F401
     import paper_2507_01522_amd as cx
     n_ports = np.array([s.n_ports for s in specs])[ec]
     n_envs = len(ec)
+    from paper_2507_01522_amd.launch import configure
     env = cx.Env(specs, env_class=ec, seed=seed) if len(specs) > 1 else cx.Env(specs[0], n_envs=n_envs, seed=seed)
-    configure(env, name, specs)
+    configure(env, name, len(specs))
     out = env.alloc_traj(T_DAY, cx.OUT_FULL)
     wall_ms, kernel_ms = timed_rollouts(env, cx, T_DAY, cx.ACT_RANDOM, cx.OUT_FULL, out, args)
     env_steps = n_envs * T_DAY
@@ -278,7 +263,8 @@ def run_policy(args):
     weights = W.policy_weights(N, hidden=H)
     env = cx.Env(spec, n_envs=E, seed=seed)
     env.set_policy(H, weights)
-    env.set_packing(0, 8, 4)   # one-step launches: 8 lanes x 4 slots
+    from paper_2507_01522_amd.launch import POLICY_LAUNCH
+    env.set_packing(0, *POLICY_LAUNCH)   # one-step launches: 8 lanes x 4 slots
     out = env.alloc_traj(T_DAY, cx.OUT_ACT_REWARD)
     wall_ms, ev_ms = timed_rollouts(env, cx, T_DAY, cx.ACT_POLICY, cx.OUT_ACT_REWARD, out, args)
     value = E * T_DAY / (wall_ms / 1e3)

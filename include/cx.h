@@ -213,43 +213,71 @@ typedef struct {
   int32_t n_actions;             /* action bytes per env: n_ports (+1 with a battery) */
 } cx_class_info;
 
-/* Create a context of n_envs stations of one class, state = empty stations at
- * t_day = 0, g = 0.  seed keys every Philox draw.  The spec is validated here
- * (CX_E_INVALID with a message); no later call re-checks it. */
+/* Create a context of n_envs stations of one class (Sec. 3 "EV Station
+ * Layout": the capacity tree of Eq. (ArchConst); App. A.1: the endogenous
+ * per-port and exogenous state), state = empty stations at t_day = 0, g = 0.
+ * seed keys every Philox draw.  spec: host memory, read during the call and
+ * copied; *out receives the context, owned by the caller until cx_destroy.
+ * The spec is validated here (CX_E_INVALID with a message, nothing allocated);
+ * CX_E_OOM if the device state cannot be allocated.  No later call re-checks
+ * the spec. */
 cx_status cx_create(const cx_station_spec *spec, int64_t n_envs, uint64_t seed, cx_ctx **out);
 
-/* Create a context with several station classes (the uneven-batching form):
- * env e has class env_class[e]; env_class must be non-decreasing so that every
- * class is one contiguous env range.  All specs must share steps_per_episode. */
+/* Create a context with several station classes (the uneven-batching form;
+ * each class as in cx_create, Sec. 3 and App. A.1): env e has class
+ * env_class[e] (host memory, n_envs entries); env_class must be non-decreasing
+ * so that every class is one contiguous env range.  All specs must share
+ * steps_per_episode.  Errors as for cx_create. */
 cx_status cx_create_multi(const cx_station_spec *specs, int32_t n_specs, const int32_t *env_class,
                           int64_t n_envs, uint64_t seed, cx_ctx **out);
 
 /* Use this HIP stream (hipStream_t passed as void*) for all later device work. */
 cx_status cx_set_stream(cx_ctx *ctx, void *hip_stream);
 
+/* The layout of a context's records and state (host-side introspection, no
+ * device work): cx_get_info fills *info (host) with the totals -- envs, action
+ * bytes and observation floats per step, the clock, the snapshot size, the
+ * device bytes held; cx_get_class_info fills *info with class cls's env range,
+ * its offsets inside a step's action and observation records, its observation
+ * length, slot layout, tree depth and current packing.  Together they give, for
+ * env e of class c, its actions at port_offset + (e - env_begin) n_actions and
+ * its observation at obs_offset + (e - env_begin) obs_dim of every step.
+ * CX_E_INVALID for a NULL argument or a class out of range. */
 cx_status cx_get_info(const cx_ctx *ctx, cx_info *info);
 cx_status cx_get_class_info(const cx_ctx *ctx, int32_t cls, cx_class_info *info);
 
-/* Empty every station and set t_day = 0 and the returns to 0; g is kept, so a
- * new day draws new noise.  obs_dev (nullable) receives the reset observation
- * in the obs layout of one step. */
+/* Reset at the start of an episode (Supp. B.1: episodes are one day; Table 3):
+ * empty every station, set t_day = 0, the returns to 0 and the station
+ * batteries to battery_soc0; g is kept, so a new day draws new noise (and, with
+ * price days, a new exploring-start day).  obs_dev (nullable, device, caller-
+ * owned, obs_elems floats) receives the reset observation in the obs layout of
+ * one step.  Asynchronous on the context's stream. */
 cx_status cx_reset(cx_ctx *ctx, float *obs_dev);
 
-/* One environment step, one kernel launch, state read from and written back to
- * HBM (the plain form).  actions_dev: action bytes [total_ports] (EXTERNAL).
- * obs/reward/done receive one record each (layouts of cx_traj with T = 1);
- * obs_dev may be NULL. */
+/* One environment step (App. A.2 in its order: (i) apply actions -- clip by the
+ * port maximum, the charging curve and the battery room, then Eq. (ArchConst)
+ * over the capacity tree; (ii) charge stationed cars; (iii) departures; (iv)
+ * arrivals first-come-first-served; then the reward of App. A.3 and, at the
+ * end of the day, the auto-reset of Supp. B.1), one kernel launch, state read
+ * from and written back to HBM (the plain form).  actions_dev: device, caller-
+ * owned action bytes [total_ports] (EXTERNAL; bytes above the largest level
+ * are clamped).  obs/reward/done receive one record each (layouts of cx_traj
+ * with T = 1); obs_dev may be NULL.  CX_E_INVALID for a NULL actions_dev;
+ * CX_E_DEVICE (sticky) if the launch fails. */
 cx_status cx_step(cx_ctx *ctx, const uint8_t *actions_dev, float *obs_dev, float *reward_dev,
                   uint8_t *done_dev);
 
-/* cx_step with any action mode and every output of cx_traj (T = 1).
- * actions_in_dev is read only for CX_ACT_EXTERNAL. */
+/* cx_step (App. A.2 (i)-(iv), App. A.3, Supp. B.1) with any action mode and
+ * every output of cx_traj (T = 1).  actions_in_dev is read only for
+ * CX_ACT_EXTERNAL; out (host struct of device pointers, nullable members). */
 cx_status cx_step_ex(cx_ctx *ctx, cx_action_mode mode, const uint8_t *actions_in_dev,
                      const cx_traj *out);
 
-/* T steps in one persistent launch: each wave keeps its stations' state in
- * registers for all T steps and streams the records selected by out_mode to
- * *out.  actions_in_dev ([T][total_ports] uint8) is read only for EXTERNAL.
+/* T steps (each one step of App. A.2 (i)-(iv) and App. A.3, with the auto-reset
+ * of Supp. B.1 at every day end) in one persistent launch: each wave keeps its
+ * stations' state in registers for all T steps and streams the records
+ * selected by out_mode to *out (device buffers, caller-owned, layouts of
+ * cx_traj; NULL members are not written).  actions_in_dev ([T][total_ports] uint8) is read only for EXTERNAL.
  * The launch is captured once per (T, modes, buffers) into a HIP graph and
  * replayed.  Results equal T calls of cx_step_ex.
  * CX_ACT_POLICY instead runs, per step, the policy kernel (observation ->
@@ -304,10 +332,14 @@ cx_status cx_policy_sample(cx_ctx *ctx, const float *obs_dev, int64_t n, uint32_
  * the next step.  obs_dev: obs_elems floats of device memory, caller-owned. */
 cx_status cx_observe(cx_ctx *ctx, float *obs_dev);
 
-/* Snapshot / restore of the whole state (all stations, returns, g, t_day) in a
- * packing-independent host format of cx_info.state_bytes bytes, bit-exact, so a
- * restored context continues exactly as the original.  Both calls synchronise
- * the context's stream.  Format (little endian):
+/* Snapshot / restore of the whole state (the endogenous state of App. A.1 --
+ * per port the car's SoC, target, capacity, stay and last power, the user
+ * type; per env the return and the station battery -- plus g and t_day) in a
+ * packing-independent host format of cx_info.state_bytes bytes (host memory,
+ * caller-owned; CX_E_INVALID if bytes is smaller or, for cx_set_state, the
+ * snapshot does not match the context or holds out-of-range values), bit-exact, so a restored context
+ * continues exactly as the original.  Both calls synchronise the context's
+ * stream.  Format (little endian):
  *   u64 magic 0x33305843 ('CX03'), i64 n_envs, i64 ports (sum of n_ports over
  *   the envs), u32 g, i32 t_day,
  *   then per port in env/port order (29 bytes): i32 dwell (steps left; <= 0 only

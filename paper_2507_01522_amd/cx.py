@@ -375,9 +375,10 @@ class Env:
         check(lib().cx_set_state(self.h, buf, len(blob)))
 
     def state_arrays(self) -> Dict[str, np.ndarray]:
-        """Decode get_state(): per-port dwell/soc/e_rem/cap/p_last/user (env-major port
-        order), returns, and per env the station battery's SoC and last power
-        (battery classes; other envs read as 0)."""
+        """The fields of get_state() as arrays, unchanged: per port (env-major port
+        order) dwell, q = 1 - SoC, u = 1 - target SoC, cap, p_last, user, rbar; per
+        env the return and the station battery's SoC and last power (battery
+        classes; other envs read as 0); g and t_day."""
         blob = self.get_state()
         i = self.info()
         head = np.frombuffer(blob, dtype=np.uint8, count=32)
@@ -403,9 +404,6 @@ class Env:
             off += 12 * ci.n_envs
         out = {k: np.array(rec[k]) for k in rec.dtype.names}
         out["user"] = out["user"].astype(np.int32)
-        occ = (out["dwell"] > 0) | (out["user"] == 1)
-        out["soc"] = np.where(occ, 1.0 - out["q"], 0.0)
-        out["e_rem"] = np.where(occ, (out["q"] - out["u"].astype(np.float64)) * out["cap"], 0.0)
         out["ret"] = np.array(ret)
         out["batt_soc"] = bsoc
         out["batt_p"] = bp

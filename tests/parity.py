@@ -101,10 +101,22 @@ def compare_rollout(gpu, ref, specs, env_class, check_obs=True):
         compare_obs(gpu["obs"], ref["obs"], specs, env_class)
 
 
+def snapshot_soc_erem(st):
+    """SoC and the energy still wanted of every port from the snapshot's fields
+    (the library keeps a car as q = 1 - SoC and u = 1 - target SoC, so the
+    energy still wanted is (q - u) C); empty ports read 0."""
+    occ = (st["dwell"] > 0) | (st["user"] == 1)
+    soc = np.where(occ, 1.0 - st["q"], 0.0)
+    e_rem = np.where(occ, (st["q"] - st["u"].astype(np.float64)) * st["cap"], 0.0)
+    return soc, e_rem
+
+
 def compare_state(st, bs, specs, env_class, keep=None):
     """st: Env.state_arrays(); bs: oracle BatchState.  keep: optional env mask
     (envs left out after a float-decided departure went the other way)."""
     env_class = np.asarray(env_class)
+    st = dict(st)
+    st["soc"], st["e_rem"] = snapshot_soc_erem(st)
     keep = np.ones(len(env_class), bool) if keep is None else np.asarray(keep, bool)
     pk = np.repeat(keep, np.diff(bs.port_off))
     assert np.array_equal(st["dwell"][pk], bs.dwell[pk]), "dwell differs"
@@ -212,3 +224,84 @@ def compare_rollout_flips(o, gpu, ref, specs, env_class, seed, mode=1, act_in=No
             sub["actions"], rsub["act"] = gpu["actions"][:, acols], ref["act"][:, acols]
         compare_rollout(sub, rsub, specs, env_class[ks], check_obs=False)
     return flips, keep
+
+
+# ---- full-size launches, sampled ---------------------------------------------
+
+def sampled_columns(specs, env_class, ids):
+    """Columns of the action bytes and of the observation floats of envs ``ids``."""
+    ao, oo = env_layout(specs, env_class)
+    acols = np.concatenate([np.arange(ao[e], ao[e + 1]) for e in ids])
+    ocols = np.concatenate([np.arange(oo[e], oo[e + 1]) for e in ids])
+    return acols, ocols
+
+
+def subset_state(st, specs, env_class, ids):
+    """The fields of a snapshot (Env.state_arrays()) for envs ``ids`` only."""
+    n_ports = np.array([s.n_ports for s in specs])[np.asarray(env_class)]
+    po = np.concatenate([[0], np.cumsum(n_ports)]).astype(np.int64)
+    pidx = np.concatenate([np.arange(po[e], po[e + 1]) for e in ids])
+    out = {}
+    for k, v in st.items():
+        if isinstance(v, np.ndarray) and len(v) == po[-1]:
+            out[k] = v[pidx]
+        elif isinstance(v, np.ndarray) and len(v) == len(env_class):
+            out[k] = v[ids]
+        else:
+            out[k] = v
+    return out
+
+
+def block_edge_ids(ec, lanes_of_class, wpb, extra=(), seed=0, n_random=16):
+    """Envs at the edges of every class and of its launch blocks (a block runs
+    wpb waves of 64 / lanes stations): the first and last env of each class, the
+    last env of its first two blocks and the first of its second and third, plus
+    a few random ones."""
+    ec = np.asarray(ec)
+    ids = set(int(x) for x in extra)
+    for c in np.unique(ec):
+        env = np.flatnonzero(ec == c)
+        b, n = int(env[0]), len(env)
+        spb = wpb * (64 // lanes_of_class[int(c)])
+        for x in (0, n - 1, spb - 1, spb, 2 * spb - 1, 2 * spb, n - spb, n - spb - 1):
+            if 0 <= x < n:
+                ids.add(b + x)
+    rng = np.random.default_rng(seed)
+    ids |= set(int(x) for x in rng.choice(len(ec), n_random, replace=False))
+    return np.array(sorted(ids), np.int64)
+
+
+def run_full_size_sampled(cxm, o, specs, ec_full, seed, T, workload, ids, flips=False):
+    """A rollout of every env of ec_full in the launch configuration that bench.py
+    times for ``workload``; envs ``ids`` (records and final state) replayed in the
+    oracle.  flips: charge-sensitive users, accept near-tie departures (at most 1
+    in 50 sampled envs).  Returns the library's records of the sampled envs."""
+    import torch
+    from paper_2507_01522_amd.launch import configure
+    ec_full = np.asarray(ec_full, np.int32)
+    n = len(ec_full)
+    env = cxm.Env(specs, env_class=ec_full, seed=seed) if len(specs) > 1 else cxm.Env(specs[0], n_envs=n, seed=seed)
+    configure(env, workload, len(specs))
+    out = env.rollout(T, cxm.ACT_RANDOM)
+    acols, ocols = sampled_columns(specs, ec_full, ids)
+    dev = lambda a: torch.from_numpy(np.asarray(a, np.int64)).to(out["reward"].device)
+    g = {"actions": out["actions"][:, dev(acols)].cpu().numpy(),
+         "reward": out["reward"][:, dev(ids)].cpu().numpy(),
+         "done": out["done"][:, dev(ids)].cpu().numpy(),
+         "obs": out["obs"][:, dev(ocols)].cpu().numpy()}
+    del out
+    ec = ec_full[ids]
+    bs = o.BatchState([o.OracleClass(s) for s in specs], ec, env_ids=ids)
+    ref = o.rollout(bs, seed, T)
+    st = subset_state(env.state_arrays(), specs, ec_full, ids)
+    if flips:
+        first = env_mismatch_steps(g, ref, specs, ec)
+        for e in np.flatnonzero(first < T):
+            ties = near_tie_steps(o, specs[ec[e]], seed, int(ids[e]), int(first[e]) + 1)
+            assert any(first[e] - 2 <= s <= first[e] for s in ties), (ids[e], first[e])
+        assert (first < T).sum() <= max(1, len(ids) // 50)
+        compare_state(st, bs, specs, ec, keep=first >= T)
+    else:
+        compare_rollout(g, ref, specs, ec)
+        compare_state(st, bs, specs, ec)
+    return g, env

@@ -74,3 +74,38 @@ def test_gumbel_argmax_is_softmax_sampling(oracle_lib):
     for port in range(spec.n_ports):
         chi = ((counts[port] - n * p) ** 2 / (n * p)).sum()
         assert stats.chi2.sf(chi, L1 - 1) > 1e-4, (port, counts[port], n * p)
+
+
+def test_tiny_perceptron_hand_worked(oracle_lib):
+    """Two ports, levels {0, 1}, two hidden units, every operand a BF16 value,
+    worked by hand (pins the weight layouts, where tanh and the two BF16
+    roundings sit, and which logit belongs to which port and level):
+
+      obs x = (0.5, 0.25, 0.3, 0, ...); 0.3 rounds to BF16 0.30078125
+      W1 [feature][hidden]: W1[0][0] = 1, W1[1][0] = 2, W1[0][1] = -2, W1[2][1] = 4;
+      b1 = (0, 0.25)
+        a0 = 0.5 + 0.5 = 1                    h0 = bf16(tanh 1)        = 0.76171875
+        a1 = -1 + 4 * 0.30078125 + 0.25 = 0.453125
+                                              h1 = bf16(tanh 0.453125) = 0.423828125
+        (no rounding of x would give a1 = 0.45, h1 = 0.421875)
+      W2 [hidden][port * 2 + level] = ((2, -1, 0.5, 0), (0.5, 4, 0, -3)); b2 = (0, 64, 64, -1)
+        z = (2 h0 + 0.5 h1, 64 - h0 + 4 h1, 64 + 0.5 h0, -1 - 3 h1)
+          = (1.7353515625, 64.93359375, 64.380859375, -2.271484375)
+    Gumbel noise lies in [-2.9, 17.3], so port 0 takes level 1 and port 1 level 0."""
+    o = oracle_lib
+    spec = W.single_transformer(2, 1000.0).replace(n_levels=1)
+    assert spec.obs_dim == 16
+    c = o.OracleClass(spec)
+    H = 2
+    w1 = np.zeros((16, H))
+    w1[0, 0], w1[1, 0], w1[0, 1], w1[2, 1] = 1.0, 2.0, -2.0, 4.0
+    b1 = np.array([0.0, 0.25])
+    w2 = np.array([[2.0, -1.0, 0.5, 0.0], [0.5, 4.0, 0.0, -3.0]])
+    b2 = np.array([0.0, 64.0, 64.0, -1.0])
+    weights = tuple(W.bf16_bits(a.ravel()) for a in (w1, b1, w2, b2))
+    obs = np.zeros(16)
+    obs[:3] = (0.5, 0.25, 0.3)
+    for env, g in ((0, 0), (5, 123), (77, 9999)):
+        logits, k = c.policy(H, weights, obs, 21, env, g)
+        assert list(logits) == [1.7353515625, 64.93359375, 64.380859375, -2.271484375]
+        assert list(k) == [1, 0]

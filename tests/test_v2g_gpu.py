@@ -158,9 +158,10 @@ def test_served_equals_direct_and_oracle(cxm, oracle_lib):
 
 
 def test_full_size_sampled(cxm, oracle_lib):
-    """65,536 V2G stations with batteries x 288 steps in the default packing (the
-    measured configuration): every action byte's range and done flag, and 48
-    sampled stations replayed in the oracle (actions, rewards, observations)."""
+    """65,536 V2G stations with batteries x 288 steps in the default packing (16
+    lanes, 4 waves per block; the measured launch is covered by
+    test_fullsize_gpu): every action byte's range and done flag, and 48 sampled
+    stations replayed in the oracle (actions, rewards, observations)."""
     o = oracle_lib
     spec = W.v2g_station()
     n, T, seed = 65536, 288, 3
