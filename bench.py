@@ -98,11 +98,12 @@ def oracle_baseline(specs, ec, seed, T, stride, chunk=16, mode=1, min_s=10.0, th
     if threads is None:
         threads = max(1, min(16, os.cpu_count() or 1))
     used, steps, days = 1, 0, 0
+    out = None      # the output arrays are reused from chunk to chunk (no page faults in the timing)
     t0 = time.perf_counter()
     while True:
         bs = o.BatchState(classes, np.asarray(ec)[ids], env_ids=ids)
         for _ in range(max(1, T // chunk)):
-            out = o.rollout(bs, seed, min(chunk, T), mode=mode, n_threads=threads)
+            out = o.rollout(bs, seed, min(chunk, T), mode=mode, n_threads=threads, out=out)
             used = out["threads"]
             steps += min(chunk, T)
         days += 1

@@ -621,6 +621,21 @@ static void *rollout_worker(void *arg) {
   return NULL;
 }
 
+/* First env of worker w of n: contiguous env ranges holding about equal numbers
+ * of ports (a step's work grows with the ports), so that classes of different
+ * sizes do not leave some workers idle. */
+static int64_t balanced_split(const int64_t *port_off, int64_t n_envs, int32_t w, int32_t n) {
+  if (w >= n) return n_envs;
+  const int64_t target = port_off[n_envs] * w / n;
+  int64_t lo = 0, hi = n_envs;  /* the first e with port_off[e] >= target */
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) / 2;
+    if (port_off[mid] < target) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
 int32_t ox_rollout(ox_class *const *classes, const int32_t *env_class, const int64_t *env_ids,
                    int64_t n_envs, uint64_t seed, uint32_t *g, int32_t *t_day, int32_t T, int32_t mode,
                    const uint8_t *act_in, int32_t *dwell, int32_t *user, double *soc, double *e_rem,
@@ -645,7 +660,8 @@ int32_t ox_rollout(ox_class *const *classes, const int32_t *env_class, const int
     J->classes = classes; J->env_class = env_class; J->env_ids = env_ids; J->port_off = port_off;
     J->act_off = act_off; J->obs_off = obs_off;
     J->total_act = act_off[n_envs]; J->total_obs = obs_off[n_envs]; J->n_envs = n_envs;
-    J->e_begin = n_envs * w / n_threads; J->e_end = n_envs * (w + 1) / n_threads;
+    J->e_begin = balanced_split(port_off, n_envs, w, n_threads);
+    J->e_end = balanced_split(port_off, n_envs, w + 1, n_threads);
     J->seed = seed; J->g0 = *g; J->t0 = *t_day; J->T = T; J->mode = mode; J->act_in = act_in;
     J->dwell = dwell; J->user = user; J->soc = soc; J->e_rem = e_rem; J->cap = cap; J->rbar = rbar;
     J->p_last = p_last;

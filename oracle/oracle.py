@@ -349,15 +349,22 @@ class BatchState:
 
 def rollout(bs: BatchState, seed: int, T: int, mode: int = ACT_RANDOM, act_in=None,
             want_obs: bool = True, want_act: bool = True, want_info: bool = False,
-            n_threads: int = 0):
-    """Run T steps of every env; returns dict of outputs (obs, act, reward, done, info)."""
+            n_threads: int = 0, out=None):
+    """Run T steps of every env; returns dict of outputs (obs, act, reward, done, info).
+    out: the dict of an earlier call with the same T and envs, whose arrays are
+    overwritten instead of allocated."""
     if n_threads <= 0:
         n_threads = max(1, min(16, os.cpu_count() or 1))
     handles = (C.c_void_p * len(bs.classes))(*[c.h.value for c in bs.classes])
-    obs = np.zeros((T, bs.total_obs)) if want_obs else None
-    act = np.zeros((T, bs.total_act), dtype=np.uint8) if want_act else None
-    rew = np.zeros((T, bs.n_envs))
-    done = np.zeros((T, bs.n_envs), dtype=np.uint8)
+    if out is not None:
+        obs, act, rew, done = (out["obs"] if want_obs else None), (out["act"] if want_act else None), \
+            out["reward"], out["done"]
+        assert rew.shape == (T, bs.n_envs) and (obs is None or obs.shape == (T, bs.total_obs))
+    else:
+        obs = np.zeros((T, bs.total_obs)) if want_obs else None
+        act = np.zeros((T, bs.total_act), dtype=np.uint8) if want_act else None
+        rew = np.zeros((T, bs.n_envs))
+        done = np.zeros((T, bs.n_envs), dtype=np.uint8)
     info = (StepInfo * (T * bs.n_envs))() if want_info else None
     ain = None if act_in is None else np.ascontiguousarray(act_in, dtype=np.uint8)
     g = C.c_uint32(bs.g)
