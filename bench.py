@@ -209,9 +209,12 @@ def run_rollout_workload(args, name, specs, ec, seed, desc, cpu_stride):
 
 def run_uneven(args):
     specs, ec = uneven_workload()
-    return run_rollout_workload(
+    line = run_rollout_workload(
         args, "uneven-batching: 65536 stations x 288 steps, ports {8..128} mix, trees depth 1-3, random "
               "levels, full records", specs, ec, 3, "uneven stations", 8)
+    if not args.no_serve:
+        line["serve"] = serve_fixed_rate()
+    return line
 
 
 def run_tiny(args):
@@ -284,7 +287,7 @@ def run_policy(args):
     ci = env.class_info(0)
     line = base_line("env-steps/s (policy-in-the-loop rollout)", value, "env-steps/s", args, wall_ms,
                      {"workload": "policy: 1048576 stations x 288 steps, 32 ports (8 splitters x 4 under "
-                                  "400 kW), MLP 196-256-352 BF16, Gumbel-max levels, levels+rewards",
+                                  "400 kW), MLP 196-256-352 BF16, levels drawn from softmax, levels+rewards",
                       "n_envs": E, "T": T_DAY, "hidden": H, "packing": ci.lanes_per_station}, dtype="bf16")
     line["roofline"] = {"bound": "mfma", "achieved": achieved, "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
                         "frac": achieved / BF16_PEAK_TFLOPS, "traffic": None, "kernel": "k_policy",
@@ -320,6 +323,87 @@ def policy_oracle_baseline(spec, H, weights, seed, n_envs=64, min_s=10.0):
                       f"1 thread, {dt:.1f} s"}
 
 
+def serve_requests(srv, classes, reqs, paced):
+    """Submit requests (paced by their arrival times, or all at once); a client
+    thread polls the outstanding tickets and releases each as soon as it
+    finishes.  Returns (wall s, server stats of this run, latencies s, queueing s)."""
+    import paper_2507_01522_amd as cx
+    st0 = srv.stats()
+    lat, admit_wait = [], []
+    lock = threading.Lock()
+    outstanding = []
+
+    def drain():
+        n_done = 0
+        while n_done < len(reqs):
+            with lock:
+                live = list(outstanding)
+            finished = []
+            for tk in live:
+                r = srv.poll(tk)
+                if r is None:
+                    continue
+                lat.append(r.done_s - r.submit_s)
+                admit_wait.append(r.admit_s - r.submit_s)
+                srv.release(tk)
+                finished.append(tk)
+            if finished:
+                with lock:
+                    for tk in finished:
+                        outstanding.remove(tk)
+                n_done += len(finished)
+            else:
+                time.sleep(0.0005)
+
+    th = threading.Thread(target=drain)
+    th.start()
+    t0 = time.perf_counter()
+    for rq in reqs:
+        if paced:
+            d = rq.arrival_s - (time.perf_counter() - t0)
+            if d > 0:
+                time.sleep(d)
+        tk = srv.submit(classes[rq.class_index], rq.n_envs, rq.horizon, rq.seed, cx.OUT_FULL)
+        with lock:
+            outstanding.append(tk)
+    th.join()
+    wall = time.perf_counter() - t0
+    st1 = srv.stats()
+    st = {k: st1[k] - st0[k] for k in ("busy_s", "env_steps", "launches")}
+    st["peak_active"] = st1["peak_active"]
+    return wall, st, np.array(lat), np.array(admit_wait)
+
+
+def serve_summary(classes, stream, wall, st, lat, wq, rate):
+    env_steps = sum(r.n_envs * r.horizon for r in stream)
+    rec = {c: record_bytes(classes[c]) for c in range(len(classes))}
+    alg = float(sum(r.n_envs * (r.horizon * rec[r.class_index] + 2 * state_bytes(classes[r.class_index]))
+                    for r in stream))
+    return {"rate_req_per_s": rate, "requests": len(stream), "env_steps_per_s": env_steps / wall,
+            "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                          "queue_p50": float(np.percentile(wq, 50)), "queue_p99": float(np.percentile(wq, 99))},
+            "gpu_busy_s": st["busy_s"], "hbm_GBps_of_busy_time": alg / st["busy_s"] / 1e9,
+            "peak_active": st["peak_active"], "algorithmic_bytes": alg, "wall_s": wall}
+
+
+def serve_fixed_rate(rate=1000.0, n=400, seed=2003):
+    """The serving loop at a fixed Poisson request rate (continuous batching,
+    chunks of 32 steps, 200 GB budget): p50/p99 latency and env-steps/s, for the
+    default bench line."""
+    import paper_2507_01522_amd as cx
+    import workloads as W
+    classes = W.mixture_classes()
+    srv = cx.Server(200 << 30, chunk_steps=32)
+    serve_requests(srv, classes, W.request_stream(40, 1e9, seed=2002), False)   # warm-up
+    stream = W.request_stream(n, rate, seed=seed)
+    wall, st, lat, wq = serve_requests(srv, classes, stream, True)
+    srv.close()
+    out = serve_summary(classes, stream, wall, st, lat, wq, rate)
+    out["workload"] = (f"{n} Poisson requests at {rate:g}/s, 64..8192 stations, T in {{96,288,2016}}, "
+                       "uneven classes, full records, 200 GB budget")
+    return out
+
+
 def run_serve(args):
     """A Poisson stream of rollout requests (log-uniform sizes 64..8192 stations,
     horizons {96, 288, 2016}, classes of the uneven mixture, full records) at
@@ -327,88 +411,30 @@ def run_serve(args):
     import paper_2507_01522_amd as cx
     import workloads as W
     classes = W.mixture_classes()
-    budget = 200 << 30
-
-    srv = cx.Server(budget, chunk_steps=32)   # reserves the budget on the device once
-
-    def serve(reqs, paced):
-        """Submit (paced by arrival times or all at once); a client thread polls
-        the outstanding tickets and releases each as soon as it finishes."""
-        st0 = srv.stats()
-        lat, admit_wait = [], []
-        lock = threading.Lock()
-        outstanding = []
-        submitted = [0]
-
-        def drain():
-            n_done = 0
-            while n_done < len(reqs):
-                with lock:
-                    live = list(outstanding)
-                finished = []
-                for tk in live:
-                    r = srv.poll(tk)
-                    if r is None:
-                        continue
-                    lat.append(r.done_s - r.submit_s)
-                    admit_wait.append(r.admit_s - r.submit_s)
-                    srv.release(tk)
-                    finished.append(tk)
-                if finished:
-                    with lock:
-                        for tk in finished:
-                            outstanding.remove(tk)
-                    n_done += len(finished)
-                else:
-                    time.sleep(0.0005)
-
-        th = threading.Thread(target=drain)
-        th.start()
-        t0 = time.perf_counter()
-        for rq in reqs:
-            if paced:
-                d = rq.arrival_s - (time.perf_counter() - t0)
-                if d > 0:
-                    time.sleep(d)
-            tk = srv.submit(classes[rq.class_index], rq.n_envs, rq.horizon, rq.seed, cx.OUT_FULL)
-            with lock:
-                outstanding.append(tk)
-                submitted[0] += 1
-        th.join()
-        wall = time.perf_counter() - t0
-        st1 = srv.stats()
-        st = {k: st1[k] - st0[k] for k in ("busy_s", "env_steps", "launches")}
-        st["peak_active"] = st1["peak_active"]
-        return wall, st, np.array(lat), np.array(admit_wait)
-
+    srv = cx.Server(200 << 30, chunk_steps=32)   # reserves the budget on the device once
     # saturated: bursts of requests submitted at once (the better of two)
     burst = W.request_stream(600, 1e9, seed=2001)
-    serve(W.request_stream(40, 1e9, seed=2002), False)          # warm-up (code objects, arena pages)
-    wall_s = min(serve(burst, False)[0] for _ in range(2))
+    serve_requests(srv, classes, W.request_stream(40, 1e9, seed=2002), False)   # warm-up
+    wall_s = min(serve_requests(srv, classes, burst, False)[0] for _ in range(2))
     steps_s = sum(r.n_envs * r.horizon for r in burst)
     sat_rate = len(burst) / wall_s
     rate = 0.7 * sat_rate
     stream = W.request_stream(1000, rate, seed=2000)
-    wall, st, lat, wq = serve(stream, True)
+    wall, st, lat, wq = serve_requests(srv, classes, stream, True)
     srv.close()
-    env_steps = sum(r.n_envs * r.horizon for r in stream)
-    rec = {c: record_bytes(classes[c]) for c in range(len(classes))}
-    alg = float(sum(r.n_envs * (r.horizon * rec[r.class_index] + 2 * state_bytes(classes[r.class_index]))
-                    for r in stream))
-    value = env_steps / wall
-    line = base_line("env-steps/s (continuous-batching server, Poisson request stream)", value, "env-steps/s",
-                     args, wall * 1e3,
+    sm = serve_summary(classes, stream, wall, st, lat, wq, rate)
+    line = base_line("env-steps/s (continuous-batching server, Poisson request stream)", sm["env_steps_per_s"],
+                     "env-steps/s", args, wall * 1e3,
                      {"workload": "serve: 1000 Poisson requests at 0.7x saturated rate, 64..8192 stations, "
                                   "T in {96,288,2016}, uneven classes, full records, 200 GB budget",
                       "rate_req_per_s": rate, "saturated_req_per_s": sat_rate,
                       "saturated_env_steps_per_s": steps_s / wall_s, "chunk_steps": 32})
-    line["latency_s"] = {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
-                         "queue_p50": float(np.percentile(wq, 50)), "queue_p99": float(np.percentile(wq, 99))}
+    line["latency_s"] = sm["latency_s"]
     line["server"] = st
-    line["roofline"] = {"bound": "hbm", "achieved": alg / st["busy_s"] / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": alg / st["busy_s"] / 1e9 / HBM_PEAK_GBS, "traffic": None,
+    line["roofline"] = {"bound": "hbm", "achieved": sm["hbm_GBps_of_busy_time"], "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": sm["hbm_GBps_of_busy_time"] / HBM_PEAK_GBS, "traffic": None,
                         "kernel": "k_rollout (per-segment chunks)", "kernel_ms": st["busy_s"] * 1e3,
-                        "algorithmic_bytes": alg}
+                        "algorithmic_bytes": sm["algorithmic_bytes"]}
     line["cpu_baseline"] = None
     return line
 
@@ -421,6 +447,7 @@ def main():
     ap.add_argument("--workload", default="uneven", choices=["uneven", "tiny", "scale", "v2g", "users", "exo", "policy", "serve"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain per-step comparison")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement of the default line")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run a plain 2 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()

@@ -59,7 +59,7 @@ typedef enum {
   CX_ACT_EXTERNAL = 0, /* caller-provided action bytes (above lo + n_levels: clamped)     */
   CX_ACT_RANDOM = 1,   /* uniform bytes from Philox: (w * (lo + n_levels + 1)) >> 32      */
   CX_ACT_MAX = 2,      /* every port (and the battery) asks for its maximum charge        */
-  CX_ACT_POLICY = 3    /* the MLP set by cx_set_policy, Gumbel-max sampled               */
+  CX_ACT_POLICY = 3    /* the MLP set by cx_set_policy, a level drawn from its softmax   */
 } cx_action_mode;
 
 /* Which per-step records a rollout writes. */
@@ -312,7 +312,9 @@ cx_status cx_rollout_policy_noalloc(cx_ctx *ctx, int32_t T, cx_out_mode out_mode
  * n_ports*(n_levels+1) logits, BF16 weights (uint16 bit patterns, host memory):
  * w1 [obs_dim][hidden], b1 [hidden], w2 [hidden][n_ports*(n_levels+1)], b2.
  * Products run on the matrix cores in BF16 with FP32 accumulation; the level of
- * each port is argmax over its logits plus Gumbel noise from Philox.
+ * each port is drawn from the softmax of its logits: the first level whose
+ * cumulative probability exceeds u, u = (top 24 bits of word 0 of Philox
+ * (env, g, port, 3) + 1/2) 2^-24.
  * Only single-class contexts of charging-only stations (no V2G, no battery). */
 cx_status cx_set_policy(cx_ctx *ctx, int32_t hidden, const uint16_t *w1_host, const uint16_t *b1_host,
                         const uint16_t *w2_host, const uint16_t *b2_host);
@@ -322,7 +324,7 @@ cx_status cx_set_policy(cx_ctx *ctx, int32_t hidden, const uint16_t *w1_host, co
 cx_status cx_policy_logits(cx_ctx *ctx, const float *obs_dev, int64_t n, float *logits_dev);
 
 /* Levels the policy samples for n observations (obs_dev [n][obs_dim] float,
- * 16-byte aligned) at global step g: act_dev [n][n_ports] uint8, Gumbel noise
+ * 16-byte aligned) at global step g: act_dev [n][n_ports] uint8, the uniforms
  * from Philox counters (env_begin + i, g, ...) of the context's seed -- the
  * policy half of a CX_ACT_POLICY step, exactly as a rollout launches it. */
 cx_status cx_policy_sample(cx_ctx *ctx, const float *obs_dev, int64_t n, uint32_t g, uint8_t *act_dev);

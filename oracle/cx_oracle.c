@@ -701,7 +701,8 @@ static double bf16_bits_to_double(uint16_t b) {
 
 /* Policy of the policy-in-the-loop workload: a two-layer perceptron over the
  * observation, tanh hidden units, one logit per (port, level), and a level per
- * port drawn by the Gumbel-max rule with Philox noise. */
+ * port drawn from the categorical distribution softmax(logits) by inverting its
+ * distribution function with one Philox uniform. */
 void ox_policy(const ox_class *c, int32_t hidden, const uint16_t *w1, const uint16_t *b1,
                const uint16_t *w2, const uint16_t *b2, const double *obs, uint64_t seed,
                uint32_t env, uint32_t g, double *logits, int32_t *k, double *margin) {
@@ -721,29 +722,32 @@ void ox_policy(const ox_class *c, int32_t hidden, const uint16_t *w1, const uint
     for (int32_t j = 0; j < hidden; ++j) a += h[j] * bf16_bits_to_double(w2[(size_t)j * out + o]);
     z[o] = a;
   }
-  const int32_t Q = (L + 1 + 3) / 4;
   for (int32_t i = 0; i < N; ++i) {
-    int32_t best = 0;
-    double best_v = -INFINITY, second_v = -INFINITY;
-    for (int32_t q = 0; q < Q; ++q) {
-      uint32_t w[4];
-      philox_seeded(seed, env, g, (uint32_t)(i * Q + q), OX_DOM_GUM, w);
-      for (int32_t r = 0; r < 4; ++r) {
-        int32_t lev = 4 * q + r;
-        if (lev > L) break;
-        double u = ((double)(w[r] >> 8) + 0.5) * (1.0 / 16777216.0);
-        double v = z[i * (L + 1) + lev] - log(-log(u));
-        if (v > best_v) {
-          second_v = best_v;
-          best_v = v;
-          best = lev;
-        } else if (v > second_v) {
-          second_v = v;
-        }
-      }
+    const double *zi = z + (size_t)i * (L + 1);
+    /* softmax probabilities p_l = exp(z_l - max z) / W */
+    double zmax = zi[0];
+    for (int32_t l = 1; l <= L; ++l) zmax = zi[l] > zmax ? zi[l] : zmax;
+    double e[256], W = 0.0;
+    for (int32_t l = 0; l <= L; ++l) {
+      e[l] = exp(zi[l] - zmax);
+      W += e[l];
     }
-    k[i] = best;
-    if (margin) margin[i] = best_v - second_v;
+    /* u in (0, 1) from the top 24 bits of word 0 of Philox (env, g, port, 3); the
+     * level is the first l whose distribution function F_l = (p_0 + .. + p_l)
+     * exceeds u */
+    uint32_t w[4];
+    philox_seeded(seed, env, g, (uint32_t)i, OX_DOM_GUM, w);
+    const double u = ((double)(w[0] >> 8) + 0.5) * (1.0 / 16777216.0);
+    double F = 0.0, near = 1.0;
+    int32_t lev = L;
+    for (int32_t l = 0; l < L; ++l) {
+      F += e[l] / W;
+      const double d = fabs(F - u);
+      near = d < near ? d : near;
+      if (lev == L && F > u) lev = l;
+    }
+    k[i] = lev;
+    if (margin) margin[i] = near;  /* distance of u from the nearest F_l */
   }
   if (logits)
     for (int32_t o = 0; o < out; ++o) logits[o] = z[o];

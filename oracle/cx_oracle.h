@@ -37,7 +37,7 @@
  *                        dwell timing; day boundary; rollout invariants
  *                        (limits, SoC range, energy balance, occupancy)
  *   ox_policy         -- numpy FP64 products on the decoded BF16 operands;
- *                        Gumbel-max frequencies equal softmax (chi-square);
+ *                        sampled level frequencies equal softmax (chi-square);
  *                        BF16 rounding equal to torch's
  *   charge-sensitive  -- (tests/test_oracle_users.py) hand-worked departures on
  *   users (u = 1)        reaching the target, overstay and early-leave terms of
@@ -76,7 +76,7 @@ extern "C" {
 #define OX_DOM_ENV 0u       /* ctr = (env, g, 0, 0): arrivals + price noise      */
 #define OX_DOM_ACT 1u       /* ctr = (env, g >> 2, port, 1): word g & 3          */
 #define OX_DOM_CAR 2u       /* ctr = (env, g, j, 2): j-th arriving car of step g */
-#define OX_DOM_GUM 3u       /* ctr = (env, g, 3*port + q, 3): Gumbel noise       */
+#define OX_DOM_GUM 3u       /* ctr = (env, g, port, 3): the policy's level draw   */
 #define OX_DOM_USER 4u      /* ctr = (env, g, j, 4): user type of car j, word 0  */
 #define OX_DOM_DAY 5u       /* ctr = (env, g0, 0, 5): price day of the episode starting at g0 */
 
@@ -226,13 +226,14 @@ int32_t ox_rollout(ox_class *const *classes, const int32_t *env_class, const int
                    double *cap, double *rbar, double *p_last, double *batt, double *ret, double *obs, uint8_t *act,
                    double *reward, uint8_t *done, ox_step_info *info, int32_t n_threads);
 
-/* ---- policy (observation -> MLP -> Gumbel-argmax levels) ----
+/* ---- policy (observation -> MLP -> a level per port drawn from softmax) ----
  * Weights are BF16 bit patterns; W1 [in][hidden], W2 [hidden][n_ports*(L+1)].
  * The observation is rounded to BF16 first and the hidden activation after tanh;
- * both products are taken in FP64.  Level of port i: argmax over its logits
- * plus Gumbel noise -ln(-ln u), u from Philox (env, g, i Q + q, GUMBEL) word r
- * for level 4 q + r, Q = ceil((L+1)/4).  logits (n_ports*(L+1)) and margin
- * (n_ports: best minus second-best perturbed logit) may be NULL. */
+ * both products are taken in FP64.  Level of port i: the first l whose
+ * cumulative softmax probability F_l exceeds u (level L if none), u = (top 24
+ * bits of word 0 of Philox (env, g, i, 3) + 1/2) 2^-24.  logits
+ * (n_ports*(L+1)) and margin (n_ports: distance of u from the nearest F_l, l <
+ * L) may be NULL. */
 void ox_policy(const ox_class *c, int32_t hidden, const uint16_t *w1, const uint16_t *b1,
                const uint16_t *w2, const uint16_t *b2, const double *obs, uint64_t seed,
                uint32_t env, uint32_t g, double *logits, int32_t *k, double *margin);

@@ -1,7 +1,7 @@
 // cx_policy.hip -- policy-in-the-loop rollouts.  Each step runs two kernels:
 //   k_policy  obs -> BF16 -> W1 (tanh) -> W2 -> logits on the matrix cores
-//             (v_mfma_f32_16x16x32_bf16, FP32 accumulation), then per port
-//             argmax over its levels of logit + Gumbel noise from Philox;
+//             (v_mfma_f32_16x16x32_bf16, FP32 accumulation), then per port a
+//             level drawn from softmax of its logits with one Philox uniform;
 //   the library's one-step environment kernel with those levels as external
 //             actions, which writes the next observation.
 // A third kernel, k_observe, gives the observation of the state a rollout
@@ -72,24 +72,6 @@ __device__ __forceinline__ f32x4 mfma(u32x4 a, u32x4 b, f32x4 c) {
 __device__ __forceinline__ float tanh_f(float a) {
   const float e = __builtin_amdgcn_exp2f(a * 2.88539008177792681f);  // 2 / ln 2
   return 1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f);
-}
-
-// Gumbel noise -ln(-ln u) of u = (m + 1/2) 2^-24, m the top 24 bits of w.
-// The winning draws are those with u near 1, where ln u has no relative
-// accuracy in FP32; there -ln u = -ln(1 - v) with v = 1 - u exact, taken from
-// its series for v < 1/16 (truncation below 3e-6 relative) and from log2 of
-// 1 - v above.  Over all 2^24 inputs the result is within 4e-6 of the exact
-// value.
-__device__ __forceinline__ float gumbel(uint32_t w) {
-  constexpr float kLn2 = 0.693147180559945309f;
-  const uint32_t m = w >> 8;
-  const bool hi = m >= (1u << 23);
-  const float v = ((float)((1u << 24) - 1u - m) + 0.5f) * 0x1p-24f;  // 1 - u (exact when hi)
-  const float ulo = ((float)m + 0.5f) * 0x1p-24f;                    // u (exact when !hi)
-  const float e_log = -kLn2 * __builtin_amdgcn_logf(hi ? 1.0f - v : ulo);
-  const float e_ser = v * (1.0f + v * (0.5f + v * (0.333333343f + v * 0.25f)));
-  const float e = (hi && v < 0.0625f) ? e_ser : e_log;  // -ln u
-  return -kLn2 * __builtin_amdgcn_logf(e);
 }
 
 // Weight chunks pass through LDS, double-buffered: chunk c < HP holds the two
@@ -205,30 +187,23 @@ __global__ __launch_bounds__(64 * kPolWaves) void k_policy(PolicyArgs a) {
     }
   }
 
-  // ---- second product per group of 4 ports (one chunk each), then Gumbel-max
+  // ---- second product per group of 4 ports (one chunk each), then a level
+  // per port drawn from softmax of its logits
   const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
   const int out_dim = a.N * a.L1;
   for (int grp = 0; grp < a.G; ++grp) {
     const int cidx = a.HP + grp;
     const int port = 4 * grp + lg;
     if (cidx + 1 < n_chunks) fetch_chunk(a, cidx + 1, pf);
-    // Gumbel noise of this group's levels: independent of the products, so it
-    // is computed in the same straight-line block as the matrix-core work and
-    // the two overlap (lanes past the last env or port compute unused noise)
-    float gn[kPolR][kPolNT][4];
+    // the uniform of this port's draw: independent of the products, so it is
+    // computed in the same straight-line block as the matrix-core work and the
+    // two overlap (lanes past the last env or port compute unused draws)
+    float ud[kPolNT];
 #pragma unroll
     for (int n = 0; n < kPolNT; ++n) {
       const uint32_t env_id = (uint32_t)(a.env0 + e_base + 16 * n + col);
-#pragma unroll
-      for (int r = 0; r < kPolR; ++r) {
-        if (r < a.R) {
-          const U4 w4 = philox(env_id, a.g, (uint32_t)(port * a.R + r), kDomGum, k0, k1);
-          gn[r][n][0] = gumbel(w4.x);
-          gn[r][n][1] = gumbel(w4.y);
-          gn[r][n][2] = gumbel(w4.z);
-          gn[r][n][3] = gumbel(w4.w);
-        }
-      }
+      const uint32_t w = philox(env_id, a.g, (uint32_t)port, kDomGum, k0, k1).x;
+      ud[n] = ((float)(w >> 8) + 0.5f) * 0x1p-24f;
     }
     const u32x4 *w = wbuf[cidx & 1];
     f32x4 c[kPolR][kPolNT];
@@ -270,23 +245,35 @@ __global__ __launch_bounds__(64 * kPolWaves) void k_policy(PolicyArgs a) {
         }
       }
       if (a.act) {
-        int best = 0;
-        float bv = -__builtin_inff();
+        // the first level whose cumulative softmax weight exceeds u times the
+        // total (the inverse of the distribution function at u)
+        float zmax = c[0][n][0];
 #pragma unroll
-        for (int r = 0; r < kPolR; ++r) {
+        for (int r = 0; r < kPolR; ++r)
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            if (r < a.R && 4 * r + i < a.L1) zmax = fmaxf(zmax, c[r][n][i]);
+        constexpr float kLog2e = 1.44269504088896341f;
+        float ex[kPolR][4], tot = 0.f;
+#pragma unroll
+        for (int r = 0; r < kPolR; ++r)
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
-            const int lev = 4 * r + i;
-            if (r < a.R && lev < a.L1) {
-              const float v = c[r][n][i] + gn[r][n][i];
-              if (v > bv) {
-                bv = v;
-                best = lev;
-              }
-            }
+            const bool in = r < a.R && 4 * r + i < a.L1;
+            ex[r][i] = in ? __builtin_amdgcn_exp2f((c[r][n][i] - zmax) * kLog2e) : 0.f;
+            tot += ex[r][i];
           }
-        }
-        a.act[e * a.N + port] = (uint8_t)best;
+        const float target = ud[n] * tot;
+        int lev = 0;
+        float cum = 0.f;
+#pragma unroll
+        for (int r = 0; r < kPolR; ++r)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            cum += ex[r][i];
+            lev += (r < a.R && 4 * r + i < a.L1 - 1 && cum <= target) ? 1 : 0;
+          }
+        a.act[e * a.N + port] = (uint8_t)lev;
       }
     }
   }

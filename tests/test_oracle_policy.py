@@ -1,9 +1,10 @@
 """Oracle pins for the policy-in-the-loop step: BF16 rounding, the two-layer
-perceptron and the Gumbel-max draw.
+perceptron and the level draw.
 
 References: torch's own float32 -> bfloat16 conversion; numpy FP64 matrix
-products on the decoded BF16 operands; the Gumbel-max property that
-argmax(z + Gumbel) is distributed as softmax(z).
+products on the decoded BF16 operands; level frequencies against softmax(z)
+(chi-square); the inverse-distribution rule on a two-level case worked by hand
+from the Philox word (itself pinned by the known-answer vectors).
 """
 import math
 
@@ -49,9 +50,9 @@ def test_mlp_logits_match_numpy(oracle_lib):
         assert np.all((k >= 0) & (k <= 10))
 
 
-def test_gumbel_argmax_is_softmax_sampling(oracle_lib):
+def test_levels_follow_softmax(oracle_lib):
     """With W1 = 0 the logits are the bias b2; the chosen levels must then follow
-    softmax(b2) per port (Gumbel-max)."""
+    softmax(b2) per port."""
     o = oracle_lib
     spec = W.splitter_tree(1, 4, 1000.0, 1000.0)
     c = o.OracleClass(spec)
@@ -91,7 +92,8 @@ def test_tiny_perceptron_hand_worked(oracle_lib):
       W2 [hidden][port * 2 + level] = ((2, -1, 0.5, 0), (0.5, 4, 0, -3)); b2 = (0, 64, 64, -1)
         z = (2 h0 + 0.5 h1, 64 - h0 + 4 h1, 64 + 0.5 h0, -1 - 3 h1)
           = (1.7353515625, 64.93359375, 64.380859375, -2.271484375)
-    Gumbel noise lies in [-2.9, 17.3], so port 0 takes level 1 and port 1 level 0."""
+    Softmax gives port 0's level 1 and port 1's level 0 all but e^-60 of the
+    probability, so those are the levels drawn."""
     o = oracle_lib
     spec = W.single_transformer(2, 1000.0).replace(n_levels=1)
     assert spec.obs_dim == 16
@@ -109,3 +111,32 @@ def test_tiny_perceptron_hand_worked(oracle_lib):
         logits, k = c.policy(H, weights, obs, 21, env, g)
         assert list(logits) == [1.7353515625, 64.93359375, 64.380859375, -2.271484375]
         assert list(k) == [1, 0]
+
+
+def test_inverse_distribution_two_levels(oracle_lib):
+    """Levels {0, 1} with logits (0, ln 3) (bias only): p = (1/4, 3/4), so the
+    level is 0 exactly when u < 1/4, u = (top 24 bits of word 0 of Philox
+    (env, g, port, 3) + 1/2) 2^-24; the margin is |1/4 - u|."""
+    o = oracle_lib
+    spec = W.single_transformer(3, 1000.0).replace(n_levels=1)
+    c = o.OracleClass(spec)
+    H = 2
+    w1 = np.zeros((spec.obs_dim, H), np.uint16)
+    b1 = np.zeros(H, np.uint16)
+    w2 = np.zeros((H, 6), np.uint16)
+    b2 = np.zeros(6)
+    b2[1::2] = math.log(3.0)
+    b2bits = W.bf16_bits(b2)
+    z1 = bf16_to_f64(b2bits)[1]            # ln 3 rounded to BF16
+    p0 = 1.0 / (1.0 + math.exp(z1))
+    seed = 0x1234_5678_9ABC
+    zeros = 0
+    for env, g in [(e, t) for e in range(0, 40, 3) for t in range(0, 500, 37)]:
+        _, k, margin = c.policy(H, (w1, b1, w2, b2bits), np.zeros(spec.obs_dim), seed, env, g, with_margin=True)
+        for port in range(3):
+            w = o.philox([env, g, port, 3], [seed & 0xFFFFFFFF, seed >> 32])
+            u = ((int(w[0]) >> 8) + 0.5) * 2.0**-24
+            assert k[port] == (0 if u < p0 else 1), (env, g, port, u, k[port])
+            assert abs(margin[port] - abs(p0 - u)) < 1e-12
+            zeros += k[port] == 0
+    assert 0.15 < zeros / (3 * 14 * 14) < 0.35

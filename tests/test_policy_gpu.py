@@ -2,9 +2,9 @@
 
 * logits of the BF16 matrix-core MLP equal the oracle's FP64 products on the same
   BF16 operands, within the bound of one BF16 rounding flip per hidden unit;
-* every sampled level equals the oracle's Gumbel-max choice on the oracle's own
-  observation, except where the oracle's best and second-best perturbed logits
-  are closer than 1e-3 (such flips are counted and must stay rare);
+* every sampled level equals the oracle's draw on the oracle's own observation,
+  except where the uniform of the draw lies within 1e-3 of a boundary of the
+  softmax distribution function (such flips are counted and must stay rare);
 * the environment, replayed in the oracle on the GPU's levels, matches exactly
   (integers) and within the FP tolerances (rewards, observations).
 """
