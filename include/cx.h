@@ -366,13 +366,11 @@ cx_status cx_get_tables(const cx_ctx *ctx, int32_t cls, uint32_t *tpois_host, ui
 cx_status cx_set_packing(cx_ctx *ctx, int32_t cls, int32_t lanes_per_station, int32_t waves_per_block);
 
 /* on = 1: classes without padding slots, with one port maximum and efficiency
- * and one block size per tree level, packed at up to 32 lanes per station,
- * write their observation records through an LDS stage of each block, as
- * 16-byte stores of whole record runs; on = 0 (the default): every lane stores
- * its own values.  The records are bit for bit the same either way; which is
- * faster depends on the launch (the 8-32-lane classes of a mixed launch gain
- * most).  CX_E_INVALID unless on
- * is 0 or 1. */
+ * and one block size per tree level write their observation records through an
+ * LDS stage of each block, as 16-byte stores of whole record runs; on = 0 (the
+ * default): every lane stores its own values.  The records are bit for bit the
+ * same either way; which is faster depends on the launch (a mixed launch of
+ * many classes gains).  CX_E_INVALID unless on is 0 or 1. */
 cx_status cx_set_obs_stage(cx_ctx *ctx, int32_t on);
 
 /* Time every legal packing of every class on a T_probe-step rollout (state is

@@ -87,6 +87,15 @@ size_t class_block(const SpecCopy &sc, const Compiled &k, const Tables &t, unsig
     }
     d.lvl_cap_u[lvl] = cu;
   }
+  for (int b = 0; b < kMaxBlockLog2; ++b) d.blk_cap[b] = std::numeric_limits<float>::infinity();
+  d.blk_mask = 0;
+  for (int lvl = 0; lvl + 1 < k.D; ++lvl) {   // levels below the root
+    const uint32_t lb = (d.lvl_lb_uniform >> (8 * lvl)) & 0xFF;
+    if (lb < (uint32_t)kMaxBlockLog2) {
+      d.blk_cap[lb] = d.lvl_cap_u[lvl];
+      d.blk_mask |= 1u << lb;
+    }
+  }
   d.kind = k.extended() ? kKindExt : simple ? kKindSimple : kKindGeneral;
   d.simple = d.kind == kKindSimple ? 1 : 0;
   d.n_neg = k.v2g ? s.n_levels : 0;

@@ -51,5 +51,13 @@ __device__ __forceinline__ T gld(const T *p, int64_t i) {
   return ((const __attribute__((address_space(1))) T *)p)[i];
 }
 
+// Load through the constant address space: with a wave-uniform address this
+// is a scalar load (counted apart from the vector stores in flight, so using it
+// does not wait for them).
+template <class T>
+__device__ __forceinline__ T sld(const T *p, int64_t i) {
+  return ((const __attribute__((address_space(4))) T *)p)[i];
+}
+
 }  // namespace
 }  // namespace cx

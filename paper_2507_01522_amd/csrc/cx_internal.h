@@ -14,6 +14,7 @@ constexpr int kMaxSlots = 256;   // padded ports per station
 constexpr int kPoisK = 24;       // arrival counts are capped at 24 per step
 constexpr int kPoisStride = 32;  // threshold row padded with 0xFFFFFFFF for a 5-step bisection
 constexpr int kMaxWaves = 8;     // waves per block
+constexpr int kMaxBlockLog2 = 9; // aligned slot blocks of 2^0 .. 2^8 slots
 
 // Philox counter domains (word 3 of the counter); see the action / arrival
 // / noise derivations in the kernels.
@@ -26,7 +27,7 @@ constexpr int kNumPackings = 15;
 // constant uniform), and extended classes (V2G ports, a station battery or
 // charge-sensitive users).
 // kKindSimpleStaged: a SIMPLE class whose observations go through the block's
-// LDS stage (stations of at most 32 lanes; a context option, see stage_obs).
+// LDS stage (a context option, cx_set_obs_stage).
 enum : int { kKindGeneral = 0, kKindSimple = 1, kKindExt = 2, kKindSimpleStaged = 3, kNumKinds = 4 };
 __host__ __device__ constexpr int pack_lanes(int id) { return 4 << (id % 5); }
 __host__ __device__ constexpr int pack_per_lane(int id) { return 1 << (id / 5); }
@@ -54,6 +55,11 @@ struct ClassDev {
                                // one block size and one limit (all per-slot constants uniform)
   float pmax_u, inv_pmax_u;    // the port maximum of a simple class
   float lvl_cap_u[kMaxLevels]; // per level: the limit of a simple class (+inf beyond D)
+  // a simple class by block size: blk_cap[k] is the limit of the level below the
+  // root whose nodes own aligned blocks of 2^k slots (+inf if none), blk_mask
+  // bit k set where there is one
+  float blk_cap[kMaxBlockLog2];
+  uint32_t blk_mask;
   const int32_t *slot_port;    // [S]
   const float *slot_pmax;      // [S]
   const float *slot_inv_pmax;  // [S]
@@ -168,28 +174,32 @@ struct LaunchGroup {
   int wpb = 1;             // waves per block: the context's choice, halved until the LDS fits
 };
 
-// Packings whose staged kernels write observations through an LDS stage:
-// stations of at most 32 lanes.  A 64-lane station writes 256 contiguous bytes
-// per store already, and its kernels are bound by arithmetic, which the stage
-// adds to.
-__host__ __device__ constexpr bool stage_obs(int lanes) { return lanes <= 32; }
-// Does a launch group stage its observations?
+// Does a launch group stage its observations?  Its SIMPLE classes do, in every
+// packing, when the context asks for it.
 __host__ __device__ constexpr bool group_stages(int kind, int pack) {
-  return kind == kKindSimpleStaged && stage_obs(pack_lanes(pack));
+  (void)pack;
+  return kind == kKindSimpleStaged;
 }
 
-// LDS a block may take for the stay table and the two observation stages.
+// LDS a block may take for its tables and the two observation stages.
 constexpr size_t kMaxBlockLds = 64 << 10;
+// Per-step tables of a day kept in LDS when a day has at most this many steps:
+// the first four arrival thresholds of every step (one 16-byte row each) and
+// the base price of every step (so the draws ahead read no device memory).
+constexpr int kLdsExoSteps = 512;
 
 // LDS layout of a launch group's blocks: the stay table (4 << dwell_log2
-// bytes), then two observation stages of waves x stations per wave x the
-// largest observation floats, plus 3 floats to align them with HBM (rounded to
-// 16 bytes).  Returns the bytes with the stages; *stage_off / *stage_floats:
-// where the stages begin and floats per stage.
+// bytes), the per-step tables (kLdsExoSteps x 20 bytes), then two observation
+// stages of waves x stations per wave x the largest observation floats, plus 3
+// floats to align them with HBM (rounded to 16 bytes).
+inline size_t group_table_bytes(int dwell_log2) {
+  return ((((size_t)4 << dwell_log2) + 15) & ~(size_t)15) + (size_t)kLdsExoSteps * 20;
+}
+// Bytes with the stages; *stage_off / *stage_floats: where the stages begin
+// and floats per stage.
 inline size_t group_lds_bytes(int wpb, int pack, int max_obs_dim, int dwell_log2, int32_t *stage_off,
                               int32_t *stage_floats) {
-  const size_t table = (size_t)4 << dwell_log2;
-  const size_t off = (table + 15) & ~(size_t)15;
+  const size_t off = group_table_bytes(dwell_log2);
   const size_t floats =
       ((size_t)wpb * (size_t)(64 / pack_lanes(pack)) * (size_t)max_obs_dim + 3 + 3) & ~(size_t)3;
   if (stage_off) *stage_off = (int32_t)off;

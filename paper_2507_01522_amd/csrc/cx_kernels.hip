@@ -45,6 +45,19 @@ __device__ __forceinline__ int arrivals(const uint32_t *row, uint32_t w) {
   return pos;
 }
 
+// The same with the row's first four thresholds from the block's LDS copy
+// (the rest, rarely needed, from device memory).
+__device__ __forceinline__ int arrivals_lds(const __attribute__((address_space(3))) u32x4 *first4, const uint32_t *row,
+                                            uint32_t w) {
+  const u32x4 t = *first4;
+  const int m = (int)(w > t.x) + (int)(w > t.y) + (int)(w > t.z) + (int)(w > t.w);
+  if (m < 4) return m;
+  int pos = 0;
+  for (int s = 16; s >= 1; s >>= 1)
+    if (gld(row, pos + s - 1) < w) pos += s;
+  return pos;
+}
+
 // Stay length of an arriving car: 1 + #{thresholds below w}, bisecting the
 // table in LDS (staged by the block) or in device memory.
 __device__ __forceinline__ int stay_len(const uint32_t *tab, bool in_lds, int log2n, uint32_t w) {
@@ -58,6 +71,16 @@ __device__ __forceinline__ int stay_len(const uint32_t *tab, bool in_lds, int lo
       if (gld(tab, pos + s - 1) < w) pos += s;
   }
   return 1 + pos;
+}
+
+// A pointer the compiler may not know to be wave-uniform, held in scalar
+// registers (so loads through it can be scalar loads).
+template <class T>
+__device__ __forceinline__ const T *uniform_ptr(const T *p) {
+  const uint64_t v = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return reinterpret_cast<const T *>(((uint64_t)hi << 32) | lo);
 }
 
 // Exchange with the lane whose index differs in bit K (K = 0..5), for use in
@@ -87,16 +110,45 @@ __device__ __forceinline__ float xlane(float v) {
   return v;
 }
 
+// One butterfly step of a sum: v plus the value of the lane whose index
+// differs in bit K.  K = 4, 5: the two halves the row-swap instruction leaves
+// are exactly the pair to add (for a lane and its partner alike), so no select.
+template <int K>
+__device__ __forceinline__ float xsum(float v) {
+  if constexpr (K == 4) {
+    const int iv = __float_as_int(v);
+    const auto r = __builtin_amdgcn_permlane16_swap(iv, iv, false, false);
+    return __int_as_float(r[0]) + __int_as_float(r[1]);
+  } else if constexpr (K == 5) {
+    const int iv = __float_as_int(v);
+    const auto r = __builtin_amdgcn_permlane32_swap(iv, iv, false, false);
+    return __int_as_float(r[0]) + __int_as_float(r[1]);
+  } else {
+    return v + xlane<K>(v);
+  }
+}
+
 // Sum over aligned groups of L lanes (every lane receives its group's sum).
 template <int L>
 __device__ __forceinline__ float station_sum(float v) {
-  if constexpr (L > 1) v += xlane<0>(v);
-  if constexpr (L > 2) v += xlane<1>(v);
-  if constexpr (L > 4) v += xlane<2>(v);
-  if constexpr (L > 8) v += xlane<3>(v);
-  if constexpr (L > 16) v += xlane<4>(v);
-  if constexpr (L > 32) v += xlane<5>(v);
+  if constexpr (L > 1) v = xsum<0>(v);
+  if constexpr (L > 2) v = xsum<1>(v);
+  if constexpr (L > 4) v = xsum<2>(v);
+  if constexpr (L > 8) v = xsum<3>(v);
+  if constexpr (L > 16) v = xsum<4>(v);
+  if constexpr (L > 32) v = xsum<5>(v);
   return v;
+}
+
+// xsum<K> for a K known only as a loop index of an unrolled loop.
+template <int L>
+__device__ __forceinline__ float xsum_k(float v, int K) {
+  if (K == 0) return xsum<0>(v);
+  if (K == 1) return xsum<1>(v);
+  if (K == 2) return xsum<2>(v);
+  if (K == 3) return xsum<3>(v);
+  if (K == 4) return xsum<4>(v);
+  return xsum<5>(v);
 }
 
 // Masked butterfly step: lanes whose block is smaller than 2^(K+1) send 0
@@ -148,14 +200,16 @@ struct Dyn {
 // (the global "saddr" form: no 64-bit address per lane).
 template <class T>
 __device__ __forceinline__ void st_at(T *base, uint32_t byte_off, T v) {
-  *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + byte_off) = v;
+  typedef __attribute__((address_space(1))) T gT;
+  typedef __attribute__((address_space(1))) char gchar;
+  *(gT *)((gchar *)(char *)base + byte_off) = v;
 }
 template <class T>
 __device__ __forceinline__ T ld_at(const T *base, uint32_t byte_off) {
   return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + byte_off);
 }
 
-// Observation records staged in LDS (stations of up to 32 lanes).  Per step
+// Observation records staged in LDS (SIMPLE classes).  Per step
 // every lane puts its values in the block's stage (the adjacent envs of the
 // block's waves, in record order); after the step barrier the block's running
 // waves write the stage out as one contiguous run of 16-byte non-temporal
@@ -185,9 +239,9 @@ __device__ __forceinline__ void flush_stage(const lds_float *sb, float *dst, int
   }
   if (pad != 0 || ((pad + n) & 3) != 0) {  // the same in every lane
     const int head = (4 - pad) & 3;         // floats before the first whole chunk
-    if (tid < head && tid < n) dst[tid] = sb[pad + tid];
+    if (tid < head && tid < n) st_at(dst, 4u * (uint32_t)tid, (float)sb[pad + tid]);
     const int i = 4 * c_end - pad + (tid - 4);  // lanes 4..7: the floats after the last whole chunk
-    if (tid >= 4 && tid < 8 && i >= head && i < n) dst[i] = sb[pad + i];
+    if (tid >= 4 && tid < 8 && i >= head && i < n) st_at(dst, 4u * (uint32_t)i, (float)sb[pad + i]);
   }
 }
 
@@ -197,14 +251,18 @@ __device__ __forceinline__ void flush_stage(const lds_float *sb, float *dst, int
 // per-slot constant is wave-uniform (scalar registers).
 // EXT: V2G ports, a station battery, charge-sensitive users, price days and / or
 // car models (never SIMPLE); each switched on per class by a uniform flag.
-// STAGE: observations through the block's LDS stage (SIMPLE classes of up to
-// 32 lanes, when the context asks for it): stage / stage_floats are the two
+// STAGE: observations through the block's LDS stage (SIMPLE classes, when the
+// context asks for it): stage / stage_floats are the two
 // stage buffers and floats per buffer, g_blk0 the block's first group and
 // n_run the number of its waves that run.
+typedef __attribute__((address_space(3))) u32x4 lds_u32x4;
+
+// exo_tp / exo_pr: the block's LDS copies of the first four arrival thresholds
+// and the base price of every step of the day (NULL: read device memory).
 template <int L, int P, bool SIMPLE, bool EXT, bool STAGE>
 __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int group, const uint32_t *tdw,
-                                          bool tdw_lds, lds_float *stage, int stage_floats, int g_blk0,
-                                          int n_run) {
+                                          bool tdw_lds, const lds_u32x4 *exo_tp, const lds_float *exo_pr,
+                                          lds_float *stage, int stage_floats, int g_blk0, int n_run) {
   constexpr int SPW = 64 / L;
   constexpr int LOGL = (L == 4) ? 2 : (L == 8) ? 3 : (L == 16) ? 4 : (L == 32) ? 5 : 6;
   constexpr bool NOPAD = SIMPLE;  // every slot holds a port: slot s = port s
@@ -360,11 +418,23 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
       while (td >= steps_ep) td -= steps_ep;
       const uint32_t gl = g + (uint32_t)l;
       const U4 w = philox(env_id, gl, 0u, kDomEnv, k0, k1);
-      bM = active ? arrivals(C.tpois + td * kPoisStride, w.x) : 0;
+      if (exo_tp)
+        bM = active ? arrivals_lds(exo_tp + td, C.tpois + td * kPoisStride, w.x) : 0;
+      else
+        bM = active ? arrivals(C.tpois + td * kPoisStride, w.x) : 0;
       const float u1 = (float)((w.y >> 8) + 1u) * 0x1p-24f;
       const float u2 = u24(w.z);
       const float z = __builtin_amdgcn_sqrtf(-2.0f * __logf(u1)) * __builtin_amdgcn_cosf(u2);
-      float base = gld(C.glob, td * 4 + 2);
+      float base;
+      if (exo_pr) {
+        base = exo_pr[td];
+      } else {
+        // wait for the load here, where it is issued: a load still pending
+        // where the two paths join would make every step wait for all the
+        // records in flight
+        base = gld(C.glob, td * 4 + 2);
+        asm volatile("" ::"v"(base));
+      }
       if constexpr (EXT) {
         if (days) base = gld(C.price_days, episode_day(env_id, gl - (uint32_t)td, k0, k1, n_days) * steps_ep + td);
       }
@@ -397,6 +467,12 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
     const int tb = t & (L - 1);
     const int M = bcast<L>(bM, tb);
     const float pbuy = bcastf<L>(bpb, tb);
+    // the observation's time features of the step after this one (scalar loads,
+    // issued early; they do not wait for the records in flight)
+    const int t_obs = __builtin_amdgcn_readfirstlane(t_day + 1 == steps_ep ? 0 : t_day + 1);
+    const float *glob_u = uniform_ptr(C.glob);
+    const float gl_sin = sld(glob_u, 4 * t_obs), gl_cos = sld(glob_u, 4 * t_obs + 1),
+                gl_price = sld(glob_u, 4 * t_obs + 2);
 
     // ---- actions: action bytes k (level + n_neg)
     int k[P];
@@ -477,6 +553,58 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
 
     // ---- projection onto the capacity tree (Eq. ArchConst), deepest level
     // first; the root (level D-1) holds the whole station
+    float e_net, e_grid, e_out = 0.f;
+    if constexpr (SIMPLE) {
+      // Every node of a level owns an aligned block of 2^k slots, k the same for
+      // the whole level.  One butterfly over the station's slots holds, after k
+      // exchange steps, the load of each block of 2^k slots, already scaled by
+      // the levels below (a scaled block contributes its limit); so each level
+      // is checked when its block size is reached.  A slot's final factor is
+      // the product of the factors of the nodes on its path.
+      float r[P], F[P];
+#pragma unroll
+      for (int j = 0; j < P; ++j) {
+        r[j] = pw[j];
+        F[j] = 1.0f;
+      }
+      auto check = [&](int k) {
+        if ((C.blk_mask >> k) & 1u) {  // a level of blocks of 2^k slots (wave-uniform)
+          // a real (scalar) branch: most k have no level, and computing the
+          // check for every k and selecting would cost more than it saves
+          asm volatile("");
+          const float c = C.blk_cap[k];
+#pragma unroll
+          for (int j = 0; j < P; ++j) {
+            const bool over = r[j] > c;
+            F[j] = over ? F[j] * (c * frcp(r[j])) : F[j];
+            r[j] = over ? c : r[j];
+          }
+        }
+      };
+#pragma unroll
+      for (int k = 0; k < LOGL; ++k) {
+        check(k);
+#pragma unroll
+        for (int j = 0; j < P; ++j) r[j] = xsum_k<L>(r[j], k);
+      }
+      if constexpr (P >= 2) {  // blocks of 2 L slots: registers (0, 1) and (2, 3)
+        check(LOGL);
+        r[0] = r[1] = r[0] + r[1];
+        if constexpr (P == 4) r[2] = r[3] = r[2] + r[3];
+      }
+      if constexpr (P == 4) {  // blocks of 4 L slots: all four registers
+        check(LOGL + 1);
+        r[0] = r[1] = r[2] = r[3] = r[0] + r[2];
+      }
+      // the root: the whole station, delivered energy its scaled load (App. A.3)
+      const float tot = r[0];
+      const bool over = tot > c_root;
+      const float f = over ? c_root * frcp(tot) : 1.0f;
+#pragma unroll
+      for (int j = 0; j < P; ++j) pw[j] *= F[j] * f;
+      e_net = C.dt * (over ? c_root : tot);
+      e_grid = e_net * C.inv_eta_uniform;
+    } else {
 #pragma unroll
     for (int d = 0; d < kMaxLevels - 1; ++d) {
       if (d < D - 1) {
@@ -543,7 +671,6 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
     }
     // root: the station total before root scaling; the delivered energy is its
     // scaled value (App. A.3, charging only)
-    float e_net, e_grid, e_out = 0.f;
     if constexpr (EXT) {
       float tot = 0.f;
 #pragma unroll
@@ -574,7 +701,7 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
 #pragma unroll
       for (int j = 0; j < P; ++j) pw[j] *= f;
       e_net = C.dt * (over ? c_root : tot);
-      if (SIMPLE || C.uniform_eta) {
+      if (C.uniform_eta) {
         e_grid = e_net * C.inv_eta_uniform;
       } else {
         float tg = 0.f;
@@ -583,6 +710,7 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
         e_grid = C.dt * station_sum<L>(tg);
       }
     }
+    }  // projection of classes that are not SIMPLE
 
     // ---- the station battery (EXT): the (N+1)-th pole at the grid
     // connection, same curves, FP64 like the cars' q
@@ -640,8 +768,10 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
         }
         if (models) rb[j] = dep ? 0.f : rb[j];
       }
-      const float miss = fmaxf(0.0f, (qf[j] - u[j]) * cap[j]);
-      csat += dep0 ? miss : 0.0f;
+      if (C.alpha_sat != 0.0f) {  // energy still wanted by a departing car (c_satisfaction,0)
+        const float miss = fmaxf(0.0f, (qf[j] - u[j]) * cap[j]);
+        csat += dep0 ? miss : 0.0f;
+      }
       q[j] = dep ? 0.0 : q[j];
       qf[j] = dep ? 0.0f : qf[j];
       u[j] = dep ? 0.f : u[j];
@@ -771,6 +901,10 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
     // ---- records: an env's observation (byte offsets o inside its record)
     // goes to the block's LDS stage, or (wide stations) straight to HBM
     float *const ob_now = ob_t;  // this step's observation block of the segment
+    // per-lane offsets, re-read every step: with the 32-bit offset visible at
+    // each store the compiler emits the scalar-base form (no 64-bit lane address)
+    uint32_t obs_bo_t = obs_bo, act_bo_t = act_bo, env_bo_t = env_bo;
+    asm volatile("" : "+v"(obs_bo_t), "+v"(act_bo_t), "+v"(env_bo_t));
     const int pad =
         STAGE && w_obs ? (int)((reinterpret_cast<uintptr_t>(ob_now + (int64_t)env_blk0 * obs_dim) >> 2) & 3u) : 0;
     if (active) {
@@ -781,57 +915,81 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
             if (NOPAD || port[j] >= 0) {
               const bool occ = CX_OCCUPIED(j);
               const uint32_t o = 4u * (uint32_t)port[j];
-              put(o + 0u * 4u * N, occ ? 1.0f : 0.0f);
-              put(o + 1u * 4u * N, occ ? 1.0f - qf[j] : 0.0f);
-              put(o + 2u * 4u * N, occ ? qf[j] - u[j] : 0.0f);
-              put(o + 3u * 4u * N, (float)dw[j] * C.inv_steps_ep);
+              put(0u * 4u * N, o, occ ? 1.0f : 0.0f);
+              put(1u * 4u * N, o, occ ? 1.0f - qf[j] : 0.0f);
+              put(2u * 4u * N, o, occ ? qf[j] - u[j] : 0.0f);
+              put(3u * 4u * N, o, (float)dw[j] * C.inv_steps_ep);
               float rh = fminf(1.0f, qf[j] * C.inv_1mtau);
               if constexpr (EXT) {
                 if (models) rh *= rb[j] * inv_pmax[j];  // the car's curve, as a share of the port maximum
               }
-              put(o + 4u * 4u * N, occ ? rh : 0.0f);
-              put(o + 5u * 4u * N, plast[j] * inv_pmax[j]);
+              put(4u * 4u * N, o, occ ? rh : 0.0f);
+              put(5u * 4u * N, o, plast[j] * inv_pmax[j]);
               if constexpr (EXT) {
-                if (users) put(4u * (uint32_t)(C.user_obs + port[j]), cs[j] ? 1.0f : 0.0f);
+                if (users) put(4u * (uint32_t)C.user_obs, 4u * (uint32_t)port[j], cs[j] ? 1.0f : 0.0f);
               }
             }
           }
           if (l < 4) {
             const int n_occ = done ? 0 : (N - n_free + acc);
-            float gv = l == 3 ? (float)n_occ * (1.0f / (float)N) : gld(C.glob, t_day * 4 + l);
+            float gv = l == 3 ? (float)n_occ * (1.0f / (float)N) : l == 0 ? gl_sin : l == 1 ? gl_cos : gl_price;
             if constexpr (EXT) {
               if (days && l == 2) gv = gld(C.price_days, dday * steps_ep + t_day);
             }
-            put(4u * (uint32_t)(6 * N + l), gv);
+            put(4u * (uint32_t)(6 * N), 4u * (uint32_t)l, gv);
           }
           if constexpr (EXT) {
-            if (batt && l < 2) put(4u * (uint32_t)(6 * N + 4 + l), l == 0 ? (float)bsoc : bpw * C.b_inv_rate);
+            if (batt && l < 2) put(4u * (uint32_t)(6 * N + 4), 4u * (uint32_t)l, l == 0 ? (float)bsoc : bpw * C.b_inv_rate);
             if (days && l < 2)
-              put(4u * (uint32_t)(C.day_obs + l), l == 0 ? (float)dday * C.inv_n_days : (dday % 7 >= 5 ? 1.0f : 0.0f));
+              put(4u * (uint32_t)C.day_obs, 4u * (uint32_t)l, l == 0 ? (float)dday * C.inv_n_days : (dday % 7 >= 5 ? 1.0f : 0.0f));
           }
         };
         if constexpr (STAGE) {
           lds_float *sb = stage + (t & 1) * stage_floats + pad;
-          obs_record([&](uint32_t o, float v) {
+          obs_record([&](uint32_t fo, uint32_t lo, float v) {
             *reinterpret_cast<lds_float *>(reinterpret_cast<__attribute__((address_space(3))) char *>(sb) + stage_bo +
-                                           o) = v;
+                                           fo + lo) = v;
           });
         } else {
-          obs_record([&](uint32_t o, float v) { st_at(ob_now, obs_bo + o, v); });
+          // the feature's offset goes on the wave-uniform base, the lane's on its
+          // 32-bit offset
+          obs_record([&](uint32_t fo, uint32_t lo, float v) {
+            st_at((float *)((char *)ob_now + fo), obs_bo_t + lo, v);
+          });
         }
       }
       if (w_act) {
         uint8_t *ab = ab_t;
+        bool packed = false;
+        if constexpr (NOPAD) {
+          // four consecutive ports' bytes gathered into the first lane of each
+          // quad and stored as one dword (an env's bytes start at a multiple of
+          // 4, N being one; the step's row too when its base is aligned)
+          if ((reinterpret_cast<uintptr_t>(ab) & 3u) == 0) {
+            packed = true;
 #pragma unroll
-        for (int j = 0; j < P; ++j)
-          if (NOPAD || port[j] >= 0) st_at(ab, act_bo + (uint32_t)port[j], (uint8_t)k[j]);
+            for (int j = 0; j < P; ++j) {
+              const int b1 = __builtin_amdgcn_update_dpp(0, k[j], 0x55, 0xF, 0xF, false);  // quad lane 1
+              const int b2 = __builtin_amdgcn_update_dpp(0, k[j], 0xAA, 0xF, 0xF, false);  // quad lane 2
+              const int b3 = __builtin_amdgcn_update_dpp(0, k[j], 0xFF, 0xF, 0xF, false);  // quad lane 3
+              const uint32_t w4 =
+                  (uint32_t)k[j] | ((uint32_t)b1 << 8) | ((uint32_t)b2 << 16) | ((uint32_t)b3 << 24);
+              if ((l & 3) == 0) st_at((uint32_t *)ab, act_bo_t + (uint32_t)port[j], w4);
+            }
+          }
+        }
+        if (!packed) {
+#pragma unroll
+          for (int j = 0; j < P; ++j)
+            if (NOPAD || port[j] >= 0) st_at(ab, act_bo_t + (uint32_t)port[j], (uint8_t)k[j]);
+        }
         if constexpr (EXT) {
-          if (batt && l == 0) st_at(ab, act_bo + (uint32_t)N, (uint8_t)kb);
+          if (batt && l == 0) st_at(ab, act_bo_t + (uint32_t)N, (uint8_t)kb);
         }
       }
       if (l == 0) {
-        if (rw_t) st_at(rw_t, 4u * env_bo, r);
-        if (dn_t) st_at(dn_t, env_bo, (uint8_t)(done ? 1 : 0));
+        if (rw_t) st_at(rw_t, 4u * env_bo_t, r);
+        if (dn_t) st_at(dn_t, env_bo_t, (uint8_t)(done ? 1 : 0));
       }
     }
     ob_t += obs_step;
@@ -905,9 +1063,27 @@ __global__ __launch_bounds__(512) void k_rollout(LaunchArgs a) {
   // before any wave may leave)
   const uint32_t *tdw = sg.cls->tdwell;
   const bool tdw_lds = a.lds_tdwell != 0;
+  const lds_u32x4 *exo_tp = nullptr;
+  const lds_float *exo_pr = nullptr;
   if (tdw_lds) {
     const int n = 1 << sg.cls->dwell_log2;
     for (int i = threadIdx.x; i < n; i += blockDim.x) lds_tdwell[i] = gld(tdw, i);
+    // the day's per-step tables after the (16-byte aligned) stay table
+    const int steps = sg.cls->steps_ep;
+    if (steps <= kLdsExoSteps) {
+      __attribute__((address_space(3))) char *base =
+          (__attribute__((address_space(3))) char *)lds_tdwell + ((4 * n + 15) & ~15);
+      lds_u32x4 *tp = (lds_u32x4 *)base;
+      lds_float *pr = (lds_float *)(base + 16 * kLdsExoSteps);
+      const uint32_t *tpois = sg.cls->tpois;
+      const float *glob = sg.cls->glob;
+      for (int i = threadIdx.x; i < steps; i += blockDim.x) {
+        tp[i] = gld(reinterpret_cast<const u32x4 *>(tpois + (int64_t)i * kPoisStride), 0);
+        pr[i] = gld(glob, 4 * i + 2);
+      }
+      exo_tp = tp;
+      exo_pr = pr;
+    }
     __syncthreads();
     tdw = lds_tdwell;
   }
@@ -918,7 +1094,8 @@ __global__ __launch_bounds__(512) void k_rollout(LaunchArgs a) {
   const int n_run = min(W, sg.n_groups - g_blk0);  // waves of the block that run
   lds_float *stage =
       a.stage_floats > 0 ? (lds_float *)((__attribute__((address_space(3))) char *)lds_tdwell + a.stage_off) : nullptr;
-  run_group<L, P, SIMPLE, EXT, STAGE>(sg, dy, group, tdw, tdw_lds, stage, a.stage_floats, g_blk0, n_run);
+  run_group<L, P, SIMPLE, EXT, STAGE>(sg, dy, group, tdw, tdw_lds, exo_tp, exo_pr, stage, a.stage_floats, g_blk0,
+                                      n_run);
 }
 
 // Observation of empty stations at t_day = 0 for every env of one segment
@@ -951,10 +1128,10 @@ __global__ void k_fill_f64(double *p, int64_t n, double v) {
 using KernelFn = void (*)(LaunchArgs);
 
 // The kernels of one packing: general, SIMPLE, extended, SIMPLE with staged
-// observations (the SIMPLE kernel itself for 64-lane stations).
+// observations.
 #define CX_KINDS(L, P)                                                                              \
   &k_rollout<L, P, false, false, false>, &k_rollout<L, P, true, false, false>,                        \
-      &k_rollout<L, P, false, true, false>, &k_rollout<L, P, true, false, stage_obs(L)>
+      &k_rollout<L, P, false, true, false>, &k_rollout<L, P, true, false, true>
 
 // Kernel of each launch kind: packing id (P index * 5 + L index, as pack_id())
 // times kNumKinds, plus the kernel kind (kKind*).
@@ -981,7 +1158,7 @@ LaunchArgs group_args(const LaunchArgs &a, const LaunchGroup &g, size_t *lds) {
     *lds = with_stages;
   } else {
     b.stage_floats = 0;
-    *lds = (size_t)4 << g.max_dwell_log2;
+    *lds = group_table_bytes(g.max_dwell_log2);
   }
   return b;
 }

@@ -204,7 +204,7 @@ extern "C" cx_status cx_autotune(cx_ctx *ctx, int32_t T_probe, const char *cache
     // what it costs depends on the block size): every pair is timed
     bool any = false;
     for (const ClassRt &c : ctx->classes)
-      any = any || (c.n_envs > 0 && c.host_view.kind == kKindSimple && stage_obs(c.lanes));
+      any = any || (c.n_envs > 0 && c.host_view.kind == kKindSimple);
     const std::string wkey = ctx_key(ctx);
     const std::string skey = "stage" + wkey.substr(3);
     auto wit = cache.find(wkey);

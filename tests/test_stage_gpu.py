@@ -1,6 +1,6 @@
-"""The LDS observation stage (cx_set_obs_stage): with it, SIMPLE classes of up
-to 32 lanes per station write their observations through each block's stage as
-16-byte runs.  The records must be bit for bit those of lane-by-lane stores:
+"""The LDS observation stage (cx_set_obs_stage): with it, SIMPLE classes (in
+every packing) write their observations through each block's stage as 16-byte
+runs.  The records must be bit for bit those of lane-by-lane stores:
 in every packing and block size, for ragged env counts (partial blocks, runs
 that start at any 4-byte offset), across the day boundary, in one-step
 launches, in the policy loop and after autotuning (skipped while cx_autotune is
@@ -16,7 +16,7 @@ from tests import parity as PY
 pytestmark = pytest.mark.gpu
 
 # the uneven-batching classes (8..128 ports, trees 1-3 deep: SIMPLE kernels,
-# staged up to 32 lanes) plus a general class, a bidirectional one and the
+# all staged) plus a general class, a bidirectional one and the
 # dense-layout station, which keep their own kernels
 MIX = W.mixture_classes() + [W.two_charger_types(), W.v2g_station(), W.exo_station()]
 COUNTS = [5, 3, 7, 9, 1, 6, 4, 11, 2, 3, 5, 1, 2, 1, 3, 6, 5, 4]
@@ -65,11 +65,13 @@ def test_staged_equals_lane_stores(cxm, wpb):
     assert a.get_state() == b.get_state()
 
 
-@pytest.mark.parametrize("ports,lanes", [(8, 4), (8, 8), (16, 4), (16, 8), (16, 16), (32, 8), (32, 16), (32, 32)])
-def test_staged_every_packing(cxm, ports, lanes):
-    """Stations of 8-32 ports at 1, 2 or 4 slots per lane, 37 envs (a partial
-    last block), depth-2 trees."""
-    spec = W.fanout4_tree(ports, 2)
+@pytest.mark.parametrize("ports,lanes,depth", [(8, 4, 2), (8, 8, 2), (16, 4, 2), (16, 8, 2), (16, 16, 2), (32, 8, 2),
+                                               (32, 16, 2), (32, 32, 2), (64, 16, 3), (64, 32, 2), (64, 64, 3),
+                                               (128, 32, 3), (128, 64, 2), (128, 64, 3)])
+def test_staged_every_packing(cxm, ports, lanes, depth):
+    """Stations of 8-128 ports at 1, 2 or 4 slots per lane, 37 envs (a partial
+    last block), depth-2 and depth-3 trees."""
+    spec = W.fanout4_tree(ports, depth)
     ec = np.zeros(37, np.int32)
     outs = []
     for stage in (False, True):
@@ -182,3 +184,24 @@ def test_staged_class_split_into_segments(cxm, oracle_lib):
     ec = np.zeros(len(ids), np.int32)
     bs = o.BatchState([o.OracleClass(spec)], ec, env_ids=ids)
     PY.compare_rollout(g, o.rollout(bs, seed, T), [spec], ec)
+
+
+@pytest.mark.parametrize("shift", [0, 1, 2, 3])
+def test_staged_writes_stay_in_range(cxm, shift):
+    """The staged flush writes exactly the observation records: inside guard
+    bands of 1,024 floats before and after the records (whose start is moved by
+    0-3 floats, so the runs begin at every 4-byte offset of a 16-byte chunk)
+    every float keeps its sentinel, and the records equal the unstaged ones."""
+    ec = ec_of(COUNTS)
+    T, G = 37, 1024
+    a = make(cxm, MIX, ec, 47, False)
+    b = make(cxm, MIX, ec, 47, True)
+    n = T * b.info().obs_elems
+    buf = torch.full((n + 2 * G + 4,), 1234.5, dtype=torch.float32, device="cuda")
+    out_b = b.alloc_traj(T)
+    out_b["obs"] = buf[G + shift:G + shift + n].view(T, -1)
+    b.rollout(T, cxm.ACT_RANDOM, cxm.OUT_FULL, out=out_b)
+    ra = PY.to_np(a.rollout(T, cxm.ACT_RANDOM))
+    host = buf.cpu().numpy()
+    assert (host[:G + shift] == 1234.5).all() and (host[G + shift + n:] == 1234.5).all()
+    assert np.array_equal(host[G + shift:G + shift + n].reshape(T, -1), ra["obs"])
