@@ -187,6 +187,7 @@ constexpr size_t kMaxBlockLds = 64 << 10;
 // the first four arrival thresholds of every step (one 16-byte row each) and
 // the base price of every step (so the draws ahead read no device memory).
 constexpr int kLdsExoSteps = 512;
+constexpr int kLdsExoMinT = 32;   // ... in launches of at least this many steps
 
 // LDS layout of a launch group's blocks: the stay table (4 << dwell_log2
 // bytes), the per-step tables (kLdsExoSteps x 20 bytes), then two observation

@@ -1068,9 +1068,11 @@ __global__ __launch_bounds__(512) void k_rollout(LaunchArgs a) {
   if (tdw_lds) {
     const int n = 1 << sg.cls->dwell_log2;
     for (int i = threadIdx.x; i < n; i += blockDim.x) lds_tdwell[i] = gld(tdw, i);
-    // the day's per-step tables after the (16-byte aligned) stay table
+    // the day's per-step tables after the (16-byte aligned) stay table, for
+    // launches long enough to repay copying them (short ones read them from
+    // device memory)
     const int steps = sg.cls->steps_ep;
-    if (steps <= kLdsExoSteps) {
+    if (steps <= kLdsExoSteps && dy.T >= kLdsExoMinT) {
       __attribute__((address_space(3))) char *base =
           (__attribute__((address_space(3))) char *)lds_tdwell + ((4 * n + 15) & ~15);
       lds_u32x4 *tp = (lds_u32x4 *)base;
