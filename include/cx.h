@@ -57,7 +57,8 @@ typedef enum {
  * action byte per env, after its ports. */
 typedef enum {
   CX_ACT_EXTERNAL = 0, /* caller-provided action bytes (above lo + n_levels: clamped)     */
-  CX_ACT_RANDOM = 1,   /* uniform bytes from Philox: (w * (lo + n_levels + 1)) >> 32      */
+  CX_ACT_RANDOM = 1,   /* uniform bytes from Philox: (h * (lo + n_levels + 1)) >> 16, h a  */
+                       /* 16-bit half; one call per action index per 8 steps           */
   CX_ACT_MAX = 2,      /* every port (and the battery) asks for its maximum charge        */
   CX_ACT_POLICY = 3    /* the MLP set by cx_set_policy, a level drawn from its softmax   */
 } cx_action_mode;

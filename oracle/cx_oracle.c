@@ -388,8 +388,9 @@ void ox_draw_exo(const ox_class *c, uint64_t seed, uint32_t env, uint32_t g, int
   }
 }
 
-/* Levels of every action index.  RANDOM: uniform over the index's lo + L + 1
- * levels from Philox word g & 3 of counter (env, g >> 2, i, ACT); MAX: level L;
+/* Levels of every action index.  RANDOM: uniform over the index's n = lo + L + 1
+ * levels from one 16-bit half h of counter (env, g >> 3, i, ACT) -- word
+ * (g & 7) / 2, its low half on even g -- as the code (h n) / 2^16; MAX: level L;
  * EXTERNAL: the given byte minus lo, bytes above lo + L taken as lo + L. */
 void ox_draw_actions(const ox_class *c, int32_t mode, uint64_t seed, uint32_t env, uint32_t g,
                      const uint8_t *ext, int32_t *k) {
@@ -400,8 +401,9 @@ void ox_draw_actions(const ox_class *c, int32_t mode, uint64_t seed, uint32_t en
     int32_t code;
     if (mode == OX_ACT_RANDOM) {
       uint32_t w[4];
-      philox_seeded(seed, env, g >> 2, (uint32_t)i, OX_DOM_ACT, w);
-      code = (int32_t)(((uint64_t)w[g & 3u] * (uint64_t)(lo + L + 1)) >> 32);
+      philox_seeded(seed, env, g >> 3, (uint32_t)i, OX_DOM_ACT, w);
+      const uint32_t h = (g & 1u) ? (w[(g & 7u) >> 1] >> 16) : (w[(g & 7u) >> 1] & 0xFFFFu);
+      code = (int32_t)(((uint64_t)h * (uint64_t)(lo + L + 1)) >> 16);
     } else if (mode == OX_ACT_MAX) {
       code = lo + L;
     } else {

@@ -173,6 +173,14 @@ __device__ __forceinline__ float block_sum_lanes(float v, int lb) {
 
 __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// Four random action bytes from two Philox words: each 16-bit half h (low
+// half first) gives (h n) >> 16, uniform over 0..n-1 up to 1 / 65536.
+__device__ __forceinline__ uint32_t act_bytes(uint32_t wa, uint32_t wb, uint32_t n) {
+  const uint32_t b0 = __umul24(wa & 0xFFFFu, n) >> 16, b1 = __umul24(wa >> 16, n) >> 16;
+  const uint32_t b2 = __umul24(wb & 0xFFFFu, n) >> 16, b3 = __umul24(wb >> 16, n) >> 16;
+  return b0 | (b1 << 8) | (b2 << 16) | (b3 << 24);
+}
+
 template <int L>
 __device__ __forceinline__ int bcast(int v, int src) {
   if constexpr (L == 64) return __builtin_amdgcn_readlane(v, src);
@@ -351,15 +359,17 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
       bpw = sg.bp[env];
     }
   }
-  uint32_t bkp = 0;  // EXT: the battery's action bytes of the current group of 4 steps, one per byte
+  uint32_t bkp[2] = {0u, 0u};  // EXT: the battery's action bytes of the current group of 8 steps
   // limit of the root (the whole station)
   const float c_root = D == 1 ? lcap[0][0] : D == 2 ? lcap[1][0] : D == 3 ? lcap[2][0] : lcap[3][0];
 
   const uint32_t k0 = (uint32_t)sg.seed, k1 = (uint32_t)(sg.seed >> 32);
   const uint32_t env_id = (uint32_t)(sg.env0 + env);
-  const int steps_ep = C.steps_ep;
+  // the day clock is the same in every lane: kept in scalar registers, the
+  // end-of-day reset is a branch, not selects in every step
+  const int steps_ep = __builtin_amdgcn_readfirstlane(C.steps_ep);
   const int n_levels = C.n_levels;
-  int t_day = dy.t_day0;
+  int t_day = __builtin_amdgcn_readfirstlane(dy.t_day0);
   uint32_t g = dy.g0;
   int dday = 0;  // EXT: price day of the current episode (drawn at its first step)
   if constexpr (EXT) {
@@ -372,17 +382,11 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
   constexpr bool AHEAD2 = SIMPLE && L == 64;
   int bdw1 = 1;
   float bcp1 = 0.f, bs01 = 0.f, btg1 = 0.f;
-  // RANDOM: each slot's 4 Philox words of the current group of 4 steps; where
-  // PACK holds, the 4 levels they give instead, one per byte (fewer registers
-  // across the step, which pays in the 64-lane and extended kernels)
-  constexpr bool PACK = EXT || AHEAD2;
-  U4 aw[P];
-  uint32_t kp[P];
+  // RANDOM: each slot's action bytes of the current group of 8 steps, one per
+  // byte (steps 0-3 of the group in kp[0], 4-7 in kp[1])
+  uint32_t kp[P][2];
 #pragma unroll
-  for (int j = 0; j < P; ++j) {
-    aw[j] = U4{0, 0, 0, 0};
-    kp[j] = 0;
-  }
+  for (int j = 0; j < P; ++j) kp[j][0] = kp[j][1] = 0u;
   const uint64_t smask = (L == 64) ? ~0ull : (((1ull << (L & 63)) - 1ull) << sbase);
   const uint64_t below_mask = (1ull << lane) - 1ull;
 
@@ -478,36 +482,33 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
     int k[P];
     int kb = 0;  // the battery's action byte (level + n_levels)
     if (dy.mode == CX_ACT_RANDOM) {
-      if (t == 0 || (g & 3u) == 0) {
-        // action bytes are at most 254 (n_levels <= 254; 127 with discharging)
+      if (t == 0 || (g & 7u) == 0) {
+        // one Philox call gives the 8 steps' bytes: its 16-bit halves (low
+        // half first) scaled to the n byte values, (h n) >> 16; n <= 255, so
+        // the product is exact in a 24-bit multiply.  Action bytes are at most
+        // 254 (n_levels <= 254; 127 with discharging).
         const uint32_t nk = (uint32_t)(n_levels + n_neg + 1);
 #pragma unroll
         for (int j = 0; j < P; ++j) {
-          const U4 w = philox(env_id, g >> 2, (uint32_t)port[j], kDomAct, k0, k1);
-          if constexpr (PACK)
-            kp[j] = __umulhi(w.x, nk) | (__umulhi(w.y, nk) << 8) | (__umulhi(w.z, nk) << 16) | (__umulhi(w.w, nk) << 24);
-          else
-            aw[j] = w;
+          const U4 w = philox(env_id, g >> 3, (uint32_t)port[j], kDomAct, k0, k1);
+          kp[j][0] = act_bytes(w.x, w.y, nk);
+          kp[j][1] = act_bytes(w.z, w.w, nk);
         }
         if constexpr (EXT) {
           if (batt) {
-            const U4 w = philox(env_id, g >> 2, (uint32_t)N, kDomAct, k0, k1);
+            const U4 w = philox(env_id, g >> 3, (uint32_t)N, kDomAct, k0, k1);
             const uint32_t nb = (uint32_t)(2 * n_levels + 1);
-            bkp = __umulhi(w.x, nb) | (__umulhi(w.y, nb) << 8) | (__umulhi(w.z, nb) << 16) | (__umulhi(w.w, nb) << 24);
+            bkp[0] = act_bytes(w.x, w.y, nb);
+            bkp[1] = act_bytes(w.z, w.w, nb);
           }
         }
       }
-      const uint32_t sel = g & 3u, sh = 8u * sel;
+      // the step's byte (wave-uniform selection of register and byte)
+      const bool hi4 = (g & 4u) != 0;
+      const uint32_t sh = 8u * (g & 3u);
 #pragma unroll
-      for (int j = 0; j < P; ++j) {
-        if constexpr (PACK) {
-          k[j] = (int)((kp[j] >> sh) & 0xFFu);
-        } else {
-          const uint32_t w = sel == 0 ? aw[j].x : sel == 1 ? aw[j].y : sel == 2 ? aw[j].z : aw[j].w;
-          k[j] = (int)__umulhi(w, (uint32_t)(n_levels + n_neg + 1));
-        }
-      }
-      if constexpr (EXT) kb = (int)((bkp >> sh) & 0xFFu);
+      for (int j = 0; j < P; ++j) k[j] = (int)__builtin_amdgcn_ubfe(hi4 ? kp[j][1] : kp[j][0], sh, 8);
+      if constexpr (EXT) kb = (int)__builtin_amdgcn_ubfe(hi4 ? bkp[1] : bkp[0], sh, 8);
     } else if (dy.mode == CX_ACT_MAX) {
 #pragma unroll
       for (int j = 0; j < P; ++j) k[j] = n_levels + n_neg;

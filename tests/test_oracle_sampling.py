@@ -168,6 +168,19 @@ def test_price_noise_statistics(oracle_lib):
     assert abs(resid.std() - 0.02) < 0.001
 
 
+def test_random_actions_steps_independent(oracle_lib):
+    """One Philox call serves 8 steps of a port: the levels of steps 1, 2, 4 and
+    8 apart (inside a call, across its words, across calls) are independent."""
+    o = oracle_lib
+    c = o.OracleClass(W.tiny_parity_station())
+    ks = np.array([[c.draw_actions(o.ACT_RANDOM, 9, e, g)[0] for g in range(48)] for e in range(400)])
+    for lag in (1, 2, 4, 8):
+        a, b = ks[:, :-lag].ravel(), ks[:, lag:].ravel()
+        table = np.zeros((11, 11))
+        np.add.at(table, (a, b), 1)
+        assert stats.chi2_contingency(table)[1] > 1e-4, lag
+
+
 def test_random_actions_uniform(oracle_lib):
     o = oracle_lib
     c = o.OracleClass(W.tiny_parity_station())
