@@ -734,12 +734,13 @@ void ox_policy(const ox_class *c, int32_t hidden, const uint16_t *w1, const uint
       e[l] = exp(zi[l] - zmax);
       W += e[l];
     }
-    /* u in (0, 1) from the top 24 bits of word 0 of Philox (env, g, port, 3); the
+    /* u in (0, 1) from the top 24 bits of word (i / 16) mod 4 of Philox
+     * (env, g, i mod 16 + 16 (i / 64), 3) -- ports 16 apart share a call; the
      * level is the first l whose distribution function F_l = (p_0 + .. + p_l)
      * exceeds u */
     uint32_t w[4];
-    philox_seeded(seed, env, g, (uint32_t)i, OX_DOM_GUM, w);
-    const double u = ((double)(w[0] >> 8) + 0.5) * (1.0 / 16777216.0);
+    philox_seeded(seed, env, g, (uint32_t)(i % 16 + 16 * (i / 64)), OX_DOM_GUM, w);
+    const double u = ((double)(w[(i / 16) % 4] >> 8) + 0.5) * (1.0 / 16777216.0);
     double F = 0.0, near = 1.0;
     int32_t lev = L;
     for (int32_t l = 0; l < L; ++l) {

@@ -76,7 +76,7 @@ extern "C" {
 #define OX_DOM_ENV 0u       /* ctr = (env, g, 0, 0): arrivals + price noise      */
 #define OX_DOM_ACT 1u       /* ctr = (env, g >> 3, port, 1): half g & 7 of 8    */
 #define OX_DOM_CAR 2u       /* ctr = (env, g, j, 2): j-th arriving car of step g */
-#define OX_DOM_GUM 3u       /* ctr = (env, g, port, 3): the policy's level draw   */
+#define OX_DOM_GUM 3u       /* ctr = (env, g, port % 16 + 16 (port / 64), 3): the policy's draw, word (port / 16) % 4 */
 #define OX_DOM_USER 4u      /* ctr = (env, g, j, 4): user type of car j, word 0  */
 #define OX_DOM_DAY 5u       /* ctr = (env, g0, 0, 5): price day of the episode starting at g0 */
 

@@ -232,44 +232,50 @@ void build_groups(const std::vector<SegDev> &in, const std::vector<int> &log2_dw
   }
 }
 
+void class_segments(const cx_ctx *ctx, const ClassRt &c, int L, int P, std::vector<SegDev> *segs) {
+  const int spw = 64 / L;
+  // the kernels address a segment's records with 32-bit per-lane byte offsets:
+  // a class whose observation block would reach 4 GiB per step is cut into
+  // several segments (whole waves each)
+  int64_t chunk = (int64_t)(((1ull << 32) - 1) / (4ull * (uint64_t)c.comp.obs_dim));
+  chunk -= chunk % 64;
+  for (int64_t e0 = 0; e0 < c.n_envs; e0 += chunk) {
+    const int64_t n = std::min<int64_t>(chunk, c.n_envs - e0);
+    SegDev sg{};
+    sg.cls = c.dev;
+    sg.env0 = c.env_begin + e0;
+    sg.n_envs = n;
+    sg.n_groups = (int32_t)((n + spw - 1) / spw);
+    sg.pack = pack_id(L, P);
+    sg.obs_dim = c.comp.obs_dim;
+    sg.seed = ctx->seed;
+    const int64_t so = c.slot_off + e0 * c.comp.S;
+    sg.q = ctx->q + so;
+    sg.u = ctx->u + so;
+    sg.cap = ctx->cap + so;
+    sg.p_last = ctx->p_last + so;
+    sg.dwell = ctx->dwell + so;
+    sg.ret = ctx->ret + c.env_begin + e0;
+    sg.bsoc = ctx->bsoc + c.env_begin + e0;
+    sg.bp = ctx->bp + c.env_begin + e0;
+    sg.utype = ctx->utype + so;
+    sg.rbar = ctx->rbar + so;
+    sg.obs_off = c.obs_off + e0 * c.comp.obs_dim;
+    sg.act_off = c.port_off + e0 * c.comp.n_act;
+    sg.env_off = c.env_begin + e0;
+    segs->push_back(sg);
+  }
+}
+
 cx_status rebuild_segments(cx_ctx *ctx) {
   std::vector<SegDev> segs;
   std::vector<int> dl;
   std::vector<int> kind;
   for (ClassRt &c : ctx->classes) {
     if (c.n_envs == 0) continue;
-    const int L = c.lanes, P = c.comp.S / c.lanes;
-    const int spw = 64 / L;
-    // the kernels address a segment's records with 32-bit per-lane byte offsets:
-    // a class whose observation block would reach 4 GiB per step is cut into
-    // several segments (whole waves each)
-    int64_t chunk = (int64_t)(((1ull << 32) - 1) / (4ull * (uint64_t)c.comp.obs_dim));
-    chunk -= chunk % 64;
-    for (int64_t e0 = 0; e0 < c.n_envs; e0 += chunk) {
-      const int64_t n = std::min<int64_t>(chunk, c.n_envs - e0);
-      SegDev sg{};
-      sg.cls = c.dev;
-      sg.env0 = c.env_begin + e0;
-      sg.n_envs = n;
-      sg.n_groups = (int32_t)((n + spw - 1) / spw);
-      sg.pack = pack_id(L, P);
-      sg.obs_dim = c.comp.obs_dim;
-      sg.seed = ctx->seed;
-      const int64_t so = c.slot_off + e0 * c.comp.S;
-      sg.q = ctx->q + so;
-      sg.u = ctx->u + so;
-      sg.cap = ctx->cap + so;
-      sg.p_last = ctx->p_last + so;
-      sg.dwell = ctx->dwell + so;
-      sg.ret = ctx->ret + c.env_begin + e0;
-      sg.bsoc = ctx->bsoc + c.env_begin + e0;
-      sg.bp = ctx->bp + c.env_begin + e0;
-      sg.utype = ctx->utype + so;
-      sg.rbar = ctx->rbar + so;
-      sg.obs_off = c.obs_off + e0 * c.comp.obs_dim;
-      sg.act_off = c.port_off + e0 * c.comp.n_act;
-      sg.env_off = c.env_begin + e0;
-      segs.push_back(sg);
+    const size_t first = segs.size();
+    class_segments(ctx, c, c.lanes, c.comp.S / c.lanes, &segs);
+    for (size_t i = first; i < segs.size(); ++i) {
       dl.push_back(c.tab.dwell_log2);
       kind.push_back(c.host_view.kind == kKindSimple && ctx->stage_obs ? kKindSimpleStaged : c.host_view.kind);
     }

@@ -67,6 +67,7 @@ extern thread_local std::string g_last_error;
 cx_status fail_status(cx_status st, const std::string &msg);
 cx_status hip_fail(cx_ctx *ctx, hipError_t e, const char *what);
 cx_status rebuild_segments(cx_ctx *ctx);
+void class_segments(const cx_ctx *ctx, const ClassRt &c, int L, int P, std::vector<SegDev> *segs);
 void build_groups(const std::vector<SegDev> &in, const std::vector<int> &log2_dwell,
                   const std::vector<int> &kind, int wpb, std::vector<SegDev> *out,
                   std::vector<LaunchGroup> *groups);

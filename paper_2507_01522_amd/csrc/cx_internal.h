@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "cx.h"
 
 namespace cx {
@@ -139,6 +141,8 @@ struct SegDev {
   float *rbar;
 };
 
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
 // Launch-wide arguments (by value).
 struct LaunchArgs {
   const SegDev *segs;
@@ -158,6 +162,20 @@ struct LaunchArgs {
   uint8_t *done;
   const uint8_t *act_in;
   int64_t obs_stride, act_stride, env_stride;
+  // the fused policy rollout (mode CX_ACT_POLICY): the MLP's weights in
+  // fragment order, its sizes, the observation the rollout starts from, and
+  // where the block's BF16 observations, hidden units and levels sit in LDS
+  struct Pol {
+    const float *obs0;    // [envs of the segment table][in_dim], 16-byte aligned rows
+    // fragments padded with zeros to the largest sizes (8 K-steps of features,
+    // 16 hidden tiles, 8 K-steps of hidden units, 3 level tiles)
+    const u32x4 *w1f;     // [16][8][64] fragments of W1^T
+    const float *b1;      // [256]
+    const u32x4 *w2f;     // [G][3][8][64] fragments of W2^T
+    const float *b2f;     // [G][3][16]
+    int32_t in_dim, K1, HP, R, G, L1;
+    int32_t hb_off, xb_off, act_off;  // LDS byte offsets
+  } pol;
 };
 
 // One launch group: the segments of one packing, launched by the kernel
@@ -208,6 +226,30 @@ inline size_t group_lds_bytes(int wpb, int pack, int max_obs_dim, int dwell_log2
   return off + 8 * floats;
 }
 
+// The fused policy rollout: blocks of 4 waves of 8-lane stations (32 envs, two
+// 16-env tiles of the MLP).  LDS: the stay and day tables, then the stage (one
+// buffer of 32 observations), which the hidden units (8 x 2 KiB) overwrite once
+// it has been read, then the observations in BF16 (32 x 528 bytes) and a level
+// byte per port and env.  Returns the bytes; sets the offsets.
+constexpr int kPolRolloutWaves = 4;
+constexpr int kPolRolloutEnvs = kPolRolloutWaves * 8;
+constexpr int kPolXbRow = 33;  // 16-byte fragments per env row of the BF16 observations (32 used)
+inline size_t policy_rollout_lds(int dwell_log2, int obs_dim, int N, int32_t *stage_off,
+                                 int32_t *stage_floats, int32_t *hb_off, int32_t *xb_off, int32_t *act_off) {
+  auto a16 = [](size_t x) { return (x + 15) & ~(size_t)15; };
+  const size_t off = group_table_bytes(dwell_log2);
+  const size_t floats = ((size_t)kPolRolloutEnvs * obs_dim + 3) & ~(size_t)3;
+  const size_t region = a16(std::max(4 * floats, (size_t)8 * (kPolRolloutEnvs / 16) * 64 * 16));
+  const size_t xb = off + region;
+  const size_t act = xb + (size_t)kPolRolloutEnvs * 16 * kPolXbRow;
+  *stage_off = (int32_t)off;
+  *stage_floats = (int32_t)floats;
+  *hb_off = (int32_t)off;
+  *xb_off = (int32_t)xb;
+  *act_off = (int32_t)act;
+  return act + a16((size_t)kPolRolloutEnvs * N);
+}
+
 // The persistent rollout as a HIP graph with one kernel node per launch group
 // (no dependencies between them), instantiated once per launch shape and
 // re-parameterised on every call.
@@ -218,8 +260,6 @@ struct RolloutGraph {
   int n_nodes = 0;
   int shape[kNumKinds * kNumPackings][4] = {};  // kernel, blocks, waves per block, LDS bytes
 };
-
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 // Arguments of the policy kernel (cx_policy.hip): the perceptron's weights in
 // fragment order and one step's observations in, levels and / or logits out.
@@ -241,6 +281,7 @@ struct PolicyArgs {
 // Host-side launchers (defined in cx_kernels.hip).  `a.segs` is the base of
 // the device segment table; each group launches with its own slice.
 hipError_t launch_groups(const LaunchArgs &a, const LaunchGroup *groups, int n_groups, hipStream_t st);
+hipError_t launch_policy_rollout(const LaunchArgs &a, int per_lane, int n_blocks, size_t lds, hipStream_t st);
 hipError_t graph_rollout(RolloutGraph &g, const LaunchArgs &a, const LaunchGroup *groups, int n_groups,
                          hipStream_t st);
 void graph_destroy(RolloutGraph &g);

@@ -27,6 +27,7 @@
 #include <algorithm>
 
 #include "cx_device.h"
+#include "cx_mlp.h"
 #include "cx_internal.h"
 
 namespace cx {
@@ -264,13 +265,152 @@ __device__ __forceinline__ void flush_stage(const lds_float *sb, float *dst, int
 // stage buffers and floats per buffer, g_blk0 the block's first group and
 // n_run the number of its waves that run.
 typedef __attribute__((address_space(3))) u32x4 lds_u32x4;
+typedef __attribute__((address_space(3))) char lds_char;
+typedef __attribute__((address_space(3))) uint8_t lds_u8;
+
+// The fused policy rollout: after every step the block's staged observations
+// (E = 32 envs, row stride obs_dim floats) go through the MLP on the matrix
+// cores and each port gets its level for the next step, in LDS.  The products
+// are those of the standalone policy kernel, K-step by K-step in the same
+// order, so logits and levels are the same: here the block's 4 waves split the
+// hidden units (first product) and the port groups (second) among them, and
+// each wave reads its weight fragments from device memory (L2) straight into
+// the matrix-core operands.  The K-step loops run their compile-time maximum
+// (8 x 32 features, 8 x 32 hidden units, 3 level tiles) over weights padded
+// with zeros -- such steps add exact zeros -- so that they are straight-line
+// code whose loads are all issued ahead of the matrix-core work.  LDS: hb
+// (8 x 2 hidden-unit fragments, over the stage once it has been read), xb (the
+// observations in BF16, 256 features per env, zero past in_dim, rows 33
+// fragments apart so that the 16 envs of a tile fall in different banks) and
+// act (a level byte per port and env).  wv: this wave in the block.
+__device__ __forceinline__ void policy_phase(const LaunchArgs::Pol &pl, const lds_float *stage, lds_char *lds,
+                                             int obs_dim, int N, int blk_envs, int wv, uint32_t env_id0,
+                                             uint32_t g, uint32_t k0, uint32_t k1) {
+  constexpr int W = kPolRolloutWaves, NT = kPolRolloutEnvs / 16, CPR = 4 * kPolK1;  // chunks of 8 per row
+  const int lane = __lane_id(), col = lane & 15, lg = lane >> 4, tid = wv * 64 + lane;
+  const int in_dim = pl.in_dim, R = pl.R, G = pl.G, L1 = pl.L1;
+  lds_u32x4 *xb = reinterpret_cast<lds_u32x4 *>(lds + pl.xb_off);
+  lds_u32x4 *hb = reinterpret_cast<lds_u32x4 *>(lds + pl.hb_off);
+  lds_u8 *act = reinterpret_cast<lds_u8 *>(lds + pl.act_off);
+  const u32x4 zero = {0u, 0u, 0u, 0u};
+  // observations -> BF16 (features past in_dim and envs past the block's: 0);
+  // a row of the stage starts 16-byte aligned (obs_dim is a multiple of 4)
+  for (int c = tid; c < kPolRolloutEnvs * CPR; c += 64 * W) {
+    const int e = c / CPR, k = c % CPR, f = 8 * k;
+    const lds_float *row = stage + e * obs_dim + f;
+    u32x4 v = zero;
+    if (e < blk_envs) {
+      if (f + 8 <= in_dim) {
+        const f32x4 x = *reinterpret_cast<const lds_f32x4 *>(row);
+        const f32x4 y = *reinterpret_cast<const lds_f32x4 *>(row + 4);
+        v = u32x4{pack2(x.x, x.y), pack2(x.z, x.w), pack2(y.x, y.y), pack2(y.z, y.w)};
+      } else if (f < in_dim) {
+        float x[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) x[j] = f + j < in_dim ? row[j] : 0.f;
+        v = u32x4{pack2(x[0], x[1]), pack2(x[2], x[3]), pack2(x[4], x[5]), pack2(x[6], x[7])};
+      }
+    }
+    xb[e * kPolXbRow + k] = v;
+  }
+  __syncthreads();
+  // first product: this wave's pairs of 16-unit hidden tiles, both pairs per
+  // K-step so that each observation fragment is read once.  Weight fragments
+  // come in buffer loads: one resource per matrix, the fragment's offset a
+  // scalar, the lane's 16 bytes the vector offset (no 64-bit addresses).
+  constexpr int NI = kPolHP / W;
+  // vector offsets: the lane's 16 bytes, plus 4 KiB for K-steps 4..7; the
+  // step's KiB within them goes in the instruction's offset field
+  const uint32_t vo[2] = {16u * (uint32_t)lane, 16u * (uint32_t)lane + 4096u};
+  const __amdgpu_buffer_rsrc_t w1 =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<u32x4 *>(pl.w1f), (short)0, 2 * kPolHP * kPolK1 * 1024, 0x00020000);
+  const __amdgpu_buffer_rsrc_t w2 =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<u32x4 *>(pl.w2f), (short)0, G * kPolR * kPolHP * 1024, 0x00020000);
+  f32x4 c0[NI][NT], c1[NI][NT];
+#pragma unroll
+  for (int i = 0; i < NI; ++i)
+#pragma unroll
+    for (int n = 0; n < NT; ++n) c0[i][n] = c1[i][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int s = 0; s < kPolK1; ++s) {
+    u32x4 a0[NI], a1[NI];
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+      const int m = 2 * (wv + W * i);  // the pair's first tile
+      const uint32_t v = vo[s >> 2] + 1024u * (uint32_t)(s & 3);
+      a0[i] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(w1, v, m * kPolK1 * 1024, 0));
+      a1[i] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(w1, v, (m + 1) * kPolK1 * 1024, 0));
+    }
+#pragma unroll
+    for (int n = 0; n < NT; ++n) {
+      const u32x4 b = xb[(16 * n + col) * kPolXbRow + 4 * s + lg];
+#pragma unroll
+      for (int i = 0; i < NI; ++i) {
+        c0[i][n] = mfma_bf16(a0[i], b, c0[i][n]);
+        c1[i][n] = mfma_bf16(a1[i], b, c1[i][n]);
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < NI; ++i) {
+    const int mp = wv + W * i;
+    const f32x4 bA = gld(reinterpret_cast<const f32x4 *>(pl.b1 + 32 * mp + 4 * lg), 0);
+    const f32x4 bB = gld(reinterpret_cast<const f32x4 *>(pl.b1 + 32 * mp + 16 + 4 * lg), 0);
+#pragma unroll
+    for (int n = 0; n < NT; ++n) hb[(mp * NT + n) * 64 + lane] = hidden_frag(c0[i][n], c1[i][n], bA, bB);
+  }
+  __syncthreads();
+  // second product and the draw, per group of 4 ports.  The lane's ports are
+  // 4 wv + lg + 16 i (group wv + 4 i): one Philox call per env serves them all
+  U4 dw[NT];
+#pragma unroll
+  for (int n = 0; n < NT; ++n)
+    dw[n] = philox(env_id0 + (uint32_t)(16 * n + col), g, draw_index(4 * wv + lg), kDomGum, k0, k1);
+  for (int grp = wv; grp < G; grp += W) {
+    const int port = 4 * grp + lg;
+    float ud[NT];
+#pragma unroll
+    for (int n = 0; n < NT; ++n) ud[n] = draw_uniform(draw_word(dw[n], port));
+    f32x4 c[kPolR][NT];
+#pragma unroll
+    for (int r = 0; r < kPolR; ++r) {
+      const f32x4 b = gld(reinterpret_cast<const f32x4 *>(pl.b2f + (int64_t)(grp * kPolR + r) * 16 + 4 * lg), 0);
+#pragma unroll
+      for (int n = 0; n < NT; ++n) c[r][n] = b;
+    }
+#pragma unroll
+    for (int s = 0; s < kPolHP; ++s) {
+      u32x4 hv[NT];
+#pragma unroll
+      for (int n = 0; n < NT; ++n) hv[n] = hb[(s * NT + n) * 64 + lane];
+#pragma unroll
+      for (int r = 0; r < kPolR; ++r) {
+        const u32x4 wf = __builtin_bit_cast(
+            u32x4, __builtin_amdgcn_raw_buffer_load_b128(w2, vo[s >> 2] + 1024u * (uint32_t)(s & 3),
+                                                         (grp * kPolR + r) * kPolHP * 1024, 0));
+#pragma unroll
+        for (int n = 0; n < NT; ++n) c[r][n] = mfma_bf16(wf, hv[n], c[r][n]);
+      }
+    }
+#pragma unroll
+    for (int n = 0; n < NT; ++n) {
+      const int e = 16 * n + col;
+      if (port < N && e < blk_envs) {
+        const f32x4 cn[kPolR] = {c[0][n], c[1][n], c[2][n]};
+        act[e * N + port] = (uint8_t)sample_level(cn, R, L1, ud[n]);
+      }
+    }
+  }
+  __syncthreads();
+}
 
 // exo_tp / exo_pr: the block's LDS copies of the first four arrival thresholds
 // and the base price of every step of the day (NULL: read device memory).
-template <int L, int P, bool SIMPLE, bool EXT, bool STAGE>
+template <int L, int P, bool SIMPLE, bool EXT, bool STAGE, bool POL = false>
 __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int group, const uint32_t *tdw,
                                           bool tdw_lds, const lds_u32x4 *exo_tp, const lds_float *exo_pr,
-                                          lds_float *stage, int stage_floats, int g_blk0, int n_run) {
+                                          lds_float *stage, int stage_floats, int g_blk0, int n_run,
+                                          const LaunchArgs::Pol *pol = nullptr, lds_char *lds = nullptr) {
   constexpr int SPW = 64 / L;
   constexpr int LOGL = (L == 4) ? 2 : (L == 8) ? 3 : (L == 16) ? 4 : (L == 32) ? 5 : 6;
   constexpr bool NOPAD = SIMPLE;  // every slot holds a port: slot s = port s
@@ -413,6 +553,17 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
   const int64_t blk_envs = sg.n_envs - env_blk0 < (int64_t)n_run * SPW ? sg.n_envs - env_blk0 : (int64_t)n_run * SPW;
   const int n_blk = (int)blk_envs * obs_dim;
   const uint32_t stage_bo = (uint32_t)(env - env_blk0) * (uint32_t)obs_dim * 4u;
+  // the fused policy: every wave of the block takes part (waves past the last
+  // env too, their lanes inactive); the first step's levels come from the
+  // observation the rollout starts from, put in the stage
+  [[maybe_unused]] const int wv = group - g_blk0;
+  [[maybe_unused]] const uint32_t env_id0 = (uint32_t)(sg.env0 + env_blk0);
+  if constexpr (POL) {
+    const float *src = pol->obs0 + sg.obs_off + (int64_t)env_blk0 * obs_dim;
+    for (int i = wv * 64 + lane; i < n_blk; i += kPolRolloutWaves * 64) stage[i] = gld(src, i);
+    __syncthreads();
+    policy_phase(*pol, stage, lds, obs_dim, N, (int)blk_envs, wv, env_id0, g, k0, k1);
+  }
 
   for (int t = 0; t < dy.T; ++t, ++g) {
     // ---- exogenous draws for the next L steps, lane l -> step t + l: the
@@ -481,7 +632,11 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
     // ---- actions: action bytes k (level + n_neg)
     int k[P];
     int kb = 0;  // the battery's action byte (level + n_levels)
-    if (dy.mode == CX_ACT_RANDOM) {
+    if constexpr (POL) {  // the levels the policy drew after the last step
+      const lds_u8 *lv = reinterpret_cast<const lds_u8 *>(lds + pol->act_off) + (env - env_blk0) * N;
+#pragma unroll
+      for (int j = 0; j < P; ++j) k[j] = active ? (int)lv[port[j]] : 0;
+    } else if (dy.mode == CX_ACT_RANDOM) {
       if (t == 0 || (g & 7u) == 0) {
         // one Philox call gives the 8 steps' bytes: its 16-bit halves (low
         // half first) scaled to the n byte values, (h n) >> 16; n <= 255, so
@@ -906,10 +1061,12 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
     // each store the compiler emits the scalar-base form (no 64-bit lane address)
     uint32_t obs_bo_t = obs_bo, act_bo_t = act_bo, env_bo_t = env_bo;
     asm volatile("" : "+v"(obs_bo_t), "+v"(act_bo_t), "+v"(env_bo_t));
-    const int pad =
-        STAGE && w_obs ? (int)((reinterpret_cast<uintptr_t>(ob_now + (int64_t)env_blk0 * obs_dim) >> 2) & 3u) : 0;
+    // (the fused policy reads the stage from float 0: its records are 16-byte aligned)
+    const int pad = !POL && STAGE && w_obs
+                        ? (int)((reinterpret_cast<uintptr_t>(ob_now + (int64_t)env_blk0 * obs_dim) >> 2) & 3u)
+                        : 0;
     if (active) {
-      if (w_obs) {
+      if (w_obs || POL) {
         auto obs_record = [&](auto put) {
 #pragma unroll
           for (int j = 0; j < P; ++j) {
@@ -946,7 +1103,7 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
           }
         };
         if constexpr (STAGE) {
-          lds_float *sb = stage + (t & 1) * stage_floats + pad;
+          lds_float *sb = stage + (POL ? 0 : (t & 1) * stage_floats) + pad;
           obs_record([&](uint32_t fo, uint32_t lo, float v) {
             *reinterpret_cast<lds_float *>(reinterpret_cast<__attribute__((address_space(3))) char *>(sb) + stage_bo +
                                            fo + lo) = v;
@@ -1005,9 +1162,15 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
     __syncthreads();
     // the stage of this step is complete: out to HBM (the next step fills the
     // other buffer; the barrier of that step keeps this one until it is read)
-    if (STAGE && w_obs)
-      flush_stage(stage + (t & 1) * stage_floats, ob_now + (int64_t)env_blk0 * obs_dim, pad, n_blk,
+    if (STAGE && w_obs && (!POL || wv < n_run))
+      flush_stage(stage + (POL ? 0 : (t & 1) * stage_floats), ob_now + (int64_t)env_blk0 * obs_dim, pad, n_blk,
                   (group - g_blk0) * 64 + lane, n_run * 64);
+    if constexpr (POL) {
+      // the next step's levels (the phase's barriers keep the stage until the
+      // flush above has read it)
+      if (t + 1 < dy.T)
+        policy_phase(*pol, stage, lds, obs_dim, N, (int)blk_envs, wv, env_id0, g + 1u, k0, k1);
+    }
   }
 
   // ---- state back to HBM
@@ -1039,7 +1202,7 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
 
 // One kernel per packing (lanes per station L, slots per lane P) and class
 // kind (general, SIMPLE, bidirectional), so that each keeps its own register budget.
-template <int L, int P, bool SIMPLE, bool EXT, bool STAGE>
+template <int L, int P, bool SIMPLE, bool EXT, bool STAGE, bool POL = false>
 __global__ __launch_bounds__(512) void k_rollout(LaunchArgs a) {
   extern __shared__ uint32_t lds_tdwell[];
   const int b = blockIdx.x;
@@ -1093,12 +1256,13 @@ __global__ __launch_bounds__(512) void k_rollout(LaunchArgs a) {
   const int W = blockDim.x >> 6;
   const int g_blk0 = (b - sg.block_begin) * W;  // the block's first group
   const int group = __builtin_amdgcn_readfirstlane(g_blk0 + (int)(threadIdx.x >> 6));
-  if (group >= sg.n_groups) return;
+  // (the fused policy keeps every wave: all take part in the MLP)
+  if (!POL && group >= sg.n_groups) return;
   const int n_run = min(W, sg.n_groups - g_blk0);  // waves of the block that run
   lds_float *stage =
       a.stage_floats > 0 ? (lds_float *)((__attribute__((address_space(3))) char *)lds_tdwell + a.stage_off) : nullptr;
-  run_group<L, P, SIMPLE, EXT, STAGE>(sg, dy, group, tdw, tdw_lds, exo_tp, exo_pr, stage, a.stage_floats, g_blk0,
-                                      n_run);
+  run_group<L, P, SIMPLE, EXT, STAGE, POL>(sg, dy, group, tdw, tdw_lds, exo_tp, exo_pr, stage, a.stage_floats,
+                                           g_blk0, n_run, &a.pol, (lds_char *)lds_tdwell);
 }
 
 // Observation of empty stations at t_day = 0 for every env of one segment
@@ -1180,6 +1344,21 @@ hipError_t launch_groups(const LaunchArgs &a, const LaunchGroup *groups, int n_g
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+// The fused policy rollout of one SIMPLE class: stations of 8 lanes (8, 16 or
+// 32 slots), 4 waves per block (32 stations, two 16-env tiles of the MLP).
+hipError_t launch_policy_rollout(const LaunchArgs &a, int per_lane, int n_blocks, size_t lds, hipStream_t st) {
+  if (n_blocks <= 0) return hipSuccess;
+  KernelFn f = per_lane == 1   ? &k_rollout<8, 1, true, false, true, true>
+               : per_lane == 2 ? &k_rollout<8, 2, true, false, true, true>
+               : per_lane == 4 ? &k_rollout<8, 4, true, false, true, true>
+                               : nullptr;
+  if (!f) return hipErrorInvalidValue;
+  LaunchArgs b = a;
+  void *params[1] = {&b};
+  return hipLaunchKernel(reinterpret_cast<const void *>(f), dim3(n_blocks), dim3(64 * kPolRolloutWaves), params, lds,
+                         st);
 }
 
 hipError_t graph_rollout(RolloutGraph &G, const LaunchArgs &a, const LaunchGroup *groups, int n_groups,

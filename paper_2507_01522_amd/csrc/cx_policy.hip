@@ -1,24 +1,16 @@
-// cx_policy.hip -- policy-in-the-loop rollouts.  Each step runs two kernels:
+// cx_policy.hip -- policy-in-the-loop rollouts.
 //   k_policy  obs -> BF16 -> W1 (tanh) -> W2 -> logits on the matrix cores
 //             (v_mfma_f32_16x16x32_bf16, FP32 accumulation), then per port a
-//             level drawn from softmax of its logits with one Philox uniform;
-//   the library's one-step environment kernel with those levels as external
-//             actions, which writes the next observation.
-// A third kernel, k_observe, gives the observation of the state a rollout
-// starts from.
+//             level drawn from softmax of its logits with one Philox uniform.
+// A rollout of a SIMPLE class of 8, 16 or 32 slots is one launch of the fused
+// persistent kernel (the rollout kernel with this MLP between its steps,
+// cx_kernels.hip): state in registers, observations only in LDS.  Other
+// classes, and the rollout that allocates nothing, run two kernels per step:
+// k_policy, then the one-step environment kernel with its levels as external
+// actions, which writes the next observation.  k_observe gives the
+// observation of the state a rollout starts from.
 //
-// Both products are computed transposed so that no operand is ever shuffled
-// between lanes: with D = A * B on 16 x 16 tiles, lane l holds column l % 16
-// and rows 4 (l / 16) + i (i < 4) of D, and the 8 K-values of lane group
-// l / 16 of A and B.
-//   h^T [hidden x env]  = W1^T [hidden x obs] * obs^T [obs x env]
-//   z^T [logit x env]   = W2^T [logit x hidden] * h^T [hidden x env]
-// A lane thus ends the first product holding 8 hidden units of one env --
-// exactly the B operand of the second product, provided the hidden units of a
-// K-step are ordered as the lanes hold them; the host stores W2 in that order.
-// The rows of W2^T are arranged so that a lane ends the second product holding
-// all levels of one port of one env (level 4 r + i of port 4 g + l / 16 in row
-// i of tile (g, r)), so the argmax needs no exchange between lanes.
+// The layout of the two products is described in cx_mlp.h.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -29,12 +21,10 @@
 
 #include "cx_ctx.h"
 #include "cx_device.h"
+#include "cx_mlp.h"
 
 namespace cx {
 
-constexpr int kPolK1 = 8;  // K-steps of 32 observation features (obs_dim <= 256)
-constexpr int kPolHP = 8;  // K-steps of 32 hidden units (hidden <= 256)
-constexpr int kPolR = 3;   // tiles of 4 levels per port (levels + 1 <= 12)
 constexpr int kPolNT = 2;  // 16-env column tiles per wave
 constexpr int kPolWaves = 8;  // waves per block sharing each staged weight chunk
 
@@ -46,33 +36,22 @@ struct PolicyRt {
   const float *b1 = nullptr;
   const u32x4 *w2f = nullptr;
   const float *b2f = nullptr;
+  // the same weights padded to the largest sizes (zeros), for the fused
+  // rollout: W1^T [16 tiles][8 K-steps][64], b1 [256], W2^T [G][3][8][64],
+  // b2 [G][3][16]
+  const u32x4 *w1p = nullptr;
+  const float *b1p = nullptr;
+  const u32x4 *w2p = nullptr;
+  const float *b2p = nullptr;
   float *obs = nullptr;  // one step of observations (rollouts that do not return them)
   uint8_t *act = nullptr;  // one step of levels (rollouts that do not return them)
   int64_t scratch_envs = 0;
+  // the fused rollout's segment table (stations of 8 lanes, 4 waves per block)
+  SegDev *segs_dev = nullptr;
+  int n_segs = 0, n_blocks = 0;
 };
 
 namespace {
-
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-
-// FP32 -> BF16, round to nearest even (finite inputs).
-__device__ __forceinline__ uint32_t bf16_rne(float f) {
-  const uint32_t u = __float_as_uint(f);
-  return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
-}
-__device__ __forceinline__ uint32_t pack2(float lo, float hi) { return bf16_rne(lo) | (bf16_rne(hi) << 16); }
-
-__device__ __forceinline__ f32x4 mfma(u32x4 a, u32x4 b, f32x4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
-                                                 0, 0, 0);
-}
-
-// tanh a = 1 - 2 / (e^{2a} + 1); saturates correctly at both ends.
-__device__ __forceinline__ float tanh_f(float a) {
-  const float e = __builtin_amdgcn_exp2f(a * 2.88539008177792681f);  // 2 / ln 2
-  return 1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f);
-}
 
 // Weight chunks pass through LDS, double-buffered: chunk c < HP holds the two
 // W1^T tiles of hidden units 32c..32c+31 (all K-steps), chunk HP + g the R
@@ -168,8 +147,8 @@ __global__ __launch_bounds__(64 * kPolWaves) void k_policy(PolicyArgs a) {
           const u32x4 a1 = w[(a.K1 + s) * 64 + lane];
 #pragma unroll
           for (int n = 0; n < kPolNT; ++n) {
-            c0[n] = mfma(a0, ob[s][n], c0[n]);
-            c1[n] = mfma(a1, ob[s][n], c1[n]);
+            c0[n] = mfma_bf16(a0, ob[s][n], c0[n]);
+            c1[n] = mfma_bf16(a1, ob[s][n], c1[n]);
           }
         }
       }
@@ -177,12 +156,7 @@ __global__ __launch_bounds__(64 * kPolWaves) void k_policy(PolicyArgs a) {
       const f32x4 bA = gld(reinterpret_cast<const f32x4 *>(a.b1 + 32 * mp + 4 * lg), 0);
       const f32x4 bB = gld(reinterpret_cast<const f32x4 *>(a.b1 + 32 * mp + 16 + 4 * lg), 0);
 #pragma unroll
-      for (int n = 0; n < kPolNT; ++n) {
-        h[mp][n] = u32x4{pack2(tanh_f(c0[n].x + bA.x), tanh_f(c0[n].y + bA.y)),
-                         pack2(tanh_f(c0[n].z + bA.z), tanh_f(c0[n].w + bA.w)),
-                         pack2(tanh_f(c1[n].x + bB.x), tanh_f(c1[n].y + bB.y)),
-                         pack2(tanh_f(c1[n].z + bB.z), tanh_f(c1[n].w + bB.w))};
-      }
+      for (int n = 0; n < kPolNT; ++n) h[mp][n] = hidden_frag(c0[n], c1[n], bA, bB);
       __syncthreads();
     }
   }
@@ -202,8 +176,8 @@ __global__ __launch_bounds__(64 * kPolWaves) void k_policy(PolicyArgs a) {
 #pragma unroll
     for (int n = 0; n < kPolNT; ++n) {
       const uint32_t env_id = (uint32_t)(a.env0 + e_base + 16 * n + col);
-      const uint32_t w = philox(env_id, a.g, (uint32_t)port, kDomGum, k0, k1).x;
-      ud[n] = ((float)(w >> 8) + 0.5f) * 0x1p-24f;
+      const U4 w = philox(env_id, a.g, draw_index(port), kDomGum, k0, k1);
+      ud[n] = draw_uniform(draw_word(w, port));
     }
     const u32x4 *w = wbuf[cidx & 1];
     f32x4 c[kPolR][kPolNT];
@@ -222,7 +196,7 @@ __global__ __launch_bounds__(64 * kPolWaves) void k_policy(PolicyArgs a) {
           if (r < a.R) {
             const u32x4 wf = w[(r * a.HP + s) * 64 + lane];
 #pragma unroll
-            for (int n = 0; n < kPolNT; ++n) c[r][n] = mfma(wf, h[s][n], c[r][n]);
+            for (int n = 0; n < kPolNT; ++n) c[r][n] = mfma_bf16(wf, h[s][n], c[r][n]);
           }
         }
       }
@@ -245,34 +219,8 @@ __global__ __launch_bounds__(64 * kPolWaves) void k_policy(PolicyArgs a) {
         }
       }
       if (a.act) {
-        // the first level whose cumulative softmax weight exceeds u times the
-        // total (the inverse of the distribution function at u)
-        float zmax = c[0][n][0];
-#pragma unroll
-        for (int r = 0; r < kPolR; ++r)
-#pragma unroll
-          for (int i = 0; i < 4; ++i)
-            if (r < a.R && 4 * r + i < a.L1) zmax = fmaxf(zmax, c[r][n][i]);
-        constexpr float kLog2e = 1.44269504088896341f;
-        float ex[kPolR][4], tot = 0.f;
-#pragma unroll
-        for (int r = 0; r < kPolR; ++r)
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const bool in = r < a.R && 4 * r + i < a.L1;
-            ex[r][i] = in ? __builtin_amdgcn_exp2f((c[r][n][i] - zmax) * kLog2e) : 0.f;
-            tot += ex[r][i];
-          }
-        const float target = ud[n] * tot;
-        int lev = 0;
-        float cum = 0.f;
-#pragma unroll
-        for (int r = 0; r < kPolR; ++r)
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            cum += ex[r][i];
-            lev += (r < a.R && 4 * r + i < a.L1 - 1 && cum <= target) ? 1 : 0;
-          }
+        const f32x4 cn[kPolR] = {c[0][n], c[1][n], c[2][n]};
+        const int lev = sample_level(cn, a.R, a.L1, ud[n]);
         a.act[e * a.N + port] = (uint8_t)lev;
       }
     }
@@ -395,6 +343,7 @@ void free_policy(cx_ctx *ctx) {
   if (!ctx || !ctx->policy) return;
   PolicyRt *p = ctx->policy;
   if (p->mem) (void)hipFree(p->mem);
+  if (p->segs_dev) (void)hipFree(p->segs_dev);
   if (p->obs) (void)hipFree(p->obs);
   if (p->act) (void)hipFree(p->act);
   delete p;
@@ -485,11 +434,104 @@ cx_status noalloc_scratch(int device, unsigned char **ptr) {
 
 }  // namespace
 
+namespace {
+
+// The fused rollout runs SIMPLE classes of 8, 16 or 32 slots (stations of 8
+// lanes, 1, 2 or 4 slots per lane); others take the two kernels per step.
+bool fused_eligible(const cx_ctx *ctx) {
+  const ClassRt &c = ctx->classes[0];
+  const int S = c.comp.S;
+  return c.host_view.kind == kKindSimple && (S == 8 || S == 16 || S == 32);
+}
+
+cx_status ensure_fused(cx_ctx *ctx) {
+  PolicyRt &p = *ctx->policy;
+  if (p.segs_dev) return CX_OK;
+  const ClassRt &c = ctx->classes[0];
+  std::vector<SegDev> segs;
+  class_segments(ctx, c, 8, c.comp.S / 8, &segs);
+  int blocks = 0;
+  for (SegDev &sg : segs) {
+    sg.block_begin = blocks;
+    blocks += (sg.n_groups + kPolRolloutWaves - 1) / kPolRolloutWaves;
+  }
+  void *d = nullptr;
+  if (hipMalloc(&d, sizeof(SegDev) * std::max<size_t>(1, segs.size())) != hipSuccess)
+    return fail_status(CX_E_OOM, "policy rollout: segment table allocation failed");
+  hipError_t e = hipMemcpy(d, segs.data(), sizeof(SegDev) * segs.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(d);
+    return hip_fail(ctx, e, "policy rollout: segment table upload");
+  }
+  p.segs_dev = static_cast<SegDev *>(d);
+  p.n_segs = (int)segs.size();
+  p.n_blocks = blocks;
+  return CX_OK;
+}
+
+// One launch for the whole rollout: the observation the rollout starts from
+// (into the scratch), then the persistent kernel with the MLP between steps.
+cx_status fused_rollout(cx_ctx *ctx, int32_t T, cx_out_mode out_mode, const cx_traj *out, size_t lds,
+                        const LaunchArgs::Pol &lay) {
+  PolicyRt &p = *ctx->policy;
+  const ClassRt &c = ctx->classes[0];
+  const bool ret_obs = out && out_mode == CX_OUT_FULL && out->obs;
+  const bool ret_act = out && out_mode != CX_OUT_REWARD && out->actions;
+  hipError_t e = launch_observe(ctx, p.obs, ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "policy rollout: observation kernel");
+  LaunchArgs a = base_args(ctx);
+  a.segs = p.segs_dev;
+  a.n_segs = p.n_segs;
+  a.T = T;
+  a.mode = CX_ACT_POLICY;
+  a.out_mode = out_mode;
+  a.obs = ret_obs ? out->obs : nullptr;
+  a.act = ret_act ? out->actions : nullptr;
+  a.reward = out ? out->reward : nullptr;
+  a.done = out ? out->done : nullptr;
+  a.lds_tdwell = 1;
+  a.stage_off = lay.hb_off;
+  a.stage_floats = (int32_t)(((size_t)kPolRolloutEnvs * c.comp.obs_dim + 3) & ~(size_t)3);
+  a.pol = lay;
+  a.pol.obs0 = p.obs;
+  a.pol.w1f = p.w1p;
+  a.pol.b1 = p.b1p;
+  a.pol.w2f = p.w2p;
+  a.pol.b2f = p.b2p;
+  a.pol.in_dim = p.in_dim;
+  a.pol.K1 = p.K1;
+  a.pol.HP = p.HP;
+  a.pol.R = p.R;
+  a.pol.G = p.G;
+  a.pol.L1 = p.L1;
+  if ((e = launch_policy_rollout(a, c.comp.S / 8, p.n_blocks, lds, ctx->stream)) != hipSuccess)
+    return hip_fail(ctx, e, "policy rollout kernel");
+  advance_clock(ctx, T);
+  return CX_OK;
+}
+
+}  // namespace
+
 cx_status policy_step(cx_ctx *ctx, int32_t T, cx_out_mode out_mode, const cx_traj *out, bool graph) {
   (void)graph;
   if (!ctx->policy) return fail_status(CX_E_INVALID, "no policy set (cx_set_policy)");
   cx_status st = ensure_scratch(ctx);
   if (st != CX_OK) return st;
+  if (fused_eligible(ctx)) {
+    const bool ret_obs = out && out_mode == CX_OUT_FULL && out->obs;
+    if (ret_obs && (reinterpret_cast<uintptr_t>(out->obs) & 15u) != 0)
+      return fail_status(CX_E_INVALID, "policy rollout: obs buffer must be 16-byte aligned");
+    const ClassRt &c = ctx->classes[0];
+    LaunchArgs::Pol lay{};
+    int32_t stage_off = 0, stage_floats = 0;
+    const size_t lds = policy_rollout_lds(c.tab.dwell_log2, c.comp.obs_dim, c.comp.N, &stage_off,
+                                          &stage_floats, &lay.hb_off, &lay.xb_off, &lay.act_off);
+    if (lds <= kMaxBlockLds) {
+      if (T == 0) return CX_OK;
+      if ((st = ensure_fused(ctx)) != CX_OK) return st;
+      return fused_rollout(ctx, T, out_mode, out, lds, lay);
+    }
+  }
   return policy_step_with(ctx, T, out_mode, out, ctx->policy->obs, ctx->policy->act);
 }
 
@@ -552,9 +594,29 @@ cx_status cx_set_policy(cx_ctx *ctx, int32_t hidden, const uint16_t *w1, const u
           }
         }
     }
+  // padded copies: W1^T tile m, K-step s at (m * 8 + s); W2^T tile (grp, r),
+  // K-step s at ((grp * 3 + r) * 8 + s)
+  std::vector<uint16_t> w1p((size_t)2 * kPolHP * kPolK1 * 64 * 8, 0);
+  for (int m = 0; m < 2 * HP; ++m)
+    for (int s = 0; s < K1; ++s)
+      std::memcpy(&w1p[((size_t)m * kPolK1 + s) * 64 * 8], &w1f[((size_t)m * K1 + s) * 64 * 8], 64 * 8 * 2);
+  std::vector<float> b1p((size_t)32 * kPolHP, 0.f);
+  std::memcpy(b1p.data(), b1f.data(), (size_t)hidden * 4);
+  std::vector<uint16_t> w2p((size_t)G * kPolR * kPolHP * 64 * 8, 0);
+  std::vector<float> b2p((size_t)G * kPolR * 16, 0.f);
+  for (int grp = 0; grp < G; ++grp)
+    for (int r = 0; r < R; ++r) {
+      std::memcpy(&b2p[((size_t)grp * kPolR + r) * 16], &b2f[((size_t)grp * R + r) * 16], 16 * 4);
+      for (int s = 0; s < HP; ++s)
+        std::memcpy(&w2p[(((size_t)grp * kPolR + r) * kPolHP + s) * 64 * 8],
+                    &w2f[(((size_t)grp * R + r) * HP + s) * 64 * 8], 64 * 8 * 2);
+    }
   const size_t s_w1 = w1f.size() * 2, s_b1 = (size_t)hidden * 4, s_w2 = w2f.size() * 2, s_b2 = b2f.size() * 4;
+  const size_t s_w1p = w1p.size() * 2, s_b1p = b1p.size() * 4, s_w2p = w2p.size() * 2, s_b2p = b2p.size() * 4;
   auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-  const size_t bytes = al(s_w1) + al(s_b1) + al(s_w2) + al(s_b2);
+  const size_t o_w1p = al(s_w1) + al(s_b1) + al(s_w2) + al(s_b2);
+  const size_t o_b1p = o_w1p + al(s_w1p), o_w2p = o_b1p + al(s_b1p), o_b2p = o_w2p + al(s_w2p);
+  const size_t bytes = o_b2p + al(s_b2p);
   void *mem = nullptr;
   if (hipMalloc(&mem, bytes) != hipSuccess) return fail_status(CX_E_OOM, "cx_set_policy: hipMalloc failed");
   unsigned char *b = static_cast<unsigned char *>(mem);
@@ -562,8 +624,11 @@ cx_status cx_set_policy(cx_ctx *ctx, int32_t hidden, const uint16_t *w1, const u
   if ((e = hipMemcpy(b, w1f.data(), s_w1, hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(b + al(s_w1), b1f.data(), s_b1, hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(b + al(s_w1) + al(s_b1), w2f.data(), s_w2, hipMemcpyHostToDevice)) != hipSuccess ||
-      (e = hipMemcpy(b + al(s_w1) + al(s_b1) + al(s_w2), b2f.data(), s_b2, hipMemcpyHostToDevice)) !=
-          hipSuccess) {
+      (e = hipMemcpy(b + al(s_w1) + al(s_b1) + al(s_w2), b2f.data(), s_b2, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(b + o_w1p, w1p.data(), s_w1p, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(b + o_b1p, b1p.data(), s_b1p, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(b + o_w2p, w2p.data(), s_w2p, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(b + o_b2p, b2p.data(), s_b2p, hipMemcpyHostToDevice)) != hipSuccess) {
     (void)hipFree(mem);
     return hip_fail(ctx, e, "cx_set_policy upload");
   }
@@ -581,6 +646,10 @@ cx_status cx_set_policy(cx_ctx *ctx, int32_t hidden, const uint16_t *w1, const u
   p->b1 = reinterpret_cast<const float *>(b + al(s_w1));
   p->w2f = reinterpret_cast<const u32x4 *>(b + al(s_w1) + al(s_b1));
   p->b2f = reinterpret_cast<const float *>(b + al(s_w1) + al(s_b1) + al(s_w2));
+  p->w1p = reinterpret_cast<const u32x4 *>(b + o_w1p);
+  p->b1p = reinterpret_cast<const float *>(b + o_b1p);
+  p->w2p = reinterpret_cast<const u32x4 *>(b + o_w2p);
+  p->b2p = reinterpret_cast<const float *>(b + o_b2p);
   if (old) {  // keep the scratch buffers
     p->obs = old->obs; p->act = old->act; p->scratch_envs = old->scratch_envs;
     old->obs = nullptr; old->act = nullptr;

@@ -263,18 +263,21 @@ T arg(const Launch &l, size_t i) {
   return v;
 }
 
-// template arguments <L, P, SIMPLE, EXT, STAGE> of a k_rollout instance
-void rollout_params(const std::string &n, int *L, int *P, bool *simple, bool *ext, bool *stage) {
+// template arguments <L, P, SIMPLE, EXT, STAGE[, POL]> of a k_rollout instance
+void rollout_params(const std::string &n, int *L, int *P, bool *simple, bool *ext, bool *stage, bool *pol) {
   const size_t a = n.find('<');
   int l = 0, p = 0;
-  char s1[8] = {0}, s2[8] = {0}, s3[8] = {0};
-  if (a == std::string::npos || std::sscanf(n.c_str() + a, "<%d, %d, %5[a-z], %5[a-z], %5[a-z]>", &l, &p, s1, s2, s3) != 5)
-    die("cannot parse %s", n.c_str());
+  char s1[8] = {0}, s2[8] = {0}, s3[8] = {0}, s4[8] = {0};
+  const int got = a == std::string::npos ? 0
+                                         : std::sscanf(n.c_str() + a, "<%d, %d, %5[a-z], %5[a-z], %5[a-z], %5[a-z]>",
+                                                       &l, &p, s1, s2, s3, s4);
+  if (got < 5) die("cannot parse %s", n.c_str());
   *L = l;
   *P = p;
   *simple = std::strcmp(s1, "true") == 0;
   *ext = std::strcmp(s2, "true") == 0;
   *stage = std::strcmp(s3, "true") == 0;
+  *pol = got == 6 && std::strcmp(s4, "true") == 0;
 }
 
 void check_class(const cx::ClassDev *cls, const std::string &w) {
@@ -290,12 +293,36 @@ void check_class(const cx::ClassDev *cls, const std::string &w) {
 
 void run_rollout(const Launch &l, const KernelInfo &k) {
   int L, P;
-  bool simple, ext, stage;
-  rollout_params(k.name, &L, &P, &simple, &ext, &stage);
+  bool simple, ext, stage, pol;
+  rollout_params(k.name, &L, &P, &simple, &ext, &stage, &pol);
   const cx::LaunchArgs a = arg<cx::LaunchArgs>(l, 0);
   const std::string w0 = k.name;
   if (l.block.x % 64 != 0 || l.block.x == 0 || l.block.x > 512 || l.block.y != 1 || l.grid.y != 1)
     die("%s: launch shape %u x %u", w0.c_str(), l.grid.x, l.block.x);
+  if (pol) {
+    // the fused policy rollout: 4 waves of 8-lane stations, the stage, the
+    // hidden units, the BF16 observations and the levels inside the LDS
+    const cx::LaunchArgs::Pol &q = a.pol;
+    if (L != 8 || !simple || ext || !stage || (int)l.block.x != 64 * cx::kPolRolloutWaves)
+      die("%s: fused policy launch of %u threads", w0.c_str(), l.block.x);
+    if (a.mode != CX_ACT_POLICY || a.per_segment) die("%s: mode %d", w0.c_str(), a.mode);
+    if (q.K1 < 1 || q.K1 > 8 || q.HP < 1 || q.HP > 8 || q.R < 1 || q.R > 3 || q.G < 1 || q.L1 < 2 || q.L1 > 4 * q.R)
+      die("%s: MLP sizes K1 %d HP %d R %d G %d L1 %d", w0.c_str(), q.K1, q.HP, q.R, q.G, q.L1);
+    if (q.in_dim > 32 * q.K1) die("%s: in_dim %d > 32 K1", w0.c_str(), q.in_dim);
+    const size_t stage_end = (size_t)a.stage_off + 4 * (size_t)a.stage_floats;
+    const size_t hb_end = (size_t)q.hb_off + (size_t)8 * (cx::kPolRolloutEnvs / 16) * 64 * 16;
+    const size_t xb_end = (size_t)q.xb_off + (size_t)cx::kPolRolloutEnvs * 16 * cx::kPolXbRow;
+    if (a.stage_floats < cx::kPolRolloutEnvs * q.in_dim) die("%s: stage of %d floats", w0.c_str(), a.stage_floats);
+    if (q.hb_off < a.stage_off || std::max(stage_end, hb_end) > (size_t)q.xb_off || xb_end > (size_t)q.act_off)
+      die("%s: LDS regions overlap (stage %d+%zu, hb %d, xb %d, act %d)", w0.c_str(), a.stage_off,
+          stage_end - a.stage_off, q.hb_off, q.xb_off, q.act_off);
+    if ((q.xb_off | q.hb_off | a.stage_off) & 15) die("%s: LDS regions not 16-byte aligned", w0.c_str());
+    // padded fragments: 16 hidden tiles x 8 K-steps; G x 3 level tiles x 8 K-steps
+    need(q.w1f, 16 * (size_t)16 * 8 * 64, "W1 fragments", w0);
+    need(q.b1, 4 * (size_t)256, "b1", w0);
+    need(q.w2f, 16 * (size_t)q.G * 3 * 8 * 64, "W2 fragments", w0);
+    need(q.b2f, 4 * 16 * (size_t)q.G * 3, "b2", w0);
+  }
   if (a.n_segs < 1) die("%s: no segments", w0.c_str());
   need(a.segs, sizeof(cx::SegDev) * (size_t)a.n_segs, "segment table", w0);
   std::vector<cx::SegDev> segs(a.n_segs);
@@ -324,7 +351,10 @@ void run_rollout(const Launch &l, const KernelInfo &k) {
     if (kind_ext != ext) die("%s: class kind %d in a kernel with EXT = %d", w.c_str(), C.kind, (int)ext);
     if (simple && C.simple != 1) die("%s: non-SIMPLE class in a SIMPLE kernel", w.c_str());
     const int g_blk0 = ((int)b - sg.block_begin) * W;
-    if (g_blk0 >= sg.n_groups) continue;  // idle block
+    if (g_blk0 >= sg.n_groups) {
+      if (pol) die("%s: idle block in a fused policy launch", w.c_str());
+      continue;  // idle block
+    }
     const int n_run = std::min(W, sg.n_groups - g_blk0);
     const int64_t e0 = (int64_t)g_blk0 * SPW;
     const int64_t e1 = std::min<int64_t>(sg.n_envs, (int64_t)(g_blk0 + n_run) * SPW);
@@ -342,6 +372,14 @@ void run_rollout(const Launch &l, const KernelInfo &k) {
     }
     if (ext && C.has_users) need(sg.utype + e0 * S, (size_t)(n * S), "user types", w);
     if (ext && C.n_models > 0) need(sg.rbar + e0 * S, 4 * n * S, "car rates", w);
+    if (pol) {
+      if (C.n_ports != S || C.S != 8 * P) die("%s: fused policy class of %d ports in %d slots", w.c_str(), C.n_ports, C.S);
+      if ((size_t)cx::kPolRolloutEnvs * S > (size_t)l.lds - (size_t)a.pol.act_off)
+        die("%s: LDS %zu too small for the levels", w.c_str(), l.lds);
+      if (a.pol.in_dim != C.obs_dim) die("%s: MLP input %d, observation %d", w.c_str(), a.pol.in_dim, C.obs_dim);
+      if (4 * a.pol.G < C.n_ports) die("%s: %d port groups for %d ports", w.c_str(), a.pol.G, C.n_ports);
+      need(a.pol.obs0 + sg.obs_off + e0 * C.obs_dim, 4 * (size_t)(n * C.obs_dim), "start observations", w);
+    }
     // records
     int32_t T = a.T, mode = a.mode, out_mode = a.out_mode;
     float *obs = a.obs;
@@ -364,8 +402,9 @@ void run_rollout(const Launch &l, const KernelInfo &k) {
         float *base = obs + sg.obs_off + (int64_t)t * os;
         if (stage) {
           const int pad = (int)((reinterpret_cast<uintptr_t>(base + e0 * od) >> 2) & 3u);
+          if (pol && pad != 0) die("%s: fused policy observations not 16-byte aligned", w.c_str());
           const int nf = (int)(n * od);
-          const size_t need_lds = (size_t)a.stage_off + 8 * (size_t)a.stage_floats;
+          const size_t need_lds = (size_t)a.stage_off + (pol ? 4 : 8) * (size_t)a.stage_floats;
           if (a.stage_floats < pad + nf) die("%s: stage of %d floats for %d", w.c_str(), a.stage_floats, pad + nf);
           if (l.lds < need_lds) die("%s: LDS %zu < %zu with the stages", w.c_str(), l.lds, need_lds);
           if (a.stage_off < ((int32_t)4 << C.dwell_log2)) die("%s: stage overlaps the stay table", w.c_str());
