@@ -227,7 +227,7 @@ inline size_t group_lds_bytes(int wpb, int pack, int max_obs_dim, int dwell_log2
 }
 
 // The fused policy rollout: blocks of 4 waves of 8-lane stations (32 envs, two
-// 16-env tiles of the MLP).  LDS: the stay and day tables, then the stage (one
+// 16-env tiles of the MLP).  LDS: the stay table, then the stage (one
 // buffer of 32 observations), which the hidden units (8 x 2 KiB) overwrite once
 // it has been read, then the observations in BF16 (32 x 528 bytes) and a level
 // byte per port and env.  Returns the bytes; sets the offsets.
@@ -237,7 +237,7 @@ constexpr int kPolXbRow = 33;  // 16-byte fragments per env row of the BF16 obse
 inline size_t policy_rollout_lds(int dwell_log2, int obs_dim, int N, int32_t *stage_off,
                                  int32_t *stage_floats, int32_t *hb_off, int32_t *xb_off, int32_t *act_off) {
   auto a16 = [](size_t x) { return (x + 15) & ~(size_t)15; };
-  const size_t off = group_table_bytes(dwell_log2);
+  const size_t off = a16((size_t)4 << dwell_log2);  // the stay table only (no per-step tables)
   const size_t floats = ((size_t)kPolRolloutEnvs * obs_dim + 3) & ~(size_t)3;
   const size_t region = a16(std::max(4 * floats, (size_t)8 * (kPolRolloutEnvs / 16) * 64 * 16));
   const size_t xb = off + region;

@@ -275,18 +275,20 @@ typedef __attribute__((address_space(3))) uint8_t lds_u8;
 // order, so logits and levels are the same: here the block's 4 waves split the
 // hidden units (first product) and the port groups (second) among them, and
 // each wave reads its weight fragments from device memory (L2) straight into
-// the matrix-core operands.  The K-step loops run their compile-time maximum
-// (8 x 32 features, 8 x 32 hidden units, 3 level tiles) over weights padded
-// with zeros -- such steps add exact zeros -- so that they are straight-line
-// code whose loads are all issued ahead of the matrix-core work.  LDS: hb
+// the matrix-core operands.  The K-step loops have compile-time bounds (K1, the
+// class's K-steps of 32 features; 8 x 32 hidden units and 3 level tiles, the
+// largest, over weights padded with zeros -- such steps add exact zeros), so
+// that they are straight-line code whose loads are all issued ahead of the
+// matrix-core work.  LDS: hb
 // (8 x 2 hidden-unit fragments, over the stage once it has been read), xb (the
 // observations in BF16, 256 features per env, zero past in_dim, rows 33
 // fragments apart so that the 16 envs of a tile fall in different banks) and
 // act (a level byte per port and env).  wv: this wave in the block.
+template <int K1>
 __device__ __forceinline__ void policy_phase(const LaunchArgs::Pol &pl, const lds_float *stage, lds_char *lds,
                                              int obs_dim, int N, int blk_envs, int wv, uint32_t env_id0,
                                              uint32_t g, uint32_t k0, uint32_t k1) {
-  constexpr int W = kPolRolloutWaves, NT = kPolRolloutEnvs / 16, CPR = 4 * kPolK1;  // chunks of 8 per row
+  constexpr int W = kPolRolloutWaves, NT = kPolRolloutEnvs / 16, CPR = 4 * K1;  // chunks of 8 per row
   const int lane = __lane_id(), col = lane & 15, lg = lane >> 4, tid = wv * 64 + lane;
   const int in_dim = pl.in_dim, R = pl.R, G = pl.G, L1 = pl.L1;
   lds_u32x4 *xb = reinterpret_cast<lds_u32x4 *>(lds + pl.xb_off);
@@ -332,7 +334,7 @@ __device__ __forceinline__ void policy_phase(const LaunchArgs::Pol &pl, const ld
 #pragma unroll
     for (int n = 0; n < NT; ++n) c0[i][n] = c1[i][n] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int s = 0; s < kPolK1; ++s) {
+  for (int s = 0; s < K1; ++s) {
     u32x4 a0[NI], a1[NI];
 #pragma unroll
     for (int i = 0; i < NI; ++i) {
@@ -558,11 +560,14 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
   // observation the rollout starts from, put in the stage
   [[maybe_unused]] const int wv = group - g_blk0;
   [[maybe_unused]] const uint32_t env_id0 = (uint32_t)(sg.env0 + env_blk0);
+  // K-steps of 32 features of the first product: the observation of a SIMPLE
+  // class has 6 L P + 4 features
+  constexpr int kPolSteps1 = (6 * L * P + 4 + 31) / 32;
   if constexpr (POL) {
     const float *src = pol->obs0 + sg.obs_off + (int64_t)env_blk0 * obs_dim;
     for (int i = wv * 64 + lane; i < n_blk; i += kPolRolloutWaves * 64) stage[i] = gld(src, i);
     __syncthreads();
-    policy_phase(*pol, stage, lds, obs_dim, N, (int)blk_envs, wv, env_id0, g, k0, k1);
+    policy_phase<kPolSteps1>(*pol, stage, lds, obs_dim, N, (int)blk_envs, wv, env_id0, g, k0, k1);
   }
 
   for (int t = 0; t < dy.T; ++t, ++g) {
@@ -1169,7 +1174,7 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
       // the next step's levels (the phase's barriers keep the stage until the
       // flush above has read it)
       if (t + 1 < dy.T)
-        policy_phase(*pol, stage, lds, obs_dim, N, (int)blk_envs, wv, env_id0, g + 1u, k0, k1);
+        policy_phase<kPolSteps1>(*pol, stage, lds, obs_dim, N, (int)blk_envs, wv, env_id0, g + 1u, k0, k1);
     }
   }
 
@@ -1202,8 +1207,8 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
 
 // One kernel per packing (lanes per station L, slots per lane P) and class
 // kind (general, SIMPLE, bidirectional), so that each keeps its own register budget.
-template <int L, int P, bool SIMPLE, bool EXT, bool STAGE, bool POL = false>
-__global__ __launch_bounds__(512) void k_rollout(LaunchArgs a) {
+template <int L, int P, bool SIMPLE, bool EXT, bool STAGE, bool POL>
+__device__ __forceinline__ void rollout_body(LaunchArgs a) {
   extern __shared__ uint32_t lds_tdwell[];
   const int b = blockIdx.x;
   int lo = 0, hi = a.n_segs - 1;
@@ -1236,7 +1241,7 @@ __global__ __launch_bounds__(512) void k_rollout(LaunchArgs a) {
     // launches long enough to repay copying them (short ones read them from
     // device memory)
     const int steps = sg.cls->steps_ep;
-    if (steps <= kLdsExoSteps && dy.T >= kLdsExoMinT) {
+    if (!POL && steps <= kLdsExoSteps && dy.T >= kLdsExoMinT) {
       __attribute__((address_space(3))) char *base =
           (__attribute__((address_space(3))) char *)lds_tdwell + ((4 * n + 15) & ~15);
       lds_u32x4 *tp = (lds_u32x4 *)base;
@@ -1263,6 +1268,18 @@ __global__ __launch_bounds__(512) void k_rollout(LaunchArgs a) {
       a.stage_floats > 0 ? (lds_float *)((__attribute__((address_space(3))) char *)lds_tdwell + a.stage_off) : nullptr;
   run_group<L, P, SIMPLE, EXT, STAGE, POL>(sg, dy, group, tdw, tdw_lds, exo_tp, exo_pr, stage, a.stage_floats,
                                            g_blk0, n_run, &a.pol, (lds_char *)lds_tdwell);
+}
+
+template <int L, int P, bool SIMPLE, bool EXT, bool STAGE>
+__global__ __launch_bounds__(512) void k_rollout(LaunchArgs a) {
+  rollout_body<L, P, SIMPLE, EXT, STAGE, false>(a);
+}
+
+// The fused policy rollout (4 waves per block): three blocks per CU, so that
+// one block's matrix-core work and memory waits overlap the others' steps.
+template <int L, int P>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_rollout_policy(LaunchArgs a) {
+  rollout_body<L, P, true, false, true, true>(a);
 }
 
 // Observation of empty stations at t_day = 0 for every env of one segment
@@ -1350,9 +1367,9 @@ hipError_t launch_groups(const LaunchArgs &a, const LaunchGroup *groups, int n_g
 // 32 slots), 4 waves per block (32 stations, two 16-env tiles of the MLP).
 hipError_t launch_policy_rollout(const LaunchArgs &a, int per_lane, int n_blocks, size_t lds, hipStream_t st) {
   if (n_blocks <= 0) return hipSuccess;
-  KernelFn f = per_lane == 1   ? &k_rollout<8, 1, true, false, true, true>
-               : per_lane == 2 ? &k_rollout<8, 2, true, false, true, true>
-               : per_lane == 4 ? &k_rollout<8, 4, true, false, true, true>
+  KernelFn f = per_lane == 1   ? &k_rollout_policy<8, 1>
+               : per_lane == 2 ? &k_rollout_policy<8, 2>
+               : per_lane == 4 ? &k_rollout_policy<8, 4>
                                : nullptr;
   if (!f) return hipErrorInvalidValue;
   LaunchArgs b = a;

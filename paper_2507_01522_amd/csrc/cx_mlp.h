@@ -70,34 +70,33 @@ __device__ __forceinline__ uint32_t draw_word(U4 w, int port) {
 
 // The level drawn from softmax of a port's logits (level 4 r + i in c[r][i],
 // r < R, L1 levels): the first level whose cumulative softmax weight exceeds
-// u times the total, i.e. the inverse of the distribution function at u.
+// u times the total, i.e. the inverse of the distribution function at u.  The
+// weights are 2^(z log2 e - zmax log2 e) (one fused multiply-add each); the
+// running sums kept as they are formed are the cumulative weights.
 __device__ __forceinline__ int sample_level(const f32x4 (&c)[kPolR], int R, int L1, float u) {
-  float zmax = c[0][0];
+  constexpr float kLog2e = 1.44269504088896341f;
+  float zmax = c[0][0];  // level 0 always exists
 #pragma unroll
   for (int r = 0; r < kPolR; ++r)
 #pragma unroll
     for (int i = 0; i < 4; ++i)
-      if (r < R && 4 * r + i < L1) zmax = fmaxf(zmax, c[r][i]);
-  constexpr float kLog2e = 1.44269504088896341f;
-  float ex[kPolR][4], tot = 0.f;
+      if (r < R && 4 * r + i < L1) zmax = c[r][i] > zmax ? c[r][i] : zmax;
+  const float zs = zmax * kLog2e;
+  float cum[kPolR][4], tot = 0.f;
 #pragma unroll
   for (int r = 0; r < kPolR; ++r)
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const bool in = r < R && 4 * r + i < L1;
-      ex[r][i] = in ? __builtin_amdgcn_exp2f((c[r][i] - zmax) * kLog2e) : 0.f;
-      tot += ex[r][i];
+      tot += in ? __builtin_amdgcn_exp2f(__builtin_fmaf(c[r][i], kLog2e, -zs)) : 0.f;
+      cum[r][i] = tot;
     }
   const float target = u * tot;
   int lev = 0;
-  float cum = 0.f;
 #pragma unroll
   for (int r = 0; r < kPolR; ++r)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      cum += ex[r][i];
-      lev += (r < R && 4 * r + i < L1 - 1 && cum <= target) ? 1 : 0;
-    }
+    for (int i = 0; i < 4; ++i) lev += (r < R && 4 * r + i < L1 - 1 && cum[r][i] <= target) ? 1 : 0;
   return lev;
 }
 
