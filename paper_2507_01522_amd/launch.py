@@ -15,7 +15,10 @@ LAUNCH = {
     "tiny": (16, 1, False),
     "scale": (16, 1, False),
 }
-# the policy rollout's one-step launches: 8 lanes x 4 slots, 4 waves per block
+# The policy rollout of an 8-, 16- or 32-slot SIMPLE class is the fused kernel,
+# whose launch is fixed (8 lanes per station, 4 waves per block, three blocks
+# per CU); this packing serves the two-kernel path of the other classes and of
+# the rollout that allocates nothing (8 lanes x 4 slots, 4 waves per block).
 POLICY_LAUNCH = (8, 4)
 
 
