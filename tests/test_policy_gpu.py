@@ -40,14 +40,14 @@ def hidden_abs(weights, x, hidden):
     return np.abs(np.tanh(xb @ w1 + b1))
 
 
-def check_levels(o, spec, weights, obs_in, levels, seed, env_ids, g0):
+def check_levels(o, spec, weights, obs_in, levels, seed, env_ids, g0, hidden=H):
     """obs_in [T][E][obs_dim] (oracle), levels [T][E][N] (GPU). Returns flip count."""
     c = o.OracleClass(spec)
     T, E = levels.shape[:2]
     flips = 0
     for t in range(T):
         for e in range(E):
-            _, k, margin = c.policy(H, weights, obs_in[t, e], seed, int(env_ids[e]), g0 + t, with_margin=True)
+            _, k, margin = c.policy(hidden, weights, obs_in[t, e], seed, int(env_ids[e]), g0 + t, with_margin=True)
             bad = levels[t, e] != k
             if bad.any():
                 assert np.all(margin[bad] < TIE), (
@@ -57,7 +57,7 @@ def check_levels(o, spec, weights, obs_in, levels, seed, env_ids, g0):
     return flips
 
 
-def teacher_forced(o, spec, weights, seed, gout, env_ids, T, g0=0, start=None):
+def teacher_forced(o, spec, weights, seed, gout, env_ids, T, g0=0, start=None, hidden=H):
     """Replay the GPU's levels in the oracle and check rewards, done flags and
     every level against the oracle's policy on the oracle's observations."""
     E, N, dim = len(env_ids), spec.n_ports, spec.obs_dim
@@ -71,7 +71,7 @@ def teacher_forced(o, spec, weights, seed, gout, env_ids, T, g0=0, start=None):
     PY.compare_rollout({"actions": act, "reward": gout["reward"], "done": gout["done"]}, ref, [spec],
                        np.zeros(E, np.int32), check_obs=False)
     obs_in = np.concatenate([obs0[None], ref["obs"][:-1].reshape(T - 1, E, dim)]) if T > 1 else obs0[None]
-    flips = check_levels(o, spec, weights, obs_in, act.reshape(T, E, N), seed, env_ids, g0)
+    flips = check_levels(o, spec, weights, obs_in, act.reshape(T, E, N), seed, env_ids, g0, hidden)
     assert flips <= max(2, T * E * N // 2000), f"{flips} near-tie flips"
     return ref, bs
 
@@ -131,6 +131,41 @@ def test_policy_rollout_teacher_forced(cxm, oracle_lib, out_mode):
     PY.compare_state(env.state_arrays(), bs, [spec], np.zeros(E, np.int32))
     assert g["done"][287].all() and g["done"].sum() == E
     assert len(np.unique(g["actions"])) == spec.n_levels + 1
+
+
+POLICY_CLASSES = {
+    # 8 and 16 ports on aligned splitters (SIMPLE, 8 and 16 slots): the fused rollout with 1 and
+    # 2 slots per lane; 40 ports under one transformer (padded to 64 slots): two kernels per step
+    "split2x4": (lambda: W.splitter_tree(2, 4, 60.0, 120.0), 64, 4),
+    "fan16": (lambda: W.fanout4_tree(16, 2), 96, 10),
+    "flat40": (lambda: W.single_transformer(40, 600.0), 256, 7),
+}
+
+
+@pytest.mark.parametrize("name", list(POLICY_CLASSES))
+def test_policy_classes_teacher_forced(cxm, oracle_lib, name):
+    """Other station sizes, hidden sizes and level counts (hidden 64 and 96:
+    padded hidden tiles; 5 and 8 levels: a padded level tile): 37 envs (a
+    ragged last block) x 300 steps replayed in the oracle, and every record
+    and the final state equal to the rollout that allocates nothing (two
+    kernels per step), bit for bit."""
+    make_spec, hidden, n_levels = POLICY_CLASSES[name]
+    spec = make_spec().replace(n_levels=n_levels)
+    weights = W.policy_weights(spec.n_ports, hidden=hidden, n_levels=n_levels, std=0.2, seed=31)
+    E, T, seed = 37, 300, 17
+    envs = []
+    for _ in range(2):
+        e = cxm.Env(spec, n_envs=E, seed=seed)
+        e.set_policy(hidden, weights)
+        envs.append(e)
+    g = PY.to_np(envs[0].rollout(T, cxm.ACT_POLICY, cxm.OUT_FULL))
+    ref, bs = teacher_forced(oracle_lib, spec, weights, seed, g, np.arange(E), T, hidden=hidden)
+    PY.compare_obs(g["obs"], ref["obs"], [spec], np.zeros(E, np.int32))
+    PY.compare_state(envs[0].state_arrays(), bs, [spec], np.zeros(E, np.int32))
+    b = PY.to_np(envs[1].rollout_policy_noalloc(T, cxm.OUT_FULL))
+    for k in g:
+        assert np.array_equal(g[k], b[k]), k
+    assert envs[0].get_state() == envs[1].get_state()
 
 
 def test_policy_modes_agree_and_split(cxm):
