@@ -246,6 +246,30 @@ def test_policy_full_size_sampled(cxm, oracle_lib):
     teacher_forced(oracle_lib, spec, weights, seed, g, ids, T)
 
 
+def test_policy_across_segments(cxm, oracle_lib):
+    """5,600,000 stations of 32 ports: one step's observations pass 4 GiB, so
+    the fused rollout runs the class as two segments; stations on both sides
+    of the cut, at block edges and at the ends replayed in the oracle."""
+    spec = W.policy_station()
+    weights = W.policy_weights(spec.n_ports, hidden=H, std=0.2, seed=14)
+    n, T, seed = 5_600_000, 3, 19
+    chunk = ((1 << 32) - 1) // (4 * spec.obs_dim)
+    chunk -= chunk % 64
+    assert chunk < n
+    env = cxm.Env(spec, n_envs=n, seed=seed)
+    env.set_policy(H, weights)
+    out = env.rollout(T, cxm.ACT_POLICY, cxm.OUT_ACT_REWARD)
+    ids = np.array([0, 1, 31, 32, chunk - 33, chunk - 1, chunk, chunk + 1, chunk + 32, n - 33, n - 2, n - 1],
+                   np.int64)
+    N = spec.n_ports
+    cols = (ids[:, None] * N + np.arange(N)).ravel()
+    g = {"actions": out["actions"][:, torch.from_numpy(cols).cuda()].cpu().numpy(),
+         "reward": out["reward"][:, torch.from_numpy(ids).cuda()].cpu().numpy(),
+         "done": out["done"][:, torch.from_numpy(ids).cuda()].cpu().numpy()}
+    del out
+    teacher_forced(oracle_lib, spec, weights, seed, g, ids, T)
+
+
 def test_policy_invalid(cxm):
     spec = W.policy_station()
     weights = W.policy_weights(spec.n_ports, hidden=H, seed=1)

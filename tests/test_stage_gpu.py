@@ -106,7 +106,8 @@ def test_staged_matches_oracle(cxm, oracle_lib):
 
 
 def test_staged_policy_loop(cxm):
-    """Levels from the MLP, one-step launches with the stage: the same records."""
+    """Levels from the MLP with the context's stage off and on: the same records
+    (the fused policy rollout stages its observations either way)."""
     spec = W.policy_station()
     weights = W.policy_weights(spec.n_ports, hidden=256, std=0.2, seed=11)
     outs = []
