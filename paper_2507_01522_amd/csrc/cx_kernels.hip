@@ -287,7 +287,7 @@ typedef __attribute__((address_space(3))) uint8_t lds_u8;
 template <int K1>
 __device__ __forceinline__ void policy_phase(const LaunchArgs::Pol &pl, const lds_float *stage, lds_char *lds,
                                              int obs_dim, int N, int blk_envs, int wv, uint32_t env_id0,
-                                             uint32_t g, uint32_t k0, uint32_t k1) {
+                                             uint32_t g, uint32_t k0, uint32_t k1, bool convert) {
   constexpr int W = kPolRolloutWaves, NT = kPolRolloutEnvs / 16, CPR = 4 * K1;  // chunks of 8 per row
   const int lane = __lane_id(), col = lane & 15, lg = lane >> 4, tid = wv * 64 + lane;
   const int in_dim = pl.in_dim, R = pl.R, G = pl.G, L1 = pl.L1;
@@ -296,26 +296,30 @@ __device__ __forceinline__ void policy_phase(const LaunchArgs::Pol &pl, const ld
   lds_u8 *act = reinterpret_cast<lds_u8 *>(lds + pl.act_off);
   const u32x4 zero = {0u, 0u, 0u, 0u};
   // observations -> BF16 (features past in_dim and envs past the block's: 0);
-  // a row of the stage starts 16-byte aligned (obs_dim is a multiple of 4)
-  for (int c = tid; c < kPolRolloutEnvs * CPR; c += 64 * W) {
-    const int e = c / CPR, k = c % CPR, f = 8 * k;
-    const lds_float *row = stage + e * obs_dim + f;
-    u32x4 v = zero;
-    if (e < blk_envs) {
-      if (f + 8 <= in_dim) {
-        const f32x4 x = *reinterpret_cast<const lds_f32x4 *>(row);
-        const f32x4 y = *reinterpret_cast<const lds_f32x4 *>(row + 4);
-        v = u32x4{pack2(x.x, x.y), pack2(x.z, x.w), pack2(y.x, y.y), pack2(y.z, y.w)};
-      } else if (f < in_dim) {
-        float x[8];
+  // a row of the stage starts 16-byte aligned (obs_dim is a multiple of 4).
+  // Without observation records the step wrote its values straight into xb
+  // (convert = false), whose padding the first conversion zeroed.
+  if (convert) {
+    for (int c = tid; c < kPolRolloutEnvs * CPR; c += 64 * W) {
+      const int e = c / CPR, k = c % CPR, f = 8 * k;
+      const lds_float *row = stage + e * obs_dim + f;
+      u32x4 v = zero;
+      if (e < blk_envs) {
+        if (f + 8 <= in_dim) {
+          const f32x4 x = *reinterpret_cast<const lds_f32x4 *>(row);
+          const f32x4 y = *reinterpret_cast<const lds_f32x4 *>(row + 4);
+          v = u32x4{pack2(x.x, x.y), pack2(x.z, x.w), pack2(y.x, y.y), pack2(y.z, y.w)};
+        } else if (f < in_dim) {
+          float x[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) x[j] = f + j < in_dim ? row[j] : 0.f;
-        v = u32x4{pack2(x[0], x[1]), pack2(x[2], x[3]), pack2(x[4], x[5]), pack2(x[6], x[7])};
+          for (int j = 0; j < 8; ++j) x[j] = f + j < in_dim ? row[j] : 0.f;
+          v = u32x4{pack2(x[0], x[1]), pack2(x[2], x[3]), pack2(x[4], x[5]), pack2(x[6], x[7])};
+        }
       }
+      xb[e * kPolXbRow + k] = v;
     }
-    xb[e * kPolXbRow + k] = v;
+    __syncthreads();
   }
-  __syncthreads();
   // first product: this wave's pairs of 16-unit hidden tiles, both pairs per
   // K-step so that each observation fragment is read once.  Weight fragments
   // come in buffer loads: one resource per matrix, the fragment's offset a
@@ -567,7 +571,7 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
     const float *src = pol->obs0 + sg.obs_off + (int64_t)env_blk0 * obs_dim;
     for (int i = wv * 64 + lane; i < n_blk; i += kPolRolloutWaves * 64) stage[i] = gld(src, i);
     __syncthreads();
-    policy_phase<kPolSteps1>(*pol, stage, lds, obs_dim, N, (int)blk_envs, wv, env_id0, g, k0, k1);
+    policy_phase<kPolSteps1>(*pol, stage, lds, obs_dim, N, (int)blk_envs, wv, env_id0, g, k0, k1, true);
   }
 
   for (int t = 0; t < dy.T; ++t, ++g) {
@@ -1107,7 +1111,14 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
               put(4u * (uint32_t)C.day_obs, 4u * (uint32_t)l, l == 0 ? (float)dday * C.inv_n_days : (dday % 7 >= 5 ? 1.0f : 0.0f));
           }
         };
-        if constexpr (STAGE) {
+        if (POL && !w_obs) {
+          // the fused policy without observation records: the values go to
+          // the MLP's BF16 rows directly (their padding was zeroed by the
+          // first conversion)
+          typedef __attribute__((address_space(3))) uint16_t lds_u16;
+          lds_u16 *xr = reinterpret_cast<lds_u16 *>(lds + pol->xb_off) + (env - env_blk0) * (kPolXbRow * 8);
+          obs_record([&](uint32_t fo, uint32_t lo, float v) { xr[(fo + lo) >> 2] = (uint16_t)pack2(v, 0.f); });
+        } else if constexpr (STAGE) {
           lds_float *sb = stage + (POL ? 0 : (t & 1) * stage_floats) + pad;
           obs_record([&](uint32_t fo, uint32_t lo, float v) {
             *reinterpret_cast<lds_float *>(reinterpret_cast<__attribute__((address_space(3))) char *>(sb) + stage_bo +
@@ -1174,7 +1185,8 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
       // the next step's levels (the phase's barriers keep the stage until the
       // flush above has read it)
       if (t + 1 < dy.T)
-        policy_phase<kPolSteps1>(*pol, stage, lds, obs_dim, N, (int)blk_envs, wv, env_id0, g + 1u, k0, k1);
+        policy_phase<kPolSteps1>(*pol, stage, lds, obs_dim, N, (int)blk_envs, wv, env_id0, g + 1u, k0, k1,
+                                 w_obs);
     }
   }
 
@@ -1275,6 +1287,18 @@ __global__ __launch_bounds__(512) void k_rollout(LaunchArgs a) {
   rollout_body<L, P, SIMPLE, EXT, STAGE, false>(a);
 }
 
+// SIMPLE classes of 1 or 2 slots per lane: the kernel held to CX_SIMPLE_WAVES
+// waves per SIMD (96 VGPRs at 5, a few of them spilled): their step is issue-
+// bound, and the extra waves hide its latencies.
+#ifndef CX_SIMPLE_WAVES
+#define CX_SIMPLE_WAVES 5
+#endif
+template <int L, int P, bool STAGE>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(CX_SIMPLE_WAVES))) void k_rollout_simple(
+    LaunchArgs a) {
+  rollout_body<L, P, true, false, STAGE, false>(a);
+}
+
 // The fused policy rollout (4 waves per block): three blocks per CU, so that
 // one block's matrix-core work and memory waits overlap the others' steps.
 template <int L, int P>
@@ -1316,14 +1340,19 @@ using KernelFn = void (*)(LaunchArgs);
 #define CX_KINDS(L, P)                                                                              \
   &k_rollout<L, P, false, false, false>, &k_rollout<L, P, true, false, false>,                        \
       &k_rollout<L, P, false, true, false>, &k_rollout<L, P, true, false, true>
+#define CX_KINDS_SIMPLE(L, P)                                                                       \
+  &k_rollout<L, P, false, false, false>, &k_rollout_simple<L, P, false>,                              \
+      &k_rollout<L, P, false, true, false>, &k_rollout_simple<L, P, true>
 
 // Kernel of each launch kind: packing id (P index * 5 + L index, as pack_id())
 // times kNumKinds, plus the kernel kind (kKind*).
 const KernelFn kKernels[kNumKinds * kNumPackings] = {
-    CX_KINDS(4, 1), CX_KINDS(8, 1), CX_KINDS(16, 1), CX_KINDS(32, 1), CX_KINDS(64, 1),
-    CX_KINDS(4, 2), CX_KINDS(8, 2), CX_KINDS(16, 2), CX_KINDS(32, 2), CX_KINDS(64, 2),
+    CX_KINDS_SIMPLE(4, 1), CX_KINDS_SIMPLE(8, 1), CX_KINDS_SIMPLE(16, 1), CX_KINDS_SIMPLE(32, 1),
+    CX_KINDS_SIMPLE(64, 1), CX_KINDS_SIMPLE(4, 2), CX_KINDS_SIMPLE(8, 2), CX_KINDS_SIMPLE(16, 2),
+    CX_KINDS_SIMPLE(32, 2), CX_KINDS_SIMPLE(64, 2),
     CX_KINDS(4, 4), CX_KINDS(8, 4), CX_KINDS(16, 4), CX_KINDS(32, 4), CX_KINDS(64, 4)};
 #undef CX_KINDS
+#undef CX_KINDS_SIMPLE
 
 // Arguments of one group's launch: its slice of the segment table and its LDS
 // (the stay table; for staging packings the observation stages when

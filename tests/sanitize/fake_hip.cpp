@@ -268,6 +268,16 @@ void rollout_params(const std::string &n, int *L, int *P, bool *simple, bool *ex
   const size_t a = n.find('<');
   int l = 0, p = 0;
   char s1[8] = {0}, s2[8] = {0}, s3[8] = {0}, s4[8] = {0};
+  if (n.find("k_rollout_simple<") != std::string::npos) {  // SIMPLE classes: <L, P, STAGE>
+    if (a == std::string::npos || std::sscanf(n.c_str() + a, "<%d, %d, %5[a-z]>", &l, &p, s3) != 3)
+      die("cannot parse %s", n.c_str());
+    *L = l;
+    *P = p;
+    *simple = true;
+    *ext = *pol = false;
+    *stage = std::strcmp(s3, "true") == 0;
+    return;
+  }
   if (n.find("k_rollout_policy<") != std::string::npos) {  // the fused policy rollout: <L, P>
     if (a == std::string::npos || std::sscanf(n.c_str() + a, "<%d, %d>", &l, &p) != 2) die("cannot parse %s", n.c_str());
     *L = l;
@@ -449,7 +459,8 @@ void run_policy(const Launch &l) {
 
 void run_kernel(const Launch &l) {
   const KernelInfo &k = kernel(l.func);
-  if (k.name.find("k_rollout<") != std::string::npos || k.name.find("k_rollout_policy<") != std::string::npos) {
+  if (k.name.find("k_rollout<") != std::string::npos || k.name.find("k_rollout_policy<") != std::string::npos ||
+      k.name.find("k_rollout_simple<") != std::string::npos) {
     run_rollout(l, k);
   } else if (k.name.find("k_policy(") != std::string::npos) {
     run_policy(l);
