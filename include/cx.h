@@ -281,10 +281,17 @@ cx_status cx_step_ex(cx_ctx *ctx, cx_action_mode mode, const uint8_t *actions_in
  * cx_traj; NULL members are not written).  actions_in_dev ([T][total_ports] uint8) is read only for EXTERNAL.
  * The launch is captured once per (T, modes, buffers) into a HIP graph and
  * replayed.  Results equal T calls of cx_step_ex.
- * CX_ACT_POLICY instead runs, per step, the policy kernel (observation ->
- * levels, cx_policy_sample) and then the one-step kernel with those levels;
- * the observations in between stay in a scratch buffer of the context unless
- * out_mode is FULL.  Requires cx_set_policy. */
+ * CX_ACT_POLICY draws every step's levels from the policy (cx_set_policy) on
+ * the observation of the state before the step.  For a SIMPLE class of 8, 16
+ * or 32 slots (uniform per-level limits, no padding) the whole rollout is one
+ * launch of a fused persistent kernel that runs the perceptron between steps,
+ * its observations only in on-chip memory; other classes run, per step, the
+ * policy kernel (observation -> levels, as cx_policy_sample) and then the
+ * one-step kernel with those levels, the observations in between in a scratch
+ * buffer of the context unless out_mode is FULL.  Both compute the same
+ * products in the same order, so their records are the same.  The rollout
+ * starts from the observation of the current state (as cx_observe).  With
+ * CX_OUT_FULL, out->obs must be 16-byte aligned.  Requires cx_set_policy. */
 cx_status cx_rollout(cx_ctx *ctx, int32_t T, cx_action_mode mode, cx_out_mode out_mode,
                      const uint8_t *actions_in_dev, const cx_traj *out);
 
@@ -295,9 +302,9 @@ cx_status cx_rollout(cx_ctx *ctx, int32_t T, cx_action_mode mode, cx_out_mode ou
  * (total_ports bytes) -- lives in a fixed array of the library's device image,
  * CX_NOALLOC_SCRATCH_BYTES per GPU, held until the process ends, instead of a
  * buffer the context allocates.  The call allocates nothing (no hipMalloc, no
- * hipFree, no allocating library routine) and launches the same kernels as
- * cx_rollout, so its records are bit for bit those of cx_rollout with
- * CX_ACT_POLICY on an equal context.  The caller passes the outputs (out, as
+ * hipFree, no allocating library routine) and always runs the two kernels per
+ * step, whose records are bit for bit those of cx_rollout with CX_ACT_POLICY
+ * on an equal context (fused or not).  The caller passes the outputs (out, as
  * for cx_rollout) and must have created the context and set its policy
  * beforehand.  CX_E_INVALID (nothing launched) if the context needs more
  * scratch than the fixed size (about 41,000 envs of 32 ports) or has no policy.
@@ -314,8 +321,9 @@ cx_status cx_rollout_policy_noalloc(cx_ctx *ctx, int32_t T, cx_out_mode out_mode
  * w1 [obs_dim][hidden], b1 [hidden], w2 [hidden][n_ports*(n_levels+1)], b2.
  * Products run on the matrix cores in BF16 with FP32 accumulation; the level of
  * each port is drawn from the softmax of its logits: the first level whose
- * cumulative probability exceeds u, u = (top 24 bits of word 0 of Philox
- * (env, g, port, 3) + 1/2) 2^-24.
+ * cumulative probability exceeds u, u = (top 24 bits of word (port / 16) mod 4
+ * of Philox (env, g, port mod 16 + 16 (port / 64), 3) + 1/2) 2^-24 (ports 16
+ * apart share a Philox call).
  * Only single-class contexts of charging-only stations (no V2G, no battery). */
 cx_status cx_set_policy(cx_ctx *ctx, int32_t hidden, const uint16_t *w1_host, const uint16_t *b1_host,
                         const uint16_t *w2_host, const uint16_t *b2_host);
