@@ -279,11 +279,11 @@ typedef __attribute__((address_space(3))) uint8_t lds_u8;
 // class's K-steps of 32 features; 8 x 32 hidden units and 3 level tiles, the
 // largest, over weights padded with zeros -- such steps add exact zeros), so
 // that they are straight-line code whose loads are all issued ahead of the
-// matrix-core work.  LDS: hb
-// (8 x 2 hidden-unit fragments, over the stage once it has been read), xb (the
-// observations in BF16, 256 features per env, zero past in_dim, rows 33
-// fragments apart so that the 16 envs of a tile fall in different banks) and
-// act (a level byte per port and env).  wv: this wave in the block.
+// matrix-core work.  LDS: hb (8 x 2 hidden-unit fragments, over the stage once
+// it has been read), xb (the observations in BF16, 256 features per env, zero
+// past in_dim, rows 33 fragments apart so that the 16 envs of a tile fall in
+// different banks) and act (a level byte per port and env).  wv: this wave in
+// the block; convert: the step left its observations in the FP32 stage.
 template <int K1>
 __device__ __forceinline__ void policy_phase(const LaunchArgs::Pol &pl, const lds_float *stage, lds_char *lds,
                                              int obs_dim, int N, int blk_envs, int wv, uint32_t env_id0,
@@ -1218,7 +1218,8 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
 #undef CX_OCCUPIED
 
 // One kernel per packing (lanes per station L, slots per lane P) and class
-// kind (general, SIMPLE, bidirectional), so that each keeps its own register budget.
+// kind (general, SIMPLE, bidirectional), so that each keeps its own register
+// budget; the entry points below add the launch bounds of each kind.
 template <int L, int P, bool SIMPLE, bool EXT, bool STAGE, bool POL>
 __device__ __forceinline__ void rollout_body(LaunchArgs a) {
   extern __shared__ uint32_t lds_tdwell[];
