@@ -541,7 +541,6 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
   const uint32_t act_bo = (uint32_t)env * (uint32_t)n_act;
   const uint32_t env_bo = (uint32_t)env;
   // wave-uniform record pointers of the current step, advanced every step
-  // (a record that is not written keeps a NULL pointer and a zero stride)
   const bool w_obs = dy.out_mode == CX_OUT_FULL && dy.obs != nullptr;
   const bool w_act = (dy.out_mode == CX_OUT_FULL || dy.out_mode == CX_OUT_ACT_REWARD) && dy.act != nullptr;
   float *ob_t = w_obs ? dy.obs + sg.obs_off : nullptr;
@@ -552,6 +551,9 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
   const int64_t obs_step = w_obs ? dy.obs_stride : 0;
   const int64_t act_step = (w_act || ai_t) ? dy.act_stride : 0;
   const int64_t env_step = (rw_t || dn_t) ? dy.env_stride : 0;
+  // rewards and done flags share their step: each is written under its own
+  // flag (with one of them NULL, its advanced pointer is no address)
+  const bool w_rew = rw_t != nullptr, w_done = dn_t != nullptr;
   // the block's LDS observation stage (staging packings, whenever observations
   // are written): the block's first env, the floats the block writes per step
   // and this lane's env in the stage
@@ -1162,8 +1164,8 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
         }
       }
       if (l == 0) {
-        if (rw_t) st_at(rw_t, 4u * env_bo_t, r);
-        if (dn_t) st_at(dn_t, env_bo_t, (uint8_t)(done ? 1 : 0));
+        if (w_rew) st_at(rw_t, 4u * env_bo_t, r);
+        if (w_done) st_at(dn_t, env_bo_t, (uint8_t)(done ? 1 : 0));
       }
     }
     ob_t += obs_step;
@@ -1217,13 +1219,24 @@ __device__ __forceinline__ void run_group(const SegDev &sg, const Dyn &dy, int g
 
 #undef CX_OCCUPIED
 
+// The launch's blocks are dealt to the chip's 8 XCDs in turn (block i to XCD
+// i mod 8).  Numbered so that each XCD's blocks are consecutive, blocks of
+// adjacent envs, whose small records (actions, rewards, done flags) share
+// 128-byte lines, write those lines through the same L2.
+__device__ __forceinline__ int xcd_block() {
+  const int i = blockIdx.x, n = gridDim.x;
+  const int x = i & 7, q = n >> 3, r = n & 7;
+  return x * q + (x < r ? x : r) + (i >> 3);
+}
+
 // One kernel per packing (lanes per station L, slots per lane P) and class
 // kind (general, SIMPLE, bidirectional), so that each keeps its own register
 // budget; the entry points below add the launch bounds of each kind.
 template <int L, int P, bool SIMPLE, bool EXT, bool STAGE, bool POL>
 __device__ __forceinline__ void rollout_body(LaunchArgs a) {
   extern __shared__ uint32_t lds_tdwell[];
-  const int b = blockIdx.x;
+  // (the staged kernels, whose blocks write whole runs of adjacent envs)
+  const int b = STAGE ? __builtin_amdgcn_readfirstlane(xcd_block()) : (int)blockIdx.x;
   int lo = 0, hi = a.n_segs - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
