@@ -105,6 +105,24 @@ def test_staged_matches_oracle(cxm, oracle_lib):
     PY.compare_state(env.state_arrays(), bs, specs, ec)
 
 
+@pytest.mark.parametrize("stage", [False, True])
+def test_empty_classes(cxm, oracle_lib, stage):
+    """Classes with no envs before, between and after populated ones: they get
+    no segment and shift no record; the others match the oracle."""
+    o = oracle_lib
+    specs = W.mixture_classes()[:7] + [W.v2g_station()]
+    counts = [0, 3, 0, 5, 0, 0, 2, 0]
+    ec = ec_of(counts)
+    env = make(cxm, specs, ec, 48, stage)
+    info = env.info()
+    assert info.n_envs == sum(counts)
+    assert [env.class_info(c).n_envs for c in range(len(specs))] == counts
+    g = PY.to_np(env.rollout(60, cxm.ACT_RANDOM))
+    bs = o.BatchState([o.OracleClass(s) for s in specs], ec)
+    PY.compare_rollout(g, o.rollout(bs, 48, 60), specs, ec)
+    PY.compare_state(env.state_arrays(), bs, specs, ec)
+
+
 def test_staged_policy_loop(cxm):
     """Levels from the MLP with the context's stage off and on: the same records
     (the fused policy rollout stages its observations either way)."""
