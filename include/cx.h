@@ -410,7 +410,7 @@ void cx_destroy(cx_ctx *ctx);
 typedef struct cx_server cx_server;
 
 typedef struct {
-  int32_t chunk_steps;      /* steps per launch (default 32) */
+  int32_t chunk_steps;      /* steps per launch (default 144) */
   int32_t max_active;       /* cap on concurrently admitted requests (default 256) */
   int32_t waves_per_block;  /* default 4 */
   int32_t simulate_ns;      /* 0: run on the GPU.  > 0: no device is touched and a chunk

@@ -461,7 +461,7 @@ cx_status cx_server_create(size_t hbm_budget_bytes, const cx_server_opts *opts, 
   if (hbm_budget_bytes == 0) return fail(CX_E_INVALID, "budget must be > 0");
   cx_server_opts o{32, 256, 4, 0};
   if (opts) o = *opts;
-  if (o.chunk_steps <= 0) o.chunk_steps = 32;
+  if (o.chunk_steps <= 0) o.chunk_steps = 144;
   if (o.max_active <= 0) o.max_active = 256;
   if (o.waves_per_block <= 0) o.waves_per_block = 4;
   if (o.chunk_steps > 4096 || o.max_active > 65536 || o.waves_per_block > kMaxWaves || o.simulate_ns < 0)

@@ -445,7 +445,7 @@ class Server:
     station class, size and horizon share every launch; results are identical
     alone or in a mix.  simulate_ns > 0 runs the scheduler on a host clock only."""
 
-    def __init__(self, budget_bytes: int, chunk_steps: int = 32, max_active: int = 256,
+    def __init__(self, budget_bytes: int, chunk_steps: int = 144, max_active: int = 256,
                  waves_per_block: int = 4, simulate_ns: int = 0):
         if simulate_ns <= 0 and not torch.cuda.is_available():
             raise CxError(-3, "no HIP device visible to torch")
